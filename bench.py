@@ -1,0 +1,243 @@
+"""Benchmark of the permutation-avoiding FFT convolution on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+
+Default workload: 3-D periodic convolution, 256 x 256 x 256 complex128,
+radix 4 per axis, input iid N(0,1), filter = unit-sum periodic Gaussian of
+width 4 (seeded synthetic data).  A step is one full convolution
+y = x (*) h with the filter spectrum resident on the device and the input
+already in HBM.  Prints ONE JSON line: conv/s, the roofline of the dominant
+kernel (the axis-pass kernel, timed with HIP events on its own stream during
+the timed region), the explicit-permutation comparison variant on the same
+GPU, per-convolution latency percentiles, the error against the FP64 oracle,
+and the oracle itself timed on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import glob
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2506_12718_amd", "csrc", "*"))):
+        if f.endswith((".hip", ".h", ".cpp")):
+            with open(f, "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(workload):
+    """HBM bytes per launch of the dominant kernel from committed rocprofv3
+    counter runs, if they were taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "%s_traffic.json" % workload)
+    if not os.path.exists(path):
+        return None
+    try:
+        with open(path) as f:
+            d = json.load(f)
+        if d.get("kernel_source_hash") != kernel_source_hash():
+            return None
+        return d.get("hbm_bytes_per_launch")
+    except Exception:
+        return None
+
+
+def pct(a, q):
+    return float(np.percentile(np.asarray(a), q))
+
+
+# ----------------------------------------------------------------- workloads
+
+def wl_conv3d(dtype_name):
+    from paper_2506_12718_amd import inputs
+    x, h = inputs.conv3d_gaussian()
+    return dict(name="conv3d_256_%s_r4" % dtype_name, x=x, h=h, radix=[4, 4, 4],
+                domain="spatial", rhos=[[4] * 4] * 3,
+                config={"workload": "3-D periodic convolution 256x256x256, radix 4 per axis, "
+                                    "x iid N(0,1), wrapped Gaussian filter sigma=4",
+                        "dims": [256, 256, 256], "radix": 4, "filter": "gaussian_sigma4"})
+
+
+def wl_conv1d(dtype_name):
+    from paper_2506_12718_amd import inputs
+    x, h = inputs.conv1d_4096()
+    return dict(name="conv1d_4096_%s_r4" % dtype_name, x=x, h=h, radix=[4], domain="spatial",
+                rhos=[[4] * 6],
+                config={"workload": "1-D circular convolution n=4096, radix 4, single instance",
+                        "dims": [4096], "radix": 4})
+
+
+def wl_conv2d(dtype_name):
+    from paper_2506_12718_amd import inputs
+    x, hh = inputs.spectral_filter_case(31, (2187, 2187))
+    return dict(name="conv2d_2187_%s_r3" % dtype_name, x=x, h=hh, radix=[3, 3],
+                domain="spectral_natural", rhos=[[3] * 7] * 2,
+                config={"workload": "2-D convolution 2187x2187, radix 3, spectral filter",
+                        "dims": [2187, 2187], "radix": 3})
+
+
+def wl_conv1d5(dtype_name):
+    from paper_2506_12718_amd import inputs
+    x, hh = inputs.spectral_filter_case(32, (5 ** 9,))
+    return dict(name="conv1d_5p9_%s_r5" % dtype_name, x=x, h=hh, radix=[5],
+                domain="spectral_natural", rhos=[[5] * 9],
+                config={"workload": "1-D convolution n=5^9=1953125, radix 5, spectral filter",
+                        "dims": [5 ** 9], "radix": 5})
+
+
+WORKLOADS = {"conv3d": wl_conv3d, "conv1d": wl_conv1d, "conv2d": wl_conv2d, "conv1d5": wl_conv1d5}
+
+
+def measure(pafc, torch, wl, tdtype, variant, steps, warmup):
+    """Plan, set the filter, warm up, then time `steps` convolutions with a
+    HIP event around every kernel launch.  Returns a dict of results."""
+    plan = pafc.Plan(wl["x"].shape, tdtype, radix=wl["radix"], variant=variant)
+    xd = torch.from_numpy(wl["x"]).to(tdtype).cuda()
+    hd = torch.from_numpy(wl["h"]).to(tdtype).cuda()
+    yd = torch.empty_like(xd)
+    plan.set_filter(hd, domain=wl["domain"])
+    del hd
+    for _ in range(warmup):
+        plan.convolve(xd, out=yd)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ms_pass, bytes_pass, ms_rep = plan.profile_passes(xd, yd, reps=steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    desc = pafc.describe(wl["x"].shape, "c128" if tdtype == torch.complex128 else "c64",
+                         wl["radix"], variant)
+    y = yd.cpu().numpy()
+    plan.close()
+    del xd, yd
+    torch.cuda.empty_cache()
+    return dict(wall=wall, ms_pass=ms_pass, bytes_pass=bytes_pass, ms_rep=ms_rep, desc=desc, y=y,
+                labels=desc["conv_passes"])
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="conv3d", choices=sorted(WORKLOADS))
+    ap.add_argument("--dtype", default="c128", choices=["c128", "c64"])
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing and error check")
+    ap.add_argument("--no-compare", action="store_true", help="skip the comparison variants")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(each convolution runs on a single MI355X); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2506_12718_amd as pafc
+    pafc.lib()
+    torch.cuda.set_device(0)
+    tdtype = torch.complex128 if args.dtype == "c128" else torch.complex64
+    wl = WORKLOADS[args.workload](args.dtype)
+    N = wl["x"].size
+    elem = 16 if args.dtype == "c128" else 8
+
+    print("bench: %s steps=%d warmup=%d" % (wl["name"], args.steps, args.warmup),
+          file=sys.stderr, flush=True)
+    main_r = measure(pafc, torch, wl, tdtype, "perm_free", args.steps, args.warmup)
+    total_s = sum(main_r["ms_rep"]) / 1e3
+    value = args.steps / main_r["wall"]
+    ms_step = main_r["wall"] * 1e3 / args.steps
+
+    # dominant kernel: the axis-pass kernel (every pass of this plan)
+    kern = [i for i, l in enumerate(main_r["labels"]) if not l.startswith(("mul", "permute"))]
+    k_ms = sum(main_r["ms_pass"][i] for i in kern)
+    k_bytes = sum(main_r["bytes_pass"][i] for i in kern)
+    nlaunch = len(kern)
+    achieved = (k_bytes / nlaunch) / (k_ms / nlaunch * 1e-3) / 1e9
+    traffic = load_traffic(wl["name"])
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "kernel": "pass_kernel", "launches_per_conv": nlaunch,
+            "alg_bytes_per_launch": k_bytes / nlaunch,
+            "avg_launch_ms": round(k_ms / nlaunch, 5)}
+    alg_bytes = main_r["desc"]["hbm_bytes_conv"]
+    out = {
+        "metric": "convolutions/s + HBM GB/s (% roofline), perm-free vs explicit-perm; p99 latency",
+        "value": round(value, 3),
+        "unit": "conv/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.dtype == "c128" else "f32",
+        "data": "synthetic",
+        "config": dict(wl["config"], variant="perm_free", dtype=args.dtype,
+                       passes=main_r["labels"]),
+        "hbm_gbps_alg": round(alg_bytes * value / 1e9, 1),
+        "hbm_frac_alg": round(alg_bytes * value / 1e9 / HBM_PEAK_GBS, 4),
+        "alg_bytes_per_conv": alg_bytes,
+        "latency_ms": {"p50": round(pct(main_r["ms_rep"], 50), 5),
+                       "p99": round(pct(main_r["ms_rep"], 99), 5),
+                       "mean": round(total_s * 1e3 / args.steps, 5)},
+        "ms_per_pass": [round(v, 5) for v in main_r["ms_pass"]],
+        "roofline": roof,
+    }
+    if not args.no_compare:
+        comp = {}
+        for variant in ("explicit_perm", "perm_free_unfused"):
+            print("bench: comparison variant %s" % variant, file=sys.stderr, flush=True)
+            r = measure(pafc, torch, wl, tdtype, variant, max(5, args.steps // 2), 2)
+            v = len(r["ms_rep"]) / r["wall"]
+            comp[variant] = {
+                "conv_per_s": round(v, 3),
+                "ms_per_conv": round(1e3 / v, 5),
+                "p99_ms": round(pct(r["ms_rep"], 99), 5),
+                "alg_bytes_per_conv": r["desc"]["hbm_bytes_conv"],
+                "hbm_gbps_alg": round(r["desc"]["hbm_bytes_conv"] * v / 1e9, 1),
+                "ms_per_pass": [round(t, 5) for t in r["ms_pass"]],
+                "passes": r["labels"],
+                "max_abs_diff_vs_perm_free": float(np.abs(r["y"] - main_r["y"]).max()),
+            }
+        comp["speedup_perm_free_over_explicit"] = round(
+            value / comp["explicit_perm"]["conv_per_s"], 3)
+        out["compare"] = comp
+    if not args.no_cpu:
+        import oracle
+        print("bench: oracle on host cores", file=sys.stderr, flush=True)
+        x = wl["x"]
+        h = wl["h"]
+        if args.dtype == "c64":
+            x = x.astype(np.complex64).astype(np.complex128)
+            h = h.astype(np.complex64).astype(np.complex128)
+        t0 = time.perf_counter()
+        if wl["domain"] == "spatial":
+            ref = oracle.conv_fft(x, h, wl["rhos"])
+        else:
+            ref = oracle.fft(h * oracle.fft(x, wl["rhos"]), wl["rhos"], inverse=True)
+        t_cpu = time.perf_counter() - t0
+        err = float(np.linalg.norm(main_r["y"] - ref) / np.linalg.norm(ref))
+        out["rel_l2_vs_fp64_oracle"] = err
+        out["cpu_baseline"] = {
+            "value": round(1.0 / t_cpu, 5), "unit": "conv/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": "one full convolution of the same workload (standard FFT route with "
+                      "explicit index reversal, FP64, OpenMP over pencils); %.2f s" % t_cpu}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,281 @@
+/*
+ * pafc.h -- permutation-avoiding FFT-based circular convolution on AMD
+ * Instinct MI355X (gfx950).  C ABI.
+ *
+ * The operation (Venkovic & Anzt, arXiv 2506.12718, Sec. "1D problem",
+ * eq. convolution, and Sec. "Multi-dimensional problem",
+ * eq. convolution-multi-dimensional): for complex arrays X, H of shape
+ * n_1 x ... x n_d (d = 1, 2, 3), row-major with the last index fastest
+ * (definition of vec in Sec. "Multi-dimensional problem"),
+ *
+ *     Y = DFT^{-1}( DFT(H) o DFT(X) ),   i.e.  Y_j = sum_k X_k H_{(j-k) mod n}
+ *
+ * with DFT sign w_n = exp(-2 pi i / n).  It is evaluated without any index
+ * reversal (eq. 35 and the d-way form of Sec. "Permutation-avoiding
+ * multi-dimensional convolution"; mixed radix: Sec. "Mixed-radix
+ * framework"):
+ *
+ *     vec(Y) = (conj A_1 (x) ... (x) conj A_d) [ Hdr o (A_1^T (x) ... (x) A_d^T) vec(X) ]
+ *
+ * where A_i^T is a decimation-in-frequency transform that leaves its output
+ * in digit-reversed order, Hdr = (A_1^T (x) ... (x) A_d^T) vec(H) / N is the
+ * filter spectrum held in that same order on the device, and conj A_i is a
+ * decimation-in-time inverse that takes digit-reversed input and returns
+ * natural order.  N = n_1 ... n_d.
+ *
+ * Conventions for every call:
+ *   - Complex data are interleaved (re, im): PAFC_C64 = 2 x float (8 bytes
+ *     per element, torch.complex64), PAFC_C128 = 2 x double (16 bytes,
+ *     torch.complex128).
+ *   - Pointers named *_dev are device pointers (hipMalloc or equivalent) on
+ *     the device that was current when the plan was created.  The caller
+ *     owns them.
+ *   - hip_stream is a hipStream_t passed as void*; NULL means the default
+ *     stream.  Every call that takes a stream is stream-ordered and
+ *     asynchronous: it enqueues work and returns without a host sync.
+ *   - No exception crosses the ABI; every call returns a pafc_status.
+ *   - A plan owns device memory (twiddles, filter spectrum, scratch) that is
+ *     shared by all calls on that plan: a single plan must be used on one
+ *     stream at a time.  Distinct plans are independent.
+ */
+#ifndef PAFC_H
+#define PAFC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum pafc_status {
+  PAFC_SUCCESS = 0,
+  PAFC_ERROR_INVALID_VALUE = 1,    /* null/misaligned pointer, bad ndim, n_i < 2, bad enum */
+  PAFC_ERROR_UNSUPPORTED_SIZE = 2, /* prime factor outside {2,3,5}, or n_i != r^t for an explicit uniform radix */
+  PAFC_ERROR_OUT_OF_MEMORY = 3,    /* device allocation failed */
+  PAFC_ERROR_DEVICE = 4,           /* HIP runtime or launch error */
+  PAFC_ERROR_FILTER_NOT_SET = 5    /* pafc_convolve before pafc_set_filter */
+} pafc_status;
+
+typedef enum pafc_dtype {
+  PAFC_C64 = 1,  /* complex float32, interleaved */
+  PAFC_C128 = 2  /* complex float64, interleaved */
+} pafc_dtype;
+
+typedef enum pafc_variant {
+  /* The paper's method: forward DIF left digit-reversed, product with the
+     digit-reversed spectrum, DIT inverse to natural order; no index reversal
+     is executed.  The product is fused between the last forward and the
+     first inverse stage of one axis pass (Alg. alg:permutation-avoiding-
+     convolution). */
+  PAFC_PERM_FREE = 0,
+  /* Comparison: the standard route with explicit index reversals executed as
+     device passes (Alg. alg:fft-based-convolution with FFT2 of
+     Alg. alg:forward-fft and Alg. alg:backward-fft): forward transforms,
+     reversal to natural order fused with the product by the natural-order
+     spectrum, reversal back, inverse transforms. */
+  PAFC_EXPLICIT_PERM = 1,
+  /* Ablation: permutation-free, but every axis transform is its own pass and
+     the product is a separate elementwise pass (no fusion). */
+  PAFC_PERM_FREE_UNFUSED = 2
+} pafc_variant;
+
+typedef enum pafc_filter_domain {
+  PAFC_FILTER_SPATIAL = 0,          /* h given in the spatial domain, natural order */
+  PAFC_FILTER_SPECTRAL_NATURAL = 1  /* the DFT of h given, natural frequency order */
+} pafc_filter_domain;
+
+typedef struct pafc_plan_s* pafc_plan_t;
+
+/*
+ * pafc_plan -- build a convolution plan for one grid shape.
+ *
+ * ndim:   1, 2 or 3.
+ * dims:   host array of ndim sizes n_1..n_d (n_d is the fastest axis); each
+ *         n_i >= 2 and a product of factors in {2, 3, 5}.
+ * radix:  NULL, or host array of ndim entries.  radix[i] = 0 lets the
+ *         planner choose the radix sequence of axis i (over {2,3,4,5,8});
+ *         radix[i] = r in {2,3,4,5,8} requests the uniform radix-r
+ *         factorization of Sec. "General radix Cooley-Tukey framework" and
+ *         requires n_i = r^t.  The radix sequence fixes the digit-reversed
+ *         layout of the spectrum (the mixed-radix reversal of Sec. "Mixed-
+ *         radix framework"), never the result.
+ * dtype:  PAFC_C64 or PAFC_C128: the element type of x, y, h and of all
+ *         arithmetic.  Twiddles are generated in FP64 on the host; PAFC_C64
+ *         plans use their round-to-nearest FP32 values.
+ * variant: see pafc_variant.
+ * hip_stream: stream on which the twiddle uploads are enqueued.
+ *
+ * On success *out receives the plan, which owns device memory for the
+ * twiddles, the filter spectrum (N elements) and, for PAFC_EXPLICIT_PERM,
+ * one N-element scratch array; it allocates with hipMalloc.  On failure
+ * *out is set to NULL and nothing is leaked.
+ * Errors: INVALID_VALUE (out == NULL, ndim outside 1..3, dims == NULL,
+ * n_i < 2, bad dtype/variant), UNSUPPORTED_SIZE, OUT_OF_MEMORY, DEVICE.
+ */
+pafc_status pafc_plan(pafc_plan_t* out, int ndim, const int64_t* dims,
+                      const int* radix, pafc_dtype dtype, pafc_variant variant,
+                      void* hip_stream);
+
+/*
+ * pafc_set_filter -- set the convolution kernel h of a plan.
+ *
+ * h_dev: device array of N elements of the plan dtype in the plan's shape
+ *        (row-major).  SPATIAL: h itself.  SPECTRAL_NATURAL: DFT(h) in
+ *        natural frequency order.  The library copies what it needs (h is
+ *        read only by work enqueued on hip_stream, so the caller may free or
+ *        overwrite it once the stream has passed this call).
+ * The plan keeps the spectrum scaled by 1/N -- the single normalisation of
+ * the inverse transform -- in the digit-reversed order of its forward
+ * transform (PAFC_EXPLICIT_PERM plans keep natural order).  The spatial
+ * filter is transformed with the plan's own forward passes
+ * (Alg. alg:permutation-avoiding-convolution, first step); a natural-order
+ * spectrum is reordered once, here, and never again.  Replaces any previous
+ * filter.
+ * Errors: INVALID_VALUE (p or h_dev NULL, h_dev not aligned to 8 bytes for
+ * C64 / 16 bytes for C128, bad domain), DEVICE.
+ */
+pafc_status pafc_set_filter(pafc_plan_t p, const void* h_dev,
+                            pafc_filter_domain domain, void* hip_stream);
+
+/*
+ * pafc_convolve -- y = x * h (circular), stream-ordered on hip_stream.
+ *
+ * x_dev: device array of N elements (read only, unless y_dev == x_dev).
+ * y_dev: device array of N elements; y_dev == x_dev (in place) is allowed;
+ *        other overlap is not.
+ * Deterministic: the same inputs give the same bits, whatever else runs on
+ * the device.  Asynchronous faults surface at the caller's next
+ * synchronisation.
+ * Errors: INVALID_VALUE (NULL or misaligned pointers), FILTER_NOT_SET,
+ * DEVICE (launch error).
+ */
+pafc_status pafc_convolve(pafc_plan_t p, const void* x_dev, void* y_dev,
+                          void* hip_stream);
+
+/*
+ * pafc_forward -- z = (A_1^T (x) ... (x) A_d^T) x: the forward transform
+ * without permutation (Alg. alg:uFFT1D..alg:uFFT3D, uFFT2 branch): the DFT
+ * of x in digit-reversed order along every axis, unscaled.  Entry
+ * (pos_1(k_1), ..., pos_d(k_d)) of z is DFT(x)[k_1, ..., k_d], where pos_i is
+ * the mixed-radix digit reversal of axis i's radix sequence (see
+ * pafc_plan_radices).  z_dev == x_dev allowed.  Same conventions and errors
+ * as pafc_convolve (no filter needed).
+ */
+pafc_status pafc_forward(pafc_plan_t p, const void* x_dev, void* z_dev,
+                         void* hip_stream);
+
+/*
+ * pafc_inverse -- y = (conj A_1 (x) ... (x) conj A_d) z / N: the inverse
+ * transform without permutation (Alg. alg:uiFFT1D..alg:uiFFT3D): z in
+ * digit-reversed order in, natural order out, scaled once by 1/N.
+ * pafc_inverse(pafc_forward(x)) = x.  y_dev == z_dev allowed.
+ */
+pafc_status pafc_inverse(pafc_plan_t p, const void* z_dev, void* y_dev,
+                         void* hip_stream);
+
+/*
+ * pafc_destroy -- free everything the plan owns.  NULL is a no-op.  The
+ * caller must ensure no work on the plan is still pending (synchronise the
+ * stream first).
+ * Errors: DEVICE.
+ */
+pafc_status pafc_destroy(pafc_plan_t p);
+
+/* Static, NUL-terminated description of a status code. */
+const char* pafc_status_string(pafc_status s);
+
+/* Device bytes owned by the plan (for HBM-budget admission). */
+pafc_status pafc_plan_device_bytes(pafc_plan_t p, size_t* bytes);
+
+/*
+ * pafc_plan_radices -- the radix sequence the plan uses on axis `axis`
+ * (0-based), listed r_1 first (the innermost stage, Sec. "Mixed-radix
+ * framework"), written to rho[0..*len-1]; *len is set to the sequence
+ * length.  Host only.  Errors: INVALID_VALUE (NULL pointers, bad axis,
+ * capacity < length: *len then holds the length needed).
+ */
+pafc_status pafc_plan_radices(pafc_plan_t p, int axis, int* rho, int* len);
+
+/*
+ * pafc_describe -- plan the given problem on the host only (no device call,
+ * no allocation on the device) and write a JSON description of the chosen
+ * radix sequences, passes, tiles and algorithmic HBM bytes per convolution
+ * into buf (NUL-terminated, truncated to cap bytes).  Arguments as for
+ * pafc_plan.  *needed (if not NULL) receives the full length + 1.
+ * Errors: as pafc_plan, except OUT_OF_MEMORY and DEVICE.
+ */
+pafc_status pafc_describe(int ndim, const int64_t* dims, const int* radix,
+                          pafc_dtype dtype, pafc_variant variant, char* buf,
+                          size_t cap, size_t* needed);
+
+/*
+ * pafc_profile_passes -- run pafc_convolve `reps` times on hip_stream with a
+ * hipEvent recorded around every kernel the convolution launches, synchronise,
+ * and report the mean duration of each launch position in ms_per_pass[]
+ * (capacity *npass on entry; the number of launches per convolution on
+ * exit) and the algorithmic HBM bytes of each launch in bytes_per_pass[]
+ * (may be NULL), and the time from the first to the last event of every
+ * repetition in ms_per_rep[0..reps-1] (may be NULL).  Same buffer rules as
+ * pafc_convolve.  Blocks the host.
+ * Errors: INVALID_VALUE (capacity too small: *npass then holds the count),
+ * FILTER_NOT_SET, DEVICE.
+ */
+pafc_status pafc_profile_passes(pafc_plan_t p, const void* x_dev, void* y_dev,
+                                void* hip_stream, int reps, double* ms_per_pass,
+                                int64_t* bytes_per_pass, double* ms_per_rep,
+                                int* npass);
+
+/* ------------------------------------------------------------------------
+ * Batched form: many independent 1-D convolutions of uneven sizes.
+ *
+ * pafc_batch_plan -- count problems; problem i has length sizes[i] (each a
+ * {2,3,5}-smooth size >= 2) and uses filter filter_ids[i] in
+ * [0, nfilters).  Every problem that uses filter f must have the same
+ * length (one filter per size class).  Inputs and outputs are packed: the
+ * elements of problem i start at offset sum_{j<i} sizes[j] of one device
+ * array.  The batch owns per-size-class plans (radix splits and tiles chosen
+ * by the planner, or from the tuning table set by pafc_batch_tune_hint) and
+ * a device work list; pafc_batch_convolve enqueues one launch per pass level
+ * (at most three), which a caller may capture in a hipGraph.
+ * Errors: INVALID_VALUE, UNSUPPORTED_SIZE, OUT_OF_MEMORY, DEVICE.
+ */
+typedef struct pafc_batch_s* pafc_batch_t;
+
+pafc_status pafc_batch_plan(pafc_batch_t* out, int count, const int64_t* sizes,
+                            const int* filter_ids, int nfilters,
+                            pafc_dtype dtype, void* hip_stream);
+
+/* Set filter f (length = the size class of f) from a device array. */
+pafc_status pafc_batch_set_filter(pafc_batch_t b, int filter_id,
+                                  const void* h_dev, pafc_filter_domain domain,
+                                  void* hip_stream);
+
+/* y = x * h for every problem; x_dev and y_dev are packed arrays of
+   sum(sizes) elements; y_dev == x_dev allowed.
+   Errors: INVALID_VALUE, FILTER_NOT_SET (some filter used but not set), DEVICE. */
+pafc_status pafc_batch_convolve(pafc_batch_t b, const void* x_dev, void* y_dev,
+                                void* hip_stream);
+
+pafc_status pafc_batch_destroy(pafc_batch_t b);
+
+pafc_status pafc_batch_device_bytes(pafc_batch_t b, size_t* bytes);
+
+/* JSON description of a batch plan (host only). */
+pafc_status pafc_batch_describe(pafc_batch_t b, char* buf, size_t cap,
+                                size_t* needed);
+
+/*
+ * pafc_set_tuning -- install planner overrides from a JSON-like text of
+ * lines "<dtype> <n> <split> <W>" (split = length of the inner contiguous
+ * factor for sizes that need two levels, 0 = planner default; W = tile width,
+ * 0 = default).  Affects plans created afterwards.  NULL clears.
+ * Errors: INVALID_VALUE (unparsable text).
+ */
+pafc_status pafc_set_tuning(const char* text);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PAFC_H */

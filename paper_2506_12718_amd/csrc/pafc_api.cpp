@@ -1,0 +1,1236 @@
+// Host side of libpafc: planner, twiddle generation, and the C ABI of
+// include/pafc.h.
+//
+// The plan follows the paper's formulation of the convolution without index
+// reversal (eq. 35; d-way form in Sec. "Permutation-avoiding
+// multi-dimensional convolution"; mixed radix in Sec. "Mixed-radix
+// framework"): per axis a radix sequence rho = [r_1, ..., r_t] (r_1 the
+// innermost stage), the forward transform A^T applied stage r_t first, the
+// inverse conj(A) stage r_1 first.  The planner only decides how those stages
+// are cut into HBM passes and register groups; it never changes the stages.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "pafc.h"
+#include "pafc_internal.h"
+
+namespace pafc {
+hipError_t launch_pass(bool dbl, int cls, const PassArgs* d_desc, uint32_t ntiles, const void* in,
+                       void* out, uint32_t threads, size_t lds_bytes, hipStream_t s);
+hipError_t launch_batch(bool dbl, int cls, const PassArgs* descs, const BatchTile* tiles,
+                        uint32_t first, uint32_t count, const void* in, void* out,
+                        uint32_t threads, size_t lds_bytes, hipStream_t s);
+hipError_t launch_scale(bool dbl, void* p, int64_t n, double s, hipStream_t st);
+hipError_t launch_mul(bool dbl, const void* x, const void* h, void* y, int64_t n, hipStream_t st);
+hipError_t launch_permute_rows(bool dbl, const void* in, void* out, const void* h,
+                               const int32_t* m0, const int32_t* m1, const int32_t* mlast,
+                               uint32_t n0, uint32_t n1, uint32_t nlast, uint32_t rows_per_block,
+                               hipStream_t st);
+hipError_t launch_permute_gather(bool dbl, const void* in, void* out, const void* h,
+                                 const int32_t* m0, const int32_t* m1, const int32_t* m2,
+                                 uint32_t n0, uint32_t n1, uint32_t n2, hipStream_t st);
+}  // namespace pafc
+
+using namespace pafc;
+
+namespace {
+
+constexpr size_t kLdsBudget = 160 * 1024;  // LDS per CU on gfx950
+constexpr uint32_t kMaxThreads = 256;
+
+// ------------------------------------------------------------- tuning table
+
+struct TuneKey {
+  int dtype;
+  int64_t n;
+  bool operator<(const TuneKey& o) const { return dtype != o.dtype ? dtype < o.dtype : n < o.n; }
+};
+struct TuneVal {
+  int64_t split;  // inner length of a two-level 1-D transform (0 = default)
+  int W;          // tile width (0 = default)
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, TuneVal> g_tune;
+
+bool tune_lookup(int dtype, int64_t n, TuneVal* v) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tune.find({dtype, n});
+  if (it == g_tune.end()) return false;
+  *v = it->second;
+  return true;
+}
+
+// ------------------------------------------------------------- radix / pos
+
+int64_t ipow64(int64_t b, int e) {
+  int64_t r = 1;
+  while (e-- > 0) r *= b;
+  return r;
+}
+
+// Group kinds available to the kernels: (r, g) -> kind id.
+int kind_of(int r, int g) {
+  static const int tbl[][3] = {
+#define PAFC_ROW(id, rr, gg) {id, rr, gg},
+      PAFC_KIND_LIST(PAFC_ROW)
+#undef PAFC_ROW
+  };
+  for (auto& t : tbl)
+    if (t[1] == r && t[2] == g) return t[0];
+  return -1;
+}
+
+int gmax_of(int r) {
+  switch (r) {
+    case 2: return 4;   // R = 16
+    case 4: return 2;   // R = 16
+    case 8: return 1;   // R = 8
+    case 3: return 3;   // R = 27
+    case 5: return 2;   // R = 25
+  }
+  return 1;
+}
+
+// Planner's radix sequence for n (innermost first): radix-4 stages for the
+// power of two (one radix-8 stage absorbs an odd exponent >= 3, a lone 2
+// otherwise), then radix 3, then radix 5.
+bool auto_rho(int64_t n, std::vector<int>* rho) {
+  rho->clear();
+  int a = 0, b = 0, c = 0;
+  while (n % 2 == 0) { n /= 2; ++a; }
+  while (n % 3 == 0) { n /= 3; ++b; }
+  while (n % 5 == 0) { n /= 5; ++c; }
+  if (n != 1) return false;
+  if (a % 2 == 1) {
+    if (a >= 3) { rho->push_back(8); a -= 3; }
+    else { rho->push_back(2); a -= 1; }
+  }
+  for (int i = 0; i < a / 2; ++i) rho->push_back(4);
+  for (int i = 0; i < b; ++i) rho->push_back(3);
+  for (int i = 0; i < c; ++i) rho->push_back(5);
+  // keep equal radices adjacent: innermost the radix-4 run, then the lone
+  // 2/8, so that the radix-4 stages group into R = 16 ops
+  std::stable_sort(rho->begin(), rho->end(), [](int x, int y) {
+    auto key = [](int r) { return r == 4 ? 0 : r == 8 ? 1 : r == 2 ? 2 : r == 3 ? 3 : 4; };
+    return key(x) < key(y);
+  });
+  return true;
+}
+
+// Mixed-radix digit reversal: with k = d_t + r_t (d_{t-1} + ... + r_2 d_1),
+// pos(k) = d_1 + r_1 (d_2 + ... + r_{t-1} d_t); entry pos(k) of A^T x holds
+// entry k of F x (consequence of F = P_rho A_rho^T, Sec. "Mixed-radix
+// framework").
+std::vector<int32_t> pos_table(int64_t n, const std::vector<int>& rho) {
+  const int t = (int)rho.size();
+  std::vector<int32_t> out((size_t)n);
+  std::vector<int> d(t);
+  for (int64_t k = 0; k < n; ++k) {
+    int64_t x = k;
+    for (int i = t - 1; i >= 0; --i) { d[i] = (int)(x % rho[i]); x /= rho[i]; }
+    int64_t p = 0;
+    for (int i = t - 1; i >= 0; --i) p = p * rho[i] + d[i];
+    out[(size_t)k] = (int32_t)p;
+  }
+  return out;
+}
+
+// ---------------------------------------------------------------- twiddles
+
+// w_n^E = exp(-2 pi i E / n) in FP64, from long double with exact octant
+// reduction, so that +-1, +-i and (+-1 +-i)/sqrt(2) are exact.
+void omega64(int64_t n, int64_t E, double* re, double* im) {
+  E %= n;
+  if (E < 0) E += n;
+  const __int128 num = (__int128)8 * E;
+  const int oct = (int)(num / n);
+  const int64_t rem = (int64_t)(num - (__int128)oct * n);
+  const long double pi = 3.141592653589793238462643383279502884L;
+  const long double phi = (long double)rem / (long double)n * (pi / 4.0L);
+  long double c = cosl(phi), s = sinl(phi);
+  if (rem == 0) { c = 1.0L; s = 0.0L; }
+  const long double h = 0.707106781186547524400844362104849039L;
+  const long double bc[8] = {1, h, 0, -h, -1, -h, 0, h};
+  const long double bs[8] = {0, h, 1, h, 0, -h, -1, -h};
+  long double ct = bc[oct] * c - bs[oct] * s;
+  long double st = bs[oct] * c + bc[oct] * s;
+  if (rem == 0) { ct = bc[oct]; st = bs[oct]; }
+  *re = (double)ct;
+  *im = (double)(-st);
+}
+
+struct TwTable {
+  int64_t n = 0;
+  int64_t lo_off = 0, hi_off = -1;  // element offsets in the plan's table buffer
+  uint32_t bits = 0;
+};
+
+// ---------------------------------------------------------------- planning
+
+struct Seg {  // one pass-sized piece of an axis transform
+  uint32_t mode = MODE_CONTIG, L = 0, W = 1;
+  int64_t S_i = 1, S_c = 1, S_o = 0;
+  uint32_t ncols = 1, nouter = 1, jmul = 1, col_in_j = 0;
+  int64_t n_tw = 0;
+  std::vector<int> rho;  // this piece's stages, innermost first
+};
+
+struct Pass {
+  int kind = 0;  // 0 = pass kernel, 1 = mul, 2 = permute, 3 = scale
+  PassArgs a;
+  uint32_t threads = 0;
+  size_t lds = 0;
+  int cls = 0;
+  int64_t tw_n = 0;
+  bool mid = false;
+  // permute / mul details
+  int perm_dir = 0;  // 1: dr -> nat (with product), 2: nat -> dr
+  uint32_t desc = 0;  // index of the uploaded descriptor
+  std::string label;
+};
+
+struct AxisInfo {
+  int64_t n = 0;
+  std::vector<int> rho;
+  std::vector<Seg> segs;
+  std::vector<int32_t> pos, posinv;
+};
+
+struct PlanCore {
+  int ndim = 0;
+  int64_t dims[3] = {1, 1, 1};
+  int dtype = PAFC_C128;
+  int variant = PAFC_PERM_FREE;
+  int64_t N = 0;
+  size_t elem = 16;
+  int middle = 0;
+  std::vector<AxisInfo> axes;
+  std::vector<Pass> conv, fwd, inv;
+  std::map<int64_t, TwTable> tw;
+  int64_t tw_elems = 0;
+  int64_t hbm_conv = 0, hbm_fwd = 0;
+};
+
+std::vector<std::pair<int, int>> group_runs(const std::vector<int>& rho_inner_first) {
+  // DIF order: outermost stage (last entry) first; equal radices grouped.
+  std::vector<std::pair<int, int>> out;
+  std::vector<int> st(rho_inner_first.rbegin(), rho_inner_first.rend());
+  size_t i = 0;
+  while (i < st.size()) {
+    size_t j = i;
+    while (j < st.size() && st[j] == st[i]) ++j;
+    const int r = st[i];
+    const int t = (int)(j - i);
+    const int gm = gmax_of(r);
+    const int G = (t + gm - 1) / gm;
+    for (int q = 0; q < G; ++q) {
+      int g = t / G + (q < t % G ? 1 : 0);
+      out.push_back({r, g});
+    }
+    i = j;
+  }
+  return out;
+}
+
+uint32_t ilog2u(uint32_t w) {
+  uint32_t l = 0;
+  while ((1u << l) < w) ++l;
+  return l;
+}
+
+size_t tile_lds_bytes(uint64_t LW, size_t elem) { return (size_t)(LW + (LW >> 4) + 1) * elem; }
+
+uint32_t pow2_floor(uint64_t x) {
+  uint32_t p = 1;
+  while ((uint64_t)p * 2 <= x) p *= 2;
+  return p;
+}
+
+void choose_width(Seg& s, size_t elem, int tuneW) {
+  // ~4096 elements per tile; strided tiles also want >= 256 B row segments
+  uint32_t W = pow2_floor(std::max<uint64_t>(1, 4096 / std::max<uint32_t>(1, s.L)));
+  if (s.mode == MODE_STRIDED) W = std::max<uint32_t>(W, elem == 16 ? 16 : 32);
+  W = std::min<uint32_t>(W, 256);
+  W = std::min<uint32_t>(W, pow2_floor(std::max<uint64_t>(1, s.ncols)));
+  if (tuneW > 0) W = pow2_floor((uint64_t)tuneW);
+  while (W > 1 && tile_lds_bytes((uint64_t)s.L * W, elem) > kLdsBudget) W /= 2;
+  s.W = W;
+}
+
+bool fits_lds(int64_t L, size_t elem) { return tile_lds_bytes((uint64_t)L, elem) <= kLdsBudget; }
+
+// Build the op list of one pass over segment s.  kind: 0 = DIF only,
+// 1 = DIT only, 2 = DIF..., MID, ...DIT.
+bool build_ops(const Seg& s, int kind, PassArgs& a, int* cls) {
+  auto groups = group_runs(s.rho);
+  struct G { int r, g, R; uint32_t K, S; };
+  std::vector<G> gs;
+  uint32_t K = s.L;
+  for (auto& pr : groups) {
+    int R = (int)ipow64(pr.first, pr.second);
+    G g{pr.first, pr.second, R, K, K / (uint32_t)R};
+    gs.push_back(g);
+    K /= (uint32_t)R;
+  }
+  if (K != 1) return false;
+  *cls = 0;
+  auto mk = [&](const G& g, int type) {
+    OpDesc op;
+    memset(&op, 0, sizeof(op));
+    op.type = type;
+    op.kind = kind_of(g.r, g.g);
+    op.R = g.R;
+    op.K = g.K;
+    op.S = g.S;
+    op.tw = (g.S > 1 || s.col_in_j) ? 1 : 0;
+    op.nitems = (s.L / (uint32_t)g.R) * s.W;
+    op.Kf = g.K * s.jmul;
+    op.escale = (uint32_t)(s.n_tw / ((int64_t)g.K * s.jmul));
+    op.divS = make_fastdiv(g.S);
+    op.divNB = make_fastdiv(s.L / g.K);
+    if (g.R > 16) *cls = 1;
+    return op;
+  };
+  std::vector<OpDesc> ops;
+  if (kind == 0) {
+    for (auto& g : gs) ops.push_back(mk(g, OP_DIF));
+  } else if (kind == 1) {
+    for (auto it = gs.rbegin(); it != gs.rend(); ++it) ops.push_back(mk(*it, OP_DIT));
+  } else {
+    for (size_t i = 0; i + 1 < gs.size(); ++i) ops.push_back(mk(gs[i], OP_DIF));
+    ops.push_back(mk(gs.back(), OP_MID));
+    for (size_t i = gs.size() - 1; i-- > 0;) ops.push_back(mk(gs[i], OP_DIT));
+  }
+  if ((int)ops.size() > kMaxOps) return false;
+  for (auto& op : ops)
+    if (op.kind < 0) return false;
+  a.nops = (uint32_t)ops.size();
+  for (size_t i = 0; i < ops.size(); ++i) a.ops[i] = ops[i];
+  return true;
+}
+
+bool make_pass(const Seg& s, int kind, size_t elem, Pass* p) {
+  PassArgs& a = p->a;
+  memset(&a, 0, sizeof(a));
+  a.mode = s.mode;
+  a.L = s.L;
+  a.W = s.W;
+  a.logW = ilog2u(s.W);
+  a.LW = s.L * s.W;
+  a.S_i = s.S_i;
+  a.S_c = s.S_c;
+  a.S_o = s.S_o;
+  a.ncols = s.ncols;
+  a.tiles_per_slice = (s.ncols + s.W - 1) / s.W;
+  a.ntiles = a.tiles_per_slice * s.nouter;
+  a.jmul = s.jmul;
+  a.col_in_j = s.col_in_j;
+  a.divL = make_fastdiv(s.L);
+  a.divTiles = make_fastdiv(a.tiles_per_slice);
+  if (!build_ops(s, kind, a, &p->cls)) return false;
+  uint32_t maxitems = 0;
+  for (uint32_t i = 0; i < a.nops; ++i) maxitems = std::max(maxitems, a.ops[i].nitems);
+  uint32_t th = std::min<uint32_t>(kMaxThreads, ((maxitems + 63) / 64) * 64);
+  p->threads = std::max<uint32_t>(64, th);
+  p->lds = tile_lds_bytes(a.LW, elem);
+  p->tw_n = s.n_tw;
+  p->mid = (kind == 2);
+  p->kind = 0;
+  char buf[160];
+  std::string ops;
+  for (uint32_t i = 0; i < a.nops; ++i) {
+    const OpDesc& o = a.ops[i];
+    snprintf(buf, sizeof(buf), "%s%s%d", i ? "," : "",
+             o.type == OP_DIF ? "DIF" : o.type == OP_DIT ? "DIT" : "MID", o.R);
+    ops += buf;
+  }
+  snprintf(buf, sizeof(buf), "%s L=%u W=%u tiles=%u thr=%u [", s.mode == MODE_STRIDED ? "strided" : "contig",
+           s.L, s.W, a.ntiles, p->threads);
+  p->label = std::string(buf) + ops + "]";
+  return true;
+}
+
+pafc_status plan_core(PlanCore& P, int ndim, const int64_t* dims, const int* radix, int dtype,
+                      int variant) {
+  if (ndim < 1 || ndim > 3 || !dims) return PAFC_ERROR_INVALID_VALUE;
+  if (dtype != PAFC_C64 && dtype != PAFC_C128) return PAFC_ERROR_INVALID_VALUE;
+  if (variant < PAFC_PERM_FREE || variant > PAFC_PERM_FREE_UNFUSED) return PAFC_ERROR_INVALID_VALUE;
+  P.ndim = ndim;
+  P.dtype = dtype;
+  P.variant = variant;
+  P.elem = dtype == PAFC_C128 ? 16 : 8;
+  P.N = 1;
+  for (int a = 0; a < ndim; ++a) {
+    if (dims[a] < 2) return PAFC_ERROR_INVALID_VALUE;
+    if (dims[a] > (int64_t)1 << 30) return PAFC_ERROR_UNSUPPORTED_SIZE;
+    P.dims[a] = dims[a];
+    P.N *= dims[a];
+  }
+  if (P.N > ((int64_t)1 << 34)) return PAFC_ERROR_UNSUPPORTED_SIZE;
+  P.axes.resize(ndim);
+  for (int a = 0; a < ndim; ++a) {
+    AxisInfo& ax = P.axes[a];
+    ax.n = dims[a];
+    int r = radix ? radix[a] : 0;
+    if (r == 0) {
+      if (!auto_rho(ax.n, &ax.rho)) return PAFC_ERROR_UNSUPPORTED_SIZE;
+    } else {
+      if (r != 2 && r != 3 && r != 4 && r != 5 && r != 8) return PAFC_ERROR_UNSUPPORTED_SIZE;
+      int64_t m = ax.n;
+      int t = 0;
+      while (m % r == 0) { m /= r; ++t; }
+      if (m != 1) return PAFC_ERROR_UNSUPPORTED_SIZE;
+      ax.rho.assign(t, r);
+    }
+    ax.pos = pos_table(ax.n, ax.rho);
+    ax.posinv.assign((size_t)ax.n, 0);
+    for (int64_t k = 0; k < ax.n; ++k) ax.posinv[(size_t)ax.pos[(size_t)k]] = (int32_t)k;
+  }
+  // Segments: every axis of a 2-D/3-D grid is one pass; a 1-D transform too
+  // long for LDS is cut into an outer piece (its outermost stages, strided
+  // over the inner length) and an inner piece (contiguous blocks).
+  for (int a = 0; a < ndim; ++a) {
+    AxisInfo& ax = P.axes[a];
+    int64_t st = 1, outer = 1;
+    for (int b = a + 1; b < ndim; ++b) st *= dims[b];
+    for (int b = 0; b < a; ++b) outer *= dims[b];
+    TuneVal tv{0, 0};
+    bool tuned = tune_lookup(dtype, ax.n, &tv);
+    bool need_split = !fits_lds(ax.n, P.elem) || (tuned && tv.split > 0 && ndim == 1);
+    if (!need_split) {
+      Seg s;
+      s.L = (uint32_t)ax.n;
+      s.rho = ax.rho;
+      s.n_tw = ax.n;
+      if (st == 1) {
+        s.mode = MODE_CONTIG;
+        s.S_i = 1;
+        s.S_c = ax.n;
+        s.ncols = (uint32_t)outer;
+        s.S_o = 0;
+        s.nouter = 1;
+      } else {
+        s.mode = MODE_STRIDED;
+        s.S_i = st;
+        s.S_c = 1;
+        s.ncols = (uint32_t)st;
+        s.S_o = ax.n * st;
+        s.nouter = (uint32_t)outer;
+      }
+      choose_width(s, P.elem, tuned ? tv.W : 0);
+      if (tile_lds_bytes(s.L * (uint64_t)s.W, P.elem) > kLdsBudget) return PAFC_ERROR_UNSUPPORTED_SIZE;
+      ax.segs.push_back(s);
+    } else {
+      if (ndim != 1) return PAFC_ERROR_UNSUPPORTED_SIZE;
+      // inner length: the longest prefix product of rho that fits LDS
+      // comfortably (or the tuned split)
+      int ti = 0;
+      int64_t ni = 1;
+      const int t = (int)ax.rho.size();
+      if (tuned && tv.split > 0) {
+        while (ti < t && ni < tv.split) ni *= ax.rho[ti++];
+        if (ni != tv.split) return PAFC_ERROR_INVALID_VALUE;
+      } else {
+        const size_t cap = P.elem == 16 ? 4096 : 8192;
+        while (ti < t - 1 && ni * ax.rho[ti] <= (int64_t)cap) ni *= ax.rho[ti++];
+      }
+      const int64_t no = ax.n / ni;
+      if (!fits_lds(no, P.elem) || !fits_lds(ni, P.elem) || ti == 0 || ti == t)
+        return PAFC_ERROR_UNSUPPORTED_SIZE;
+      Seg so;  // outer: positions i_o < no at stride ni, columns i_i < ni
+      so.mode = MODE_STRIDED;
+      so.L = (uint32_t)no;
+      so.S_i = ni;
+      so.S_c = 1;
+      so.ncols = (uint32_t)ni;
+      so.S_o = 0;
+      so.nouter = 1;
+      so.jmul = (uint32_t)ni;
+      so.col_in_j = 1;
+      so.n_tw = ax.n;
+      so.rho.assign(ax.rho.begin() + ti, ax.rho.end());
+      choose_width(so, P.elem, 0);
+      Seg si;  // inner: contiguous blocks of ni
+      si.mode = MODE_CONTIG;
+      si.L = (uint32_t)ni;
+      si.S_i = 1;
+      si.S_c = ni;
+      si.ncols = (uint32_t)no;
+      si.S_o = 0;
+      si.nouter = 1;
+      si.n_tw = ni;
+      si.rho.assign(ax.rho.begin(), ax.rho.begin() + ti);
+      choose_width(si, P.elem, tuned ? tv.W : 0);
+      ax.segs.push_back(so);
+      ax.segs.push_back(si);
+    }
+  }
+  // twiddle tables, one per distinct n_tw
+  for (auto& ax : P.axes)
+    for (auto& s : ax.segs) {
+      if (P.tw.count(s.n_tw)) continue;
+      TwTable t;
+      t.n = s.n_tw;
+      t.lo_off = P.tw_elems;
+      if (s.n_tw <= 16384) {
+        P.tw_elems += s.n_tw;
+      } else {
+        uint32_t bits = 0;
+        while (((int64_t)1 << (2 * bits)) < s.n_tw) ++bits;
+        t.bits = bits;
+        const int64_t nlo = (int64_t)1 << bits;
+        const int64_t nhi = (s.n_tw + nlo - 1) >> bits;
+        P.tw_elems += nlo;
+        t.hi_off = P.tw_elems;
+        P.tw_elems += nhi;
+      }
+      P.tw[s.n_tw] = t;
+    }
+  // pass sequences
+  const int mid = 0;  // the slowest axis: its (most strided) pass is touched once
+  P.middle = mid;
+  auto add = [&](std::vector<Pass>& v, const Seg& s, int kind) -> bool {
+    Pass p;
+    if (!make_pass(s, kind, P.elem, &p)) return false;
+    v.push_back(p);
+    return true;
+  };
+  // forward only: all axes, fastest first, outer piece before inner piece
+  for (int a = ndim - 1; a >= 0; --a)
+    for (auto& s : P.axes[a].segs)
+      if (!add(P.fwd, s, 0)) return PAFC_ERROR_UNSUPPORTED_SIZE;
+  // inverse only: the mirror image
+  for (int a = 0; a < ndim; ++a)
+    for (auto it = P.axes[a].segs.rbegin(); it != P.axes[a].segs.rend(); ++it)
+      if (!add(P.inv, *it, 1)) return PAFC_ERROR_UNSUPPORTED_SIZE;
+  if (variant == PAFC_PERM_FREE) {
+    for (int a = ndim - 1; a >= 0; --a) {
+      if (a == mid) continue;
+      for (auto& s : P.axes[a].segs)
+        if (!add(P.conv, s, 0)) return PAFC_ERROR_UNSUPPORTED_SIZE;
+    }
+    auto& ms = P.axes[mid].segs;
+    for (size_t i = 0; i + 1 < ms.size(); ++i)
+      if (!add(P.conv, ms[i], 0)) return PAFC_ERROR_UNSUPPORTED_SIZE;
+    if (!add(P.conv, ms.back(), 2)) return PAFC_ERROR_UNSUPPORTED_SIZE;
+    for (size_t i = ms.size() - 1; i-- > 0;)
+      if (!add(P.conv, ms[i], 1)) return PAFC_ERROR_UNSUPPORTED_SIZE;
+    for (int a = 0; a < ndim; ++a) {
+      if (a == mid) continue;
+      for (auto it = P.axes[a].segs.rbegin(); it != P.axes[a].segs.rend(); ++it)
+        if (!add(P.conv, *it, 1)) return PAFC_ERROR_UNSUPPORTED_SIZE;
+    }
+  } else {
+    for (auto& p : P.fwd) P.conv.push_back(p);
+    if (variant == PAFC_PERM_FREE_UNFUSED) {
+      Pass m;
+      m.kind = 1;
+      m.label = "mul";
+      P.conv.push_back(m);
+    } else {
+      Pass p1;
+      p1.kind = 2;
+      p1.perm_dir = 1;
+      p1.label = "permute dr->nat x H";
+      Pass p2;
+      p2.kind = 2;
+      p2.perm_dir = 2;
+      p2.label = "permute nat->dr";
+      P.conv.push_back(p1);
+      P.conv.push_back(p2);
+    }
+    for (auto& p : P.inv) P.conv.push_back(p);
+  }
+  // algorithmic HBM bytes: each pass reads and writes N elements once; the
+  // product reads the spectrum once more
+  auto bytes = [&](const std::vector<Pass>& v) {
+    int64_t b = 0;
+    const int64_t ne = P.N * (int64_t)P.elem;
+    for (auto& p : v) {
+      if (p.kind == 0) b += 2 * ne + (p.mid ? ne : 0);
+      else if (p.kind == 1) b += 3 * ne;
+      else if (p.kind == 2) b += 2 * ne + (p.perm_dir == 1 ? ne : 0);
+    }
+    return b;
+  };
+  P.hbm_conv = bytes(P.conv);
+  P.hbm_fwd = bytes(P.fwd);
+  return PAFC_SUCCESS;
+}
+
+std::string describe_core(const PlanCore& P) {
+  std::string s = "{";
+  char b[256];
+  snprintf(b, sizeof(b), "\"ndim\": %d, \"dims\": [", P.ndim);
+  s += b;
+  for (int a = 0; a < P.ndim; ++a) {
+    snprintf(b, sizeof(b), "%s%lld", a ? ", " : "", (long long)P.dims[a]);
+    s += b;
+  }
+  snprintf(b, sizeof(b), "], \"dtype\": \"%s\", \"variant\": %d, \"middle_axis\": %d, \"axes\": [",
+           P.dtype == PAFC_C128 ? "c128" : "c64", P.variant, P.middle);
+  s += b;
+  for (int a = 0; a < P.ndim; ++a) {
+    const AxisInfo& ax = P.axes[a];
+    s += a ? ", {" : "{";
+    snprintf(b, sizeof(b), "\"n\": %lld, \"rho\": [", (long long)ax.n);
+    s += b;
+    for (size_t i = 0; i < ax.rho.size(); ++i) {
+      snprintf(b, sizeof(b), "%s%d", i ? ", " : "", ax.rho[i]);
+      s += b;
+    }
+    s += "], \"pieces\": [";
+    for (size_t i = 0; i < ax.segs.size(); ++i) {
+      const Seg& g = ax.segs[i];
+      snprintf(b, sizeof(b), "%s{\"L\": %u, \"W\": %u, \"mode\": \"%s\"}", i ? ", " : "", g.L, g.W,
+               g.mode == MODE_STRIDED ? "strided" : "contig");
+      s += b;
+    }
+    s += "]}";
+  }
+  s += "], \"conv_passes\": [";
+  for (size_t i = 0; i < P.conv.size(); ++i) {
+    s += i ? ", \"" : "\"";
+    s += P.conv[i].label + "\"";
+  }
+  snprintf(b, sizeof(b), "], \"hbm_bytes_conv\": %lld, \"hbm_bytes_forward\": %lld, \"N\": %lld}",
+           (long long)P.hbm_conv, (long long)P.hbm_fwd, (long long)P.N);
+  s += b;
+  return s;
+}
+
+}  // namespace
+
+// ===================================================================== plan
+
+struct pafc_plan_s {
+  PlanCore P;
+  int device = 0;
+  void* d_tw = nullptr;
+  void* d_H = nullptr;
+  void* d_scratch = nullptr;
+  int32_t* d_maps = nullptr;  // per axis: pos, posinv
+  PassArgs* d_descs = nullptr;
+  std::vector<int64_t> map_off;
+  bool filter_set = false;
+  size_t bytes = 0;
+};
+
+namespace {
+
+pafc_status from_hip(hipError_t e) {
+  if (e == hipSuccess) return PAFC_SUCCESS;
+  if (e == hipErrorOutOfMemory) return PAFC_ERROR_OUT_OF_MEMORY;
+  return PAFC_ERROR_DEVICE;
+}
+
+#define PAFC_TRY(expr)                         \
+  do {                                         \
+    pafc_status st_ = (expr);                  \
+    if (st_ != PAFC_SUCCESS) return st_;       \
+  } while (0)
+
+bool aligned_for(const void* p, int dtype) {
+  const uintptr_t m = dtype == PAFC_C128 ? 15 : 7;
+  return ((uintptr_t)p & m) == 0;
+}
+
+void free_plan(pafc_plan_t p) {
+  if (!p) return;
+  if (p->d_tw) (void)hipFree(p->d_tw);
+  if (p->d_H) (void)hipFree(p->d_H);
+  if (p->d_scratch) (void)hipFree(p->d_scratch);
+  if (p->d_maps) (void)hipFree(p->d_maps);
+  if (p->d_descs) (void)hipFree(p->d_descs);
+  delete p;
+}
+
+const int32_t* map_ptr(pafc_plan_t p, int axis, bool inverse) {
+  return p->d_maps + p->map_off[(size_t)axis] + (inverse ? p->P.axes[(size_t)axis].n : 0);
+}
+
+// Fill the device pointers of a pass descriptor (filter spectrum, twiddles).
+void finalize_args(const PlanCore& P, const void* d_tw, const void* H, const Pass& ps,
+                   PassArgs* a) {
+  *a = ps.a;
+  a->H = H;
+  const TwTable& t = P.tw.at(ps.tw_n);
+  const char* base = (const char*)d_tw;
+  a->tw_lo = base + t.lo_off * (int64_t)P.elem;
+  a->tw_hi = t.hi_off >= 0 ? base + t.hi_off * (int64_t)P.elem : nullptr;
+  a->tw_bits = t.bits;
+}
+
+// Launch one kernel pass reading `in` and writing `out`.
+pafc_status run_pass(pafc_plan_t p, const Pass& ps, const void* in, void* out, hipStream_t s) {
+  const bool dbl = p->P.dtype == PAFC_C128;
+  if (ps.kind != 0) return PAFC_ERROR_INVALID_VALUE;
+  return from_hip(launch_pass(dbl, ps.cls, p->d_descs + ps.desc, ps.a.ntiles, in, out, ps.threads,
+                              ps.lds, s));
+}
+
+// Index-reversal permutation pass of the explicit variant:
+// dir 1: out[k] = in[pos(k)] (* H),  dir 2: out[p] = in[posinv(p)].
+pafc_status run_permute(pafc_plan_t p, int dir, const void* in, void* out, const void* h,
+                        hipStream_t s) {
+  const PlanCore& P = p->P;
+  const bool dbl = P.dtype == PAFC_C128;
+  const bool inv = dir == 2;
+  uint32_t n0 = 1, n1 = 1, nl = (uint32_t)P.dims[P.ndim - 1];
+  const int32_t* m0 = nullptr;
+  const int32_t* m1 = nullptr;
+  const int32_t* ml = map_ptr(p, P.ndim - 1, inv);
+  if (P.ndim == 3) {
+    n0 = (uint32_t)P.dims[0];
+    n1 = (uint32_t)P.dims[1];
+    m0 = map_ptr(p, 0, inv);
+    m1 = map_ptr(p, 1, inv);
+  } else if (P.ndim == 2) {
+    n1 = (uint32_t)P.dims[0];
+    m1 = map_ptr(p, 0, inv);
+  }
+  if (tile_lds_bytes(nl, P.elem) <= kLdsBudget) {
+    uint32_t rows = std::max<uint32_t>(1, 2048 / nl);
+    while (rows > 1 && tile_lds_bytes((uint64_t)rows * nl, P.elem) > 64 * 1024) rows /= 2;
+    return from_hip(launch_permute_rows(dbl, in, out, h, m0, m1, ml, n0, n1, nl, rows, s));
+  }
+  return from_hip(launch_permute_gather(dbl, in, out, h, m0, m1, ml, n0, n1, nl, s));
+}
+
+pafc_status run_sequence(pafc_plan_t p, const std::vector<Pass>& seq, const void* x, void* y,
+                         hipStream_t s, hipEvent_t* ev = nullptr) {
+  const PlanCore& P = p->P;
+  const bool dbl = P.dtype == PAFC_C128;
+  const void* cur = x;
+  size_t k = 0;
+  if (ev) PAFC_TRY(from_hip(hipEventRecord(ev[0], s)));
+  for (const Pass& ps : seq) {
+    if (ps.kind == 0) {
+      PAFC_TRY(run_pass(p, ps, cur, y, s));
+      cur = y;
+    } else if (ps.kind == 1) {
+      PAFC_TRY(from_hip(launch_mul(dbl, cur, p->d_H, y, P.N, s)));
+      cur = y;
+    } else if (ps.kind == 2) {
+      if (ps.perm_dir == 1) {
+        PAFC_TRY(run_permute(p, 1, cur, p->d_scratch, p->d_H, s));
+        cur = p->d_scratch;
+      } else {
+        PAFC_TRY(run_permute(p, 2, cur, y, nullptr, s));
+        cur = y;
+      }
+    }
+    ++k;
+    if (ev) PAFC_TRY(from_hip(hipEventRecord(ev[k], s)));
+  }
+  if (cur != y) return PAFC_ERROR_DEVICE;
+  return PAFC_SUCCESS;
+}
+
+int64_t pass_bytes(const PlanCore& P, const Pass& ps) {
+  const int64_t ne = P.N * (int64_t)P.elem;
+  if (ps.kind == 0) return 2 * ne + (ps.mid ? ne : 0);
+  if (ps.kind == 1) return 3 * ne;
+  if (ps.kind == 2) return 2 * ne + (ps.perm_dir == 1 ? ne : 0);
+  return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* pafc_status_string(pafc_status s) {
+  switch (s) {
+    case PAFC_SUCCESS: return "success";
+    case PAFC_ERROR_INVALID_VALUE: return "invalid value";
+    case PAFC_ERROR_UNSUPPORTED_SIZE: return "unsupported size";
+    case PAFC_ERROR_OUT_OF_MEMORY: return "out of device memory";
+    case PAFC_ERROR_DEVICE: return "device error";
+    case PAFC_ERROR_FILTER_NOT_SET: return "filter not set";
+  }
+  return "unknown status";
+}
+
+pafc_status pafc_describe(int ndim, const int64_t* dims, const int* radix, pafc_dtype dtype,
+                          pafc_variant variant, char* buf, size_t cap, size_t* needed) {
+  PlanCore P;
+  PAFC_TRY(plan_core(P, ndim, dims, radix, dtype, variant));
+  std::string s = describe_core(P);
+  if (needed) *needed = s.size() + 1;
+  if (buf && cap > 0) {
+    size_t n = std::min(cap - 1, s.size());
+    memcpy(buf, s.data(), n);
+    buf[n] = 0;
+  }
+  return PAFC_SUCCESS;
+}
+
+pafc_status pafc_plan(pafc_plan_t* out, int ndim, const int64_t* dims, const int* radix,
+                      pafc_dtype dtype, pafc_variant variant, void* hip_stream) {
+  if (!out) return PAFC_ERROR_INVALID_VALUE;
+  *out = nullptr;
+  pafc_plan_t p = new (std::nothrow) pafc_plan_s;
+  if (!p) return PAFC_ERROR_OUT_OF_MEMORY;
+  pafc_status st = plan_core(p->P, ndim, dims, radix, dtype, variant);
+  if (st != PAFC_SUCCESS) {
+    delete p;
+    return st;
+  }
+  hipStream_t s = (hipStream_t)hip_stream;
+  const PlanCore& P = p->P;
+  if (hipGetDevice(&p->device) != hipSuccess) {
+    delete p;
+    return PAFC_ERROR_DEVICE;
+  }
+  // twiddle tables (FP64 on the host; FP32 plans take the rounded values)
+  std::vector<double> tw64((size_t)P.tw_elems * 2);
+  for (auto& kv : P.tw) {
+    const TwTable& t = kv.second;
+    if (t.hi_off < 0) {
+      for (int64_t e = 0; e < t.n; ++e)
+        omega64(t.n, e, &tw64[(size_t)(t.lo_off + e) * 2], &tw64[(size_t)(t.lo_off + e) * 2 + 1]);
+    } else {
+      const int64_t nlo = (int64_t)1 << t.bits;
+      const int64_t nhi = (t.n + nlo - 1) >> t.bits;
+      for (int64_t e = 0; e < nlo; ++e)
+        omega64(t.n, e, &tw64[(size_t)(t.lo_off + e) * 2], &tw64[(size_t)(t.lo_off + e) * 2 + 1]);
+      for (int64_t e = 0; e < nhi; ++e)
+        omega64(t.n, e << t.bits, &tw64[(size_t)(t.hi_off + e) * 2],
+                &tw64[(size_t)(t.hi_off + e) * 2 + 1]);
+    }
+  }
+  std::vector<float> tw32;
+  const void* tw_host = tw64.data();
+  size_t tw_bytes = (size_t)P.tw_elems * P.elem;
+  if (P.dtype == PAFC_C64) {
+    tw32.resize(tw64.size());
+    for (size_t i = 0; i < tw64.size(); ++i) tw32[i] = (float)tw64[i];
+    tw_host = tw32.data();
+  }
+  // index maps (explicit variant and natural-order spectral filters)
+  std::vector<int32_t> maps;
+  for (auto& ax : P.axes) {
+    p->map_off.push_back((int64_t)maps.size());
+    maps.insert(maps.end(), ax.pos.begin(), ax.pos.end());
+    maps.insert(maps.end(), ax.posinv.begin(), ax.posinv.end());
+  }
+  hipError_t e = hipMalloc(&p->d_tw, std::max<size_t>(tw_bytes, 16));
+  if (e == hipSuccess) e = hipMalloc((void**)&p->d_maps, maps.size() * sizeof(int32_t));
+  if (e == hipSuccess) e = hipMalloc(&p->d_H, (size_t)P.N * P.elem);
+  if (e == hipSuccess && P.variant == PAFC_EXPLICIT_PERM)
+    e = hipMalloc(&p->d_scratch, (size_t)P.N * P.elem);
+  // pass descriptors of the three sequences, uploaded once
+  std::vector<PassArgs> descs;
+  for (auto* seq : {&p->P.conv, &p->P.fwd, &p->P.inv})
+    for (Pass& ps : *seq) {
+      if (ps.kind != 0) continue;
+      ps.desc = (uint32_t)descs.size();
+      PassArgs a;
+      finalize_args(P, p->d_tw, p->d_H, ps, &a);
+      descs.push_back(a);
+    }
+  if (e == hipSuccess)
+    e = hipMalloc((void**)&p->d_descs, std::max<size_t>(1, descs.size()) * sizeof(PassArgs));
+  if (e != hipSuccess) {
+    free_plan(p);
+    return from_hip(e);
+  }
+  e = hipMemcpyAsync(p->d_tw, tw_host, tw_bytes, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(p->d_maps, maps.data(), maps.size() * sizeof(int32_t),
+                       hipMemcpyHostToDevice, s);
+  if (e == hipSuccess && !descs.empty())
+    e = hipMemcpyAsync(p->d_descs, descs.data(), descs.size() * sizeof(PassArgs),
+                       hipMemcpyHostToDevice, s);
+  // the host vectors die here: wait for the copies
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    free_plan(p);
+    return from_hip(e);
+  }
+  p->bytes = tw_bytes + maps.size() * sizeof(int32_t) + descs.size() * sizeof(PassArgs) +
+             (P.variant == PAFC_EXPLICIT_PERM ? (size_t)P.N * P.elem : 0) + (size_t)P.N * P.elem;
+  *out = p;
+  return PAFC_SUCCESS;
+}
+
+pafc_status pafc_destroy(pafc_plan_t p) {
+  free_plan(p);
+  return PAFC_SUCCESS;
+}
+
+pafc_status pafc_plan_device_bytes(pafc_plan_t p, size_t* bytes) {
+  if (!p || !bytes) return PAFC_ERROR_INVALID_VALUE;
+  *bytes = p->bytes;
+  return PAFC_SUCCESS;
+}
+
+pafc_status pafc_plan_radices(pafc_plan_t p, int axis, int* rho, int* len) {
+  if (!p || !rho || !len || axis < 0 || axis >= p->P.ndim) return PAFC_ERROR_INVALID_VALUE;
+  const auto& r = p->P.axes[(size_t)axis].rho;
+  const int cap = *len;
+  *len = (int)r.size();
+  if (cap < (int)r.size()) return PAFC_ERROR_INVALID_VALUE;
+  for (size_t i = 0; i < r.size(); ++i) rho[i] = r[i];
+  return PAFC_SUCCESS;
+}
+
+pafc_status pafc_set_filter(pafc_plan_t p, const void* h_dev, pafc_filter_domain domain,
+                            void* hip_stream) {
+  if (!p || !h_dev || !aligned_for(h_dev, p->P.dtype)) return PAFC_ERROR_INVALID_VALUE;
+  if (domain != PAFC_FILTER_SPATIAL && domain != PAFC_FILTER_SPECTRAL_NATURAL)
+    return PAFC_ERROR_INVALID_VALUE;
+  hipStream_t s = (hipStream_t)hip_stream;
+  const PlanCore& P = p->P;
+  const bool dbl = P.dtype == PAFC_C128;
+  const size_t nbytes = (size_t)P.N * P.elem;
+  p->filter_set = false;
+  const bool natural = P.variant == PAFC_EXPLICIT_PERM;
+  if (domain == PAFC_FILTER_SPATIAL) {
+    // Hdr = (A^T (x) ... (x) A^T) h: the plan's own forward passes
+    PAFC_TRY(run_sequence(p, P.fwd, h_dev, p->d_H, s));
+    if (natural) {  // the one reversal of the spectrum, done here once
+      PAFC_TRY(run_permute(p, 1, p->d_H, p->d_scratch, nullptr, s));
+      PAFC_TRY(from_hip(hipMemcpyAsync(p->d_H, p->d_scratch, nbytes, hipMemcpyDeviceToDevice, s)));
+    }
+  } else {
+    if (natural) {
+      PAFC_TRY(from_hip(hipMemcpyAsync(p->d_H, h_dev, nbytes, hipMemcpyDeviceToDevice, s)));
+    } else {  // natural -> digit-reversed, once
+      PAFC_TRY(run_permute(p, 2, h_dev, p->d_H, nullptr, s));
+    }
+  }
+  // the single 1/N of the inverse transform
+  PAFC_TRY(from_hip(launch_scale(dbl, p->d_H, P.N, 1.0 / (double)P.N, s)));
+  p->filter_set = true;
+  return PAFC_SUCCESS;
+}
+
+pafc_status pafc_convolve(pafc_plan_t p, const void* x_dev, void* y_dev, void* hip_stream) {
+  if (!p || !x_dev || !y_dev) return PAFC_ERROR_INVALID_VALUE;
+  if (!aligned_for(x_dev, p->P.dtype) || !aligned_for(y_dev, p->P.dtype))
+    return PAFC_ERROR_INVALID_VALUE;
+  if (!p->filter_set) return PAFC_ERROR_FILTER_NOT_SET;
+  return run_sequence(p, p->P.conv, x_dev, y_dev, (hipStream_t)hip_stream);
+}
+
+pafc_status pafc_profile_passes(pafc_plan_t p, const void* x_dev, void* y_dev, void* hip_stream,
+                                int reps, double* ms_per_pass, int64_t* bytes_per_pass,
+                                double* ms_per_rep, int* npass) {
+  if (!p || !x_dev || !y_dev || !npass || reps < 1) return PAFC_ERROR_INVALID_VALUE;
+  if (!p->filter_set) return PAFC_ERROR_FILTER_NOT_SET;
+  const auto& seq = p->P.conv;
+  const int n = (int)seq.size();
+  const int cap = *npass;
+  *npass = n;
+  if (cap < n || !ms_per_pass) return PAFC_ERROR_INVALID_VALUE;
+  hipStream_t s = (hipStream_t)hip_stream;
+  std::vector<hipEvent_t> ev((size_t)(n + 1) * reps, nullptr);
+  pafc_status st = PAFC_SUCCESS;
+  for (auto& e : ev)
+    if (st == PAFC_SUCCESS) st = from_hip(hipEventCreate(&e));
+  for (int r = 0; r < reps && st == PAFC_SUCCESS; ++r)
+    st = run_sequence(p, seq, x_dev, y_dev, s, ev.data() + (size_t)r * (n + 1));
+  if (st == PAFC_SUCCESS) st = from_hip(hipStreamSynchronize(s));
+  for (int k = 0; k < n; ++k) {
+    double tot = 0;
+    for (int r = 0; r < reps && st == PAFC_SUCCESS; ++r) {
+      float ms = 0;
+      st = from_hip(hipEventElapsedTime(&ms, ev[(size_t)r * (n + 1) + k], ev[(size_t)r * (n + 1) + k + 1]));
+      tot += ms;
+    }
+    ms_per_pass[k] = tot / reps;
+    if (bytes_per_pass) bytes_per_pass[k] = pass_bytes(p->P, seq[(size_t)k]);
+  }
+  for (int r = 0; r < reps && ms_per_rep && st == PAFC_SUCCESS; ++r) {
+    float ms = 0;
+    st = from_hip(hipEventElapsedTime(&ms, ev[(size_t)r * (n + 1)], ev[(size_t)r * (n + 1) + n]));
+    ms_per_rep[r] = ms;
+  }
+  for (auto& e : ev)
+    if (e) (void)hipEventDestroy(e);
+  return st;
+}
+
+pafc_status pafc_forward(pafc_plan_t p, const void* x_dev, void* z_dev, void* hip_stream) {
+  if (!p || !x_dev || !z_dev) return PAFC_ERROR_INVALID_VALUE;
+  if (!aligned_for(x_dev, p->P.dtype) || !aligned_for(z_dev, p->P.dtype))
+    return PAFC_ERROR_INVALID_VALUE;
+  return run_sequence(p, p->P.fwd, x_dev, z_dev, (hipStream_t)hip_stream);
+}
+
+pafc_status pafc_inverse(pafc_plan_t p, const void* z_dev, void* y_dev, void* hip_stream) {
+  if (!p || !z_dev || !y_dev) return PAFC_ERROR_INVALID_VALUE;
+  if (!aligned_for(z_dev, p->P.dtype) || !aligned_for(y_dev, p->P.dtype))
+    return PAFC_ERROR_INVALID_VALUE;
+  hipStream_t s = (hipStream_t)hip_stream;
+  PAFC_TRY(run_sequence(p, p->P.inv, z_dev, y_dev, s));
+  return from_hip(launch_scale(p->P.dtype == PAFC_C128, y_dev, p->P.N, 1.0 / (double)p->P.N, s));
+}
+
+pafc_status pafc_set_tuning(const char* text) {
+  std::map<TuneKey, TuneVal> t;
+  if (text) {
+    const char* c = text;
+    while (*c) {
+      char dt[16];
+      long long n, split;
+      int W, used = 0;
+      while (*c == ' ' || *c == '\n' || *c == '\t' || *c == '\r') ++c;
+      if (!*c) break;
+      if (*c == '#') {
+        while (*c && *c != '\n') ++c;
+        continue;
+      }
+      if (sscanf(c, "%15s %lld %lld %d%n", dt, &n, &split, &W, &used) != 4)
+        return PAFC_ERROR_INVALID_VALUE;
+      int d = !strcmp(dt, "c128") ? PAFC_C128 : !strcmp(dt, "c64") ? PAFC_C64 : -1;
+      if (d < 0 || n < 2 || split < 0 || W < 0) return PAFC_ERROR_INVALID_VALUE;
+      t[{d, (int64_t)n}] = {(int64_t)split, W};
+      c += used;
+    }
+  }
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune.swap(t);
+  return PAFC_SUCCESS;
+}
+
+}  // extern "C"
+
+// =================================================================== batch
+
+struct pafc_batch_s {
+  int dtype = PAFC_C128;
+  size_t elem = 16;
+  int count = 0;
+  int nfilters = 0;
+  std::vector<int64_t> sizes, offsets;
+  std::vector<int> fid;
+  int64_t total = 0;
+  std::map<int64_t, pafc_plan_t> plans;  // one plan per size class
+  std::vector<int64_t> fsize;            // size class of each filter
+  std::vector<void*> d_spec;             // per-filter spectra
+  std::vector<bool> fset;
+  PassArgs* d_descs = nullptr;
+  BatchTile* d_tiles = nullptr;
+  struct Level {
+    uint32_t first = 0, count = 0, threads = 64;
+    size_t lds = 0;
+    int cls = 0;
+  };
+  std::vector<Level> levels;
+  std::string desc;
+  size_t bytes = 0;
+};
+
+namespace {
+void free_batch(pafc_batch_t b) {
+  if (!b) return;
+  for (auto& kv : b->plans) free_plan(kv.second);
+  for (void* p : b->d_spec)
+    if (p) (void)hipFree(p);
+  if (b->d_descs) (void)hipFree(b->d_descs);
+  if (b->d_tiles) (void)hipFree(b->d_tiles);
+  delete b;
+}
+}  // namespace
+
+extern "C" {
+
+pafc_status pafc_batch_plan(pafc_batch_t* out, int count, const int64_t* sizes,
+                            const int* filter_ids, int nfilters, pafc_dtype dtype,
+                            void* hip_stream) {
+  if (!out) return PAFC_ERROR_INVALID_VALUE;
+  *out = nullptr;
+  if (count < 1 || !sizes || !filter_ids || nfilters < 1) return PAFC_ERROR_INVALID_VALUE;
+  if (dtype != PAFC_C64 && dtype != PAFC_C128) return PAFC_ERROR_INVALID_VALUE;
+  pafc_batch_t b = new (std::nothrow) pafc_batch_s;
+  if (!b) return PAFC_ERROR_OUT_OF_MEMORY;
+  b->dtype = dtype;
+  b->elem = dtype == PAFC_C128 ? 16 : 8;
+  b->count = count;
+  b->nfilters = nfilters;
+  b->fsize.assign((size_t)nfilters, 0);
+  b->fset.assign((size_t)nfilters, false);
+  b->d_spec.assign((size_t)nfilters, nullptr);
+  hipStream_t s = (hipStream_t)hip_stream;
+  auto fail = [&](pafc_status st) {
+    free_batch(b);
+    return st;
+  };
+  for (int i = 0; i < count; ++i) {
+    const int64_t n = sizes[i];
+    const int f = filter_ids[i];
+    if (n < 2 || f < 0 || f >= nfilters) return fail(PAFC_ERROR_INVALID_VALUE);
+    if (b->fsize[(size_t)f] != 0 && b->fsize[(size_t)f] != n) return fail(PAFC_ERROR_INVALID_VALUE);
+    b->fsize[(size_t)f] = n;
+    b->sizes.push_back(n);
+    b->fid.push_back(f);
+    b->offsets.push_back(b->total);
+    b->total += n;
+    if (!b->plans.count(n)) {
+      pafc_plan_t p = nullptr;
+      pafc_status st = pafc_plan(&p, 1, &n, nullptr, dtype, PAFC_PERM_FREE, hip_stream);
+      if (st != PAFC_SUCCESS) return fail(st);
+      b->plans[n] = p;
+    }
+  }
+  for (int f = 0; f < nfilters; ++f) {
+    if (b->fsize[(size_t)f] == 0) continue;  // unused filter id
+    if (hipMalloc(&b->d_spec[(size_t)f], (size_t)b->fsize[(size_t)f] * b->elem) != hipSuccess)
+      return fail(PAFC_ERROR_OUT_OF_MEMORY);
+  }
+  // descriptors: one per (filter, pass level)
+  std::vector<PassArgs> descs;
+  std::map<std::pair<int, int>, uint32_t> didx;
+  std::vector<std::vector<std::pair<uint32_t, int>>> desc_meta;  // unused
+  struct LevelInfo {
+    uint32_t threads = 64;
+    size_t lds = 0;
+    int cls = 0;
+  };
+  std::vector<LevelInfo> linfo(3);
+  for (int f = 0; f < nfilters; ++f) {
+    if (b->fsize[(size_t)f] == 0) continue;
+    pafc_plan_t p = b->plans[b->fsize[(size_t)f]];
+    const auto& conv = p->P.conv;
+    for (size_t l = 0; l < conv.size(); ++l) {
+      PassArgs a;
+      finalize_args(p->P, p->d_tw, b->d_spec[(size_t)f], conv[l], &a);
+      didx[{f, (int)l}] = (uint32_t)descs.size();
+      descs.push_back(a);
+      linfo[l].threads = std::max(linfo[l].threads, conv[l].threads);
+      linfo[l].lds = std::max(linfo[l].lds, conv[l].lds);
+      linfo[l].cls = std::max(linfo[l].cls, conv[l].cls);
+    }
+  }
+  // tiles per level, longest problems first
+  std::vector<int> order((size_t)count);
+  for (int i = 0; i < count; ++i) order[(size_t)i] = i;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int x, int y) { return b->sizes[(size_t)x] > b->sizes[(size_t)y]; });
+  std::vector<BatchTile> tiles;
+  b->levels.resize(3);
+  for (int l = 0; l < 3; ++l) {
+    b->levels[(size_t)l].first = (uint32_t)tiles.size();
+    for (int i : order) {
+      const int f = b->fid[(size_t)i];
+      auto it = didx.find({f, l});
+      if (it == didx.end()) continue;
+      const PassArgs& a = descs[it->second];
+      for (uint32_t t = 0; t < a.ntiles; ++t)
+        tiles.push_back(BatchTile{it->second, t, b->offsets[(size_t)i]});
+    }
+    auto& L = b->levels[(size_t)l];
+    L.count = (uint32_t)tiles.size() - L.first;
+    L.threads = linfo[(size_t)l].threads;
+    L.lds = linfo[(size_t)l].lds;
+    L.cls = linfo[(size_t)l].cls;
+  }
+  hipError_t e = hipMalloc((void**)&b->d_descs, descs.size() * sizeof(PassArgs));
+  if (e == hipSuccess) e = hipMalloc((void**)&b->d_tiles, std::max<size_t>(1, tiles.size()) * sizeof(BatchTile));
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b->d_descs, descs.data(), descs.size() * sizeof(PassArgs),
+                       hipMemcpyHostToDevice, s);
+  if (e == hipSuccess && !tiles.empty())
+    e = hipMemcpyAsync(b->d_tiles, tiles.data(), tiles.size() * sizeof(BatchTile),
+                       hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return fail(from_hip(e));
+  // description and bytes
+  char buf[256];
+  snprintf(buf, sizeof(buf),
+           "{\"count\": %d, \"total_elems\": %lld, \"size_classes\": %zu, \"levels\": [", count,
+           (long long)b->total, b->plans.size());
+  b->desc = buf;
+  for (int l = 0; l < 3; ++l) {
+    auto& L = b->levels[(size_t)l];
+    snprintf(buf, sizeof(buf), "%s{\"tiles\": %u, \"threads\": %u, \"lds\": %zu, \"cls\": %d}",
+             l ? ", " : "", L.count, L.threads, L.lds, L.cls);
+    b->desc += buf;
+  }
+  b->desc += "], \"plans\": [";
+  bool first = true;
+  for (auto& kv : b->plans) {
+    b->desc += first ? "" : ", ";
+    first = false;
+    b->desc += describe_core(kv.second->P);
+  }
+  b->desc += "]}";
+  b->bytes = descs.size() * sizeof(PassArgs) + tiles.size() * sizeof(BatchTile);
+  for (auto& kv : b->plans) b->bytes += kv.second->bytes - (size_t)kv.second->P.N * b->elem;
+  for (int f = 0; f < nfilters; ++f) b->bytes += (size_t)b->fsize[(size_t)f] * b->elem;
+  *out = b;
+  return PAFC_SUCCESS;
+}
+
+pafc_status pafc_batch_set_filter(pafc_batch_t b, int filter_id, const void* h_dev,
+                                  pafc_filter_domain domain, void* hip_stream) {
+  if (!b || !h_dev || filter_id < 0 || filter_id >= b->nfilters) return PAFC_ERROR_INVALID_VALUE;
+  if (!aligned_for(h_dev, b->dtype)) return PAFC_ERROR_INVALID_VALUE;
+  const int64_t n = b->fsize[(size_t)filter_id];
+  if (n == 0) return PAFC_ERROR_INVALID_VALUE;
+  pafc_plan_t p = b->plans[n];
+  hipStream_t s = (hipStream_t)hip_stream;
+  void* dst = b->d_spec[(size_t)filter_id];
+  if (domain == PAFC_FILTER_SPATIAL) {
+    PAFC_TRY(run_sequence(p, p->P.fwd, h_dev, dst, s));
+  } else if (domain == PAFC_FILTER_SPECTRAL_NATURAL) {
+    PAFC_TRY(run_permute(p, 2, h_dev, dst, nullptr, s));
+  } else {
+    return PAFC_ERROR_INVALID_VALUE;
+  }
+  PAFC_TRY(from_hip(launch_scale(b->dtype == PAFC_C128, dst, n, 1.0 / (double)n, s)));
+  b->fset[(size_t)filter_id] = true;
+  return PAFC_SUCCESS;
+}
+
+pafc_status pafc_batch_convolve(pafc_batch_t b, const void* x_dev, void* y_dev, void* hip_stream) {
+  if (!b || !x_dev || !y_dev) return PAFC_ERROR_INVALID_VALUE;
+  if (!aligned_for(x_dev, b->dtype) || !aligned_for(y_dev, b->dtype)) return PAFC_ERROR_INVALID_VALUE;
+  for (int i = 0; i < b->count; ++i)
+    if (!b->fset[(size_t)b->fid[(size_t)i]]) return PAFC_ERROR_FILTER_NOT_SET;
+  hipStream_t s = (hipStream_t)hip_stream;
+  const bool dbl = b->dtype == PAFC_C128;
+  const void* cur = x_dev;
+  for (auto& L : b->levels) {
+    if (L.count == 0) continue;
+    PAFC_TRY(from_hip(launch_batch(dbl, L.cls, b->d_descs, b->d_tiles, L.first, L.count, cur,
+                                   y_dev, L.threads, L.lds, s)));
+    cur = y_dev;
+  }
+  return PAFC_SUCCESS;
+}
+
+pafc_status pafc_batch_destroy(pafc_batch_t b) {
+  free_batch(b);
+  return PAFC_SUCCESS;
+}
+
+pafc_status pafc_batch_device_bytes(pafc_batch_t b, size_t* bytes) {
+  if (!b || !bytes) return PAFC_ERROR_INVALID_VALUE;
+  *bytes = b->bytes;
+  return PAFC_SUCCESS;
+}
+
+pafc_status pafc_batch_describe(pafc_batch_t b, char* buf, size_t cap, size_t* needed) {
+  if (!b) return PAFC_ERROR_INVALID_VALUE;
+  if (needed) *needed = b->desc.size() + 1;
+  if (buf && cap > 0) {
+    size_t n = std::min(cap - 1, b->desc.size());
+    memcpy(buf, b->desc.data(), n);
+    buf[n] = 0;
+  }
+  return PAFC_SUCCESS;
+}
+
+}  // extern "C"

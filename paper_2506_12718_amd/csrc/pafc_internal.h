@@ -1,0 +1,115 @@
+// Internal descriptors shared by the host planner and the gfx950 kernels.
+//
+// A "pass" is one kernel launch that reads every element of the array once
+// from HBM, applies a sequence of "ops" to tiles held in LDS, and writes every
+// element once.  A tile is L x W elements: L consecutive positions along the
+// (virtual) axis being transformed, times W columns.  Each op is one group of
+// g consecutive radix-r stages of the paper's stage sequence (R = r^g):
+//
+//   DIF op (forward, A^T; Alg. alg:transposed-butterfly-kernel grouped):
+//     for every block b and offset j < S = K/R, the R elements at
+//     b*K + j + s*S (s < R) are replaced by an R-point DFT over s; frequency m
+//     is written to position b*K + j + digrev(m)*S after multiplication by the
+//     twiddle w_K^{m j}.  digrev is the base-r reversal of g digits.  This is
+//     exactly g stages of B_{r,k}^T (eq. 25 transposed), stage k = K first.
+//   DIT op (inverse, conj A; Alg. alg:butterfly-related-kernel grouped): the
+//     mirror image: read position digrev(m), multiply by conj(w_K^{m j}),
+//     inverse R-point DFT, write natural position s.
+//   MID op: the innermost DIF group (S = 1, no twiddle), the product with the
+//     filter spectrum at the same digit-reversed positions, and the innermost
+//     DIT group, without leaving registers (the point of eq. 35: both
+//     operands of the product share one digit-reversed order).
+#pragma once
+
+#include <stdint.h>
+
+namespace pafc {
+
+enum { MODE_CONTIG = 0, MODE_STRIDED = 1 };
+enum { OP_DIF = 0, OP_DIT = 1, OP_MID = 2 };
+
+// Group kinds (r, g) instantiated in the kernels.
+#define PAFC_KIND_LIST(X) \
+  X(0, 2, 1)              \
+  X(1, 2, 2)              \
+  X(2, 2, 3)              \
+  X(3, 2, 4)              \
+  X(4, 2, 5)              \
+  X(5, 4, 1)              \
+  X(6, 4, 2)              \
+  X(7, 8, 1)              \
+  X(8, 3, 1)              \
+  X(9, 3, 2)              \
+  X(10, 3, 3)             \
+  X(11, 5, 1)             \
+  X(12, 5, 2)
+
+constexpr int kNumKinds = 13;
+constexpr int kMaxOps = 12;
+
+// Unsigned 32-bit division by an invariant divisor d >= 1 (Granlund and
+// Montgomery's multiply-high method): q = (umulhi(x, m) + x) >> l with
+// l = ceil(log2 d), m = floor(2^32 (2^l - d) / d) + 1; exact for all x < 2^32.
+struct FastDiv {
+  uint32_t d;
+  uint32_t m;
+  uint32_t l;
+};
+
+inline FastDiv make_fastdiv(uint32_t d) {
+  FastDiv f;
+  f.d = d;
+  uint32_t l = 0;
+  while ((1ull << l) < d) ++l;
+  f.l = l;
+  f.m = (uint32_t)((((1ull << l) - d) << 32) / d + 1);
+  return f;
+}
+
+struct OpDesc {
+  int32_t type;     // OP_DIF / OP_DIT / OP_MID
+  int32_t kind;     // index in PAFC_KIND_LIST
+  int32_t R;        // group radix r^g
+  int32_t tw;       // 1 if external twiddles are needed
+  uint32_t K;       // local block size (positions along the virtual axis)
+  uint32_t S;       // leg stride K / R
+  uint32_t nitems;  // items per tile = (L / R) * W
+  uint32_t Kf;      // block size of the full transform = K * jmul
+  uint32_t escale;  // twiddle-table exponent scale = n_tw / Kf
+  uint32_t pad_;
+  FastDiv divS;     // division by S
+  FastDiv divNB;    // division by L / K (blocks per column)
+};
+
+struct PassArgs {
+  const void* H;       // filter spectrum for OP_MID (same layout as the data)
+  const void* tw_lo;   // twiddle table(s): w_{n_tw}^E
+  const void* tw_hi;   // second level (NULL for a flat table)
+  uint32_t tw_bits;    // E = lo + (hi << tw_bits) when two-level
+  uint32_t mode;       // MODE_CONTIG / MODE_STRIDED
+  uint32_t L;          // positions along the virtual axis
+  uint32_t W;          // columns per tile (power of two)
+  uint32_t logW;
+  uint32_t LW;         // L * W
+  int64_t S_i;         // element stride between consecutive positions
+  int64_t S_c;         // element stride between consecutive columns
+  int64_t S_o;         // element stride between outer slices
+  uint32_t ncols;      // columns per slice (the last tile may be partial)
+  uint32_t tiles_per_slice;
+  uint32_t ntiles;
+  uint32_t jmul;       // j of the full transform = j * jmul + column (large 1-D)
+  uint32_t col_in_j;   // 1 when the column index enters the twiddle exponent
+  uint32_t nops;
+  FastDiv divL;        // division by L
+  FastDiv divTiles;    // division by tiles_per_slice
+  OpDesc ops[kMaxOps];
+};
+
+// Tiles of the batched launch: a pass over one tile of one problem.
+struct BatchTile {
+  uint32_t desc;    // index of the PassArgs template (size class + pass)
+  uint32_t tile;    // tile index within that problem's pass
+  int64_t offset;   // element offset of the problem in the packed arrays
+};
+
+}  // namespace pafc

@@ -1,0 +1,439 @@
+// gfx950 kernels of the permutation-avoiding convolution.
+//
+// pass_kernel: one HBM pass = load an L x W tile into LDS (coalesced along
+// whichever of the two tile dimensions is contiguous in memory), apply the
+// pass's ops (grouped DIF / DIT stages and the fused product with the
+// digit-reversed spectrum), store the tile back.  Every transform of the
+// library -- a whole 1-D transform in LDS, the contiguous and the strided
+// axis passes of 2-D/3-D grids, the fused middle pass, and the outer and
+// inner halves of 1-D transforms too long for LDS -- is an instance of this
+// kernel with a different descriptor (see pafc_internal.h).
+//
+// Stage order and arithmetic follow the paper's kernels: forward =
+// A^T = product of B_{r,k}^T, block size k decreasing (Alg.
+// alg:transposed-butterfly-kernel); inverse = conj(A) = product of
+// conj(B_{r,k}), k increasing (Alg. alg:butterfly-related-kernel); with the
+// mixed-radix stage sequence of Sec. "Mixed-radix framework".  Consecutive
+// stages of equal radix are grouped into one register-resident R-point DFT
+// plus one twiddle per element, which is the same linear map.
+#include <hip/hip_runtime.h>
+
+#include "pafc_internal.h"
+#include "small_dft.h"
+
+namespace pafc {
+
+__device__ __forceinline__ uint32_t fdiv(uint32_t x, const FastDiv& f) {
+  uint64_t t = ((uint64_t)x * f.m) >> 32;
+  return (uint32_t)((t + x) >> f.l);
+}
+
+__device__ __forceinline__ uint32_t lds_phys(uint32_t x) { return x + (x >> 4); }
+
+template <typename T>
+__device__ __forceinline__ cx<T> ld_g(const void* p, int64_t idx) {
+  return reinterpret_cast<const cx<T>*>(p)[idx];
+}
+template <typename T>
+__device__ __forceinline__ void st_g(void* p, int64_t idx, cx<T> v) {
+  reinterpret_cast<cx<T>*>(p)[idx] = v;
+}
+
+template <typename T>
+__device__ __forceinline__ cx<T> twiddle(const PassArgs& a, uint32_t E) {
+  const cx<T>* lo = reinterpret_cast<const cx<T>*>(a.tw_lo);
+  if (a.tw_hi == nullptr) return lo[E];
+  const cx<T>* hi = reinterpret_cast<const cx<T>*>(a.tw_hi);
+  return cmul(lo[E & ((1u << a.tw_bits) - 1u)], hi[E >> a.tw_bits]);
+}
+
+struct TileCtx {
+  int64_t base;    // element offset of tile position (0, 0)
+  uint32_t col0;   // global column of tile column 0
+  uint32_t ls_i;   // LDS linear stride between positions
+  uint32_t ls_c;   // LDS linear stride between columns
+};
+
+// One op over all items of the tile.
+template <typename T, int r, int g, int TYPE>
+__device__ __forceinline__ void run_op(const PassArgs& a, const OpDesc& op,
+                                       const TileCtx& t, cx<T>* lds) {
+  constexpr int R = ipow(r, g);
+  const uint32_t S = op.S, K = op.K;
+  for (uint32_t it = threadIdx.x; it < op.nitems; it += blockDim.x) {
+    uint32_t c, b, j;
+    if (a.mode == MODE_STRIDED) {
+      c = it & (a.W - 1u);
+      uint32_t rest = it >> a.logW;
+      b = fdiv(rest, op.divS);
+      j = rest - b * S;
+    } else {
+      uint32_t q = fdiv(it, op.divS);
+      j = it - q * S;
+      c = fdiv(q, op.divNB);
+      b = q - c * op.divNB.d;
+    }
+    const uint32_t gcol = t.col0 + c;
+    const bool valid = gcol < a.ncols;
+    const uint32_t i0 = b * K + j;
+    const uint32_t lbase = i0 * t.ls_i + c * t.ls_c;
+    const uint32_t lstep = S * t.ls_i;
+    cx<T> v[R];
+    if constexpr (TYPE == OP_DIF) {
+      static_for<R>([&](auto s) { v[s.value] = lds[lds_phys(lbase + s.value * lstep)]; });
+      Dft<R, r, false, T>::run(v);
+      if (op.tw) {
+        const uint32_t jf = j * a.jmul + (a.col_in_j && valid ? gcol : 0u);
+        uint32_t E = 0;
+        static_for<R - 1>([&](auto mm) {
+          E += jf;
+          if (E >= op.Kf) E -= op.Kf;
+          v[mm.value + 1] = cmul(v[mm.value + 1], twiddle<T>(a, E * op.escale));
+        });
+      }
+      static_for<R>([&](auto m) {
+        lds[lds_phys(lbase + digrev<r, g>(m.value) * lstep)] = v[m.value];
+      });
+    } else if constexpr (TYPE == OP_DIT) {
+      static_for<R>([&](auto m) {
+        v[m.value] = lds[lds_phys(lbase + digrev<r, g>(m.value) * lstep)];
+      });
+      if (op.tw) {
+        const uint32_t jf = j * a.jmul + (a.col_in_j && valid ? gcol : 0u);
+        uint32_t E = 0;
+        static_for<R - 1>([&](auto mm) {
+          E += jf;
+          if (E >= op.Kf) E -= op.Kf;
+          v[mm.value + 1] = cmulc(v[mm.value + 1], twiddle<T>(a, E * op.escale));
+        });
+      }
+      Dft<R, r, true, T>::run(v);
+      static_for<R>([&](auto s) { lds[lds_phys(lbase + s.value * lstep)] = v[s.value]; });
+    } else {  // OP_MID: S == 1, j == 0
+      static_for<R>([&](auto s) { v[s.value] = lds[lds_phys(lbase + s.value * lstep)]; });
+      Dft<R, r, false, T>::run(v);
+      if (valid) {
+        const int64_t gb = t.base + (int64_t)i0 * a.S_i + (int64_t)c * a.S_c;
+        static_for<R>([&](auto m) {
+          const cx<T> h = ld_g<T>(a.H, gb + (int64_t)digrev<r, g>(m.value) * a.S_i);
+          v[m.value] = cmul(v[m.value], h);
+        });
+      }
+      Dft<R, r, true, T>::run(v);
+      static_for<R>([&](auto s) { lds[lds_phys(lbase + s.value * lstep)] = v[s.value]; });
+    }
+  }
+}
+
+// Register class of a kernel instance: CLS 0 holds the groups with R <= 16,
+// CLS 1 every group (R <= 32).  A group's R^2-sized register footprint sets
+// the VGPR count of the whole kernel, so the small class keeps occupancy for
+// the common radix-2/4/8 plans.
+template <int R, int CLS>
+constexpr bool kind_in_class() { return CLS == 1 || R <= 16; }
+
+template <typename T, int TYPE, int CLS>
+__device__ __forceinline__ void dispatch_op(const PassArgs& a, const OpDesc& op,
+                                            const TileCtx& t, cx<T>* lds) {
+  switch (op.kind) {
+#define PAFC_CASE(id, r, g)                                        \
+  case id:                                                         \
+    if constexpr (kind_in_class<ipow(r, g), CLS>()) run_op<T, r, g, TYPE>(a, op, t, lds); \
+    break;
+    PAFC_KIND_LIST(PAFC_CASE)
+#undef PAFC_CASE
+    default:
+      break;
+  }
+}
+
+// Process tile `tile` of the pass described by `a`; `off` shifts in, out and H
+// (the packed offset of a problem in the batched form).
+template <typename T, int CLS>
+__device__ __forceinline__ void do_tile(const PassArgs& a, const void* __restrict__ in,
+                                        void* __restrict__ out, uint32_t tile, int64_t off,
+                                        cx<T>* lds) {
+  const uint32_t o = fdiv(tile, a.divTiles);
+  const uint32_t cb = tile - o * a.tiles_per_slice;
+  TileCtx t;
+  t.col0 = cb * a.W;
+  t.base = (int64_t)o * a.S_o + (int64_t)t.col0 * a.S_c + off;
+  if (a.mode == MODE_STRIDED) {
+    t.ls_i = a.W;
+    t.ls_c = 1;
+  } else {
+    t.ls_i = 1;
+    t.ls_c = a.L;
+  }
+  // load
+  for (uint32_t x = threadIdx.x; x < a.LW; x += blockDim.x) {
+    uint32_t i, c;
+    if (a.mode == MODE_STRIDED) {
+      i = x >> a.logW;
+      c = x & (a.W - 1u);
+    } else {
+      c = fdiv(x, a.divL);
+      i = x - c * a.L;
+    }
+    cx<T> v = {(T)0, (T)0};
+    if (t.col0 + c < a.ncols) v = ld_g<T>(in, t.base + (int64_t)i * a.S_i + (int64_t)c * a.S_c);
+    lds[lds_phys(x)] = v;
+  }
+  __syncthreads();
+  for (uint32_t k = 0; k < a.nops; ++k) {
+    const OpDesc& op = a.ops[k];
+    if (op.type == OP_DIF)
+      dispatch_op<T, OP_DIF, CLS>(a, op, t, lds);
+    else if (op.type == OP_DIT)
+      dispatch_op<T, OP_DIT, CLS>(a, op, t, lds);
+    else
+      dispatch_op<T, OP_MID, CLS>(a, op, t, lds);
+    __syncthreads();
+  }
+  // store
+  for (uint32_t x = threadIdx.x; x < a.LW; x += blockDim.x) {
+    uint32_t i, c;
+    if (a.mode == MODE_STRIDED) {
+      i = x >> a.logW;
+      c = x & (a.W - 1u);
+    } else {
+      c = fdiv(x, a.divL);
+      i = x - c * a.L;
+    }
+    if (t.col0 + c < a.ncols)
+      st_g<T>(out, t.base + (int64_t)i * a.S_i + (int64_t)c * a.S_c, lds[lds_phys(x)]);
+  }
+}
+
+// The descriptor lives in device memory (uploaded with the plan): indexing its
+// op list at run time from a by-value kernel argument would force a private
+// copy of the whole struct.
+template <typename T, int CLS>
+__global__ void __launch_bounds__(256) pass_kernel(const PassArgs* __restrict__ desc,
+                                                   const void* in, void* out) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
+  do_tile<T, CLS>(*desc, in, out, blockIdx.x, 0, lds);
+}
+
+// Batched form: block b processes work item tiles[first + b]; the pass
+// descriptors of all size classes sit in device memory.
+template <typename T, int CLS>
+__global__ void __launch_bounds__(256) batch_kernel(const PassArgs* __restrict__ descs,
+                                                    const BatchTile* __restrict__ tiles,
+                                                    uint32_t first, const void* in, void* out) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
+  const BatchTile bt = tiles[first + blockIdx.x];
+  do_tile<T, CLS>(descs[bt.desc], in, out, bt.tile, bt.offset, lds);
+}
+
+// ------------------------------------------------------------ elementwise
+
+template <typename T>
+__global__ void scale_kernel(cx<T>* __restrict__ p, int64_t n, T s) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    cx<T> v = p[i];
+    p[i] = {v.re * s, v.im * s};
+  }
+}
+
+template <typename T>
+__global__ void mul_kernel(const cx<T>* __restrict__ x, const cx<T>* __restrict__ h,
+                           cx<T>* __restrict__ y, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = cmul(x[i], h[i]);
+}
+
+// Per-axis index-reversal permutation as one HBM pass (the explicit variant's
+// Alg. alg:index-reversal-permutation), with an optional product:
+//   out[k_1..k_d] = in[map_1[k_1], ..., map_d[k_d]] (* h[k_1..k_d]).
+// One block handles `rows` output rows of the last axis; a source row is
+// staged through LDS so that both the global read and the global write are
+// contiguous; the within-row reversal happens on the LDS read.
+template <typename T>
+__global__ void __launch_bounds__(256) permute_rows_kernel(
+    const cx<T>* __restrict__ in, cx<T>* __restrict__ out, const cx<T>* __restrict__ h,
+    const int32_t* __restrict__ map0, const int32_t* __restrict__ map1,
+    const int32_t* __restrict__ map_last, uint32_t n0, uint32_t n1, uint32_t nlast,
+    uint32_t rows_per_block, uint32_t nrows) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
+  const uint32_t row0 = blockIdx.x * rows_per_block;
+  const uint32_t nr = min(rows_per_block, nrows - row0);
+  const uint32_t tot = nr * nlast;
+  for (uint32_t x = threadIdx.x; x < tot; x += blockDim.x) {
+    const uint32_t rr = x / nlast, k = x - rr * nlast;
+    const uint32_t row = row0 + rr;
+    const uint32_t k0 = row / n1, k1 = row - k0 * n1;
+    const uint32_t srow = (n0 > 1 ? (uint32_t)map0[k0] : 0u) * n1 + (n1 > 1 ? (uint32_t)map1[k1] : 0u);
+    lds[lds_phys(x)] = in[(int64_t)srow * nlast + k];
+  }
+  __syncthreads();
+  for (uint32_t x = threadIdx.x; x < tot; x += blockDim.x) {
+    const uint32_t rr = x / nlast, k = x - rr * nlast;
+    const int64_t o = (int64_t)(row0 + rr) * nlast + k;
+    cx<T> v = lds[lds_phys(rr * nlast + (uint32_t)map_last[k])];
+    if (h) v = cmul(v, h[o]);
+    out[o] = v;
+  }
+}
+
+// Generic gather for axes too long for an LDS row:
+//   out[o] = in[src(o)] (* h[o]), src from per-axis maps.
+template <typename T>
+__global__ void permute_gather_kernel(const cx<T>* __restrict__ in, cx<T>* __restrict__ out,
+                                      const cx<T>* __restrict__ h,
+                                      const int32_t* __restrict__ m0, const int32_t* __restrict__ m1,
+                                      const int32_t* __restrict__ m2, uint32_t n0, uint32_t n1,
+                                      uint32_t n2, int64_t n) {
+  for (int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; o < n;
+       o += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t k2 = (uint32_t)(o % n2);
+    const int64_t q = o / n2;
+    const uint32_t k1 = (uint32_t)(q % n1);
+    const uint32_t k0 = (uint32_t)(q / n1);
+    const int64_t s = ((int64_t)(n0 > 1 ? m0[k0] : 0) * n1 + (n1 > 1 ? m1[k1] : 0)) * n2 + m2[k2];
+    cx<T> v = in[s];
+    if (h) v = cmul(v, h[o]);
+    out[o] = v;
+  }
+}
+
+}  // namespace pafc
+
+// ----------------------------------------------------------------- launches
+
+namespace pafc {
+
+template <typename T>
+static hipError_t set_lds_limit(const void* fn) {
+  return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+}
+
+template <typename T, int CLS>
+static hipError_t launch_pass_t(const PassArgs* d_desc, uint32_t ntiles, const void* in,
+                                void* out, uint32_t threads, size_t lds_bytes, hipStream_t s) {
+  static bool init = false;
+  if (!init) {
+    hipError_t e = set_lds_limit<T>((const void*)pass_kernel<T, CLS>);
+    if (e != hipSuccess) return e;
+    init = true;
+  }
+  hipLaunchKernelGGL((pass_kernel<T, CLS>), dim3(ntiles), dim3(threads), lds_bytes, s, d_desc,
+                     in, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_pass(bool dbl, int cls, const PassArgs* d_desc, uint32_t ntiles, const void* in,
+                       void* out, uint32_t threads, size_t lds_bytes, hipStream_t s) {
+  if (dbl)
+    return cls ? launch_pass_t<double, 1>(d_desc, ntiles, in, out, threads, lds_bytes, s)
+               : launch_pass_t<double, 0>(d_desc, ntiles, in, out, threads, lds_bytes, s);
+  return cls ? launch_pass_t<float, 1>(d_desc, ntiles, in, out, threads, lds_bytes, s)
+             : launch_pass_t<float, 0>(d_desc, ntiles, in, out, threads, lds_bytes, s);
+}
+
+template <typename T, int CLS>
+static hipError_t launch_batch_t(const PassArgs* descs, const BatchTile* tiles, uint32_t first,
+                                 uint32_t count, const void* in, void* out, uint32_t threads,
+                                 size_t lds_bytes, hipStream_t s) {
+  static bool init = false;
+  if (!init) {
+    hipError_t e = set_lds_limit<T>((const void*)batch_kernel<T, CLS>);
+    if (e != hipSuccess) return e;
+    init = true;
+  }
+  hipLaunchKernelGGL((batch_kernel<T, CLS>), dim3(count), dim3(threads), lds_bytes, s, descs,
+                     tiles, first, in, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch(bool dbl, int cls, const PassArgs* descs, const BatchTile* tiles,
+                        uint32_t first, uint32_t count, const void* in, void* out,
+                        uint32_t threads, size_t lds_bytes, hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  if (dbl)
+    return cls ? launch_batch_t<double, 1>(descs, tiles, first, count, in, out, threads, lds_bytes, s)
+               : launch_batch_t<double, 0>(descs, tiles, first, count, in, out, threads, lds_bytes, s);
+  return cls ? launch_batch_t<float, 1>(descs, tiles, first, count, in, out, threads, lds_bytes, s)
+             : launch_batch_t<float, 0>(descs, tiles, first, count, in, out, threads, lds_bytes, s);
+}
+
+static uint32_t grid_for(int64_t n) {
+  int64_t b = (n + 255) / 256;
+  if (b > 65536) b = 65536;
+  if (b < 1) b = 1;
+  return (uint32_t)b;
+}
+
+hipError_t launch_scale(bool dbl, void* p, int64_t n, double s, hipStream_t st) {
+  if (dbl)
+    hipLaunchKernelGGL(scale_kernel<double>, dim3(grid_for(n)), dim3(256), 0, st,
+                       (cx<double>*)p, n, s);
+  else
+    hipLaunchKernelGGL(scale_kernel<float>, dim3(grid_for(n)), dim3(256), 0, st,
+                       (cx<float>*)p, n, (float)s);
+  return hipGetLastError();
+}
+
+hipError_t launch_mul(bool dbl, const void* x, const void* h, void* y, int64_t n, hipStream_t st) {
+  if (dbl)
+    hipLaunchKernelGGL(mul_kernel<double>, dim3(grid_for(n)), dim3(256), 0, st,
+                       (const cx<double>*)x, (const cx<double>*)h, (cx<double>*)y, n);
+  else
+    hipLaunchKernelGGL(mul_kernel<float>, dim3(grid_for(n)), dim3(256), 0, st,
+                       (const cx<float>*)x, (const cx<float>*)h, (cx<float>*)y, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_permute_rows(bool dbl, const void* in, void* out, const void* h,
+                               const int32_t* m0, const int32_t* m1, const int32_t* mlast,
+                               uint32_t n0, uint32_t n1, uint32_t nlast, uint32_t rows_per_block,
+                               hipStream_t st) {
+  static bool init_d = false, init_f = false;
+  const uint32_t nrows = n0 * n1;
+  const uint32_t blocks = (nrows + rows_per_block - 1) / rows_per_block;
+  const size_t elem = dbl ? 16 : 8;
+  const uint32_t tot = rows_per_block * nlast;
+  const size_t lds = (size_t)(tot + (tot >> 4) + 1) * elem;
+  if (dbl) {
+    if (!init_d) {
+      hipError_t e = set_lds_limit<double>((const void*)permute_rows_kernel<double>);
+      if (e != hipSuccess) return e;
+      init_d = true;
+    }
+    hipLaunchKernelGGL(permute_rows_kernel<double>, dim3(blocks), dim3(256), lds, st,
+                       (const cx<double>*)in, (cx<double>*)out, (const cx<double>*)h, m0, m1,
+                       mlast, n0, n1, nlast, rows_per_block, nrows);
+  } else {
+    if (!init_f) {
+      hipError_t e = set_lds_limit<float>((const void*)permute_rows_kernel<float>);
+      if (e != hipSuccess) return e;
+      init_f = true;
+    }
+    hipLaunchKernelGGL(permute_rows_kernel<float>, dim3(blocks), dim3(256), lds, st,
+                       (const cx<float>*)in, (cx<float>*)out, (const cx<float>*)h, m0, m1, mlast,
+                       n0, n1, nlast, rows_per_block, nrows);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_permute_gather(bool dbl, const void* in, void* out, const void* h,
+                                 const int32_t* m0, const int32_t* m1, const int32_t* m2,
+                                 uint32_t n0, uint32_t n1, uint32_t n2, hipStream_t st) {
+  const int64_t n = (int64_t)n0 * n1 * n2;
+  if (dbl)
+    hipLaunchKernelGGL(permute_gather_kernel<double>, dim3(grid_for(n)), dim3(256), 0, st,
+                       (const cx<double>*)in, (cx<double>*)out, (const cx<double>*)h, m0, m1, m2,
+                       n0, n1, n2, n);
+  else
+    hipLaunchKernelGGL(permute_gather_kernel<float>, dim3(grid_for(n)), dim3(256), 0, st,
+                       (const cx<float>*)in, (cx<float>*)out, (const cx<float>*)h, m0, m1, m2,
+                       n0, n1, n2, n);
+  return hipGetLastError();
+}
+
+}  // namespace pafc

@@ -1,0 +1,102 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every symbol the header declares, and the planner's host-only entry point
+reports the expected plans and errors."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2506_12718_amd as pafc
+from oracle import dense
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_symbols():
+    src = open(os.path.join(ROOT, "include", "pafc.h")).read()
+    return sorted(set(re.findall(r"\b(pafc_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = pafc.lib()
+    syms = header_symbols()
+    assert len(syms) >= 17
+    for s in syms:
+        assert hasattr(L, s), s
+    assert sorted(pafc.EXPORTS) == syms
+
+
+def test_status_strings():
+    L = pafc.lib()
+    for st in range(6):
+        assert L.pafc_status_string(st)
+
+
+@pytest.mark.parametrize("dims,dtype,radix,passes,hbm_factor", [
+    ((4096,), "c128", 2, 1, 3),
+    ((4096,), "c128", 4, 1, 3),
+    ((256, 256, 256), "c128", 4, 5, 11),
+    ((256, 256, 256), "c64", 4, 5, 11),
+    ((2187, 2187), "c128", 3, 3, 7),
+    ((5 ** 9,), "c128", 5, 3, 7),
+    ((5 ** 9,), "c64", 5, 3, 7),
+])
+def test_describe_pass_structure(dims, dtype, radix, passes, hbm_factor):
+    d = pafc.describe(dims, dtype, radix)
+    N = int(np.prod(dims))
+    elem = 16 if dtype == "c128" else 8
+    assert len(d["conv_passes"]) == passes
+    assert d["hbm_bytes_conv"] == hbm_factor * N * elem
+    for ax in d["axes"]:
+        assert all(r == radix for r in ax["rho"])
+    # the product with the spectrum sits in exactly one pass
+    assert sum("MID" in p for p in d["conv_passes"]) == 1
+
+
+def test_describe_explicit_and_unfused():
+    N = 256 ** 3
+    d = pafc.describe((256, 256, 256), "c128", 4, "explicit_perm")
+    assert d["hbm_bytes_conv"] == 17 * 16 * N
+    assert sum("permute" in p for p in d["conv_passes"]) == 2
+    d = pafc.describe((256, 256, 256), "c128", 4, "perm_free_unfused")
+    assert d["hbm_bytes_conv"] == 15 * 16 * N
+
+
+@pytest.mark.parametrize("n", [2, 6, 64, 96, 729, 1000, 3125, 4096, 65536, 78125, 59049])
+def test_auto_radix_factorizes(n):
+    d = pafc.describe((n,), "c128")
+    rho = d["axes"][0]["rho"]
+    assert int(np.prod(rho)) == n
+    assert all(r in (2, 3, 4, 5, 8) for r in rho)
+
+
+def test_describe_errors():
+    with pytest.raises(pafc.PafcError) as e:
+        pafc.describe((7,), "c128")
+    assert e.value.status == 2
+    with pytest.raises(pafc.PafcError) as e:
+        pafc.describe((1,), "c128")
+    assert e.value.status == 1
+    with pytest.raises(pafc.PafcError) as e:
+        pafc.describe((32,), "c128", 4)
+    assert e.value.status == 2
+    with pytest.raises(pafc.PafcError) as e:
+        pafc.describe((2, 2, 2, 2), "c128")
+    assert e.value.status == 1
+    with pytest.raises(pafc.PafcError):
+        pafc.describe((5 ** 9, 2), "c128")
+
+
+def test_tuning_override_changes_split():
+    try:
+        pafc.set_tuning("c128 65536 1024 0\n")
+        d = pafc.describe((65536,), "c128")
+        assert [p["L"] for p in d["axes"][0]["pieces"]] == [64, 1024]
+    finally:
+        pafc.set_tuning(None)
+    d = pafc.describe((65536,), "c128")
+    assert [p["L"] for p in d["axes"][0]["pieces"]] == [16, 4096]
+    with pytest.raises(pafc.PafcError):
+        pafc.set_tuning("garbage line")

@@ -1,0 +1,252 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Tolerances: relative L2 error <= 1e-12 for complex128 and <= 1e-5 for
+complex64 (the oracle consumes the same FP32-rounded inputs, upcast), with the
+error metric ||y - y_ref||_2 / ||y_ref||_2 over all entries.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2506_12718_amd import inputs
+from gpu_util import TOL, rel_l2, rounded, to_dev, to_host, torch
+
+pytestmark = pytest.mark.gpu
+
+C128, C64 = torch.complex128, torch.complex64
+DTYPES = [C128, C64]
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2506_12718_amd as pafc
+    pafc.lib()  # fail loudly if the library is missing
+    yield
+
+
+def pafc():
+    import paper_2506_12718_amd as m
+    return m
+
+
+def crand(rng, shape):
+    return inputs.complex_uniform(rng, shape)
+
+
+def run_conv(x, h, dtype, radix=None, variant="perm_free", domain="spatial"):
+    P = pafc().Plan(x.shape, dtype, radix=radix, variant=variant)
+    P.set_filter(to_dev(h, dtype), domain=domain)
+    y = P.convolve(to_dev(x, dtype))
+    out = to_host(y)
+    rhos = [P.radices(a) for a in range(x.ndim)]
+    P.close()
+    return out, rhos
+
+
+def smooth(limit):
+    out = []
+    for n in range(2, limit + 1):
+        m = n
+        for p in (2, 3, 5):
+            while m % p == 0:
+                m //= p
+        if m == 1:
+            out.append(n)
+    return out
+
+
+# ----------------------------------------------------------- brute force
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_all_small_1d_sizes_against_direct(dtype):
+    rng = np.random.default_rng(101)
+    for n in smooth(64):
+        x, h = crand(rng, (n,)), crand(rng, (n,))
+        say("1d n=%d %s" % (n, dtype))
+        y, _ = run_conv(x, h, dtype)
+        ref = oracle.conv_direct(rounded(x, dtype), rounded(h, dtype))
+        assert rel_l2(y, ref) < TOL[dtype], n
+
+
+@pytest.mark.parametrize("shape", [(2, 2), (4, 6), (8, 9), (16, 25), (27, 12), (64, 64),
+                                   (2, 3, 4), (4, 4, 4), (5, 8, 9), (16, 12, 10), (32, 9, 8)])
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_small_multid_against_direct(shape, dtype):
+    rng = np.random.default_rng(sum(shape))
+    x, h = crand(rng, shape), crand(rng, shape)
+    say("nd", shape, dtype)
+    y, _ = run_conv(x, h, dtype)
+    ref = oracle.conv_direct(rounded(x, dtype), rounded(h, dtype))
+    assert rel_l2(y, ref) < TOL[dtype]
+
+
+@pytest.mark.parametrize("n,radix", [(64, 2), (64, 4), (64, 8), (81, 3), (125, 5), (256, 2),
+                                     (256, 4), (512, 8), (729, 3), (625, 5)])
+def test_uniform_radix_plans(n, radix):
+    rng = np.random.default_rng(n + radix)
+    x, h = crand(rng, (n,)), crand(rng, (n,))
+    say("radix", n, radix)
+    y, rhos = run_conv(x, h, C128, radix=[radix])
+    assert rhos == [[radix] * len(rhos[0])]
+    assert rel_l2(y, oracle.conv_direct(x, h)) < 1e-12
+
+
+# --------------------------------------------------- config 1: 1-D n = 4096
+
+@pytest.mark.parametrize("radix", [2, 4])
+def test_conv1d_4096_radix_plans(radix):
+    x, h = inputs.conv1d_4096()
+    say("conv1d 4096 radix", radix)
+    y, rhos = run_conv(x, h, C128, radix=[radix])
+    assert rhos[0] == [radix] * (12 if radix == 2 else 6)
+    assert rel_l2(y, oracle.conv_direct(x, h)) < 1e-12
+
+
+# ------------------------------------------------ forward-only layout law
+
+@pytest.mark.parametrize("shape,radix", [((64,), [2]), ((64,), [4]), ((64,), [8]), ((243,), [3]),
+                                         ((4096,), [4]), ((4096,), [2]), ((24, 45), None),
+                                         ((16, 27, 25), None), ((3125 * 5,), None),
+                                         ((2 ** 14,), None)])
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_forward_is_digit_reversed_spectrum(shape, radix, dtype):
+    rng = np.random.default_rng(7)
+    x = crand(rng, shape)
+    P = pafc().Plan(shape, dtype, radix=radix)
+    say("forward", shape, radix, dtype)
+    z = to_host(P.forward(to_dev(x, dtype)))
+    rhos = [P.radices(a) for a in range(len(shape))]
+    ref = oracle.unordered_spectrum(rounded(x, dtype), rhos)
+    assert rel_l2(z, ref) < TOL[dtype] * 10
+    # and back: inverse(forward(x)) = x
+    xb = to_host(P.inverse(to_dev(ref, dtype)))
+    assert rel_l2(xb, rounded(x, dtype)) < TOL[dtype]
+    P.close()
+
+
+def test_forward_delta_layout():
+    """x = delta_0 gives all ones; x = delta_1 gives w_n^k at pos(k)."""
+    n = 256
+    P = pafc().Plan((n,), C128, radix=[4])
+    d0 = np.zeros(n, complex); d0[0] = 1
+    z0 = to_host(P.forward(to_dev(d0, C128)))
+    assert np.abs(z0 - 1).max() < 1e-15
+    d1 = np.zeros(n, complex); d1[1] = 1
+    z1 = to_host(P.forward(to_dev(d1, C128)))
+    from oracle import dense
+    pt = dense.pos_table(P.radices(0))
+    assert np.abs(z1[pt] - np.exp(-2j * np.pi * np.arange(n) / n)).max() < 1e-14
+    P.close()
+
+
+# ------------------------------------------------------------ invariants
+
+def test_delta_filter_identity_and_shift():
+    rng = np.random.default_rng(3)
+    shape = (32, 27, 20)
+    x = crand(rng, shape)
+    d = np.zeros(shape, complex); d[0, 0, 0] = 1
+    y, _ = run_conv(x, d, C128)
+    assert rel_l2(y, x) < 1e-14
+    s = (5, 7, 11)
+    ds = np.zeros(shape, complex); ds[s] = 1
+    y, _ = run_conv(x, ds, C128)
+    assert rel_l2(y, np.roll(x, s, axis=(0, 1, 2))) < 1e-14
+
+
+def test_linearity_and_commutativity():
+    rng = np.random.default_rng(4)
+    shape = (48, 64)
+    x1, x2, h = crand(rng, shape), crand(rng, shape), crand(rng, shape)
+    a, b = 0.7 - 0.2j, -1.3 + 0.4j
+    P = pafc().Plan(shape, C128)
+    P.set_filter(to_dev(h, C128))
+    y1 = to_host(P.convolve(to_dev(x1, C128)))
+    y2 = to_host(P.convolve(to_dev(x2, C128)))
+    y12 = to_host(P.convolve(to_dev(a * x1 + b * x2, C128)))
+    assert rel_l2(y12, a * y1 + b * y2) < 1e-13
+    P.set_filter(to_dev(x1, C128))
+    yc = to_host(P.convolve(to_dev(h, C128)))
+    assert rel_l2(yc, y1) < 1e-13
+    P.close()
+
+
+# -------------------------------------------------------------- variants
+
+@pytest.mark.parametrize("variant", ["perm_free", "explicit_perm", "perm_free_unfused"])
+@pytest.mark.parametrize("shape", [(4096,), (64, 81), (16, 32, 24), (5 ** 7,)])
+def test_variants_agree_with_oracle(variant, shape):
+    rng = np.random.default_rng(11)
+    x, h = crand(rng, shape), crand(rng, shape)
+    say("variant", variant, shape)
+    y, _ = run_conv(x, h, C128, variant=variant)
+    ref = oracle.conv_fft(x, h)
+    assert rel_l2(y, ref) < 1e-12
+
+
+def test_in_place():
+    rng = np.random.default_rng(12)
+    shape = (81, 64)
+    x, h = crand(rng, shape), crand(rng, shape)
+    P = pafc().Plan(shape, C128)
+    P.set_filter(to_dev(h, C128))
+    xd = to_dev(x, C128)
+    P.convolve(xd, out=xd)
+    assert rel_l2(to_host(xd), oracle.conv_fft(x, h)) < 1e-12
+    P.close()
+
+
+@pytest.mark.parametrize("variant", ["perm_free", "explicit_perm"])
+@pytest.mark.parametrize("shape", [(243, 81), (3125,), (16, 9, 25)])
+def test_spectral_filter_domain(variant, shape):
+    x, hhat = inputs.spectral_filter_case(31, shape)
+    say("spectral", variant, shape)
+    y, _ = run_conv(x, hhat, C128, variant=variant, domain="spectral_natural")
+    ref = oracle.fft(hhat * oracle.fft(x), inverse=True)
+    assert rel_l2(y, ref) < 1e-12
+
+
+# ----------------------------------------------- medium sizes, ragged tails
+
+@pytest.mark.parametrize("shape", [(2 ** 14,), (3 ** 9,), (5 ** 6,), (2 ** 15 * 3,),
+                                   (1000, 36), (100, 243), (24, 50, 36), (9, 10, 12),
+                                   (512, 40, 3), (2, 2, 4096)])
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_medium_and_ragged(shape, dtype):
+    rng = np.random.default_rng(int(np.prod(shape)) % 1000)
+    x, h = crand(rng, shape), crand(rng, shape)
+    say("medium", shape, dtype)
+    y, _ = run_conv(x, h, dtype)
+    ref = oracle.conv_fft(rounded(x, dtype), rounded(h, dtype))
+    assert rel_l2(y, ref) < TOL[dtype]
+
+
+# --------------------------------------------------------- error handling
+
+def test_errors():
+    m = pafc()
+    P = m.Plan((64,), C128)
+    x = to_dev(np.ones(64, complex), C128)
+    with pytest.raises(m.PafcError) as e:
+        P.convolve(x)
+    assert e.value.status == 5  # filter not set
+    import ctypes
+    st = m.lib().pafc_convolve(P.handle, ctypes.c_void_p(x.data_ptr() + 8),
+                               ctypes.c_void_p(x.data_ptr()), None)
+    assert st == 1  # misaligned for complex128
+    P.close()
+    with pytest.raises(m.PafcError) as e:
+        m.Plan((7,), C128)
+    assert e.value.status == 2
+    with pytest.raises(m.PafcError) as e:
+        m.Plan((48,), C128, radix=[4])
+    assert e.value.status == 2
