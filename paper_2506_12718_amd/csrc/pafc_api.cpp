@@ -13,6 +13,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -30,6 +31,12 @@ hipError_t launch_batch(bool dbl, int cls, const PassArgs* descs, const BatchTil
                         uint32_t first, uint32_t count, const void* in, void* out,
                         uint32_t threads, size_t lds_bytes, hipStream_t s);
 hipError_t launch_scale(bool dbl, void* p, int64_t n, double s, hipStream_t st);
+bool pipe_supported(int r, int g, int ng);
+int pipe_blocks_per_cu(bool dbl, int r, int g, int ng, int kind, int mode, uint32_t threads,
+                       size_t lds);
+hipError_t launch_pipe(bool dbl, int r, int g, int ng, int kind, int mode, const PassArgs* d,
+                       uint32_t grid, uint32_t threads, size_t lds, const void* in, void* out,
+                       hipStream_t s);
 hipError_t launch_mul(bool dbl, const void* x, const void* h, void* y, int64_t n, hipStream_t st);
 hipError_t launch_permute_rows(bool dbl, const void* in, void* out, const void* h,
                                const int32_t* m0, const int32_t* m1, const int32_t* mlast,
@@ -45,6 +52,15 @@ using namespace pafc;
 namespace {
 
 constexpr size_t kLdsBudget = 160 * 1024;  // LDS per CU on gfx950
+// Planner knobs read at plan time (autotuning and experiments):
+//   PAFC_TUNE_IO  bit mask of direct global I/O: 1 contiguous-tile loads,
+//                 2 contiguous-tile stores, 4 strided-tile loads, 8 strided-
+//                 tile stores (default 13: all but contiguous stores)
+//   PAFC_TUNE_WC / PAFC_TUNE_WS  tile width of contiguous / strided tiles
+int env_int(const char* name, int dflt) {
+  const char* v = getenv(name);
+  return v && *v ? atoi(v) : dflt;
+}
 constexpr uint32_t kMaxThreads = 256;
 
 // ------------------------------------------------------------- tuning table
@@ -195,6 +211,11 @@ struct Pass {
   // permute / mul details
   int perm_dir = 0;  // 1: dr -> nat (with product), 2: nat -> dr
   uint32_t desc = 0;  // index of the uploaded descriptor
+  // pipelined persistent kernel (uniform-radix axis, one item per thread)
+  bool pipe = false;
+  int pipe_r = 0, pipe_g = 0, pipe_ng = 0, pipe_kind = 0;
+  uint32_t pipe_grid = 0;
+  size_t pipe_lds = 0;
   std::string label;
 };
 
@@ -258,10 +279,13 @@ uint32_t pow2_floor(uint64_t x) {
 void choose_width(Seg& s, size_t elem, int tuneW) {
   // ~4096 elements per tile; strided tiles also want >= 256 B row segments
   uint32_t W = pow2_floor(std::max<uint64_t>(1, 4096 / std::max<uint32_t>(1, s.L)));
-  if (s.mode == MODE_STRIDED) W = std::max<uint32_t>(W, elem == 16 ? 16 : 32);
+  if (s.mode == MODE_STRIDED) W = std::max<uint32_t>(W, 16);
   W = std::min<uint32_t>(W, 256);
   W = std::min<uint32_t>(W, pow2_floor(std::max<uint64_t>(1, s.ncols)));
   if (tuneW > 0) W = pow2_floor((uint64_t)tuneW);
+  const int envW = env_int(s.mode == MODE_STRIDED ? "PAFC_TUNE_WS" : "PAFC_TUNE_WC", 0);
+  if (envW > 0) W = std::min<uint32_t>(pow2_floor((uint64_t)envW),
+                                       pow2_floor(std::max<uint64_t>(1, s.ncols)));
   while (W > 1 && tile_lds_bytes((uint64_t)s.L * W, elem) > kLdsBudget) W /= 2;
   s.W = W;
 }
@@ -313,6 +337,16 @@ bool build_ops(const Seg& s, int kind, PassArgs& a, int* cls) {
   if ((int)ops.size() > kMaxOps) return false;
   for (auto& op : ops)
     if (op.kind < 0) return false;
+  // Direct global I/O for the first and last op where it stays coalesced:
+  // strided tiles put consecutive columns on consecutive lanes (always
+  // coalesced); contiguous tiles put consecutive offsets j < S on
+  // consecutive lanes, which gives >= 16-element runs when S >= 16.
+  auto coalesced = [&](const OpDesc& op) { return s.mode == MODE_STRIDED || op.S >= 16; };
+  const int io = env_int("PAFC_TUNE_IO", 13);
+  const bool ld = s.mode == MODE_STRIDED ? (io & 4) : (io & 1);
+  const bool st = s.mode == MODE_STRIDED ? (io & 8) : (io & 2);
+  ops.front().src_g = (ld && coalesced(ops.front())) ? 1 : 0;
+  ops.back().dst_g = (st && coalesced(ops.back())) ? 1 : 0;
   a.nops = (uint32_t)ops.size();
   for (size_t i = 0; i < ops.size(); ++i) a.ops[i] = ops[i];
   return true;
@@ -345,6 +379,26 @@ bool make_pass(const Seg& s, int kind, size_t elem, Pass* p) {
   p->tw_n = s.n_tw;
   p->mid = (kind == 2);
   p->kind = 0;
+  // pipelined kernel: every group of the piece has the same (r, g), each op
+  // has one item per thread, flat twiddles of the piece's own length
+  {
+    auto groups = group_runs(s.rho);
+    bool uni = !groups.empty();
+    for (auto& gr : groups) uni = uni && gr == groups[0];
+    const int ng = (int)groups.size();
+    bool ok = env_int("PAFC_PIPE", 1) != 0 && uni && pipe_supported(groups[0].first, groups[0].second, ng) &&
+              s.col_in_j == 0 && s.jmul == 1 && s.n_tw == (int64_t)s.L;
+    for (uint32_t i = 0; ok && i < a.nops; ++i) ok = a.ops[i].nitems == p->threads;
+    if (ok) {
+      p->pipe = true;
+      p->pipe_r = groups[0].first;
+      p->pipe_g = groups[0].second;
+      p->pipe_ng = ng;
+      p->pipe_kind = kind;
+      const uint64_t LW = a.LW;
+      p->pipe_lds = (size_t)(((LW + (LW >> 4) + 2) & ~1ull) + s.L) * elem;
+    }
+  }
   char buf[160];
   std::string ops;
   for (uint32_t i = 0; i < a.nops; ++i) {
@@ -674,6 +728,10 @@ void finalize_args(const PlanCore& P, const void* d_tw, const void* H, const Pas
 pafc_status run_pass(pafc_plan_t p, const Pass& ps, const void* in, void* out, hipStream_t s) {
   const bool dbl = p->P.dtype == PAFC_C128;
   if (ps.kind != 0) return PAFC_ERROR_INVALID_VALUE;
+  if (ps.pipe && ps.pipe_grid > 0)
+    return from_hip(launch_pipe(dbl, ps.pipe_r, ps.pipe_g, ps.pipe_ng, ps.pipe_kind, ps.a.mode,
+                                p->d_descs + ps.desc, ps.pipe_grid, ps.threads, ps.pipe_lds, in,
+                                out, s));
   return from_hip(launch_pass(dbl, ps.cls, p->d_descs + ps.desc, ps.a.ntiles, in, out, ps.threads,
                               ps.lds, s));
 }
@@ -828,6 +886,24 @@ pafc_status pafc_plan(pafc_plan_t* out, int ndim, const int64_t* dims, const int
   if (e == hipSuccess) e = hipMalloc(&p->d_H, (size_t)P.N * P.elem);
   if (e == hipSuccess && P.variant == PAFC_EXPLICIT_PERM)
     e = hipMalloc(&p->d_scratch, (size_t)P.N * P.elem);
+  // persistent grids of the pipelined passes: resident blocks per CU x CUs
+  {
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess)
+      ncu = 0;
+    for (auto* seq : {&p->P.conv, &p->P.fwd, &p->P.inv})
+      for (Pass& ps : *seq) {
+        if (!ps.pipe) continue;
+        int nb = ncu > 0 ? pipe_blocks_per_cu(P.dtype == PAFC_C128, ps.pipe_r, ps.pipe_g,
+                                              ps.pipe_ng, ps.pipe_kind, (int)ps.a.mode,
+                                              ps.threads, ps.pipe_lds)
+                         : 0;
+        const int64_t want = (int64_t)nb * ncu;
+        ps.pipe_grid = (uint32_t)std::min<int64_t>(want, ps.a.ntiles);
+        if (nb <= 0) ps.pipe = false;
+        else ps.label += " pipe";
+      }
+  }
   // pass descriptors of the three sequences, uploaded once
   std::vector<PassArgs> descs;
   for (auto* seq : {&p->P.conv, &p->P.fwd, &p->P.inv})

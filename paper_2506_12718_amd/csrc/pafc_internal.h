@@ -76,7 +76,8 @@ struct OpDesc {
   uint32_t nitems;  // items per tile = (L / R) * W
   uint32_t Kf;      // block size of the full transform = K * jmul
   uint32_t escale;  // twiddle-table exponent scale = n_tw / Kf
-  uint32_t pad_;
+  uint16_t src_g;   // 1: the op reads its inputs straight from global memory
+  uint16_t dst_g;   // 1: the op writes its outputs straight to global memory
   FastDiv divS;     // division by S
   FastDiv divNB;    // division by L / K (blocks per column)
 };

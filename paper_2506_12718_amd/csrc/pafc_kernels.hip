@@ -18,34 +18,9 @@
 // plus one twiddle per element, which is the same linear map.
 #include <hip/hip_runtime.h>
 
-#include "pafc_internal.h"
-#include "small_dft.h"
+#include "kernel_common.h"
 
 namespace pafc {
-
-__device__ __forceinline__ uint32_t fdiv(uint32_t x, const FastDiv& f) {
-  uint64_t t = ((uint64_t)x * f.m) >> 32;
-  return (uint32_t)((t + x) >> f.l);
-}
-
-__device__ __forceinline__ uint32_t lds_phys(uint32_t x) { return x + (x >> 4); }
-
-template <typename T>
-__device__ __forceinline__ cx<T> ld_g(const void* p, int64_t idx) {
-  return reinterpret_cast<const cx<T>*>(p)[idx];
-}
-template <typename T>
-__device__ __forceinline__ void st_g(void* p, int64_t idx, cx<T> v) {
-  reinterpret_cast<cx<T>*>(p)[idx] = v;
-}
-
-template <typename T>
-__device__ __forceinline__ cx<T> twiddle(const PassArgs& a, uint32_t E) {
-  const cx<T>* lo = reinterpret_cast<const cx<T>*>(a.tw_lo);
-  if (a.tw_hi == nullptr) return lo[E];
-  const cx<T>* hi = reinterpret_cast<const cx<T>*>(a.tw_hi);
-  return cmul(lo[E & ((1u << a.tw_bits) - 1u)], hi[E >> a.tw_bits]);
-}
 
 struct TileCtx {
   int64_t base;    // element offset of tile position (0, 0)
@@ -54,10 +29,14 @@ struct TileCtx {
   uint32_t ls_c;   // LDS linear stride between columns
 };
 
-// One op over all items of the tile.
+// One op over all items of the tile.  An op reads its R inputs from LDS or,
+// when it is the first op of the pass and its access is coalesced
+// (op.src_g), straight from global memory; symmetrically it writes to LDS or
+// (op.dst_g, last op) straight to global memory.
 template <typename T, int r, int g, int TYPE>
-__device__ __forceinline__ void run_op(const PassArgs& a, const OpDesc& op,
-                                       const TileCtx& t, cx<T>* lds) {
+__device__ __forceinline__ void run_op(const PassArgs& a, const OpDesc& op, const TileCtx& t,
+                                       cx<T>* lds, const void* __restrict__ in,
+                                       void* __restrict__ out) {
   constexpr int R = ipow(r, g);
   const uint32_t S = op.S, K = op.K;
   for (uint32_t it = threadIdx.x; it < op.nitems; it += blockDim.x) {
@@ -78,9 +57,23 @@ __device__ __forceinline__ void run_op(const PassArgs& a, const OpDesc& op,
     const uint32_t i0 = b * K + j;
     const uint32_t lbase = i0 * t.ls_i + c * t.ls_c;
     const uint32_t lstep = S * t.ls_i;
+    const int64_t gbase = t.base + (int64_t)i0 * a.S_i + (int64_t)c * a.S_c;
+    const int64_t gstep = (int64_t)S * a.S_i;
+    // element at offset k*S along the axis from position i0
+    auto get = [&](int k) -> cx<T> {
+      if (op.src_g) return valid ? ld_g<T>(in, gbase + k * gstep) : cx<T>{(T)0, (T)0};
+      return lds[lds_phys(lbase + k * lstep)];
+    };
+    auto put = [&](int k, cx<T> v) {
+      if (op.dst_g) {
+        if (valid) st_g<T>(out, gbase + k * gstep, v);
+      } else {
+        lds[lds_phys(lbase + k * lstep)] = v;
+      }
+    };
     cx<T> v[R];
     if constexpr (TYPE == OP_DIF) {
-      static_for<R>([&](auto s) { v[s.value] = lds[lds_phys(lbase + s.value * lstep)]; });
+      static_for<R>([&](auto s) { v[s.value] = get(s.value); });
       Dft<R, r, false, T>::run(v);
       if (op.tw) {
         const uint32_t jf = j * a.jmul + (a.col_in_j && valid ? gcol : 0u);
@@ -91,13 +84,9 @@ __device__ __forceinline__ void run_op(const PassArgs& a, const OpDesc& op,
           v[mm.value + 1] = cmul(v[mm.value + 1], twiddle<T>(a, E * op.escale));
         });
       }
-      static_for<R>([&](auto m) {
-        lds[lds_phys(lbase + digrev<r, g>(m.value) * lstep)] = v[m.value];
-      });
+      static_for<R>([&](auto m) { put(digrev<r, g>(m.value), v[m.value]); });
     } else if constexpr (TYPE == OP_DIT) {
-      static_for<R>([&](auto m) {
-        v[m.value] = lds[lds_phys(lbase + digrev<r, g>(m.value) * lstep)];
-      });
+      static_for<R>([&](auto m) { v[m.value] = get(digrev<r, g>(m.value)); });
       if (op.tw) {
         const uint32_t jf = j * a.jmul + (a.col_in_j && valid ? gcol : 0u);
         uint32_t E = 0;
@@ -108,19 +97,18 @@ __device__ __forceinline__ void run_op(const PassArgs& a, const OpDesc& op,
         });
       }
       Dft<R, r, true, T>::run(v);
-      static_for<R>([&](auto s) { lds[lds_phys(lbase + s.value * lstep)] = v[s.value]; });
+      static_for<R>([&](auto s) { put(s.value, v[s.value]); });
     } else {  // OP_MID: S == 1, j == 0
-      static_for<R>([&](auto s) { v[s.value] = lds[lds_phys(lbase + s.value * lstep)]; });
+      static_for<R>([&](auto s) { v[s.value] = get(s.value); });
       Dft<R, r, false, T>::run(v);
       if (valid) {
-        const int64_t gb = t.base + (int64_t)i0 * a.S_i + (int64_t)c * a.S_c;
         static_for<R>([&](auto m) {
-          const cx<T> h = ld_g<T>(a.H, gb + (int64_t)digrev<r, g>(m.value) * a.S_i);
+          const cx<T> h = ld_g<T>(a.H, gbase + (int64_t)digrev<r, g>(m.value) * a.S_i);
           v[m.value] = cmul(v[m.value], h);
         });
       }
       Dft<R, r, true, T>::run(v);
-      static_for<R>([&](auto s) { lds[lds_phys(lbase + s.value * lstep)] = v[s.value]; });
+      static_for<R>([&](auto s) { put(s.value, v[s.value]); });
     }
   }
 }
@@ -134,11 +122,12 @@ constexpr bool kind_in_class() { return CLS == 1 || R <= 16; }
 
 template <typename T, int TYPE, int CLS>
 __device__ __forceinline__ void dispatch_op(const PassArgs& a, const OpDesc& op,
-                                            const TileCtx& t, cx<T>* lds) {
+                                            const TileCtx& t, cx<T>* lds,
+                                            const void* __restrict__ in, void* __restrict__ out) {
   switch (op.kind) {
 #define PAFC_CASE(id, r, g)                                        \
   case id:                                                         \
-    if constexpr (kind_in_class<ipow(r, g), CLS>()) run_op<T, r, g, TYPE>(a, op, t, lds); \
+    if constexpr (kind_in_class<ipow(r, g), CLS>()) run_op<T, r, g, TYPE>(a, op, t, lds, in, out); \
     break;
     PAFC_KIND_LIST(PAFC_CASE)
 #undef PAFC_CASE
@@ -165,49 +154,51 @@ __device__ __forceinline__ void do_tile(const PassArgs& a, const void* __restric
     t.ls_i = 1;
     t.ls_c = a.L;
   }
-  // load
-  for (uint32_t x = threadIdx.x; x < a.LW; x += blockDim.x) {
-    uint32_t i, c;
-    if (a.mode == MODE_STRIDED) {
-      i = x >> a.logW;
-      c = x & (a.W - 1u);
-    } else {
-      c = fdiv(x, a.divL);
-      i = x - c * a.L;
+  // load (unless the first op reads global memory itself)
+  if (!a.ops[0].src_g) {
+    for (uint32_t x = threadIdx.x; x < a.LW; x += blockDim.x) {
+      uint32_t i, c;
+      if (a.mode == MODE_STRIDED) {
+        i = x >> a.logW;
+        c = x & (a.W - 1u);
+      } else {
+        c = fdiv(x, a.divL);
+        i = x - c * a.L;
+      }
+      cx<T> v = {(T)0, (T)0};
+      if (t.col0 + c < a.ncols) v = ld_g<T>(in, t.base + (int64_t)i * a.S_i + (int64_t)c * a.S_c);
+      lds[lds_phys(x)] = v;
     }
-    cx<T> v = {(T)0, (T)0};
-    if (t.col0 + c < a.ncols) v = ld_g<T>(in, t.base + (int64_t)i * a.S_i + (int64_t)c * a.S_c);
-    lds[lds_phys(x)] = v;
-  }
-  __syncthreads();
-  for (uint32_t k = 0; k < a.nops; ++k) {
-    const OpDesc& op = a.ops[k];
-    if (op.type == OP_DIF)
-      dispatch_op<T, OP_DIF, CLS>(a, op, t, lds);
-    else if (op.type == OP_DIT)
-      dispatch_op<T, OP_DIT, CLS>(a, op, t, lds);
-    else
-      dispatch_op<T, OP_MID, CLS>(a, op, t, lds);
     __syncthreads();
   }
-  // store
-  for (uint32_t x = threadIdx.x; x < a.LW; x += blockDim.x) {
-    uint32_t i, c;
-    if (a.mode == MODE_STRIDED) {
-      i = x >> a.logW;
-      c = x & (a.W - 1u);
-    } else {
-      c = fdiv(x, a.divL);
-      i = x - c * a.L;
+  const uint32_t nops = a.nops;
+  for (uint32_t k = 0; k < nops; ++k) {
+    const OpDesc& op = a.ops[k];
+    if (op.type == OP_DIF)
+      dispatch_op<T, OP_DIF, CLS>(a, op, t, lds, in, out);
+    else if (op.type == OP_DIT)
+      dispatch_op<T, OP_DIT, CLS>(a, op, t, lds, in, out);
+    else
+      dispatch_op<T, OP_MID, CLS>(a, op, t, lds, in, out);
+    if (k + 1 < nops || !op.dst_g) __syncthreads();
+  }
+  // store (unless the last op wrote global memory itself)
+  if (!a.ops[nops - 1].dst_g) {
+    for (uint32_t x = threadIdx.x; x < a.LW; x += blockDim.x) {
+      uint32_t i, c;
+      if (a.mode == MODE_STRIDED) {
+        i = x >> a.logW;
+        c = x & (a.W - 1u);
+      } else {
+        c = fdiv(x, a.divL);
+        i = x - c * a.L;
+      }
+      if (t.col0 + c < a.ncols)
+        st_g<T>(out, t.base + (int64_t)i * a.S_i + (int64_t)c * a.S_c, lds[lds_phys(x)]);
     }
-    if (t.col0 + c < a.ncols)
-      st_g<T>(out, t.base + (int64_t)i * a.S_i + (int64_t)c * a.S_c, lds[lds_phys(x)]);
   }
 }
 
-// The descriptor lives in device memory (uploaded with the plan): indexing its
-// op list at run time from a by-value kernel argument would force a private
-// copy of the whole struct.
 template <typename T, int CLS>
 __global__ void __launch_bounds__(256) pass_kernel(const PassArgs* __restrict__ desc,
                                                    const void* in, void* out) {

@@ -1,0 +1,294 @@
+// Persistent, software-pipelined pass kernel for uniform-radix axes.
+//
+// Same arithmetic as pass_kernel (grouped DIF / DIT stages of the paper's
+// transposed and conjugate butterfly kernels, and the fused product with the
+// digit-reversed spectrum), specialised at compile time for an axis of
+// length L = R^NG split into NG groups of one radix R = r^g.  Each thread owns
+// exactly one R-element item of every group.  A block stays resident and
+// walks the tiles blockIdx.x, blockIdx.x + gridDim.x, ...; while it
+// computes one tile, the global loads of the next tile (its first group's
+// inputs and, for the middle pass, its filter values) are already in flight.
+// Twiddles are staged once per block in LDS, so no global load other than
+// the prefetch sits in the loop and the in-order vector-memory counter never
+// makes a group wait on the prefetch.
+#include "kernel_common.h"
+
+namespace pafc {
+
+enum { PIPE_FWD = 0, PIPE_INV = 1, PIPE_MID = 2 };
+
+template <int R, int NG, int KIND>
+struct PipeShape {
+  static constexpr int L = ipow(R, NG);
+  static constexpr int NOPS = KIND == PIPE_MID ? 2 * NG - 1 : NG;
+  // op i of the pass: its type and its level k (block size K = L / R^k)
+  static constexpr int type(int i) {
+    return KIND == PIPE_FWD ? OP_DIF
+           : KIND == PIPE_INV ? OP_DIT
+                              : (i < NG - 1 ? OP_DIF : i == NG - 1 ? OP_MID : OP_DIT);
+  }
+  static constexpr int level(int i) {
+    return KIND == PIPE_FWD ? i : KIND == PIPE_INV ? NG - 1 - i : (i < NG ? i : 2 * NG - 2 - i);
+  }
+};
+
+struct Item {
+  uint32_t c, j, i0;
+  bool valid;
+};
+
+template <int R, int L, int K, int MODE>
+__device__ __forceinline__ Item item_of(uint32_t tid, uint32_t W, uint32_t logW, uint32_t col0,
+                                        uint32_t ncols) {
+  constexpr uint32_t S = K / R, NB = L / K;
+  Item it;
+  uint32_t b;
+  if (MODE == MODE_STRIDED) {
+    it.c = tid & (W - 1u);
+    const uint32_t rest = tid >> logW;
+    b = rest / S;
+    it.j = rest - b * S;
+  } else {
+    const uint32_t q = tid / S;
+    it.j = tid - q * S;
+    it.c = q / NB;
+    b = q - it.c * NB;
+  }
+  it.i0 = b * K + it.j;
+  it.valid = col0 + it.c < ncols;
+  return it;
+}
+
+template <typename T, int r, int g, int NG, int KIND, int MODE>
+__global__ void __launch_bounds__(256) pipe_kernel(const PassArgs* __restrict__ desc,
+                                                   const void* __restrict__ in,
+                                                   void* __restrict__ out) {
+  constexpr int R = ipow(r, g);
+  using Sh = PipeShape<R, NG, KIND>;
+  constexpr int L = Sh::L;
+  constexpr int NOPS = Sh::NOPS;
+  constexpr int MID_OP = NG - 1;
+  // the first op reads global memory directly unless it is the contiguous
+  // inverse (its first group has leg stride 1: load the tile linearly)
+  constexpr bool LINEAR_LOAD = (MODE == MODE_CONTIG && KIND == PIPE_INV);
+  // the last op writes global memory directly unless it is the contiguous
+  // forward (its last group has leg stride 1: store the tile linearly)
+  constexpr bool LINEAR_STORE = (MODE == MODE_CONTIG && KIND == PIPE_FWD);
+
+  const PassArgs& a = *desc;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
+  const uint32_t LW = a.LW;
+  cx<T>* tw = lds + ((LW + (LW >> 4) + 2) & ~1u);
+  const uint32_t tid = threadIdx.x;
+  const uint32_t nthr = blockDim.x;
+  const uint32_t W = a.W, logW = a.logW;
+  const uint32_t ls_i = MODE == MODE_STRIDED ? W : 1u;
+  const uint32_t ls_c = MODE == MODE_STRIDED ? 1u : (uint32_t)L;
+
+  {
+    const cx<T>* lo = reinterpret_cast<const cx<T>*>(a.tw_lo);
+    for (uint32_t e = tid; e < (uint32_t)L; e += nthr) tw[e] = lo[e];
+  }
+
+  auto tile_base = [&](uint32_t tile, uint32_t& col0) -> int64_t {
+    const uint32_t o = fdiv(tile, a.divTiles);
+    const uint32_t cb = tile - o * a.tiles_per_slice;
+    col0 = cb * W;
+    return (int64_t)o * a.S_o + (int64_t)col0 * a.S_c;
+  };
+
+  // prefetch registers: the first op's inputs (or this thread's share of the
+  // linear tile load) and, for the middle pass, the filter values of the MID
+  // op of the same tile
+  cx<T> pre[R];
+  cx<T> preh[KIND == PIPE_MID ? R : 1];
+
+  auto fetch_x = [&](uint32_t tile) {
+    uint32_t col0;
+    const int64_t base = tile_base(tile, col0);
+    if constexpr (LINEAR_LOAD) {
+      static_for<R>([&](auto q) {
+        const uint32_t x = tid + nthr * q.value;
+        const uint32_t c = x / (uint32_t)L, i = x - c * (uint32_t)L;
+        pre[q.value] = (col0 + c < a.ncols) ? ld_g<T>(in, base + (int64_t)i + (int64_t)c * a.S_c)
+                                            : cx<T>{(T)0, (T)0};
+      });
+    } else {
+      constexpr int k0 = Sh::level(0);
+      constexpr int K0 = L / ipow(R, k0);
+      constexpr int S0 = K0 / R;
+      const Item it = item_of<R, L, K0, MODE>(tid, W, logW, col0, a.ncols);
+      const int64_t gb = base + (int64_t)it.i0 * a.S_i + (int64_t)it.c * a.S_c;
+      static_for<R>([&](auto s) {
+        // DIF reads natural positions, DIT reads digit-reversed ones
+        constexpr int p = Sh::type(0) == OP_DIT ? digrev<r, g>(s.value) : s.value;
+        pre[s.value] = it.valid ? ld_g<T>(in, gb + (int64_t)(p * S0) * a.S_i) : cx<T>{(T)0, (T)0};
+      });
+    }
+  };
+  auto fetch_h = [&](uint32_t tile) {
+    if constexpr (KIND == PIPE_MID) {
+      uint32_t col0;
+      const int64_t base = tile_base(tile, col0);
+      const Item it = item_of<R, L, R, MODE>(tid, W, logW, col0, a.ncols);
+      const int64_t gb = base + (int64_t)it.i0 * a.S_i + (int64_t)it.c * a.S_c;
+      static_for<R>([&](auto m) {
+        preh[m.value] = it.valid ? ld_g<T>(a.H, gb + (int64_t)digrev<r, g>(m.value) * a.S_i)
+                                 : cx<T>{(T)0, (T)0};
+      });
+    }
+  };
+
+  uint32_t tile = blockIdx.x;
+  if (tile < a.ntiles) {
+    fetch_x(tile);
+    fetch_h(tile);
+  }
+  __syncthreads();  // twiddles visible
+
+  while (tile < a.ntiles) {
+    const uint32_t next = tile + gridDim.x;
+    uint32_t col0;
+    const int64_t base = tile_base(tile, col0);
+    if constexpr (LINEAR_LOAD) {
+      static_for<R>([&](auto q) { lds[lds_phys(tid + nthr * q.value)] = pre[q.value]; });
+      if (next < a.ntiles) fetch_x(next);  // pre is free again
+      __syncthreads();
+    }
+    static_for<NOPS>([&](auto opi) {
+      constexpr int i = decltype(opi)::value;
+      constexpr int type = Sh::type(i);
+      constexpr int k = Sh::level(i);
+      constexpr int K = L / ipow(R, k);
+      constexpr int S = K / R;
+      constexpr bool first = (i == 0) && !LINEAR_LOAD;
+      constexpr bool last = (i == NOPS - 1) && !LINEAR_STORE;
+      const Item it = item_of<R, L, K, MODE>(tid, W, logW, col0, a.ncols);
+      const uint32_t lbase = it.i0 * ls_i + it.c * ls_c;
+      const int64_t gb = base + (int64_t)it.i0 * a.S_i + (int64_t)it.c * a.S_c;
+      cx<T> v[R];
+      // inputs
+      static_for<R>([&](auto s) {
+        constexpr int p = type == OP_DIT ? digrev<r, g>(s.value) : s.value;
+        if constexpr (first)
+          v[s.value] = pre[s.value];
+        else
+          v[s.value] = lds[lds_phys(lbase + (uint32_t)(p * S) * ls_i)];
+      });
+      if constexpr (i == 0 && !LINEAR_LOAD) {
+        // the inputs are in registers: start loading the next tile now
+        if (next < a.ntiles) fetch_x(next);
+      }
+      if constexpr (type == OP_DIF) {
+        Dft<R, r, false, T>::run(v);
+        if constexpr (S > 1) {
+          uint32_t E = 0;
+          static_for<R - 1>([&](auto mm) {
+            E += it.j;
+            if (E >= (uint32_t)K) E -= (uint32_t)K;
+            v[mm.value + 1] = cmul(v[mm.value + 1], tw[E * (uint32_t)(L / K)]);
+          });
+        }
+      } else if constexpr (type == OP_DIT) {
+        if constexpr (S > 1) {
+          uint32_t E = 0;
+          static_for<R - 1>([&](auto mm) {
+            E += it.j;
+            if (E >= (uint32_t)K) E -= (uint32_t)K;
+            v[mm.value + 1] = cmulc(v[mm.value + 1], tw[E * (uint32_t)(L / K)]);
+          });
+        }
+        Dft<R, r, true, T>::run(v);
+      } else {  // MID
+        Dft<R, r, false, T>::run(v);
+        static_for<R>([&](auto m) { v[m.value] = cmul(v[m.value], preh[m.value]); });
+        if (next < a.ntiles) fetch_h(next);
+        Dft<R, r, true, T>::run(v);
+      }
+      // outputs
+      static_for<R>([&](auto s) {
+        // DIF writes frequency m at its digit-reversed position
+        constexpr int p = type == OP_DIF ? digrev<r, g>(s.value) : s.value;
+        if constexpr (last) {
+          if (it.valid) st_g<T>(out, gb + (int64_t)(p * S) * a.S_i, v[s.value]);
+        } else {
+          lds[lds_phys(lbase + (uint32_t)(p * S) * ls_i)] = v[s.value];
+        }
+      });
+      if constexpr (!last) __syncthreads();
+    });
+    if constexpr (LINEAR_STORE) {
+      static_for<R>([&](auto q) {
+        const uint32_t x = tid + nthr * q.value;
+        const uint32_t c = x / (uint32_t)L, i = x - c * (uint32_t)L;
+        if (col0 + c < a.ncols) st_g<T>(out, base + (int64_t)i + (int64_t)c * a.S_c, lds[lds_phys(x)]);
+      });
+    }
+    __syncthreads();  // LDS free for the next tile
+    tile = next;
+  }
+}
+
+// ------------------------------------------------------------ launches
+
+#define PAFC_PIPE_SHAPES(X)   \
+  X(4, 2, 2) /* L = 256 */    \
+  X(4, 2, 3) /* L = 4096 */   \
+  X(2, 4, 2) /* L = 256 */    \
+  X(2, 4, 3) /* L = 4096 */   \
+  X(8, 1, 2) /* L = 64 */     \
+  X(8, 1, 3) /* L = 512 */    \
+  X(4, 2, 1) /* L = 16 */
+
+template <typename T, int r, int g, int NG>
+static const void* pipe_fn(int kind, int mode) {
+#define PAFC_PIPE_SEL(K, M) \
+  if (kind == K && mode == M) return (const void*)pipe_kernel<T, r, g, NG, K, M>;
+  PAFC_PIPE_SEL(PIPE_FWD, MODE_CONTIG)
+  PAFC_PIPE_SEL(PIPE_FWD, MODE_STRIDED)
+  PAFC_PIPE_SEL(PIPE_INV, MODE_CONTIG)
+  PAFC_PIPE_SEL(PIPE_INV, MODE_STRIDED)
+  PAFC_PIPE_SEL(PIPE_MID, MODE_CONTIG)
+  PAFC_PIPE_SEL(PIPE_MID, MODE_STRIDED)
+#undef PAFC_PIPE_SEL
+  return nullptr;
+}
+
+static const void* pipe_lookup(bool dbl, int r, int g, int ng, int kind, int mode) {
+#define PAFC_PIPE_GO(rr, gg, nn)                                                          \
+  if (r == rr && g == gg && ng == nn)                                                     \
+    return dbl ? pipe_fn<double, rr, gg, nn>(kind, mode) : pipe_fn<float, rr, gg, nn>(kind, mode);
+  PAFC_PIPE_SHAPES(PAFC_PIPE_GO)
+#undef PAFC_PIPE_GO
+  return nullptr;
+}
+
+bool pipe_supported(int r, int g, int ng) {
+  return pipe_lookup(true, r, g, ng, PIPE_FWD, MODE_CONTIG) != nullptr;
+}
+
+// Resident blocks per CU of a pipelined kernel instance (0 on error).
+int pipe_blocks_per_cu(bool dbl, int r, int g, int ng, int kind, int mode, uint32_t threads,
+                       size_t lds) {
+  const void* fn = pipe_lookup(dbl, r, g, ng, kind, mode);
+  if (!fn) return 0;
+  if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) != hipSuccess)
+    return 0;
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, (int)threads, lds) != hipSuccess) return 0;
+  return nb;
+}
+
+hipError_t launch_pipe(bool dbl, int r, int g, int ng, int kind, int mode, const PassArgs* d,
+                       uint32_t grid, uint32_t threads, size_t lds, const void* in, void* out,
+                       hipStream_t s) {
+  const void* fn = pipe_lookup(dbl, r, g, ng, kind, mode);
+  if (!fn) return hipErrorInvalidValue;
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  if (e != hipSuccess) return e;
+  void* args[] = {(void*)&d, (void*)&in, (void*)&out};
+  return hipLaunchKernel(fn, dim3(grid), dim3(threads), args, lds, s);
+}
+
+}  // namespace pafc
