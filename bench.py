@@ -30,18 +30,10 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 
 
-def kernel_source_hash():
-    h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2506_12718_amd", "csrc", "*"))):
-        if f.endswith((".hip", ".h", ".cpp")):
-            with open(f, "rb") as fh:
-                h.update(fh.read())
-    return h.hexdigest()[:16]
-
-
 def load_traffic(workload):
     """HBM bytes per launch of the dominant kernel from committed rocprofv3
-    counter runs, if they were taken on the current kernel source."""
+    counter runs, if they were taken on the current kernel sources."""
+    from paper_2506_12718_amd.profiling import kernel_source_hash
     path = os.path.join(ROOT, "profiles", "%s_traffic.json" % workload)
     if not os.path.exists(path):
         return None
@@ -136,6 +128,8 @@ def main():
     ap.add_argument("--dtype", default="c128", choices=["c128", "c64"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing and error check")
     ap.add_argument("--no-compare", action="store_true", help="skip the comparison variants")
+    ap.add_argument("--calibrate", action="store_true",
+                    help="run only the plain streaming copy of 256 MiB (counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -147,6 +141,20 @@ def main():
     import paper_2506_12718_amd as pafc
     pafc.lib()
     torch.cuda.set_device(0)
+    if args.calibrate:
+        nbytes = 256 << 20
+        a = torch.zeros(nbytes // 16, dtype=torch.complex128, device="cuda")
+        b = torch.empty_like(a)
+        pafc.stream_copy(a, b)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(10):
+            pafc.stream_copy(a, b)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / 10
+        print(json.dumps({"calibration_copy_bytes": nbytes, "ms": dt * 1e3,
+                          "GBps_read_plus_write": 2 * nbytes / dt / 1e9}))
+        return
     tdtype = torch.complex128 if args.dtype == "c128" else torch.complex64
     wl = WORKLOADS[args.workload](args.dtype)
     N = wl["x"].size
@@ -159,18 +167,23 @@ def main():
     value = args.steps / main_r["wall"]
     ms_step = main_r["wall"] * 1e3 / args.steps
 
-    # dominant kernel: the axis-pass kernel (every pass of this plan)
-    kern = [i for i, l in enumerate(main_r["labels"]) if not l.startswith(("mul", "permute"))]
-    k_ms = sum(main_r["ms_pass"][i] for i in kern)
-    k_bytes = sum(main_r["bytes_pass"][i] for i in kern)
-    nlaunch = len(kern)
-    achieved = (k_bytes / nlaunch) / (k_ms / nlaunch * 1e-3) / 1e9
+    # dominant kernel: the single most expensive launch of a convolution (for
+    # multi-pass plans the fused middle pass, which also reads the spectrum)
+    dom = max(range(len(main_r["ms_pass"])), key=lambda i: main_r["ms_pass"][i])
+    dom_ms = main_r["ms_pass"][dom]
+    dom_bytes = main_r["bytes_pass"][dom]
+    achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
     traffic = load_traffic(wl["name"])
+    kern = [i for i, l in enumerate(main_r["labels"]) if not l.startswith(("mul", "permute"))]
+    all_ms = sum(main_r["ms_pass"][i] for i in kern)
+    all_bytes = sum(main_r["bytes_pass"][i] for i in kern)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "kernel": "pass_kernel", "launches_per_conv": nlaunch,
-            "alg_bytes_per_launch": k_bytes / nlaunch,
-            "avg_launch_ms": round(k_ms / nlaunch, 5)}
+            "kernel": main_r["labels"][dom], "alg_bytes_per_launch": dom_bytes,
+            "avg_launch_ms": round(dom_ms, 5),
+            "all_passes": {"launches": len(kern), "alg_bytes": all_bytes,
+                           "ms": round(all_ms, 5),
+                           "achieved": round(all_bytes / (all_ms * 1e-3) / 1e9, 1)}}
     alg_bytes = main_r["desc"]["hbm_bytes_conv"]
     out = {
         "metric": "convolutions/s + HBM GB/s (% roofline), perm-free vs explicit-perm; p99 latency",

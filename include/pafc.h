@@ -226,6 +226,16 @@ pafc_status pafc_profile_passes(pafc_plan_t p, const void* x_dev, void* y_dev,
                                 int64_t* bytes_per_pass, double* ms_per_rep,
                                 int* npass);
 
+/*
+ * pafc_stream_copy -- a plain streaming copy of `bytes` bytes (multiple of
+ * 16) from src_dev to dst_dev on hip_stream.  Not part of the convolution:
+ * it is the reference kernel of known traffic used to calibrate hardware
+ * byte counters (one read and one write of every byte).
+ * Errors: INVALID_VALUE (NULL, misaligned, bytes not a multiple of 16), DEVICE.
+ */
+pafc_status pafc_stream_copy(const void* src_dev, void* dst_dev, size_t bytes,
+                             void* hip_stream);
+
 /* ------------------------------------------------------------------------
  * Batched form: many independent 1-D convolutions of uneven sizes.
  *

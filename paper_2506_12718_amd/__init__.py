@@ -40,7 +40,8 @@ EXPORTS = ("pafc_plan", "pafc_set_filter", "pafc_convolve", "pafc_forward",
            "pafc_plan_device_bytes", "pafc_plan_radices", "pafc_describe",
            "pafc_batch_plan", "pafc_batch_set_filter", "pafc_batch_convolve",
            "pafc_batch_destroy", "pafc_batch_device_bytes",
-           "pafc_batch_describe", "pafc_set_tuning", "pafc_profile_passes")
+           "pafc_batch_describe", "pafc_set_tuning", "pafc_profile_passes",
+           "pafc_stream_copy")
 
 
 class PafcError(RuntimeError):
@@ -83,6 +84,7 @@ def lib():
             "pafc_batch_device_bytes": [vp, ctypes.POINTER(sz)],
             "pafc_batch_describe": [vp, ctypes.c_char_p, sz, ctypes.POINTER(sz)],
             "pafc_set_tuning": [ctypes.c_char_p],
+            "pafc_stream_copy": [vp, vp, sz, vp],
             "pafc_profile_passes": [vp, vp, vp, vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
                                     ctypes.POINTER(ctypes.c_int64),
                                     ctypes.POINTER(ctypes.c_double), ip],
@@ -159,6 +161,14 @@ def describe(dims, dtype="c128", radix=None, variant="perm_free"):
                              ctypes.byref(need))
     _check(st, "pafc_describe")
     return json.loads(buf.value.decode())
+
+
+def stream_copy(src, dst, stream=None):
+    """Plain streaming copy (the counter-calibration kernel)."""
+    nbytes = src.numel() * src.element_size()
+    assert dst.numel() * dst.element_size() == nbytes
+    _check(lib().pafc_stream_copy(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()),
+                                  nbytes, _stream(stream)), "pafc_stream_copy")
 
 
 def set_tuning(text):

@@ -38,6 +38,7 @@ hipError_t launch_pipe(bool dbl, int r, int g, int ng, int kind, int mode, const
                        uint32_t grid, uint32_t threads, size_t lds, const void* in, void* out,
                        hipStream_t s);
 hipError_t launch_mul(bool dbl, const void* x, const void* h, void* y, int64_t n, hipStream_t st);
+hipError_t launch_stream_copy(const void* src, void* dst, int64_t n16, hipStream_t st);
 hipError_t launch_permute_rows(bool dbl, const void* in, void* out, const void* h,
                                const int32_t* m0, const int32_t* m1, const int32_t* mlast,
                                uint32_t n0, uint32_t n1, uint32_t nlast, uint32_t rows_per_block,
@@ -397,6 +398,10 @@ bool make_pass(const Seg& s, int kind, size_t elem, Pass* p) {
       p->pipe_kind = kind;
       const uint64_t LW = a.LW;
       p->pipe_lds = (size_t)(((LW + (LW >> 4) + 2) & ~1ull) + s.L) * elem;
+      char nm[96];
+      snprintf(nm, sizeof(nm), " pipe_kernel<%s,%d,%d,%d,%d,%d>", elem == 16 ? "double" : "float",
+               p->pipe_r, p->pipe_g, ng, kind, (int)s.mode);
+      p->label += nm;
     }
   }
   char buf[160];
@@ -901,7 +906,6 @@ pafc_status pafc_plan(pafc_plan_t* out, int ndim, const int64_t* dims, const int
         const int64_t want = (int64_t)nb * ncu;
         ps.pipe_grid = (uint32_t)std::min<int64_t>(want, ps.a.ntiles);
         if (nb <= 0) ps.pipe = false;
-        else ps.label += " pipe";
       }
   }
   // pass descriptors of the three sequences, uploaded once
@@ -1051,6 +1055,12 @@ pafc_status pafc_inverse(pafc_plan_t p, const void* z_dev, void* y_dev, void* hi
   hipStream_t s = (hipStream_t)hip_stream;
   PAFC_TRY(run_sequence(p, p->P.inv, z_dev, y_dev, s));
   return from_hip(launch_scale(p->P.dtype == PAFC_C128, y_dev, p->P.N, 1.0 / (double)p->P.N, s));
+}
+
+pafc_status pafc_stream_copy(const void* src_dev, void* dst_dev, size_t bytes, void* hip_stream) {
+  if (!src_dev || !dst_dev || (bytes % 16) != 0) return PAFC_ERROR_INVALID_VALUE;
+  if (((uintptr_t)src_dev & 15) || ((uintptr_t)dst_dev & 15)) return PAFC_ERROR_INVALID_VALUE;
+  return from_hip(launch_stream_copy(src_dev, dst_dev, (int64_t)(bytes / 16), (hipStream_t)hip_stream));
 }
 
 pafc_status pafc_set_tuning(const char* text) {

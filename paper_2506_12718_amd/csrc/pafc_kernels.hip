@@ -230,6 +230,14 @@ __global__ void scale_kernel(cx<T>* __restrict__ p, int64_t n, T s) {
   }
 }
 
+// Plain streaming copy (counter calibration).
+__global__ void stream_copy_kernel(const double2* __restrict__ a, double2* __restrict__ b,
+                                   int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    b[i] = a[i];
+}
+
 template <typename T>
 __global__ void mul_kernel(const cx<T>* __restrict__ x, const cx<T>* __restrict__ h,
                            cx<T>* __restrict__ y, int64_t n) {
@@ -367,6 +375,12 @@ hipError_t launch_scale(bool dbl, void* p, int64_t n, double s, hipStream_t st) 
   else
     hipLaunchKernelGGL(scale_kernel<float>, dim3(grid_for(n)), dim3(256), 0, st,
                        (cx<float>*)p, n, (float)s);
+  return hipGetLastError();
+}
+
+hipError_t launch_stream_copy(const void* src, void* dst, int64_t n16, hipStream_t st) {
+  hipLaunchKernelGGL(stream_copy_kernel, dim3(grid_for(n16)), dim3(256), 0, st,
+                     (const double2*)src, (double2*)dst, n16);
   return hipGetLastError();
 }
 
