@@ -398,10 +398,6 @@ bool make_pass(const Seg& s, int kind, size_t elem, Pass* p) {
       p->pipe_kind = kind;
       const uint64_t LW = a.LW;
       p->pipe_lds = (size_t)(((LW + (LW >> 4) + 2) & ~1ull) + s.L) * elem;
-      char nm[96];
-      snprintf(nm, sizeof(nm), " pipe_kernel<%s,%d,%d,%d,%d,%d>", elem == 16 ? "double" : "float",
-               p->pipe_r, p->pipe_g, ng, kind, (int)s.mode);
-      p->label += nm;
     }
   }
   char buf[160];
@@ -415,6 +411,12 @@ bool make_pass(const Seg& s, int kind, size_t elem, Pass* p) {
   snprintf(buf, sizeof(buf), "%s L=%u W=%u tiles=%u thr=%u [", s.mode == MODE_STRIDED ? "strided" : "contig",
            s.L, s.W, a.ntiles, p->threads);
   p->label = std::string(buf) + ops + "]";
+  if (p->pipe) {
+    char nm[96];
+    snprintf(nm, sizeof(nm), " pipe_kernel<%s,%d,%d,%d,%d,%d>", elem == 16 ? "double" : "float",
+             p->pipe_r, p->pipe_g, p->pipe_ng, kind, (int)s.mode);
+    p->label += nm;
+  }
   return true;
 }
 
