@@ -271,6 +271,20 @@ pafc_status pafc_batch_destroy(pafc_batch_t b);
 
 pafc_status pafc_batch_device_bytes(pafc_batch_t b, size_t* bytes);
 
+/*
+ * pafc_batch_profile -- run pafc_batch_convolve `reps` times with a hipEvent
+ * around every launch (one launch per pass level), synchronise, and report
+ * the mean ms of each level, its algorithmic HBM bytes (one read and one
+ * write of every element of every problem in the level, plus each filter
+ * spectrum once in the level that multiplies by it), and the ms of every
+ * repetition (ms_per_rep may be NULL).  *nlevel: capacity in, count out.
+ * Errors: as pafc_batch_convolve; INVALID_VALUE if the capacity is too small.
+ */
+pafc_status pafc_batch_profile(pafc_batch_t b, const void* x_dev, void* y_dev,
+                               void* hip_stream, int reps, double* ms_per_level,
+                               int64_t* bytes_per_level, double* ms_per_rep,
+                               int* nlevel);
+
 /* JSON description of a batch plan (host only). */
 pafc_status pafc_batch_describe(pafc_batch_t b, char* buf, size_t cap,
                                 size_t* needed);

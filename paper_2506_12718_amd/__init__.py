@@ -41,7 +41,7 @@ EXPORTS = ("pafc_plan", "pafc_set_filter", "pafc_convolve", "pafc_forward",
            "pafc_batch_plan", "pafc_batch_set_filter", "pafc_batch_convolve",
            "pafc_batch_destroy", "pafc_batch_device_bytes",
            "pafc_batch_describe", "pafc_set_tuning", "pafc_profile_passes",
-           "pafc_stream_copy")
+           "pafc_stream_copy", "pafc_batch_profile")
 
 
 class PafcError(RuntimeError):
@@ -85,6 +85,9 @@ def lib():
             "pafc_batch_describe": [vp, ctypes.c_char_p, sz, ctypes.POINTER(sz)],
             "pafc_set_tuning": [ctypes.c_char_p],
             "pafc_stream_copy": [vp, vp, sz, vp],
+            "pafc_batch_profile": [vp, vp, vp, vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                                   ctypes.POINTER(ctypes.c_int64),
+                                   ctypes.POINTER(ctypes.c_double), ip],
             "pafc_profile_passes": [vp, vp, vp, vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
                                     ctypes.POINTER(ctypes.c_int64),
                                     ctypes.POINTER(ctypes.c_double), ip],
@@ -318,6 +321,21 @@ class Batch:
                                          ctypes.c_void_p(out.data_ptr()), _stream(stream)),
                "pafc_batch_convolve")
         return out
+
+    def profile_levels(self, x, out, reps=10, stream=None):
+        """Run `reps` batched convolutions with a HIP event around every
+        launch.  Returns (mean ms per level, algorithmic bytes per level, ms of
+        every repetition)."""
+        n = ctypes.c_int(8)
+        ms = (ctypes.c_double * 8)()
+        by = (ctypes.c_int64 * 8)()
+        per = (ctypes.c_double * int(reps))()
+        _check(lib().pafc_batch_profile(self._h, ctypes.c_void_p(x.data_ptr()),
+                                        ctypes.c_void_p(out.data_ptr()), _stream(stream),
+                                        int(reps), ms, by, per, ctypes.byref(n)),
+               "pafc_batch_profile")
+        return ([ms[i] for i in range(n.value)], [by[i] for i in range(n.value)],
+                [per[i] for i in range(int(reps))])
 
     def describe(self):
         need = ctypes.c_size_t(0)

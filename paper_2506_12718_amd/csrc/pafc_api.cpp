@@ -353,6 +353,35 @@ bool build_ops(const Seg& s, int kind, PassArgs& a, int* cls) {
   return true;
 }
 
+// Host-side bounds check of a pass descriptor, with the kernels' own index
+// formulas: every tile touches positions i < L of valid columns c at
+// base + i*S_i + c*S_c (base = o*S_o + col0*S_c); every op reads and writes
+// positions b*K + j + s*S < L; twiddle indices stay below n_tw.  `extent` is
+// the number of elements of the array (and of the filter spectrum) the pass
+// runs over.
+bool validate_pass(const PassArgs& a, int64_t extent, int64_t n_tw) {
+  if (a.L == 0 || a.W == 0 || (a.W & (a.W - 1)) != 0 || a.LW != a.L * a.W) return false;
+  if (a.tiles_per_slice != (a.ncols + a.W - 1) / a.W) return false;
+  if (a.ntiles % a.tiles_per_slice != 0) return false;
+  const int64_t nouter = a.ntiles / a.tiles_per_slice;
+  const int64_t last_col = (int64_t)a.ncols - 1;
+  const int64_t maxidx = (nouter - 1) * a.S_o + last_col * a.S_c + (int64_t)(a.L - 1) * a.S_i;
+  if (maxidx >= extent || a.S_i <= 0 || a.S_c <= 0 || a.S_o < 0) return false;
+  if (a.nops == 0 || a.nops > (uint32_t)kMaxOps) return false;
+  uint32_t K = a.L;
+  for (uint32_t k = 0; k < a.nops; ++k) {
+    const OpDesc& op = a.ops[k];
+    if (op.K == 0 || op.R < 2 || op.S * (uint32_t)op.R != op.K || a.L % op.K != 0) return false;
+    if (op.nitems != (a.L / (uint32_t)op.R) * a.W) return false;
+    if (op.Kf != op.K * a.jmul || (int64_t)op.Kf * op.escale != n_tw) return false;
+    if (op.divS.d != op.S || op.divNB.d != a.L / op.K) return false;
+    if (op.type == OP_MID && op.S != 1) return false;
+    if (a.col_in_j && a.jmul != a.ncols) return false;
+    (void)K;
+  }
+  return true;
+}
+
 bool make_pass(const Seg& s, int kind, size_t elem, Pass* p) {
   PassArgs& a = p->a;
   memset(&a, 0, sizeof(a));
@@ -611,6 +640,9 @@ pafc_status plan_core(PlanCore& P, int ndim, const int64_t* dims, const int* rad
     }
     for (auto& p : P.inv) P.conv.push_back(p);
   }
+  for (auto* seq : {&P.conv, &P.fwd, &P.inv})
+    for (const Pass& ps : *seq)
+      if (ps.kind == 0 && !validate_pass(ps.a, P.N, ps.tw_n)) return PAFC_ERROR_UNSUPPORTED_SIZE;
   // algorithmic HBM bytes: each pass reads and writes N elements once; the
   // product reads the spectrum once more
   auto bytes = [&](const std::vector<Pass>& v) {
@@ -1114,6 +1146,7 @@ struct pafc_batch_s {
     uint32_t first = 0, count = 0, threads = 64;
     size_t lds = 0;
     int cls = 0;
+    int64_t bytes = 0;  // algorithmic HBM bytes of the level
   };
   std::vector<Level> levels;
   std::string desc;
@@ -1220,9 +1253,33 @@ pafc_status pafc_batch_plan(pafc_batch_t* out, int count, const int64_t* sizes,
     }
     auto& L = b->levels[(size_t)l];
     L.count = (uint32_t)tiles.size() - L.first;
+    std::vector<bool> fseen((size_t)nfilters, false);
+    for (int i = 0; i < count; ++i) {
+      const int f = b->fid[(size_t)i];
+      auto it2 = didx.find({f, l});
+      if (it2 == didx.end()) continue;
+      L.bytes += 2 * b->sizes[(size_t)i] * (int64_t)b->elem;
+      const pafc_plan_t pp = b->plans[b->sizes[(size_t)i]];
+      if (pp->P.conv[(size_t)l].mid && !fseen[(size_t)f]) {
+        fseen[(size_t)f] = true;
+        L.bytes += b->sizes[(size_t)i] * (int64_t)b->elem;
+      }
+    }
     L.threads = linfo[(size_t)l].threads;
     L.lds = linfo[(size_t)l].lds;
     L.cls = linfo[(size_t)l].cls;
+  }
+  // every tile's problem must lie inside the packed arrays, and its
+  // descriptor must have been built for that problem's length (the filter
+  // spectrum it reads has that length)
+  {
+    std::vector<int64_t> desc_n(descs.size(), 0);
+    for (auto& kv : didx) desc_n[kv.second] = b->fsize[(size_t)kv.first.first];
+    for (const BatchTile& t : tiles) {
+      const int64_t n = desc_n[t.desc];
+      if (t.offset < 0 || t.offset + n > b->total || t.tile >= descs[t.desc].ntiles)
+        return fail(PAFC_ERROR_INVALID_VALUE);
+    }
   }
   hipError_t e = hipMalloc((void**)&b->d_descs, descs.size() * sizeof(PassArgs));
   if (e == hipSuccess) e = hipMalloc((void**)&b->d_tiles, std::max<size_t>(1, tiles.size()) * sizeof(BatchTile));
@@ -1297,6 +1354,58 @@ pafc_status pafc_batch_convolve(pafc_batch_t b, const void* x_dev, void* y_dev, 
     cur = y_dev;
   }
   return PAFC_SUCCESS;
+}
+
+pafc_status pafc_batch_profile(pafc_batch_t b, const void* x_dev, void* y_dev, void* hip_stream,
+                               int reps, double* ms_per_level, int64_t* bytes_per_level,
+                               double* ms_per_rep, int* nlevel) {
+  if (!b || !x_dev || !y_dev || !nlevel || reps < 1 || !ms_per_level) return PAFC_ERROR_INVALID_VALUE;
+  std::vector<size_t> used;
+  for (size_t l = 0; l < b->levels.size(); ++l)
+    if (b->levels[l].count) used.push_back(l);
+  const int n = (int)used.size();
+  const int cap = *nlevel;
+  *nlevel = n;
+  if (cap < n) return PAFC_ERROR_INVALID_VALUE;
+  for (int i = 0; i < b->count; ++i)
+    if (!b->fset[(size_t)b->fid[(size_t)i]]) return PAFC_ERROR_FILTER_NOT_SET;
+  hipStream_t s = (hipStream_t)hip_stream;
+  const bool dbl = b->dtype == PAFC_C128;
+  std::vector<hipEvent_t> ev((size_t)(n + 1) * reps, nullptr);
+  pafc_status st = PAFC_SUCCESS;
+  for (auto& e : ev)
+    if (st == PAFC_SUCCESS) st = from_hip(hipEventCreate(&e));
+  for (int r = 0; r < reps && st == PAFC_SUCCESS; ++r) {
+    hipEvent_t* E = ev.data() + (size_t)r * (n + 1);
+    st = from_hip(hipEventRecord(E[0], s));
+    const void* cur = x_dev;
+    for (int k = 0; k < n && st == PAFC_SUCCESS; ++k) {
+      auto& L = b->levels[used[(size_t)k]];
+      st = from_hip(launch_batch(dbl, L.cls, b->d_descs, b->d_tiles, L.first, L.count, cur, y_dev,
+                                 L.threads, L.lds, s));
+      cur = y_dev;
+      if (st == PAFC_SUCCESS) st = from_hip(hipEventRecord(E[k + 1], s));
+    }
+  }
+  if (st == PAFC_SUCCESS) st = from_hip(hipStreamSynchronize(s));
+  for (int k = 0; k < n && st == PAFC_SUCCESS; ++k) {
+    double tot = 0;
+    for (int r = 0; r < reps && st == PAFC_SUCCESS; ++r) {
+      float ms = 0;
+      st = from_hip(hipEventElapsedTime(&ms, ev[(size_t)r * (n + 1) + k], ev[(size_t)r * (n + 1) + k + 1]));
+      tot += ms;
+    }
+    ms_per_level[k] = tot / reps;
+    if (bytes_per_level) bytes_per_level[k] = b->levels[used[(size_t)k]].bytes;
+  }
+  for (int r = 0; r < reps && ms_per_rep && st == PAFC_SUCCESS; ++r) {
+    float ms = 0;
+    st = from_hip(hipEventElapsedTime(&ms, ev[(size_t)r * (n + 1)], ev[(size_t)r * (n + 1) + n]));
+    ms_per_rep[r] = ms;
+  }
+  for (auto& e : ev)
+    if (e) (void)hipEventDestroy(e);
+  return st;
 }
 
 pafc_status pafc_batch_destroy(pafc_batch_t b) {

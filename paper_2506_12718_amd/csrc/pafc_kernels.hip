@@ -23,7 +23,10 @@
 namespace pafc {
 
 struct TileCtx {
-  int64_t base;    // element offset of tile position (0, 0)
+  int64_t base;    // element offset of tile position (0, 0) in the data arrays
+  int64_t off;     // packed offset of the problem (0 outside the batched form);
+                   // the filter spectrum is per problem, so it is indexed
+                   // without it
   uint32_t col0;   // global column of tile column 0
   uint32_t ls_i;   // LDS linear stride between positions
   uint32_t ls_c;   // LDS linear stride between columns
@@ -102,8 +105,9 @@ __device__ __forceinline__ void run_op(const PassArgs& a, const OpDesc& op, cons
       static_for<R>([&](auto s) { v[s.value] = get(s.value); });
       Dft<R, r, false, T>::run(v);
       if (valid) {
+        const int64_t hb = gbase - t.off;
         static_for<R>([&](auto m) {
-          const cx<T> h = ld_g<T>(a.H, gbase + (int64_t)digrev<r, g>(m.value) * a.S_i);
+          const cx<T> h = ld_g<T>(a.H, hb + (int64_t)digrev<r, g>(m.value) * a.S_i);
           v[m.value] = cmul(v[m.value], h);
         });
       }
@@ -147,6 +151,7 @@ __device__ __forceinline__ void do_tile(const PassArgs& a, const void* __restric
   TileCtx t;
   t.col0 = cb * a.W;
   t.base = (int64_t)o * a.S_o + (int64_t)t.col0 * a.S_c + off;
+  t.off = off;
   if (a.mode == MODE_STRIDED) {
     t.ls_i = a.W;
     t.ls_c = 1;

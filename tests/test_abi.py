@@ -100,3 +100,23 @@ def test_tuning_override_changes_split():
     assert [p["L"] for p in d["axes"][0]["pieces"]] == [16, 4096]
     with pytest.raises(pafc.PafcError):
         pafc.set_tuning("garbage line")
+
+
+def _smooth(n):
+    for q in (2, 3, 5):
+        while n % q == 0:
+            n //= q
+    return n == 1
+
+
+def test_every_descriptor_passes_the_host_bounds_check():
+    """pafc_describe runs the planner's bounds check (the kernels' own index
+    formulas) on every pass; any shape it accepts is in bounds."""
+    import itertools
+    for dt in ("c128", "c64"):
+        for n in [n for n in range(2, 100000) if _smooth(n)][::7] + [5 ** 9, 2 ** 20, 3 ** 12]:
+            pafc.describe((n,), dt)
+        for a, b in itertools.product([2, 3, 81, 100, 2187], [2, 9, 125, 729, 4096]):
+            pafc.describe((a, b), dt)
+        for a, b, c in itertools.product([2, 32, 81, 256], [3, 48, 256], [2, 100, 256]):
+            pafc.describe((a, b, c), dt)

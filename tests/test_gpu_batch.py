@@ -1,0 +1,146 @@
+"""GPU parity of the batched form (many independent 1-D convolutions of
+uneven, mixed-radix sizes) against the CPU oracle, and of its hipGraph replay
+against eager execution."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2506_12718_amd import inputs
+from gpu_util import TOL, rel_l2, rounded, to_dev, to_host, torch
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def pafc():
+    import paper_2506_12718_amd as m
+    return m
+
+
+def pack(xs):
+    return np.concatenate([np.asarray(x).ravel() for x in xs])
+
+
+def unpack(y, sizes):
+    out, o = [], 0
+    for n in sizes:
+        out.append(y[o:o + n])
+        o += n
+    return out
+
+
+def check_batch(sizes, fids, filters, xs, dtype, spectral=False, sample=None):
+    m = pafc()
+    B = m.Batch(sizes, fids, len(filters), dtype)
+    for f, h in filters.items():
+        B.set_filter(f, to_dev(h, dtype), domain="spectral_natural" if spectral else "spatial")
+    y = to_host(B.convolve(to_dev(pack(xs), dtype)))
+    ys = unpack(y, sizes)
+    idx = range(len(sizes)) if sample is None else sample
+    for i in idx:
+        x = rounded(xs[i], dtype)
+        h = rounded(filters[fids[i]], dtype)
+        if spectral:
+            ref = oracle.fft(h * oracle.fft(x), inverse=True)
+        else:
+            ref = oracle.conv_fft(x, h)
+        assert rel_l2(ys[i], ref) < TOL[dtype], (i, sizes[i])
+    B.close()
+    return ys
+
+
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+def test_small_mixed_batch(dtype):
+    rng = np.random.default_rng(5)
+    classes = [16, 27, 64, 81, 125, 243, 256, 625, 1024, 4096, 3 ** 8, 2 ** 14, 5 ** 6, 3 ** 9]
+    sizes = [classes[i] for i in rng.integers(0, len(classes), 60)] + classes
+    filters = {k: inputs.complex_uniform(rng, (n,)) for k, n in enumerate(classes)}
+    fids = [classes.index(n) for n in sizes]
+    xs = [inputs.complex_uniform(rng, (n,)) for n in sizes]
+    say("small batch", dtype, len(sizes))
+    check_batch(sizes, fids, filters, xs, dtype)
+
+
+def test_two_filters_per_size_class_and_spectral():
+    rng = np.random.default_rng(6)
+    sizes = [256, 256, 243, 243, 256]
+    fids = [0, 1, 2, 3, 1]
+    filters = {0: inputs.complex_normal(rng, (256,)), 1: inputs.complex_normal(rng, (256,)),
+               2: inputs.complex_normal(rng, (243,)), 3: inputs.complex_normal(rng, (243,))}
+    xs = [inputs.complex_uniform(rng, (n,)) for n in sizes]
+    check_batch(sizes, fids, filters, xs, torch.complex128, spectral=True)
+
+
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+def test_full_batched_workload_sampled(dtype):
+    """The 4096-problem batched workload in the launch configuration the
+    benchmark times; 48 problems (the largest of every size class first)
+    checked against the oracle."""
+    psizes, xs, filters = inputs.batched_problems()
+    classes = sorted(filters)
+    fids = [classes.index(n) for n in psizes]
+    filt = {classes.index(n): h for n, h in filters.items()}
+    first_of = {}
+    for i, n in enumerate(psizes):
+        first_of.setdefault(n, i)
+    sample = sorted(set(list(first_of.values()) + list(np.random.default_rng(0).integers(0, 4096, 30))))
+    say("full batch", dtype, sum(psizes))
+    check_batch(psizes, fids, filt, xs, dtype, sample=sample)
+
+
+def test_batch_graph_replays_match_eager():
+    rng = np.random.default_rng(8)
+    classes = [64, 243, 3125, 2 ** 14]
+    sizes = [classes[i] for i in rng.integers(0, 4, 40)]
+    filters = {k: inputs.complex_uniform(rng, (n,)) for k, n in enumerate(classes)}
+    fids = [classes.index(n) for n in sizes]
+    xs = [inputs.complex_uniform(rng, (n,)) for n in sizes]
+    m = pafc()
+    B = m.Batch(sizes, fids, len(classes), torch.complex128)
+    for f, h in filters.items():
+        B.set_filter(f, to_dev(h, torch.complex128))
+    x = to_dev(pack(xs), torch.complex128)
+    eager = to_host(B.convolve(x))
+    y = torch.empty_like(x)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        B.convolve(x, out=y, stream=s)  # warm-up outside the graph
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g, stream=s):
+            B.convolve(x, out=y, stream=s)
+    torch.cuda.synchronize()
+    for rep in range(4):
+        y.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(to_host(y), eager), rep
+        # eager work between replays
+        _ = B.convolve(x)
+        torch.cuda.synchronize()
+    B.close()
+
+
+def test_batch_errors():
+    m = pafc()
+    with pytest.raises(m.PafcError):
+        m.Batch([256, 128], [0, 0], 1, torch.complex128)  # one filter, two sizes
+    B = m.Batch([64, 64], [0, 0], 1, torch.complex128)
+    with pytest.raises(m.PafcError) as e:
+        B.convolve(to_dev(np.zeros(128, complex), torch.complex128))
+    assert e.value.status == 5
+    B.close()
