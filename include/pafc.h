@@ -35,8 +35,12 @@
  *     asynchronous: it enqueues work and returns without a host sync.
  *   - No exception crosses the ABI; every call returns a pafc_status.
  *   - A plan owns device memory (twiddles, filter spectrum, scratch) that is
- *     shared by all calls on that plan: a single plan must be used on one
- *     stream at a time.  Distinct plans are independent.
+ *     shared by all calls on that plan.  pafc_convolve on a PAFC_PERM_FREE or
+ *     PAFC_PERM_FREE_UNFUSED plan only reads plan-owned memory, so such a
+ *     plan may run convolutions concurrently on several streams, provided
+ *     pafc_set_filter does not overlap them; a PAFC_EXPLICIT_PERM plan
+ *     writes its scratch array and must be used on one stream at a time.
+ *     Distinct plans are independent.
  */
 #ifndef PAFC_H
 #define PAFC_H

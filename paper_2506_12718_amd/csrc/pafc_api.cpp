@@ -106,13 +106,17 @@ int kind_of(int r, int g) {
   return -1;
 }
 
+int env_int(const char* name, int dflt);
+
+// Largest group of consecutive radix-r stages fused into one register op.
+// Groups with R > 16 need the large register class of the kernels.
 int gmax_of(int r) {
   switch (r) {
-    case 2: return 4;   // R = 16
-    case 4: return 2;   // R = 16
-    case 8: return 1;   // R = 8
-    case 3: return 3;   // R = 27
-    case 5: return 2;   // R = 25
+    case 2: return 4;                               // R = 16
+    case 4: return 2;                               // R = 16
+    case 8: return 1;                               // R = 8
+    case 3: return env_int("PAFC_TUNE_GMAX3", 3);   // R = 27 (9 with 2)
+    case 5: return env_int("PAFC_TUNE_GMAX5", 2);   // R = 25 (5 with 1)
   }
   return 1;
 }

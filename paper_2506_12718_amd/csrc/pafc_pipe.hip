@@ -285,8 +285,8 @@ hipError_t launch_pipe(bool dbl, int r, int g, int ng, int kind, int mode, const
                        hipStream_t s) {
   const void* fn = pipe_lookup(dbl, r, g, ng, kind, mode);
   if (!fn) return hipErrorInvalidValue;
-  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-  if (e != hipSuccess) return e;
+  // the LDS limit of every instance is raised when its occupancy is queried
+  // at plan time (pipe_blocks_per_cu), before any launch
   void* args[] = {(void*)&d, (void*)&in, (void*)&out};
   return hipLaunchKernel(fn, dim3(grid), dim3(threads), args, lds, s);
 }

@@ -1,0 +1,299 @@
+"""Serving loop: continuous batching of convolution requests on one GPU.
+
+Requests (a grid shape, a filter id and an input) arrive over time.  The
+server
+
+* admits a request when a stream slot is free and its device memory fits
+  the HBM budget (input/output buffers plus, on a cache miss, the plan with
+  its filter spectrum);
+* keeps plans, twiddles and filter spectra resident in an LRU cache keyed by
+  (shape, filter), evicting only entries no in-flight request uses;
+* runs every admitted request on one of S HIP streams, so requests that
+  arrive while others are on the GPU overlap with them on the device;
+* detects completions with stream events and records latency
+  (arrival -> completion) and throughput.
+
+Results do not depend on what else runs: every convolution is the same
+deterministic kernel sequence on its own buffers (the plan state it shares
+with concurrent requests -- twiddles and spectrum -- is only read).
+
+The executor is pluggable: ``GpuExecutor`` drives the C ABI through the
+Python binding; the tests also drive the admission and cache logic with a
+host-only fake executor.
+"""
+from __future__ import annotations
+
+import collections
+import heapq
+import threading
+import time
+from dataclasses import dataclass, field
+from typing import Any, Callable, Optional
+
+
+@dataclass
+class Request:
+    rid: int
+    dims: tuple
+    fid: int
+    x: Any = None              # device tensor (GPU executor) or opaque token
+    arrival: float = 0.0       # host clock, seconds
+    start: float = 0.0         # admitted to a stream
+    done: float = 0.0          # completion observed
+    out: Any = None
+    slot: int = -1
+    meta: dict = field(default_factory=dict)
+
+
+class PlanCache:
+    """LRU cache of (shape, filter) -> prepared plan with a byte budget."""
+
+    def __init__(self, budget_bytes: int):
+        self.budget = int(budget_bytes)
+        self.entries = collections.OrderedDict()   # key -> [obj, bytes, refs]
+        self.bytes = 0
+        self.hits = 0
+        self.misses = 0
+        self.evictions = 0
+
+    def get(self, key):
+        e = self.entries.get(key)
+        if e is None:
+            return None
+        self.entries.move_to_end(key)
+        self.hits += 1
+        return e
+
+    def can_fit(self, extra: int, reserved: int) -> bool:
+        """Can `extra` more bytes fit, evicting unused entries if needed?"""
+        free = self.budget - reserved - self.bytes
+        if extra <= free:
+            return True
+        reclaim = sum(b for (o, b, r) in self.entries.values() if r == 0)
+        return extra <= free + reclaim
+
+    def make_room(self, extra: int, reserved: int, release: Callable):
+        for key in list(self.entries.keys()):
+            if self.budget - reserved - self.bytes >= extra:
+                break
+            obj, b, refs = self.entries[key]
+            if refs == 0:
+                del self.entries[key]
+                self.bytes -= b
+                self.evictions += 1
+                release(obj)
+
+    def put(self, key, obj, nbytes):
+        self.misses += 1
+        self.entries[key] = [obj, int(nbytes), 0]
+        self.bytes += int(nbytes)
+        return self.entries[key]
+
+
+class Server:
+    """Admission, caching and continuous batching over an executor."""
+
+    def __init__(self, executor, budget_bytes=64 << 30, slots=4, clock=time.perf_counter):
+        self.ex = executor
+        self.cache = PlanCache(budget_bytes)
+        self.slots = slots
+        self.clock = clock
+        self.pending = collections.deque()
+        self.inflight = {}            # slot -> request
+        self.free_slots = list(range(slots))
+        self.reserved = 0             # bytes of in-flight request buffers
+        self.completed = []
+        self.max_inflight = 0
+        self.lock = threading.Lock()
+
+    # -- admission
+    def submit(self, req: Request):
+        with self.lock:
+            self.pending.append(req)
+
+    def _admit_one(self) -> bool:
+        if not self.pending or not self.free_slots:
+            return False
+        req = self.pending[0]
+        key = (tuple(req.dims), req.fid)
+        entry = self.cache.get(key)
+        need = self.ex.request_bytes(req)
+        extra = need + (0 if entry is not None else self.ex.plan_bytes(req))
+        if not self.cache.can_fit(extra, self.reserved):
+            if self.inflight:
+                return False  # wait for completions to free memory
+            if entry is None and need + self.ex.plan_bytes(req) > self.cache.budget:
+                raise MemoryError("request %d does not fit the HBM budget" % req.rid)
+        self.pending.popleft()
+        slot = self.free_slots.pop()
+        if entry is None:
+            self.cache.make_room(extra, self.reserved, self.ex.release_plan)
+            plan = self.ex.prepare(req, slot)
+            entry = self.cache.put(key, plan, self.ex.plan_bytes(req))
+        entry[2] += 1
+        self.reserved += need
+        req.slot = slot
+        req.start = self.clock()
+        req.meta["entry"] = entry
+        self.ex.launch(req, entry[0], slot)
+        self.inflight[slot] = req
+        self.max_inflight = max(self.max_inflight, len(self.inflight))
+        return True
+
+    def _reap(self) -> int:
+        n = 0
+        for slot, req in list(self.inflight.items()):
+            if self.ex.finished(req):
+                req.done = self.clock()
+                entry = req.meta.pop("entry")
+                entry[2] -= 1
+                self.reserved -= self.ex.request_bytes(req)
+                self.ex.complete(req)
+                del self.inflight[slot]
+                self.free_slots.append(slot)
+                self.completed.append(req)
+                n += 1
+        return n
+
+    def step(self) -> int:
+        """One scheduling round: reap completions, admit what fits."""
+        with self.lock:
+            n = self._reap()
+            while self._admit_one():
+                pass
+        return n
+
+    def idle(self) -> bool:
+        with self.lock:
+            return not self.pending and not self.inflight
+
+    def drain(self, poll=2e-5):
+        while not self.idle():
+            if self.step() == 0:
+                time.sleep(poll)
+
+
+def run_open_loop(server: Server, requests, rate_hz: float, seed: int = 5,
+                  make_input: Optional[Callable] = None, poll=2e-5):
+    """Offer `requests` with Poisson arrivals at `rate_hz` (exponential gaps
+    from a seeded generator) and serve them; returns the completed list."""
+    import numpy as np
+    rng = np.random.default_rng([seed, 1])
+    gaps = rng.exponential(1.0 / rate_hz, size=len(requests))
+    t0 = server.clock()
+    due = t0
+    i = 0
+    while i < len(requests) or not server.idle():
+        now = server.clock()
+        while i < len(requests) and due <= now:
+            req = requests[i]
+            req.arrival = due
+            if make_input is not None:
+                req.x = make_input(req)
+            server.submit(req)
+            due += gaps[i]
+            i += 1
+        if server.step() == 0:
+            time.sleep(poll)
+    return server.completed
+
+
+def run_closed_loop(server: Server, requests, make_input=None):
+    """All requests offered at once (capacity measurement)."""
+    t0 = server.clock()
+    for r in requests:
+        r.arrival = t0
+        if make_input is not None:
+            r.x = make_input(r)
+        server.submit(r)
+    server.drain()
+    return server.completed
+
+
+def latency_stats(reqs):
+    import numpy as np
+    lat = np.array([r.done - r.arrival for r in reqs]) * 1e3
+    span = max(r.done for r in reqs) - min(r.arrival for r in reqs)
+    return {"n": len(reqs), "p50_ms": float(np.percentile(lat, 50)),
+            "p99_ms": float(np.percentile(lat, 99)), "mean_ms": float(lat.mean()),
+            "throughput_per_s": len(reqs) / span if span > 0 else float("inf")}
+
+
+class GpuExecutor:
+    """Runs requests through the permutation-avoiding convolution library.
+
+    prepare(): plan for the request's shape + set_filter with the request's
+    Gaussian filter (built on the device from its separable 1-D factors),
+    enqueued on the slot's stream.  launch(): convolve on the slot's stream
+    into a fresh output buffer, after waiting for the plan's filter to be
+    ready.  finished(): the completion event has fired.
+    """
+
+    def __init__(self, dtype=None, sigma_of=None, slots=4):
+        import torch
+        import paper_2506_12718_amd as pafc
+        self.torch = torch
+        self.pafc = pafc
+        self.dtype = dtype if dtype is not None else torch.complex64
+        self.elem = 8 if self.dtype == torch.complex64 else 16
+        self.streams = [torch.cuda.Stream() for _ in range(slots)]
+        self.sigma_of = sigma_of
+        self.prepared = 0
+
+    def request_bytes(self, req):
+        n = 1
+        for d in req.dims:
+            n *= d
+        return n * self.elem  # the output buffer (the input is the caller's)
+
+    def plan_bytes(self, req):
+        n = 1
+        for d in req.dims:
+            n *= d
+        return n * self.elem + 64 * 1024  # spectrum + twiddles, descriptors
+
+    def filter_tensor(self, dims, sigma):
+        torch = self.torch
+        from paper_2506_12718_amd import inputs
+        h = None
+        for n in dims:
+            g = inputs.wrapped_gaussian_1d(int(n), sigma)
+            g = torch.from_numpy(g / g.sum()).to(torch.float64).cuda()
+            h = g if h is None else torch.multiply(h.unsqueeze(-1), g)
+        return h.to(self.dtype).contiguous()
+
+    def prepare(self, req, slot):
+        torch = self.torch
+        s = self.streams[slot]
+        with torch.cuda.stream(s):
+            plan = self.pafc.Plan(req.dims, self.dtype, stream=s)
+            sigma = self.sigma_of(req.dims, req.fid)
+            h = self.filter_tensor(req.dims, sigma)
+            plan.set_filter(h, stream=s)
+            ev = torch.cuda.Event()
+            ev.record(s)
+            h.record_stream(s)
+        self.prepared += 1
+        return {"plan": plan, "ready": ev}
+
+    def release_plan(self, obj):
+        obj["ready"].synchronize()
+        obj["plan"].close()
+
+    def launch(self, req, obj, slot):
+        torch = self.torch
+        s = self.streams[slot]
+        s.wait_event(obj["ready"])
+        with torch.cuda.stream(s):
+            out = torch.empty(req.dims, dtype=self.dtype, device="cuda")
+            obj["plan"].convolve(req.x, out=out, stream=s)
+            ev = torch.cuda.Event()
+            ev.record(s)
+        req.out = out
+        req.meta["ev"] = ev
+
+    def finished(self, req):
+        return req.meta["ev"].query()
+
+    def complete(self, req):
+        req.meta.pop("ev", None)

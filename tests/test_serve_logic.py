@@ -1,0 +1,124 @@
+"""Admission, caching and continuous-batching logic of the server, driven on
+the CPU by a fake executor (no GPU)."""
+import pytest
+
+from paper_2506_12718_amd.serve import Request, Server, latency_stats, run_closed_loop
+
+
+class FakeClock:
+    def __init__(self):
+        self.t = 0.0
+
+    def __call__(self):
+        self.t += 1e-6
+        return self.t
+
+
+class FakeExecutor:
+    """A request finishes `polls` finished() queries after launch."""
+
+    def __init__(self, polls=3, elem=8):
+        self.polls = polls
+        self.elem = elem
+        self.prepared = []
+        self.released = []
+        self.live_plans = set()
+        self.max_bytes_seen = 0
+
+    def _n(self, req):
+        n = 1
+        for d in req.dims:
+            n *= d
+        return n
+
+    def request_bytes(self, req):
+        return self._n(req) * self.elem
+
+    def plan_bytes(self, req):
+        return self._n(req) * self.elem
+
+    def prepare(self, req, slot):
+        key = (tuple(req.dims), req.fid)
+        self.prepared.append(key)
+        self.live_plans.add(key)
+        return {"key": key}
+
+    def release_plan(self, obj):
+        self.released.append(obj["key"])
+        self.live_plans.discard(obj["key"])
+
+    def launch(self, req, obj, slot):
+        assert obj["key"] in self.live_plans  # never run on an evicted plan
+        req.meta["left"] = self.polls
+        req.out = ("y", req.rid)
+
+    def finished(self, req):
+        req.meta["left"] -= 1
+        return req.meta["left"] <= 0
+
+    def complete(self, req):
+        pass
+
+
+def mk(n, dims=(64, 64), fid=0):
+    return [Request(rid=i, dims=dims, fid=fid) for i in range(n)]
+
+
+def test_slots_bound_inflight_and_fifo():
+    ex = FakeExecutor()
+    s = Server(ex, budget_bytes=1 << 40, slots=3, clock=FakeClock())
+    reqs = mk(20)
+    done = run_closed_loop(s, reqs)
+    assert len(done) == 20
+    assert s.max_inflight == 3
+    assert sorted(r.rid for r in done) == list(range(20))
+    starts = [r.start for r in sorted(done, key=lambda r: r.rid)]
+    assert starts == sorted(starts)  # admitted in arrival order
+
+
+def test_plan_cache_hits_when_budget_allows():
+    ex = FakeExecutor()
+    s = Server(ex, budget_bytes=1 << 40, slots=4, clock=FakeClock())
+    reqs = [Request(rid=i, dims=(32, 32), fid=i % 3) for i in range(30)]
+    run_closed_loop(s, reqs)
+    assert len(ex.prepared) == 3
+    assert s.cache.hits == 27 and s.cache.evictions == 0
+
+
+def test_budget_forces_eviction_and_queueing():
+    ex = FakeExecutor(polls=2)
+    n = 64 * 64 * 8
+    # room for two plans and two request buffers
+    s = Server(ex, budget_bytes=4 * n, slots=4, clock=FakeClock())
+    reqs = [Request(rid=i, dims=(64, 64), fid=i % 4) for i in range(24)]
+    done = run_closed_loop(s, reqs)
+    assert len(done) == 24
+    assert s.cache.evictions > 0
+    assert len(ex.prepared) > 4
+    assert s.max_inflight <= 2
+    assert s.cache.bytes + s.reserved <= 4 * n
+
+
+def test_entries_in_use_are_never_evicted():
+    ex = FakeExecutor(polls=5)
+    n = 32 * 32 * 8
+    s = Server(ex, budget_bytes=3 * n, slots=2, clock=FakeClock())
+    reqs = [Request(rid=i, dims=(32, 32), fid=i % 5) for i in range(40)]
+    run_closed_loop(s, reqs)  # FakeExecutor.launch asserts the plan is live
+    assert len(s.completed) == 40
+
+
+def test_request_larger_than_budget_raises():
+    ex = FakeExecutor()
+    s = Server(ex, budget_bytes=1000, slots=2, clock=FakeClock())
+    s.submit(Request(rid=0, dims=(64, 64), fid=0))
+    with pytest.raises(MemoryError):
+        s.drain()
+
+
+def test_latency_stats():
+    reqs = mk(4)
+    for i, r in enumerate(reqs):
+        r.arrival, r.done = float(i), float(i) + 0.001 * (i + 1)
+    st = latency_stats(reqs)
+    assert st["n"] == 4 and abs(st["p50_ms"] - 2.5) < 1e-9
