@@ -294,11 +294,19 @@ pafc_status pafc_batch_describe(pafc_batch_t b, char* buf, size_t cap,
                                 size_t* needed);
 
 /*
- * pafc_set_tuning -- install planner overrides from a JSON-like text of
- * lines "<dtype> <n> <split> <W>" (split = length of the inner contiguous
- * factor for sizes that need two levels, 0 = planner default; W = tile width,
- * 0 = default).  Affects plans created afterwards.  NULL clears.
- * Errors: INVALID_VALUE (unparsable text).
+ * pafc_set_tuning -- install planner overrides for plans created afterwards.
+ * text: lines "<c64|c128> <n> <split> <W>" or
+ * "<c64|c128> <n> <split> <W> <Wo> <g3> <g5>" ('#' starts a comment), keyed
+ * by element type and axis length n:
+ *   split  inner length of a 1-D transform cut into an outer (strided) and an
+ *          inner (contiguous) pass; 0 = planner default
+ *   W, Wo  tile width of the axis pass (of the inner piece when split) and
+ *          of the outer piece; 0 = default
+ *   g3, g5 largest number of radix-3 (<= 3) and radix-5 (<= 2) stages fused
+ *          into one register group; 0 = default (3 and 2)
+ * None of these changes the result, only the pass and register schedule.
+ * NULL clears the table.  Errors: INVALID_VALUE (unparsable text; the
+ * previous table stays).
  */
 pafc_status pafc_set_tuning(const char* text);
 

@@ -99,7 +99,23 @@ def lib():
         L.pafc_status_string.argtypes = [ctypes.c_int]
         L.pafc_status_string.restype = ctypes.c_char_p
         _lib = L
+        _load_tuning_table(L)
     return _lib
+
+
+TUNING_TABLE = os.path.join(_HERE, "tuning", "mi355x.txt")
+
+
+def _load_tuning_table(L):
+    """Install the autotuner's table (schedule choices only; results do not
+    depend on it) unless PAFC_NO_TUNING_TABLE is set."""
+    if os.environ.get("PAFC_NO_TUNING_TABLE") or not os.path.exists(TUNING_TABLE):
+        return
+    with open(TUNING_TABLE) as f:
+        text = f.read()
+    st = L.pafc_set_tuning(text.encode())
+    if st != 0:
+        raise PafcError(st, "loading %s" % TUNING_TABLE)
 
 
 def _status_string(st):

@@ -72,8 +72,11 @@ struct TuneKey {
   bool operator<(const TuneKey& o) const { return dtype != o.dtype ? dtype < o.dtype : n < o.n; }
 };
 struct TuneVal {
-  int64_t split;  // inner length of a two-level 1-D transform (0 = default)
-  int W;          // tile width (0 = default)
+  int64_t split = 0;  // inner length of a two-level 1-D transform (0 = default)
+  int W = 0;          // tile width of the axis (inner piece when split; 0 = default)
+  int Wo = 0;         // tile width of the outer piece of a split 1-D transform
+  int gmax3 = 0;      // largest group of radix-3 stages (0 = default)
+  int gmax5 = 0;      // largest group of radix-5 stages (0 = default)
 };
 std::mutex g_tune_mu;
 std::map<TuneKey, TuneVal> g_tune;
@@ -110,13 +113,18 @@ int env_int(const char* name, int dflt);
 
 // Largest group of consecutive radix-r stages fused into one register op.
 // Groups with R > 16 need the large register class of the kernels.
-int gmax_of(int r) {
+struct GroupCaps {
+  int g3 = 3;  // R = 27 (9 with 2)
+  int g5 = 2;  // R = 25 (5 with 1)
+};
+
+int gmax_of(int r, const GroupCaps& gc) {
   switch (r) {
-    case 2: return 4;                               // R = 16
-    case 4: return 2;                               // R = 16
-    case 8: return 1;                               // R = 8
-    case 3: return env_int("PAFC_TUNE_GMAX3", 3);   // R = 27 (9 with 2)
-    case 5: return env_int("PAFC_TUNE_GMAX5", 2);   // R = 25 (5 with 1)
+    case 2: return 4;  // R = 16
+    case 4: return 2;  // R = 16
+    case 8: return 1;  // R = 8
+    case 3: return gc.g3;
+    case 5: return gc.g5;
   }
   return 1;
 }
@@ -203,6 +211,7 @@ struct Seg {  // one pass-sized piece of an axis transform
   uint32_t ncols = 1, nouter = 1, jmul = 1, col_in_j = 0;
   int64_t n_tw = 0;
   std::vector<int> rho;  // this piece's stages, innermost first
+  GroupCaps caps;
 };
 
 struct Pass {
@@ -246,7 +255,8 @@ struct PlanCore {
   int64_t hbm_conv = 0, hbm_fwd = 0;
 };
 
-std::vector<std::pair<int, int>> group_runs(const std::vector<int>& rho_inner_first) {
+std::vector<std::pair<int, int>> group_runs(const std::vector<int>& rho_inner_first,
+                                            const GroupCaps& gc) {
   // DIF order: outermost stage (last entry) first; equal radices grouped.
   std::vector<std::pair<int, int>> out;
   std::vector<int> st(rho_inner_first.rbegin(), rho_inner_first.rend());
@@ -256,7 +266,7 @@ std::vector<std::pair<int, int>> group_runs(const std::vector<int>& rho_inner_fi
     while (j < st.size() && st[j] == st[i]) ++j;
     const int r = st[i];
     const int t = (int)(j - i);
-    const int gm = gmax_of(r);
+    const int gm = gmax_of(r, gc);
     const int G = (t + gm - 1) / gm;
     for (int q = 0; q < G; ++q) {
       int g = t / G + (q < t % G ? 1 : 0);
@@ -300,7 +310,7 @@ bool fits_lds(int64_t L, size_t elem) { return tile_lds_bytes((uint64_t)L, elem)
 // Build the op list of one pass over segment s.  kind: 0 = DIF only,
 // 1 = DIT only, 2 = DIF..., MID, ...DIT.
 bool build_ops(const Seg& s, int kind, PassArgs& a, int* cls) {
-  auto groups = group_runs(s.rho);
+  auto groups = group_runs(s.rho, s.caps);
   struct G { int r, g, R; uint32_t K, S; };
   std::vector<G> gs;
   uint32_t K = s.L;
@@ -416,7 +426,7 @@ bool make_pass(const Seg& s, int kind, size_t elem, Pass* p) {
   // pipelined kernel: every group of the piece has the same (r, g), each op
   // has one item per thread, flat twiddles of the piece's own length
   {
-    auto groups = group_runs(s.rho);
+    auto groups = group_runs(s.rho, s.caps);
     bool uni = !groups.empty();
     for (auto& gr : groups) uni = uni && gr == groups[0];
     const int ng = (int)groups.size();
@@ -497,14 +507,19 @@ pafc_status plan_core(PlanCore& P, int ndim, const int64_t* dims, const int* rad
     int64_t st = 1, outer = 1;
     for (int b = a + 1; b < ndim; ++b) st *= dims[b];
     for (int b = 0; b < a; ++b) outer *= dims[b];
-    TuneVal tv{0, 0};
+    TuneVal tv;
     bool tuned = tune_lookup(dtype, ax.n, &tv);
-    bool need_split = !fits_lds(ax.n, P.elem) || (tuned && tv.split > 0 && ndim == 1);
+    GroupCaps caps;
+    caps.g3 = tuned && tv.gmax3 > 0 ? tv.gmax3 : env_int("PAFC_TUNE_GMAX3", 3);
+    caps.g5 = tuned && tv.gmax5 > 0 ? tv.gmax5 : env_int("PAFC_TUNE_GMAX5", 2);
+    bool need_split = !fits_lds(ax.n, P.elem) ||
+                      (tuned && tv.split > 0 && tv.split < ax.n && ndim == 1);
     if (!need_split) {
       Seg s;
       s.L = (uint32_t)ax.n;
       s.rho = ax.rho;
       s.n_tw = ax.n;
+      s.caps = caps;
       if (st == 1) {
         s.mode = MODE_CONTIG;
         s.S_i = 1;
@@ -552,7 +567,8 @@ pafc_status plan_core(PlanCore& P, int ndim, const int64_t* dims, const int* rad
       so.col_in_j = 1;
       so.n_tw = ax.n;
       so.rho.assign(ax.rho.begin() + ti, ax.rho.end());
-      choose_width(so, P.elem, 0);
+      so.caps = caps;
+      choose_width(so, P.elem, tuned ? tv.Wo : 0);
       Seg si;  // inner: contiguous blocks of ni
       si.mode = MODE_CONTIG;
       si.L = (uint32_t)ni;
@@ -563,6 +579,7 @@ pafc_status plan_core(PlanCore& P, int ndim, const int64_t* dims, const int* rad
       si.nouter = 1;
       si.n_tw = ni;
       si.rho.assign(ax.rho.begin(), ax.rho.begin() + ti);
+      si.caps = caps;
       choose_width(si, P.elem, tuned ? tv.W : 0);
       ax.segs.push_back(so);
       ax.segs.push_back(si);
@@ -1106,21 +1123,28 @@ pafc_status pafc_set_tuning(const char* text) {
   if (text) {
     const char* c = text;
     while (*c) {
+      const char* eol = strchr(c, '\n');
+      std::string line(c, eol ? (size_t)(eol - c) : strlen(c));
+      c = eol ? eol + 1 : c + strlen(c);
+      const size_t h = line.find('#');
+      if (h != std::string::npos) line.resize(h);
+      if (line.find_first_not_of(" \t\r") == std::string::npos) continue;
       char dt[16];
-      long long n, split;
-      int W, used = 0;
-      while (*c == ' ' || *c == '\n' || *c == '\t' || *c == '\r') ++c;
-      if (!*c) break;
-      if (*c == '#') {
-        while (*c && *c != '\n') ++c;
-        continue;
-      }
-      if (sscanf(c, "%15s %lld %lld %d%n", dt, &n, &split, &W, &used) != 4)
+      long long n = 0, split = 0;
+      int W = 0, Wo = 0, g3 = 0, g5 = 0;
+      const int got = sscanf(line.c_str(), "%15s %lld %lld %d %d %d %d", dt, &n, &split, &W, &Wo,
+                             &g3, &g5);
+      if (got != 4 && got != 7) return PAFC_ERROR_INVALID_VALUE;
+      const int d = !strcmp(dt, "c128") ? PAFC_C128 : !strcmp(dt, "c64") ? PAFC_C64 : -1;
+      if (d < 0 || n < 2 || split < 0 || W < 0 || Wo < 0 || g3 < 0 || g3 > 3 || g5 < 0 || g5 > 2)
         return PAFC_ERROR_INVALID_VALUE;
-      int d = !strcmp(dt, "c128") ? PAFC_C128 : !strcmp(dt, "c64") ? PAFC_C64 : -1;
-      if (d < 0 || n < 2 || split < 0 || W < 0) return PAFC_ERROR_INVALID_VALUE;
-      t[{d, (int64_t)n}] = {(int64_t)split, W};
-      c += used;
+      TuneVal v;
+      v.split = split;
+      v.W = W;
+      v.Wo = Wo;
+      v.gmax3 = g3;
+      v.gmax5 = g5;
+      t[{d, (int64_t)n}] = v;
     }
   }
   std::lock_guard<std::mutex> lk(g_tune_mu);

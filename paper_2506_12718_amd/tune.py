@@ -1,0 +1,174 @@
+"""Autotuner for the planner's schedule choices.
+
+For every (element type, axis length) it searches, on the GPU, the choices
+that change only the schedule -- never the result:
+
+* g3 / g5: how many radix-3 / radix-5 stages are fused into one register
+  group (larger groups: fewer LDS round trips, more registers);
+* split: the inner length of a 1-D transform cut into an outer (strided) and
+  an inner (contiguous) pass;
+* W / Wo: the tile widths of the inner and outer pieces.
+
+The search is greedy coordinate descent from the planner's defaults: each
+coordinate in turn takes the candidate with the lowest measured time (ties
+within 2 % keep the current value).  Times come from HIP events around the
+library's own launches (`Batch.profile_levels` for batched size classes,
+`Plan.profile_passes` for whole grids).  The result is a table in the format
+of `pafc_set_tuning`, written to ``tuning/<device>.txt`` and loaded by the
+binding on first use.
+
+    python -m paper_2506_12718_amd.tune [--dtypes c128 c64] [--out PATH]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+DEFAULT_TABLE = os.path.join(HERE, "tuning", "mi355x.txt")
+
+BATCH_SIZES = [2 ** e for e in range(8, 17)] + [3 ** e for e in range(6, 11)] + \
+              [5 ** e for e in range(4, 8)]
+GRIDS = [((2187, 2187), 3), ((5 ** 9,), 5)]
+
+
+def _factors(n):
+    f = {}
+    for p in (2, 3, 5):
+        while n % p == 0:
+            f[p] = f.get(p, 0) + 1
+            n //= p
+    return f
+
+
+def line(dt, n, cfg):
+    return "%s %d %d %d %d %d %d" % (dt, n, cfg["split"], cfg["W"], cfg["Wo"], cfg["g3"], cfg["g5"])
+
+
+class Timer:
+    def __init__(self, pafc, torch, dt, reps=5):
+        self.pafc, self.torch, self.dt, self.reps = pafc, torch, dt, reps
+        self.tdt = torch.complex128 if dt == "c128" else torch.complex64
+
+    def batch(self, n):
+        torch = self.torch
+        count = max(2, (1 << 24) // n)
+        B = self.pafc.Batch([n] * count, [0] * count, 1, self.tdt)
+        h = torch.ones(n, dtype=self.tdt, device="cuda")
+        B.set_filter(0, h)
+        x = torch.ones(n * count, dtype=self.tdt, device="cuda")
+        y = torch.empty_like(x)
+        B.convolve(x, out=y)
+        ms, _, _ = B.profile_levels(x, y, reps=self.reps)
+        B.close()
+        return sum(ms)
+
+    def grid(self, dims, radix):
+        torch = self.torch
+        P = self.pafc.Plan(dims, self.tdt, radix=[radix] * len(dims))
+        h = torch.ones(dims, dtype=self.tdt, device="cuda")
+        P.set_filter(h)
+        x = torch.ones(dims, dtype=self.tdt, device="cuda")
+        y = torch.empty_like(x)
+        P.convolve(x, out=y)
+        ms, _, _ = P.profile_passes(x, y, reps=self.reps)
+        P.close()
+        return sum(ms)
+
+
+def candidates(pafc, dt, n, key, cfg):
+    f = _factors(n)
+    if key == "g3":
+        return [2, 3] if 3 in f else []
+    if key == "g5":
+        return [1, 2] if 5 in f else []
+    d = pafc.describe((n,), dt)
+    rho = d["axes"][0]["rho"]
+    elem = 16 if dt == "c128" else 8
+    fits = lambda L: (L + L // 16 + 1) * elem <= 160 * 1024
+    if key == "split":
+        out, p = [0], 1
+        for r in rho[:-1]:
+            p *= r
+            if p >= 128 and fits(p) and fits(n // p) and p < n:
+                out.append(p)
+        return out if len(out) > 1 else []
+    pieces = d["axes"][0]["pieces"]
+    split = cfg["split"] or (pieces[1]["L"] if len(pieces) == 2 else 0)
+    if not split:
+        return []
+    if key == "W":
+        return [w for w in (1, 2, 4, 8) if fits(split * w)]
+    if key == "Wo":
+        return [w for w in (8, 16, 32, 64, 128) if fits((n // split) * w)]
+    return []
+
+
+def tune_one(pafc, timer, dt, n, measure):
+    cfg = {"split": 0, "W": 0, "Wo": 0, "g3": 0, "g5": 0}
+    pafc.set_tuning(None)
+    best = measure()
+    log = [("default", best)]
+    for key in ("g3", "g5", "split", "W", "Wo"):
+        pafc.set_tuning(line(dt, n, cfg) if any(cfg.values()) else None)
+        cands = candidates(pafc, dt, n, key, cfg)
+        for v in cands:
+            if v == cfg[key]:
+                continue
+            trial = dict(cfg, **{key: v})
+            try:
+                pafc.set_tuning(line(dt, n, trial))
+                t = measure()
+            except Exception as e:  # a candidate the planner rejects
+                log.append((line(dt, n, trial), "rejected: %s" % e))
+                continue
+            log.append((line(dt, n, trial), t))
+            if t < best * 0.98:
+                best, cfg = t, trial
+    pafc.set_tuning(None)
+    return cfg, best, log
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--dtypes", nargs="+", default=["c128", "c64"])
+    ap.add_argument("--out", default=DEFAULT_TABLE)
+    ap.add_argument("--reps", type=int, default=5)
+    a = ap.parse_args(argv)
+    os.environ["PAFC_NO_TUNING_TABLE"] = "1"
+    import torch
+    import paper_2506_12718_amd as pafc
+    dev = torch.cuda.get_device_properties(0)
+    lines = ["# pafc planner tuning table (python -m paper_2506_12718_amd.tune)",
+             "# device: %s (%s)" % (dev.name, getattr(dev, "gcnArchName", "?")),
+             "# format: dtype n split W Wo g3 g5   (0 = planner default)"]
+    report = []
+    for dt in a.dtypes:
+        timer = Timer(pafc, torch, dt, reps=a.reps)
+        # whole grids first; a batched size class with the same axis length
+        # keeps the grid's entry (the table is keyed by axis length)
+        jobs = [(dims[0], (lambda d=dims, r=radix: timer.grid(d, r))) for dims, radix in GRIDS]
+        jobs += [(n, (lambda n=n: timer.batch(n))) for n in BATCH_SIZES
+                 if n not in [d[0] for d, _ in GRIDS]]
+        for n, measure in jobs:
+            cfg, t, log = tune_one(pafc, timer, dt, n, measure)
+            default_t = log[0][1]
+            print(json.dumps({"dtype": dt, "n": n, "cfg": cfg, "ms": round(t, 5),
+                              "default_ms": round(default_t, 5),
+                              "gain": round(default_t / t, 3)}), flush=True)
+            report.append((dt, n, cfg))
+            if any(cfg.values()):
+                lines.append(line(dt, n, cfg) + "   # %.4f ms vs %.4f default" % (t, default_t))
+    os.makedirs(os.path.dirname(a.out), exist_ok=True)
+    with open(a.out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("wrote", a.out, flush=True)
+
+
+if __name__ == "__main__":
+    main()
