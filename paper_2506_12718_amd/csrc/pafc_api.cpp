@@ -212,6 +212,7 @@ struct Seg {  // one pass-sized piece of an axis transform
   uint32_t mode = MODE_CONTIG, L = 0, W = 1;
   int64_t S_i = 1, S_c = 1, S_o = 0;
   uint32_t ncols = 1, nouter = 1, jmul = 1, col_in_j = 0;
+  uint32_t jcdiv = 1;  // column -> inner position of an outer piece
   int64_t n_tw = 0;
   std::vector<int> rho;  // this piece's stages, innermost first
   GroupCaps caps;
@@ -393,7 +394,7 @@ bool validate_pass(const PassArgs& a, int64_t extent, int64_t n_tw) {
     if (op.Kf != op.K * a.jmul || (int64_t)op.Kf * op.escale != n_tw) return false;
     if (op.divS.d != op.S || op.divNB.d != a.L / op.K) return false;
     if (op.type == OP_MID && op.S != 1) return false;
-    if (a.col_in_j && a.jmul != a.ncols) return false;
+    if (a.col_in_j && (uint64_t)a.jmul * a.divJc.d != a.ncols) return false;
     (void)K;
   }
   return true;
@@ -417,6 +418,7 @@ bool make_pass(const Seg& s, int kind, size_t elem, Pass* p) {
   a.col_in_j = s.col_in_j;
   a.divL = make_fastdiv(s.L);
   a.divTiles = make_fastdiv(a.tiles_per_slice);
+  a.divJc = make_fastdiv(s.jcdiv);
   if (!build_ops(s, kind, a, &p->cls)) return false;
   uint32_t maxitems = 0;
   for (uint32_t i = 0; i < a.nops; ++i) maxitems = std::max(maxitems, a.ops[i].nitems);
@@ -515,9 +517,26 @@ pafc_status plan_core(PlanCore& P, int ndim, const int64_t* dims, const int* rad
     GroupCaps caps;
     caps.g3 = tuned && tv.gmax3 > 0 ? tv.gmax3 : env_int("PAFC_TUNE_GMAX3", 3);
     caps.g5 = tuned && tv.gmax5 > 0 ? tv.gmax5 : env_int("PAFC_TUNE_GMAX5", 2);
-    bool need_split = !fits_lds(ax.n, P.elem) ||
-                      (tuned && tv.split > 0 && tv.split < ax.n && ndim == 1);
-    if (!need_split) {
+    // Cut the axis into an outer piece (its outermost stages, strided over
+    // the inner length) and an inner piece when its whole-axis tile would not
+    // fit LDS, when a strided tile 16 columns wide would leave the CU with a
+    // single resident block, or when the tuning table says so (1-D only: the
+    // table is measured on 1-D transforms).
+    const int t = (int)ax.rho.size();
+    auto tile16 = [&](int64_t L) { return tile_lds_bytes((uint64_t)L * 16, P.elem); };
+    int ti = 0;
+    int64_t ni = 1;
+    if (tuned && tv.split > 0 && tv.split < ax.n && ndim == 1) {
+      while (ti < t && ni < tv.split) ni *= ax.rho[ti++];
+      if (ni != tv.split) return PAFC_ERROR_INVALID_VALUE;
+    } else if (!fits_lds(ax.n, P.elem) && st == 1) {
+      const size_t cap = P.elem == 16 ? 4096 : 8192;
+      while (ti < t - 1 && ni * ax.rho[ti] <= (int64_t)cap) ni *= ax.rho[ti++];
+    } else if (st > 1 && tile16(ax.n) > 72 * 1024) {
+      while (ti < t - 1 && tile16(ni * ax.rho[ti]) <= 72 * 1024) ni *= ax.rho[ti++];
+      if (ax.n / ni < 2) ti = 0, ni = 1;
+    }
+    if (ti == 0) {
       Seg s;
       s.L = (uint32_t)ax.n;
       s.rho = ax.rho;
@@ -542,47 +561,47 @@ pafc_status plan_core(PlanCore& P, int ndim, const int64_t* dims, const int* rad
       if (tile_lds_bytes(s.L * (uint64_t)s.W, P.elem) > kLdsBudget) return PAFC_ERROR_UNSUPPORTED_SIZE;
       ax.segs.push_back(s);
     } else {
-      if (ndim != 1) return PAFC_ERROR_UNSUPPORTED_SIZE;
-      // inner length: the longest prefix product of rho that fits LDS
-      // comfortably (or the tuned split)
-      int ti = 0;
-      int64_t ni = 1;
-      const int t = (int)ax.rho.size();
-      if (tuned && tv.split > 0) {
-        while (ti < t && ni < tv.split) ni *= ax.rho[ti++];
-        if (ni != tv.split) return PAFC_ERROR_INVALID_VALUE;
-      } else {
-        const size_t cap = P.elem == 16 ? 4096 : 8192;
-        while (ti < t - 1 && ni * ax.rho[ti] <= (int64_t)cap) ni *= ax.rho[ti++];
-      }
       const int64_t no = ax.n / ni;
-      if (!fits_lds(no, P.elem) || !fits_lds(ni, P.elem) || ti == 0 || ti == t)
+      if (!fits_lds(no, P.elem) || !fits_lds(ni, P.elem) || ti == t) return PAFC_ERROR_UNSUPPORTED_SIZE;
+      if ((uint64_t)ni * st >= (1ull << 32) || (uint64_t)outer * no >= (1ull << 32))
         return PAFC_ERROR_UNSUPPORTED_SIZE;
-      Seg so;  // outer: positions i_o < no at stride ni, columns i_i < ni
+      // element (o, i_o, i_i, f) of the axis sits at
+      // o*n*st + i_o*ni*st + i_i*st + f
+      Seg so;  // outer: positions i_o < no at stride ni*st, columns (i_i, f)
       so.mode = MODE_STRIDED;
       so.L = (uint32_t)no;
-      so.S_i = ni;
+      so.S_i = ni * st;
       so.S_c = 1;
-      so.ncols = (uint32_t)ni;
-      so.S_o = 0;
-      so.nouter = 1;
+      so.ncols = (uint32_t)(ni * st);
+      so.S_o = ax.n * st;
+      so.nouter = (uint32_t)outer;
       so.jmul = (uint32_t)ni;
       so.col_in_j = 1;
+      so.jcdiv = (uint32_t)st;
       so.n_tw = ax.n;
       so.rho.assign(ax.rho.begin() + ti, ax.rho.end());
       so.caps = caps;
       choose_width(so, P.elem, tuned ? tv.Wo : 0);
-      Seg si;  // inner: contiguous blocks of ni
-      si.mode = MODE_CONTIG;
+      Seg si;  // inner: positions i_i < ni, one block per (o, i_o)
       si.L = (uint32_t)ni;
-      si.S_i = 1;
-      si.S_c = ni;
-      si.ncols = (uint32_t)no;
-      si.S_o = 0;
-      si.nouter = 1;
       si.n_tw = ni;
       si.rho.assign(ax.rho.begin(), ax.rho.begin() + ti);
       si.caps = caps;
+      if (st == 1) {
+        si.mode = MODE_CONTIG;
+        si.S_i = 1;
+        si.S_c = ni;
+        si.ncols = (uint32_t)(outer * no);
+        si.S_o = 0;
+        si.nouter = 1;
+      } else {
+        si.mode = MODE_STRIDED;
+        si.S_i = st;
+        si.S_c = 1;
+        si.ncols = (uint32_t)st;
+        si.S_o = ni * st;
+        si.nouter = (uint32_t)(outer * no);
+      }
       choose_width(si, P.elem, tuned ? tv.W : 0);
       ax.segs.push_back(so);
       ax.segs.push_back(si);
@@ -820,7 +839,8 @@ pafc_status run_permute(pafc_plan_t p, int dir, const void* in, void* out, const
     m1 = map_ptr(p, 0, inv);
   }
   const bool pow2 = (nl & (nl - 1)) == 0;
-  if (pow2 && nl <= 4096 && ((uint64_t)n0 * n1 * nl) % 4096 == 0) {
+  if (pow2 && nl <= 4096 && ((uint64_t)n0 * n1 * nl) % 4096 == 0 &&
+      (size_t)(4096 + 256 + 2) * P.elem + ((size_t)nl + n0 + n1) * 4 <= 96 * 1024) {
     const uint32_t log_nl = ilog2u(nl);
     return from_hip(launch_permute_pipe(dbl, in, out, h, m0, m1, ml, n0, n1, log_nl, s));
   }

@@ -98,11 +98,13 @@ struct PassArgs {
   uint32_t ncols;      // columns per slice (the last tile may be partial)
   uint32_t tiles_per_slice;
   uint32_t ntiles;
-  uint32_t jmul;       // j of the full transform = j * jmul + column (large 1-D)
+  uint32_t jmul;       // j of the full transform = j * jmul + column / divJc.d
   uint32_t col_in_j;   // 1 when the column index enters the twiddle exponent
   uint32_t nops;
   FastDiv divL;        // division by L
   FastDiv divTiles;    // division by tiles_per_slice
+  FastDiv divJc;       // column -> inner position of an outer piece (the
+                       // stride of the axis; 1 for a 1-D transform)
   OpDesc ops[kMaxOps];
 };
 

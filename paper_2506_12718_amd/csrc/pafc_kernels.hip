@@ -81,7 +81,7 @@ __device__ __forceinline__ void run_op(const PassArgs& a, const OpDesc& op, cons
       static_for<R>([&](auto s) { v[s.value] = get(s.value); });
       Dft<R, r, false, T>::run(v);
       if (op.tw) {
-        const uint32_t jf = j * a.jmul + (a.col_in_j && valid ? gcol : 0u);
+        const uint32_t jf = j * a.jmul + (a.col_in_j && valid ? fdiv(gcol, a.divJc) : 0u);
         uint32_t E = 0;
         static_for<R - 1>([&](auto mm) {
           E += jf;
@@ -93,7 +93,7 @@ __device__ __forceinline__ void run_op(const PassArgs& a, const OpDesc& op, cons
     } else if constexpr (TYPE == OP_DIT) {
       static_for<R>([&](auto m) { v[m.value] = get(digrev<r, g>(m.value)); });
       if (op.tw) {
-        const uint32_t jf = j * a.jmul + (a.col_in_j && valid ? gcol : 0u);
+        const uint32_t jf = j * a.jmul + (a.col_in_j && valid ? fdiv(gcol, a.divJc) : 0u);
         uint32_t E = 0;
         static_for<R - 1>([&](auto mm) {
           E += jf;
@@ -303,11 +303,18 @@ __global__ void __launch_bounds__(256) permute_pipe_kernel(
   constexpr uint32_t TILE = 256 * EPT;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
+  // the three index maps live in LDS: a global load in the address chain of
+  // the prefetch would wait behind earlier loads on the in-order counter
   int32_t* lmap = reinterpret_cast<int32_t*>(lds + TILE + (TILE >> 4) + 2);
   const uint32_t nl = 1u << log_nl;
+  int32_t* lmap0 = lmap + nl;
+  int32_t* lmap1 = lmap0 + n0;
   const uint32_t rows_per_tile = TILE >> log_nl;
   const uint32_t tid = threadIdx.x;
   for (uint32_t k = tid; k < nl; k += 256) lmap[k] = map_last[k];
+  for (uint32_t k = tid; k < n0; k += 256) lmap0[k] = n0 > 1 ? map0[k] : 0;
+  for (uint32_t k = tid; k < n1; k += 256) lmap1[k] = n1 > 1 ? map1[k] : 0;
+  __syncthreads();
   cx<T> pre[EPT], preh[EPT];
   auto fetch = [&](uint32_t tile) {
     const uint32_t row0 = tile * rows_per_tile;
@@ -316,7 +323,7 @@ __global__ void __launch_bounds__(256) permute_pipe_kernel(
       const uint32_t x = tid + 256u * q;
       const uint32_t row = row0 + (x >> log_nl), k = x & (nl - 1u);
       const uint32_t k0 = fdiv(row, div_n1), k1 = row - k0 * n1;
-      const uint32_t srow = (n0 > 1 ? (uint32_t)map0[k0] : 0u) * n1 + (n1 > 1 ? (uint32_t)map1[k1] : 0u);
+      const uint32_t srow = (uint32_t)lmap0[k0] * n1 + (uint32_t)lmap1[k1];
       pre[q] = in[((int64_t)srow << log_nl) + k];
     }
   };
@@ -331,7 +338,6 @@ __global__ void __launch_bounds__(256) permute_pipe_kernel(
     fetch(tile);
     fetch_h(tile);
   }
-  __syncthreads();
   while (tile < ntiles) {
     const uint32_t next = tile + gridDim.x;
 #pragma unroll
@@ -507,22 +513,21 @@ hipError_t launch_permute_pipe(bool dbl, const void* in, void* out, const void* 
   if ((1u << log_nl) > tile || total % tile != 0) return hipErrorInvalidValue;
   const uint32_t ntiles = (uint32_t)(total / tile);
   const size_t elem = dbl ? 16 : 8;
-  const size_t lds = (size_t)(tile + (tile >> 4) + 2) * elem + ((size_t)1 << log_nl) * 4;
+  const size_t lds = (size_t)(tile + (tile >> 4) + 2) * elem + (((size_t)1 << log_nl) + n0 + n1) * 4;
+  if (lds > 96 * 1024) return hipErrorInvalidValue;
   const void* fn = dbl ? (const void*)permute_pipe_kernel<double> : (const void*)permute_pipe_kernel<float>;
   static bool init[2] = {false, false};
-  static int nb[2] = {0, 0};
   if (!init[dbl]) {
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (e != hipSuccess) return e;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb[dbl], fn, 256, 80 * 1024);
-    if (e != hipSuccess) return e;
     init[dbl] = true;
   }
-  int dev = 0, ncu = 0;
-  if (hipGetDevice(&dev) != hipSuccess ||
+  int nb = 0, dev = 0, ncu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, 256, lds) != hipSuccess ||
+      hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return hipErrorInvalidValue;
-  const uint32_t grid = std::min<uint32_t>(ntiles, (uint32_t)std::max(1, nb[dbl]) * ncu);
+  const uint32_t grid = std::min<uint32_t>(ntiles, (uint32_t)std::max(1, nb) * ncu);
   const FastDiv dn1 = make_fastdiv(n1);
   if (dbl)
     hipLaunchKernelGGL(permute_pipe_kernel<double>, dim3(grid), dim3(256), lds, st,

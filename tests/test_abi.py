@@ -39,7 +39,7 @@ def test_status_strings():
     ((4096,), "c128", 4, 1, 3),
     ((256, 256, 256), "c128", 4, 5, 11),
     ((256, 256, 256), "c64", 4, 5, 11),
-    ((2187, 2187), "c128", 3, 3, 7),
+    ((2187, 2187), "c128", 3, 5, 11),  # strided axis cut into two pieces
     ((5 ** 9,), "c128", 5, 3, 7),
     ((5 ** 9,), "c64", 5, 3, 7),
 ])

@@ -250,3 +250,18 @@ def test_errors():
     with pytest.raises(m.PafcError) as e:
         m.Plan((48,), C128, radix=[4])
     assert e.value.status == 2
+
+
+@pytest.mark.parametrize("shape", [(729, 100), (2187, 12), (512, 20, 6), (81, 729, 8), (1024, 3)])
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_split_strided_axes(shape, dtype):
+    """Strided axes too long for a 16-column tile are cut into an outer and an
+    inner pass (twiddles of the outer piece depend on the inner position)."""
+    rng = np.random.default_rng(int(np.prod(shape)) % 977)
+    x, h = crand(rng, shape), crand(rng, shape)
+    say("split strided", shape, dtype)
+    m = pafc()
+    d = m.describe(shape, "c128" if dtype == C128 else "c64")
+    y, _ = run_conv(x, h, dtype)
+    ref = oracle.conv_fft(rounded(x, dtype), rounded(h, dtype))
+    assert rel_l2(y, ref) < TOL[dtype], d["conv_passes"]
