@@ -46,7 +46,7 @@ hipError_t launch_permute_rows(bool dbl, const void* in, void* out, const void* 
 hipError_t launch_permute_gather(bool dbl, const void* in, void* out, const void* h,
                                  const int32_t* m0, const int32_t* m1, const int32_t* m2,
                                  uint32_t n0, uint32_t n1, uint32_t n2, hipStream_t st);
-hipError_t launch_permute_pipe(bool dbl, const void* in, void* out, const void* h,
+hipError_t launch_permute_tile(bool dbl, const void* in, void* out, const void* h,
                                const int32_t* m0, const int32_t* m1, const int32_t* mlast,
                                uint32_t n0, uint32_t n1, uint32_t log_nl, hipStream_t st);
 }  // namespace pafc
@@ -839,10 +839,9 @@ pafc_status run_permute(pafc_plan_t p, int dir, const void* in, void* out, const
     m1 = map_ptr(p, 0, inv);
   }
   const bool pow2 = (nl & (nl - 1)) == 0;
-  if (pow2 && nl <= 4096 && ((uint64_t)n0 * n1 * nl) % 4096 == 0 &&
-      (size_t)(4096 + 256 + 2) * P.elem + ((size_t)nl + n0 + n1) * 4 <= 96 * 1024) {
+  if (pow2 && nl <= 4096 && ((uint64_t)n0 * n1 * nl) % 4096 == 0) {
     const uint32_t log_nl = ilog2u(nl);
-    return from_hip(launch_permute_pipe(dbl, in, out, h, m0, m1, ml, n0, n1, log_nl, s));
+    return from_hip(launch_permute_tile(dbl, in, out, h, m0, m1, ml, n0, n1, log_nl, s));
   }
   if (tile_lds_bytes(nl, P.elem) <= kLdsBudget) {
     uint32_t rows = std::max<uint32_t>(1, 2048 / nl);

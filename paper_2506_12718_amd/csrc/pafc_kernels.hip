@@ -287,75 +287,49 @@ __global__ void __launch_bounds__(256) permute_rows_kernel(
   }
 }
 
-// Persistent, prefetching form of the same row permutation for rows whose
-// length NL is a power of two dividing 4096: a tile is 4096 / NL whole output
-// rows (16 elements per thread at 256 threads).  The next tile's source rows
-// (and the spectrum values of the current one) are loaded into registers
-// while the current tile is written out, so the HBM pipe stays busy as in a
-// copy; the within-row reversal is the LDS read.
+// One-tile-per-block form: 4096 / NL whole output rows per block (NL a power
+// of two), index maps staged in LDS, every source row load issued before the
+// first store so that many blocks per CU keep loads in flight as in a copy.
 template <typename T>
-__global__ void __launch_bounds__(256) permute_pipe_kernel(
+__global__ void __launch_bounds__(256) permute_tile_kernel(
     const cx<T>* __restrict__ in, cx<T>* __restrict__ out, const cx<T>* __restrict__ h,
     const int32_t* __restrict__ map0, const int32_t* __restrict__ map1,
     const int32_t* __restrict__ map_last, uint32_t n0, uint32_t n1, uint32_t log_nl,
-    uint32_t ntiles, FastDiv div_n1) {
+    FastDiv div_n1) {
   constexpr int EPT = 16;
   constexpr uint32_t TILE = 256 * EPT;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
-  // the three index maps live in LDS: a global load in the address chain of
-  // the prefetch would wait behind earlier loads on the in-order counter
   int32_t* lmap = reinterpret_cast<int32_t*>(lds + TILE + (TILE >> 4) + 2);
   const uint32_t nl = 1u << log_nl;
-  int32_t* lmap0 = lmap + nl;
-  int32_t* lmap1 = lmap0 + n0;
   const uint32_t rows_per_tile = TILE >> log_nl;
+  int32_t* lsrc = lmap + nl;  // source row of each output row of the tile
   const uint32_t tid = threadIdx.x;
+  const uint32_t row0 = blockIdx.x * rows_per_tile;
   for (uint32_t k = tid; k < nl; k += 256) lmap[k] = map_last[k];
-  for (uint32_t k = tid; k < n0; k += 256) lmap0[k] = n0 > 1 ? map0[k] : 0;
-  for (uint32_t k = tid; k < n1; k += 256) lmap1[k] = n1 > 1 ? map1[k] : 0;
-  __syncthreads();
-  cx<T> pre[EPT], preh[EPT];
-  auto fetch = [&](uint32_t tile) {
-    const uint32_t row0 = tile * rows_per_tile;
-#pragma unroll
-    for (int q = 0; q < EPT; ++q) {
-      const uint32_t x = tid + 256u * q;
-      const uint32_t row = row0 + (x >> log_nl), k = x & (nl - 1u);
-      const uint32_t k0 = fdiv(row, div_n1), k1 = row - k0 * n1;
-      const uint32_t srow = (uint32_t)lmap0[k0] * n1 + (uint32_t)lmap1[k1];
-      pre[q] = in[((int64_t)srow << log_nl) + k];
-    }
-  };
-  auto fetch_h = [&](uint32_t tile) {
-    if (!h) return;
-    const int64_t base = (int64_t)tile * TILE;
-#pragma unroll
-    for (int q = 0; q < EPT; ++q) preh[q] = h[base + tid + 256u * q];
-  };
-  uint32_t tile = blockIdx.x;
-  if (tile < ntiles) {
-    fetch(tile);
-    fetch_h(tile);
+  for (uint32_t r = tid; r < rows_per_tile; r += 256) {
+    const uint32_t row = row0 + r;
+    const uint32_t k0 = fdiv(row, div_n1), k1 = row - k0 * n1;
+    lsrc[r] = (int32_t)((n0 > 1 ? (uint32_t)map0[k0] : 0u) * n1 + (n1 > 1 ? (uint32_t)map1[k1] : 0u));
   }
-  while (tile < ntiles) {
-    const uint32_t next = tile + gridDim.x;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * TILE;
+  cx<T> v[EPT];
 #pragma unroll
-    for (int q = 0; q < EPT; ++q) lds[lds_phys(tid + 256u * q)] = pre[q];
-    if (next < ntiles) fetch(next);
-    __syncthreads();
-    const int64_t base = (int64_t)tile * TILE;
+  for (int q = 0; q < EPT; ++q) {
+    const uint32_t x = tid + 256u * q;
+    v[q] = in[((int64_t)lsrc[x >> log_nl] << log_nl) + (x & (nl - 1u))];
+  }
 #pragma unroll
-    for (int q = 0; q < EPT; ++q) {
-      const uint32_t x = tid + 256u * q;
-      const uint32_t rr = x >> log_nl, k = x & (nl - 1u);
-      cx<T> v = lds[lds_phys((rr << log_nl) + (uint32_t)lmap[k])];
-      if (h) v = cmul(v, preh[q]);
-      out[base + x] = v;
-    }
-    if (next < ntiles) fetch_h(next);
-    __syncthreads();
-    tile = next;
+  for (int q = 0; q < EPT; ++q) lds[lds_phys(tid + 256u * q)] = v[q];
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < EPT; ++q) {
+    const uint32_t x = tid + 256u * q;
+    const uint32_t rr = x >> log_nl, k = x & (nl - 1u);
+    cx<T> w = lds[lds_phys((rr << log_nl) + (uint32_t)lmap[k])];
+    if (h) w = cmul(w, h[base + x]);
+    out[base + x] = w;
   }
 }
 
@@ -505,7 +479,7 @@ hipError_t launch_permute_rows(bool dbl, const void* in, void* out, const void* 
   return hipGetLastError();
 }
 
-hipError_t launch_permute_pipe(bool dbl, const void* in, void* out, const void* h,
+hipError_t launch_permute_tile(bool dbl, const void* in, void* out, const void* h,
                                const int32_t* m0, const int32_t* m1, const int32_t* mlast,
                                uint32_t n0, uint32_t n1, uint32_t log_nl, hipStream_t st) {
   const uint32_t tile = 4096;
@@ -513,30 +487,23 @@ hipError_t launch_permute_pipe(bool dbl, const void* in, void* out, const void* 
   if ((1u << log_nl) > tile || total % tile != 0) return hipErrorInvalidValue;
   const uint32_t ntiles = (uint32_t)(total / tile);
   const size_t elem = dbl ? 16 : 8;
-  const size_t lds = (size_t)(tile + (tile >> 4) + 2) * elem + (((size_t)1 << log_nl) + n0 + n1) * 4;
-  if (lds > 96 * 1024) return hipErrorInvalidValue;
-  const void* fn = dbl ? (const void*)permute_pipe_kernel<double> : (const void*)permute_pipe_kernel<float>;
+  const size_t lds = (size_t)(tile + (tile >> 4) + 2) * elem + (((size_t)1 << log_nl) + (tile >> log_nl)) * 4;
+  const void* fn = dbl ? (const void*)permute_tile_kernel<double> : (const void*)permute_tile_kernel<float>;
   static bool init[2] = {false, false};
   if (!init[dbl]) {
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (e != hipSuccess) return e;
     init[dbl] = true;
   }
-  int nb = 0, dev = 0, ncu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, 256, lds) != hipSuccess ||
-      hipGetDevice(&dev) != hipSuccess ||
-      hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-    return hipErrorInvalidValue;
-  const uint32_t grid = std::min<uint32_t>(ntiles, (uint32_t)std::max(1, nb) * ncu);
   const FastDiv dn1 = make_fastdiv(n1);
   if (dbl)
-    hipLaunchKernelGGL(permute_pipe_kernel<double>, dim3(grid), dim3(256), lds, st,
+    hipLaunchKernelGGL(permute_tile_kernel<double>, dim3(ntiles), dim3(256), lds, st,
                        (const cx<double>*)in, (cx<double>*)out, (const cx<double>*)h, m0, m1,
-                       mlast, n0, n1, log_nl, ntiles, dn1);
+                       mlast, n0, n1, log_nl, dn1);
   else
-    hipLaunchKernelGGL(permute_pipe_kernel<float>, dim3(grid), dim3(256), lds, st,
+    hipLaunchKernelGGL(permute_tile_kernel<float>, dim3(ntiles), dim3(256), lds, st,
                        (const cx<float>*)in, (cx<float>*)out, (const cx<float>*)h, m0, m1, mlast,
-                       n0, n1, log_nl, ntiles, dn1);
+                       n0, n1, log_nl, dn1);
   return hipGetLastError();
 }
 
