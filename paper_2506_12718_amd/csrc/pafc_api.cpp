@@ -295,6 +295,14 @@ uint32_t pow2_floor(uint64_t x) {
   return p;
 }
 
+// Bytes of the LDS two-level twiddle copy of a piece (see make_pass).
+size_t twl_bytes(int64_t n_tw, size_t elem) {
+  uint32_t b = 0;
+  while (((int64_t)1 << (2 * b)) < n_tw) ++b;
+  const int64_t nhi = (n_tw + ((int64_t)1 << b) - 1) >> b;
+  return (size_t)(((int64_t)1 << b) + nhi + 2) * elem;
+}
+
 void choose_width(Seg& s, size_t elem, int tuneW) {
   // ~4096 elements per tile; strided tiles also want >= 256 B row segments
   uint32_t W = pow2_floor(std::max<uint64_t>(1, 4096 / std::max<uint32_t>(1, s.L)));
@@ -305,7 +313,8 @@ void choose_width(Seg& s, size_t elem, int tuneW) {
   const int envW = env_int(s.mode == MODE_STRIDED ? "PAFC_TUNE_WS" : "PAFC_TUNE_WC", 0);
   if (envW > 0) W = std::min<uint32_t>(pow2_floor((uint64_t)envW),
                                        pow2_floor(std::max<uint64_t>(1, s.ncols)));
-  while (W > 1 && tile_lds_bytes((uint64_t)s.L * W, elem) > kLdsBudget) W /= 2;
+  while (W > 1 && tile_lds_bytes((uint64_t)s.L * W, elem) + twl_bytes(s.n_tw, elem) > kLdsBudget)
+    W /= 2;
   s.W = W;
 }
 
@@ -386,6 +395,11 @@ bool validate_pass(const PassArgs& a, int64_t extent, int64_t n_tw) {
   const int64_t maxidx = (nouter - 1) * a.S_o + last_col * a.S_c + (int64_t)(a.L - 1) * a.S_i;
   if (maxidx >= extent || a.S_i <= 0 || a.S_c <= 0 || a.S_o < 0) return false;
   if (a.nops == 0 || a.nops > (uint32_t)kMaxOps) return false;
+  // LDS twiddle tables: lo has 2^b entries, hi covers every exponent < n_tw,
+  // and the flat source table is read at e << b < n_tw only
+  if (((int64_t)a.twl_nhi << a.twl_bits) < n_tw || (((int64_t)a.twl_nhi - 1) << a.twl_bits) >= n_tw)
+    return false;
+  if (((int64_t)1 << a.twl_bits) > n_tw && n_tw > 1) return false;
   uint32_t K = a.L;
   for (uint32_t k = 0; k < a.nops; ++k) {
     const OpDesc& op = a.ops[k];
@@ -424,7 +438,18 @@ bool make_pass(const Seg& s, int kind, size_t elem, Pass* p) {
   for (uint32_t i = 0; i < a.nops; ++i) maxitems = std::max(maxitems, a.ops[i].nitems);
   uint32_t th = std::min<uint32_t>(kMaxThreads, ((maxitems + 63) / 64) * 64);
   p->threads = std::max<uint32_t>(64, th);
-  p->lds = tile_lds_bytes(a.LW, elem);
+  // LDS copy of the twiddles, two-level with ~sqrt(n_tw) entries per level
+  // (the same split rule as the global table when that one is two-level)
+  {
+    uint32_t b = 0;
+    while (((int64_t)1 << (2 * b)) < s.n_tw) ++b;
+    a.twl_bits = b;
+    a.twl_nhi = (uint32_t)((s.n_tw + ((int64_t)1 << b) - 1) >> b);
+    const uint64_t LW = a.LW;
+    a.twl_off = (uint32_t)((LW + (LW >> 4) + 2) & ~1ull);
+  }
+  p->lds = (size_t)(a.twl_off + (1u << a.twl_bits) + a.twl_nhi) * elem;
+  if (p->lds > kLdsBudget) return false;
   p->tw_n = s.n_tw;
   p->mid = (kind == 2);
   p->kind = 0;

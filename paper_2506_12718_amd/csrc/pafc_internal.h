@@ -105,6 +105,9 @@ struct PassArgs {
   FastDiv divTiles;    // division by tiles_per_slice
   FastDiv divJc;       // column -> inner position of an outer piece (the
                        // stride of the axis; 1 for a 1-D transform)
+  uint32_t twl_bits;   // LDS copy of the twiddles: w^E = lo[E & (2^b - 1)] * hi[E >> b]
+  uint32_t twl_nhi;    // entries of the hi table (the lo table has 2^twl_bits)
+  uint32_t twl_off;    // element offset of the LDS tables after the tile
   OpDesc ops[kMaxOps];
 };
 

@@ -24,6 +24,28 @@
 
 namespace pafc {
 
+// Twiddle from the block's LDS copy of the two-level table.
+template <typename T>
+__device__ __forceinline__ cx<T> twiddle_lds(const PassArgs& a, const cx<T>* lds, uint32_t E) {
+  const cx<T>* lo = lds + a.twl_off;
+  const cx<T>* hi = lo + (1u << a.twl_bits);
+  return cmul(lo[E & ((1u << a.twl_bits) - 1u)], hi[E >> a.twl_bits]);
+}
+
+// Stage the two-level twiddle table in LDS (from the flat or two-level
+// global table); the caller synchronises before the first op.
+template <typename T>
+__device__ __forceinline__ void stage_twiddles(const PassArgs& a, cx<T>* lds) {
+  cx<T>* lo = lds + a.twl_off;
+  cx<T>* hi = lo + (1u << a.twl_bits);
+  const cx<T>* glo = reinterpret_cast<const cx<T>*>(a.tw_lo);
+  const cx<T>* ghi = reinterpret_cast<const cx<T>*>(a.tw_hi);
+  const uint32_t nlo = 1u << a.twl_bits;
+  for (uint32_t e = threadIdx.x; e < nlo; e += blockDim.x) lo[e] = glo[e];
+  for (uint32_t e = threadIdx.x; e < a.twl_nhi; e += blockDim.x)
+    hi[e] = ghi ? ghi[e] : glo[e << a.twl_bits];
+}
+
 struct TileCtx {
   int64_t base;    // element offset of tile position (0, 0) in the data arrays
   int64_t off;     // packed offset of the problem (0 outside the batched form);
@@ -86,7 +108,7 @@ __device__ __forceinline__ void run_op(const PassArgs& a, const OpDesc& op, cons
         static_for<R - 1>([&](auto mm) {
           E += jf;
           if (E >= op.Kf) E -= op.Kf;
-          v[mm.value + 1] = cmul(v[mm.value + 1], twiddle<T>(a, E * op.escale));
+          v[mm.value + 1] = cmul(v[mm.value + 1], twiddle_lds<T>(a, lds, E * op.escale));
         });
       }
       static_for<R>([&](auto m) { put(digrev<r, g>(m.value), v[m.value]); });
@@ -98,7 +120,7 @@ __device__ __forceinline__ void run_op(const PassArgs& a, const OpDesc& op, cons
         static_for<R - 1>([&](auto mm) {
           E += jf;
           if (E >= op.Kf) E -= op.Kf;
-          v[mm.value + 1] = cmulc(v[mm.value + 1], twiddle<T>(a, E * op.escale));
+          v[mm.value + 1] = cmulc(v[mm.value + 1], twiddle_lds<T>(a, lds, E * op.escale));
         });
       }
       Dft<R, r, true, T>::run(v);
@@ -161,6 +183,7 @@ __device__ __forceinline__ void do_tile(const PassArgs& a, const void* __restric
     t.ls_i = 1;
     t.ls_c = a.L;
   }
+  stage_twiddles<T>(a, lds);
   // load (unless the first op reads global memory itself)
   if (!a.ops[0].src_g) {
     for (uint32_t x = threadIdx.x; x < a.LW; x += blockDim.x) {
@@ -176,8 +199,8 @@ __device__ __forceinline__ void do_tile(const PassArgs& a, const void* __restric
       if (t.col0 + c < a.ncols) v = ld_g<T>(in, t.base + (int64_t)i * a.S_i + (int64_t)c * a.S_c);
       lds[lds_phys(x)] = v;
     }
-    __syncthreads();
   }
+  __syncthreads();  // tile and twiddle tables visible
   const uint32_t nops = a.nops;
   for (uint32_t k = 0; k < nops; ++k) {
     const OpDesc& op = a.ops[k];
