@@ -32,6 +32,7 @@ hipError_t launch_batch(bool dbl, int cls, const PassArgs* descs, const BatchTil
                         uint32_t threads, size_t lds_bytes, hipStream_t s);
 hipError_t launch_scale(bool dbl, void* p, int64_t n, double s, hipStream_t st);
 bool pipe_supported(int r, int g, int ng);
+
 int pipe_blocks_per_cu(bool dbl, int r, int g, int ng, int kind, int mode, uint32_t threads,
                        size_t lds);
 hipError_t launch_pipe(bool dbl, int r, int g, int ng, int kind, int mode, const PassArgs* d,
@@ -234,6 +235,7 @@ struct Pass {
   int pipe_r = 0, pipe_g = 0, pipe_ng = 0, pipe_kind = 0;
   uint32_t pipe_grid = 0;
   size_t pipe_lds = 0;
+
   std::string label;
 };
 
@@ -484,6 +486,7 @@ bool make_pass(const Seg& s, int kind, size_t elem, Pass* p) {
   snprintf(buf, sizeof(buf), "%s L=%u W=%u tiles=%u thr=%u [", s.mode == MODE_STRIDED ? "strided" : "contig",
            s.L, s.W, a.ntiles, p->threads);
   p->label = std::string(buf) + ops + "]";
+
   if (p->pipe) {
     char nm[96];
     snprintf(nm, sizeof(nm), " pipe_kernel<%s,%d,%d,%d,%d,%d>", elem == 16 ? "double" : "float",
@@ -839,6 +842,7 @@ pafc_status run_pass(pafc_plan_t p, const Pass& ps, const void* in, void* out, h
     return from_hip(launch_pipe(dbl, ps.pipe_r, ps.pipe_g, ps.pipe_ng, ps.pipe_kind, ps.a.mode,
                                 p->d_descs + ps.desc, ps.pipe_grid, ps.threads, ps.pipe_lds, in,
                                 out, s));
+
   return from_hip(launch_pass(dbl, ps.cls, p->d_descs + ps.desc, ps.a.ntiles, in, out, ps.threads,
                               ps.lds, s));
 }
@@ -1014,6 +1018,7 @@ pafc_status pafc_plan(pafc_plan_t* out, int ndim, const int64_t* dims, const int
         ps.pipe_grid = (uint32_t)std::min<int64_t>(want, ps.a.ntiles);
         if (nb <= 0) ps.pipe = false;
       }
+
   }
   // pass descriptors of the three sequences, uploaded once
   std::vector<PassArgs> descs;

@@ -18,216 +18,11 @@
 // plus one twiddle per element, which is the same linear map.
 #include <hip/hip_runtime.h>
 
-#include "kernel_common.h"
+#include "pass_engine.h"
 
 #include <algorithm>
 
 namespace pafc {
-
-// Twiddle from the block's LDS copy of the two-level table.
-template <typename T>
-__device__ __forceinline__ cx<T> twiddle_lds(const PassArgs& a, const cx<T>* lds, uint32_t E) {
-  const cx<T>* lo = lds + a.twl_off;
-  const cx<T>* hi = lo + (1u << a.twl_bits);
-  return cmul(lo[E & ((1u << a.twl_bits) - 1u)], hi[E >> a.twl_bits]);
-}
-
-// Stage the two-level twiddle table in LDS (from the flat or two-level
-// global table); the caller synchronises before the first op.
-template <typename T>
-__device__ __forceinline__ void stage_twiddles(const PassArgs& a, cx<T>* lds) {
-  cx<T>* lo = lds + a.twl_off;
-  cx<T>* hi = lo + (1u << a.twl_bits);
-  const cx<T>* glo = reinterpret_cast<const cx<T>*>(a.tw_lo);
-  const cx<T>* ghi = reinterpret_cast<const cx<T>*>(a.tw_hi);
-  const uint32_t nlo = 1u << a.twl_bits;
-  for (uint32_t e = threadIdx.x; e < nlo; e += blockDim.x) lo[e] = glo[e];
-  for (uint32_t e = threadIdx.x; e < a.twl_nhi; e += blockDim.x)
-    hi[e] = ghi ? ghi[e] : glo[e << a.twl_bits];
-}
-
-struct TileCtx {
-  int64_t base;    // element offset of tile position (0, 0) in the data arrays
-  int64_t off;     // packed offset of the problem (0 outside the batched form);
-                   // the filter spectrum is per problem, so it is indexed
-                   // without it
-  uint32_t col0;   // global column of tile column 0
-  uint32_t ls_i;   // LDS linear stride between positions
-  uint32_t ls_c;   // LDS linear stride between columns
-};
-
-// One op over all items of the tile.  An op reads its R inputs from LDS or,
-// when it is the first op of the pass and its access is coalesced
-// (op.src_g), straight from global memory; symmetrically it writes to LDS or
-// (op.dst_g, last op) straight to global memory.
-template <typename T, int r, int g, int TYPE>
-__device__ __forceinline__ void run_op(const PassArgs& a, const OpDesc& op, const TileCtx& t,
-                                       cx<T>* lds, const void* __restrict__ in,
-                                       void* __restrict__ out) {
-  constexpr int R = ipow(r, g);
-  const uint32_t S = op.S, K = op.K;
-  for (uint32_t it = threadIdx.x; it < op.nitems; it += blockDim.x) {
-    uint32_t c, b, j;
-    if (a.mode == MODE_STRIDED) {
-      c = it & (a.W - 1u);
-      uint32_t rest = it >> a.logW;
-      b = fdiv(rest, op.divS);
-      j = rest - b * S;
-    } else {
-      uint32_t q = fdiv(it, op.divS);
-      j = it - q * S;
-      c = fdiv(q, op.divNB);
-      b = q - c * op.divNB.d;
-    }
-    const uint32_t gcol = t.col0 + c;
-    const bool valid = gcol < a.ncols;
-    const uint32_t i0 = b * K + j;
-    const uint32_t lbase = i0 * t.ls_i + c * t.ls_c;
-    const uint32_t lstep = S * t.ls_i;
-    const int64_t gbase = t.base + (int64_t)i0 * a.S_i + (int64_t)c * a.S_c;
-    const int64_t gstep = (int64_t)S * a.S_i;
-    // element at offset k*S along the axis from position i0
-    auto get = [&](int k) -> cx<T> {
-      if (op.src_g) return valid ? ld_g<T>(in, gbase + k * gstep) : cx<T>{(T)0, (T)0};
-      return lds[lds_phys(lbase + k * lstep)];
-    };
-    auto put = [&](int k, cx<T> v) {
-      if (op.dst_g) {
-        if (valid) st_g<T>(out, gbase + k * gstep, v);
-      } else {
-        lds[lds_phys(lbase + k * lstep)] = v;
-      }
-    };
-    cx<T> v[R];
-    if constexpr (TYPE == OP_DIF) {
-      static_for<R>([&](auto s) { v[s.value] = get(s.value); });
-      Dft<R, r, false, T>::run(v);
-      if (op.tw) {
-        const uint32_t jf = j * a.jmul + (a.col_in_j && valid ? fdiv(gcol, a.divJc) : 0u);
-        uint32_t E = 0;
-        static_for<R - 1>([&](auto mm) {
-          E += jf;
-          if (E >= op.Kf) E -= op.Kf;
-          v[mm.value + 1] = cmul(v[mm.value + 1], twiddle_lds<T>(a, lds, E * op.escale));
-        });
-      }
-      static_for<R>([&](auto m) { put(digrev<r, g>(m.value), v[m.value]); });
-    } else if constexpr (TYPE == OP_DIT) {
-      static_for<R>([&](auto m) { v[m.value] = get(digrev<r, g>(m.value)); });
-      if (op.tw) {
-        const uint32_t jf = j * a.jmul + (a.col_in_j && valid ? fdiv(gcol, a.divJc) : 0u);
-        uint32_t E = 0;
-        static_for<R - 1>([&](auto mm) {
-          E += jf;
-          if (E >= op.Kf) E -= op.Kf;
-          v[mm.value + 1] = cmulc(v[mm.value + 1], twiddle_lds<T>(a, lds, E * op.escale));
-        });
-      }
-      Dft<R, r, true, T>::run(v);
-      static_for<R>([&](auto s) { put(s.value, v[s.value]); });
-    } else {  // OP_MID: S == 1, j == 0
-      static_for<R>([&](auto s) { v[s.value] = get(s.value); });
-      Dft<R, r, false, T>::run(v);
-      if (valid) {
-        const int64_t hb = gbase - t.off;
-        static_for<R>([&](auto m) {
-          const cx<T> h = ld_g<T>(a.H, hb + (int64_t)digrev<r, g>(m.value) * a.S_i);
-          v[m.value] = cmul(v[m.value], h);
-        });
-      }
-      Dft<R, r, true, T>::run(v);
-      static_for<R>([&](auto s) { put(s.value, v[s.value]); });
-    }
-  }
-}
-
-// Register class of a kernel instance: CLS 0 holds the groups with R <= 16,
-// CLS 1 every group (R <= 32).  A group's R^2-sized register footprint sets
-// the VGPR count of the whole kernel, so the small class keeps occupancy for
-// the common radix-2/4/8 plans.
-template <int R, int CLS>
-constexpr bool kind_in_class() { return CLS == 1 || R <= 16; }
-
-template <typename T, int TYPE, int CLS>
-__device__ __forceinline__ void dispatch_op(const PassArgs& a, const OpDesc& op,
-                                            const TileCtx& t, cx<T>* lds,
-                                            const void* __restrict__ in, void* __restrict__ out) {
-  switch (op.kind) {
-#define PAFC_CASE(id, r, g)                                        \
-  case id:                                                         \
-    if constexpr (kind_in_class<ipow(r, g), CLS>()) run_op<T, r, g, TYPE>(a, op, t, lds, in, out); \
-    break;
-    PAFC_KIND_LIST(PAFC_CASE)
-#undef PAFC_CASE
-    default:
-      break;
-  }
-}
-
-// Process tile `tile` of the pass described by `a`; `off` shifts in, out and H
-// (the packed offset of a problem in the batched form).
-template <typename T, int CLS>
-__device__ __forceinline__ void do_tile(const PassArgs& a, const void* __restrict__ in,
-                                        void* __restrict__ out, uint32_t tile, int64_t off,
-                                        cx<T>* lds) {
-  const uint32_t o = fdiv(tile, a.divTiles);
-  const uint32_t cb = tile - o * a.tiles_per_slice;
-  TileCtx t;
-  t.col0 = cb * a.W;
-  t.base = (int64_t)o * a.S_o + (int64_t)t.col0 * a.S_c + off;
-  t.off = off;
-  if (a.mode == MODE_STRIDED) {
-    t.ls_i = a.W;
-    t.ls_c = 1;
-  } else {
-    t.ls_i = 1;
-    t.ls_c = a.L;
-  }
-  stage_twiddles<T>(a, lds);
-  // load (unless the first op reads global memory itself)
-  if (!a.ops[0].src_g) {
-    for (uint32_t x = threadIdx.x; x < a.LW; x += blockDim.x) {
-      uint32_t i, c;
-      if (a.mode == MODE_STRIDED) {
-        i = x >> a.logW;
-        c = x & (a.W - 1u);
-      } else {
-        c = fdiv(x, a.divL);
-        i = x - c * a.L;
-      }
-      cx<T> v = {(T)0, (T)0};
-      if (t.col0 + c < a.ncols) v = ld_g<T>(in, t.base + (int64_t)i * a.S_i + (int64_t)c * a.S_c);
-      lds[lds_phys(x)] = v;
-    }
-  }
-  __syncthreads();  // tile and twiddle tables visible
-  const uint32_t nops = a.nops;
-  for (uint32_t k = 0; k < nops; ++k) {
-    const OpDesc& op = a.ops[k];
-    if (op.type == OP_DIF)
-      dispatch_op<T, OP_DIF, CLS>(a, op, t, lds, in, out);
-    else if (op.type == OP_DIT)
-      dispatch_op<T, OP_DIT, CLS>(a, op, t, lds, in, out);
-    else
-      dispatch_op<T, OP_MID, CLS>(a, op, t, lds, in, out);
-    if (k + 1 < nops || !op.dst_g) __syncthreads();
-  }
-  // store (unless the last op wrote global memory itself)
-  if (!a.ops[nops - 1].dst_g) {
-    for (uint32_t x = threadIdx.x; x < a.LW; x += blockDim.x) {
-      uint32_t i, c;
-      if (a.mode == MODE_STRIDED) {
-        i = x >> a.logW;
-        c = x & (a.W - 1u);
-      } else {
-        c = fdiv(x, a.divL);
-        i = x - c * a.L;
-      }
-      if (t.col0 + c < a.ncols)
-        st_g<T>(out, t.base + (int64_t)i * a.S_i + (int64_t)c * a.S_c, lds[lds_phys(x)]);
-    }
-  }
-}
 
 template <typename T, int CLS>
 __global__ void __launch_bounds__(256) pass_kernel(const PassArgs* __restrict__ desc,
