@@ -1227,11 +1227,12 @@ struct pafc_batch_s {
   std::vector<bool> fset;
   PassArgs* d_descs = nullptr;
   BatchTile* d_tiles = nullptr;
-  struct Level {
+  struct Level {  // one launch: the tiles of one pass level in one register class
+    int level = 0;
     uint32_t first = 0, count = 0, threads = 64;
     size_t lds = 0;
     int cls = 0;
-    int64_t bytes = 0;  // algorithmic HBM bytes of the level
+    int64_t bytes = 0;  // algorithmic HBM bytes of the launch
   };
   std::vector<Level> levels;
   std::string desc;
@@ -1298,13 +1299,9 @@ pafc_status pafc_batch_plan(pafc_batch_t* out, int count, const int64_t* sizes,
   // descriptors: one per (filter, pass level)
   std::vector<PassArgs> descs;
   std::map<std::pair<int, int>, uint32_t> didx;
-  std::vector<std::vector<std::pair<uint32_t, int>>> desc_meta;  // unused
-  struct LevelInfo {
-    uint32_t threads = 64;
-    size_t lds = 0;
-    int cls = 0;
-  };
-  std::vector<LevelInfo> linfo(3);
+  std::vector<uint32_t> dthreads;
+  std::vector<size_t> dlds;
+  std::vector<int> dcls;
   for (int f = 0; f < nfilters; ++f) {
     if (b->fsize[(size_t)f] == 0) continue;
     pafc_plan_t p = b->plans[b->fsize[(size_t)f]];
@@ -1314,45 +1311,45 @@ pafc_status pafc_batch_plan(pafc_batch_t* out, int count, const int64_t* sizes,
       finalize_args(p->P, p->d_tw, b->d_spec[(size_t)f], conv[l], &a);
       didx[{f, (int)l}] = (uint32_t)descs.size();
       descs.push_back(a);
-      linfo[l].threads = std::max(linfo[l].threads, conv[l].threads);
-      linfo[l].lds = std::max(linfo[l].lds, conv[l].lds);
-      linfo[l].cls = std::max(linfo[l].cls, conv[l].cls);
+      dthreads.push_back(conv[l].threads);
+      dlds.push_back(conv[l].lds);
+      dcls.push_back(conv[l].cls);
     }
   }
-  // tiles per level, longest problems first
+  // tiles per (level, register class) launch, longest problems first; the
+  // tiles of one level are independent, so splitting a level by class only
+  // lets each part run with its own kernel's occupancy
   std::vector<int> order((size_t)count);
   for (int i = 0; i < count; ++i) order[(size_t)i] = i;
   std::stable_sort(order.begin(), order.end(),
                    [&](int x, int y) { return b->sizes[(size_t)x] > b->sizes[(size_t)y]; });
   std::vector<BatchTile> tiles;
-  b->levels.resize(3);
   for (int l = 0; l < 3; ++l) {
-    b->levels[(size_t)l].first = (uint32_t)tiles.size();
-    for (int i : order) {
-      const int f = b->fid[(size_t)i];
-      auto it = didx.find({f, l});
-      if (it == didx.end()) continue;
-      const PassArgs& a = descs[it->second];
-      for (uint32_t t = 0; t < a.ntiles; ++t)
-        tiles.push_back(BatchTile{it->second, t, b->offsets[(size_t)i]});
-    }
-    auto& L = b->levels[(size_t)l];
-    L.count = (uint32_t)tiles.size() - L.first;
-    std::vector<bool> fseen((size_t)nfilters, false);
-    for (int i = 0; i < count; ++i) {
-      const int f = b->fid[(size_t)i];
-      auto it2 = didx.find({f, l});
-      if (it2 == didx.end()) continue;
-      L.bytes += 2 * b->sizes[(size_t)i] * (int64_t)b->elem;
-      const pafc_plan_t pp = b->plans[b->sizes[(size_t)i]];
-      if (pp->P.conv[(size_t)l].mid && !fseen[(size_t)f]) {
-        fseen[(size_t)f] = true;
-        L.bytes += b->sizes[(size_t)i] * (int64_t)b->elem;
+    for (int cls = 0; cls < 2; ++cls) {
+      pafc_batch_s::Level L;
+      L.level = l;
+      L.cls = cls;
+      L.first = (uint32_t)tiles.size();
+      std::vector<bool> fseen((size_t)nfilters, false);
+      for (int i : order) {
+        const int f = b->fid[(size_t)i];
+        auto it = didx.find({f, l});
+        if (it == didx.end() || dcls[it->second] != cls) continue;
+        const PassArgs& a = descs[it->second];
+        for (uint32_t t = 0; t < a.ntiles; ++t)
+          tiles.push_back(BatchTile{it->second, t, b->offsets[(size_t)i]});
+        L.threads = std::max(L.threads, dthreads[it->second]);
+        L.lds = std::max(L.lds, dlds[it->second]);
+        L.bytes += 2 * b->sizes[(size_t)i] * (int64_t)b->elem;
+        const pafc_plan_t pp = b->plans[b->sizes[(size_t)i]];
+        if (pp->P.conv[(size_t)l].mid && !fseen[(size_t)f]) {
+          fseen[(size_t)f] = true;
+          L.bytes += b->sizes[(size_t)i] * (int64_t)b->elem;
+        }
       }
+      L.count = (uint32_t)tiles.size() - L.first;
+      if (L.count) b->levels.push_back(L);
     }
-    L.threads = linfo[(size_t)l].threads;
-    L.lds = linfo[(size_t)l].lds;
-    L.cls = linfo[(size_t)l].cls;
   }
   // every tile's problem must lie inside the packed arrays, and its
   // descriptor must have been built for that problem's length (the filter
@@ -1382,10 +1379,11 @@ pafc_status pafc_batch_plan(pafc_batch_t* out, int count, const int64_t* sizes,
            "{\"count\": %d, \"total_elems\": %lld, \"size_classes\": %zu, \"levels\": [", count,
            (long long)b->total, b->plans.size());
   b->desc = buf;
-  for (int l = 0; l < 3; ++l) {
-    auto& L = b->levels[(size_t)l];
-    snprintf(buf, sizeof(buf), "%s{\"tiles\": %u, \"threads\": %u, \"lds\": %zu, \"cls\": %d}",
-             l ? ", " : "", L.count, L.threads, L.lds, L.cls);
+  for (size_t l = 0; l < b->levels.size(); ++l) {
+    auto& L = b->levels[l];
+    snprintf(buf, sizeof(buf),
+             "%s{\"level\": %d, \"tiles\": %u, \"threads\": %u, \"lds\": %zu, \"cls\": %d}",
+             l ? ", " : "", L.level, L.count, L.threads, L.lds, L.cls);
     b->desc += buf;
   }
   b->desc += "], \"plans\": [";
@@ -1431,12 +1429,10 @@ pafc_status pafc_batch_convolve(pafc_batch_t b, const void* x_dev, void* y_dev, 
     if (!b->fset[(size_t)b->fid[(size_t)i]]) return PAFC_ERROR_FILTER_NOT_SET;
   hipStream_t s = (hipStream_t)hip_stream;
   const bool dbl = b->dtype == PAFC_C128;
-  const void* cur = x_dev;
   for (auto& L : b->levels) {
-    if (L.count == 0) continue;
-    PAFC_TRY(from_hip(launch_batch(dbl, L.cls, b->d_descs, b->d_tiles, L.first, L.count, cur,
+    const void* src = L.level == 0 ? x_dev : y_dev;
+    PAFC_TRY(from_hip(launch_batch(dbl, L.cls, b->d_descs, b->d_tiles, L.first, L.count, src,
                                    y_dev, L.threads, L.lds, s)));
-    cur = y_dev;
   }
   return PAFC_SUCCESS;
 }
@@ -1446,8 +1442,7 @@ pafc_status pafc_batch_profile(pafc_batch_t b, const void* x_dev, void* y_dev, v
                                double* ms_per_rep, int* nlevel) {
   if (!b || !x_dev || !y_dev || !nlevel || reps < 1 || !ms_per_level) return PAFC_ERROR_INVALID_VALUE;
   std::vector<size_t> used;
-  for (size_t l = 0; l < b->levels.size(); ++l)
-    if (b->levels[l].count) used.push_back(l);
+  for (size_t l = 0; l < b->levels.size(); ++l) used.push_back(l);
   const int n = (int)used.size();
   const int cap = *nlevel;
   *nlevel = n;
@@ -1463,12 +1458,10 @@ pafc_status pafc_batch_profile(pafc_batch_t b, const void* x_dev, void* y_dev, v
   for (int r = 0; r < reps && st == PAFC_SUCCESS; ++r) {
     hipEvent_t* E = ev.data() + (size_t)r * (n + 1);
     st = from_hip(hipEventRecord(E[0], s));
-    const void* cur = x_dev;
     for (int k = 0; k < n && st == PAFC_SUCCESS; ++k) {
       auto& L = b->levels[used[(size_t)k]];
-      st = from_hip(launch_batch(dbl, L.cls, b->d_descs, b->d_tiles, L.first, L.count, cur, y_dev,
-                                 L.threads, L.lds, s));
-      cur = y_dev;
+      st = from_hip(launch_batch(dbl, L.cls, b->d_descs, b->d_tiles, L.first, L.count,
+                                 L.level == 0 ? x_dev : y_dev, y_dev, L.threads, L.lds, s));
       if (st == PAFC_SUCCESS) st = from_hip(hipEventRecord(E[k + 1], s));
     }
   }
