@@ -231,6 +231,15 @@ pafc_status pafc_profile_passes(pafc_plan_t p, const void* x_dev, void* y_dev,
                                 int* npass);
 
 /*
+ * pafc_twiddle -- the FP64 twiddle the planner uploads for w_n^e =
+ * exp(-2 pi i e / n) (host only): evaluated in long double with exact
+ * reduction of 8e/n to an octant, so that +-1, +-i and (+-1 +-i)/sqrt(2) are
+ * exact, then rounded once to double.  PAFC_C64 plans use the float rounding
+ * of these values.  Errors: INVALID_VALUE (n < 1, NULL outputs).
+ */
+pafc_status pafc_twiddle(int64_t n, int64_t e, double* re, double* im);
+
+/*
  * pafc_stream_copy -- a plain streaming copy of `bytes` bytes (multiple of
  * 16) from src_dev to dst_dev on hip_stream.  Not part of the convolution:
  * it is the reference kernel of known traffic used to calibrate hardware

@@ -41,7 +41,7 @@ EXPORTS = ("pafc_plan", "pafc_set_filter", "pafc_convolve", "pafc_forward",
            "pafc_batch_plan", "pafc_batch_set_filter", "pafc_batch_convolve",
            "pafc_batch_destroy", "pafc_batch_device_bytes",
            "pafc_batch_describe", "pafc_set_tuning", "pafc_profile_passes",
-           "pafc_stream_copy", "pafc_batch_profile")
+           "pafc_stream_copy", "pafc_batch_profile", "pafc_twiddle")
 
 
 class PafcError(RuntimeError):
@@ -85,6 +85,8 @@ def lib():
             "pafc_batch_describe": [vp, ctypes.c_char_p, sz, ctypes.POINTER(sz)],
             "pafc_set_tuning": [ctypes.c_char_p],
             "pafc_stream_copy": [vp, vp, sz, vp],
+            "pafc_twiddle": [ctypes.c_int64, ctypes.c_int64, ctypes.POINTER(ctypes.c_double),
+                             ctypes.POINTER(ctypes.c_double)],
             "pafc_batch_profile": [vp, vp, vp, vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
                                    ctypes.POINTER(ctypes.c_int64),
                                    ctypes.POINTER(ctypes.c_double), ip],
@@ -180,6 +182,13 @@ def describe(dims, dtype="c128", radix=None, variant="perm_free"):
                              ctypes.byref(need))
     _check(st, "pafc_describe")
     return json.loads(buf.value.decode())
+
+
+def twiddle(n, e):
+    """The FP64 twiddle w_n^e the planner generates (host only)."""
+    re, im = ctypes.c_double(), ctypes.c_double()
+    _check(lib().pafc_twiddle(int(n), int(e), ctypes.byref(re), ctypes.byref(im)), "pafc_twiddle")
+    return complex(re.value, im.value)
 
 
 def stream_copy(src, dst, stream=None):

@@ -1169,6 +1169,12 @@ pafc_status pafc_inverse(pafc_plan_t p, const void* z_dev, void* y_dev, void* hi
   return from_hip(launch_scale(p->P.dtype == PAFC_C128, y_dev, p->P.N, 1.0 / (double)p->P.N, s));
 }
 
+pafc_status pafc_twiddle(int64_t n, int64_t e, double* re, double* im) {
+  if (n < 1 || !re || !im) return PAFC_ERROR_INVALID_VALUE;
+  omega64(n, e, re, im);
+  return PAFC_SUCCESS;
+}
+
 pafc_status pafc_stream_copy(const void* src_dev, void* dst_dev, size_t bytes, void* hip_stream) {
   if (!src_dev || !dst_dev || (bytes % 16) != 0) return PAFC_ERROR_INVALID_VALUE;
   if (((uintptr_t)src_dev & 15) || ((uintptr_t)dst_dev & 15)) return PAFC_ERROR_INVALID_VALUE;

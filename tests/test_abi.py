@@ -120,3 +120,58 @@ def test_every_descriptor_passes_the_host_bounds_check():
             pafc.describe((a, b), dt)
         for a, b, c in itertools.product([2, 32, 81, 256], [3, 48, 256], [2, 100, 256]):
             pafc.describe((a, b, c), dt)
+
+
+def _exact_omega(n, e, digits=40):
+    """cos/sin of 2 pi e / n to `digits` digits with the decimal module."""
+    from decimal import Decimal, getcontext
+    getcontext().prec = digits + 10
+    pi = Decimal(0)
+    # Machin's formula
+    def atan_inv(x):
+        x = Decimal(x)
+        t, k, s = 1 / x, 0, Decimal(0)
+        while True:
+            term = t / (2 * k + 1) * (-1) ** k
+            if abs(term) < Decimal(10) ** -(digits + 5):
+                break
+            s += term
+            t /= x * x
+            k += 1
+        return s
+    pi = 16 * atan_inv(5) - 4 * atan_inv(239)
+    a = 2 * pi * (e % n) / n
+    c, s_, term, k = Decimal(0), Decimal(0), Decimal(1), 0
+    while abs(term) > Decimal(10) ** -(digits + 5) or k < 4:
+        c += term
+        k += 2
+        term = -term * a * a / (k * (k - 1))
+    term, k = a, 1
+    while abs(term) > Decimal(10) ** -(digits + 5):
+        s_ += term
+        k += 2
+        term = -term * a * a / (k * (k - 1))
+    return float(c), float(-s_)
+
+
+def test_twiddles_exact_points_and_rounding():
+    """Twiddle generation: exact at multiples of pi/4, correctly rounded (to
+    within 1 ulp) elsewhere, conjugate-symmetric."""
+    import math
+    for n in (8, 16, 256, 4096, 2187, 3125, 1953125, 65536 * 3):
+        for k in range(8):
+            if (k * n) % 8:
+                continue
+            w = pafc.twiddle(n, k * n // 8)
+            h = math.sqrt(0.5)
+            ref = [(1, 0), (h, -h), (0, -1), (-h, -h), (-1, 0), (-h, h), (0, 1), (h, h)][k]
+            assert w.real == ref[0] and w.imag == ref[1], (n, k, w)
+    rng = np.random.default_rng(0)
+    for n in (3, 5, 27, 2187, 3125, 78125, 1953125):
+        for e in rng.integers(0, n, 12):
+            w = pafc.twiddle(n, int(e))
+            c, s = _exact_omega(n, int(e))
+            assert abs(w.real - c) <= math.ulp(max(abs(c), 1e-300)) and \
+                abs(w.imag - s) <= math.ulp(max(abs(s), 1e-300)), (n, e)
+            wc = pafc.twiddle(n, n - int(e))
+            assert wc.real == w.real and wc.imag == -w.imag or e == 0
