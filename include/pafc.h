@@ -258,9 +258,10 @@ pafc_status pafc_stream_copy(const void* src_dev, void* dst_dev, size_t bytes,
  * length (one filter per size class).  Inputs and outputs are packed: the
  * elements of problem i start at offset sum_{j<i} sizes[j] of one device
  * array.  The batch owns per-size-class plans (radix splits and tiles chosen
- * by the planner, or from the tuning table set by pafc_batch_tune_hint) and
- * a device work list; pafc_batch_convolve enqueues one launch per pass level
- * (at most three), which a caller may capture in a hipGraph.
+ * by the planner, or from the table set by pafc_set_tuning) and a device
+ * work list; pafc_batch_convolve enqueues, for each pass level in turn (at
+ * most three), one launch per register class and LDS-bound occupancy
+ * present, which a caller may capture in a hipGraph.
  * Errors: INVALID_VALUE, UNSUPPORTED_SIZE, OUT_OF_MEMORY, DEVICE.
  */
 typedef struct pafc_batch_s* pafc_batch_t;
@@ -286,11 +287,12 @@ pafc_status pafc_batch_device_bytes(pafc_batch_t b, size_t* bytes);
 
 /*
  * pafc_batch_profile -- run pafc_batch_convolve `reps` times with a hipEvent
- * around every launch (one launch per pass level), synchronise, and report
- * the mean ms of each level, its algorithmic HBM bytes (one read and one
- * write of every element of every problem in the level, plus each filter
- * spectrum once in the level that multiplies by it), and the ms of every
- * repetition (ms_per_rep may be NULL).  *nlevel: capacity in, count out.
+ * around every launch (one launch per pass level, register class and
+ * LDS-bound occupancy: at most 72), synchronise, and report the mean ms of
+ * each launch, its algorithmic HBM bytes (one read and one write of every
+ * element of every problem in the launch, plus each filter spectrum once in
+ * the launch that multiplies by it), and the ms of every repetition
+ * (ms_per_rep may be NULL).  *nlevel: capacity in, count out.
  * Errors: as pafc_batch_convolve; INVALID_VALUE if the capacity is too small.
  */
 pafc_status pafc_batch_profile(pafc_batch_t b, const void* x_dev, void* y_dev,

@@ -351,9 +351,9 @@ class Batch:
         """Run `reps` batched convolutions with a HIP event around every
         launch.  Returns (mean ms per level, algorithmic bytes per level, ms of
         every repetition)."""
-        n = ctypes.c_int(8)
-        ms = (ctypes.c_double * 8)()
-        by = (ctypes.c_int64 * 8)()
+        n = ctypes.c_int(72)
+        ms = (ctypes.c_double * 72)()
+        by = (ctypes.c_int64 * 72)()
         per = (ctypes.c_double * int(reps))()
         _check(lib().pafc_batch_profile(self._h, ctypes.c_void_p(x.data_ptr()),
                                         ctypes.c_void_p(out.data_ptr()), _stream(stream),

@@ -24,6 +24,19 @@ __device__ __forceinline__ void st_g(void* p, int64_t idx, cx<T> v) {
   reinterpret_cast<cx<T>*>(p)[idx] = v;
 }
 
+// Element `idx` of an array smaller than 4 GiB: a 32-bit byte offset from the
+// uniform base pointer lets the compiler address it with one VGPR (global
+// access with a scalar base) instead of a 64-bit address pair per access.
+template <typename T>
+__device__ __forceinline__ cx<T> ld_g32(const void* p, uint32_t idx) {
+  return *reinterpret_cast<const cx<T>*>(reinterpret_cast<const char*>(p) +
+                                         idx * (uint32_t)sizeof(cx<T>));
+}
+template <typename T>
+__device__ __forceinline__ void st_g32(void* p, uint32_t idx, cx<T> v) {
+  *reinterpret_cast<cx<T>*>(reinterpret_cast<char*>(p) + idx * (uint32_t)sizeof(cx<T>)) = v;
+}
+
 template <typename T>
 __device__ __forceinline__ cx<T> twiddle(const PassArgs& a, uint32_t E) {
   const cx<T>* lo = reinterpret_cast<const cx<T>*>(a.tw_lo);

@@ -62,11 +62,14 @@ constexpr size_t kLdsBudget = 160 * 1024;  // LDS per CU on gfx950
 //                 2 contiguous-tile stores, 4 strided-tile loads, 8 strided-
 //                 tile stores (default 13: all but contiguous stores)
 //   PAFC_TUNE_WC / PAFC_TUNE_WS  tile width of contiguous / strided tiles
+//   PAFC_TUNE_MID  axis that carries the fused product (default 0, the slowest)
+//   PAFC_WIDE      0 disables the wide (1024-thread) register class
 int env_int(const char* name, int dflt) {
   const char* v = getenv(name);
   return v && *v ? atoi(v) : dflt;
 }
-constexpr uint32_t kMaxThreads = 256;
+constexpr uint32_t kMaxThreads = 256;       // register classes 0 and 1
+constexpr uint32_t kMaxWideThreads = 1024;  // register class 2 (groups R <= 9)
 
 // ------------------------------------------------------------- tuning table
 
@@ -462,8 +465,14 @@ bool make_pass(const Seg& s, int kind, size_t elem, Pass* p) {
     bool uni = !groups.empty();
     for (auto& gr : groups) uni = uni && gr == groups[0];
     const int ng = (int)groups.size();
+    // it also addresses with 32-bit byte offsets: the span of elements the
+    // pass touches must stay below 4 GiB
+    const uint64_t span = (uint64_t)(s.nouter - 1) * (uint64_t)s.S_o +
+                          (uint64_t)(s.L - 1) * (uint64_t)s.S_i +
+                          (uint64_t)(s.ncols - 1) * (uint64_t)s.S_c + 1;
     bool ok = env_int("PAFC_PIPE", 1) != 0 && uni && pipe_supported(groups[0].first, groups[0].second, ng) &&
-              s.col_in_j == 0 && s.jmul == 1 && s.n_tw == (int64_t)s.L;
+              s.col_in_j == 0 && s.jmul == 1 && s.n_tw == (int64_t)s.L &&
+              span * elem <= 0xFFFFFFFFull;
     for (uint32_t i = 0; ok && i < a.nops; ++i) ok = a.ops[i].nitems == p->threads;
     if (ok) {
       p->pipe = true;
@@ -473,6 +482,23 @@ bool make_pass(const Seg& s, int kind, size_t elem, Pass* p) {
       p->pipe_kind = kind;
       const uint64_t LW = a.LW;
       p->pipe_lds = (size_t)(((LW + (LW >> 4) + 2) & ~1ull) + s.L) * elem;
+    }
+  }
+  // wide register class: every group R <= 9 and every op at least two full
+  // rounds of a 256-thread block -> (nearly) one item per thread, up to 1024
+  // threads.  Ops with fewer items would leave most of a wide block idle and
+  // cost resident blocks (measured slower), so they stay in the small class.
+  if (!p->pipe) {
+    int maxR = 0;
+    uint32_t maxitems = 0, minitems = UINT32_MAX;
+    for (uint32_t i = 0; i < a.nops; ++i) {
+      maxR = std::max(maxR, (int)a.ops[i].R);
+      maxitems = std::max(maxitems, a.ops[i].nitems);
+      minitems = std::min(minitems, a.ops[i].nitems);
+    }
+    if (maxR <= 9 && minitems >= 2 * kMaxThreads && env_int("PAFC_WIDE", 1) != 0) {
+      p->cls = 2;
+      p->threads = std::min<uint32_t>(kMaxWideThreads, ((maxitems + 63) / 64) * 64);
     }
   }
   char buf[160];
@@ -657,7 +683,9 @@ pafc_status plan_core(PlanCore& P, int ndim, const int64_t* dims, const int* rad
       P.tw[s.n_tw] = t;
     }
   // pass sequences
-  const int mid = 0;  // the slowest axis: its (most strided) pass is touched once
+  // the axis whose last piece carries the fused product: by default the
+  // slowest axis, so its (most strided) pass is touched once
+  const int mid = std::min(ndim - 1, std::max(0, env_int("PAFC_TUNE_MID", 0)));
   P.middle = mid;
   auto add = [&](std::vector<Pass>& v, const Seg& s, int kind) -> bool {
     Pass p;
@@ -1234,6 +1262,7 @@ struct pafc_batch_s {
   PassArgs* d_descs = nullptr;
   BatchTile* d_tiles = nullptr;
   struct Level {  // one launch: the tiles of one pass level in one register class
+                  // whose LDS needs allow the same number of resident blocks
     int level = 0;
     uint32_t first = 0, count = 0, threads = 64;
     size_t lds = 0;
@@ -1322,16 +1351,20 @@ pafc_status pafc_batch_plan(pafc_batch_t* out, int count, const int64_t* sizes,
       dcls.push_back(conv[l].cls);
     }
   }
-  // tiles per (level, register class) launch, longest problems first; the
-  // tiles of one level are independent, so splitting a level by class only
-  // lets each part run with its own kernel's occupancy
+  // tiles per (level, register class, LDS occupancy) launch, longest
+  // problems first.  The tiles of one level are independent, so splitting a
+  // level only lets each part run with its own kernel's register occupancy
+  // and with the dynamic LDS of its own largest tile (a launch's LDS size is
+  // the maximum over its tiles, and sets how many blocks fit on a CU).
   std::vector<int> order((size_t)count);
   for (int i = 0; i < count; ++i) order[(size_t)i] = i;
   std::stable_sort(order.begin(), order.end(),
                    [&](int x, int y) { return b->sizes[(size_t)x] > b->sizes[(size_t)y]; });
+  auto blocks_per_cu = [](size_t lds) { return (int)std::min<size_t>(8, kLdsBudget / std::max<size_t>(lds, 1)); };
   std::vector<BatchTile> tiles;
   for (int l = 0; l < 3; ++l) {
-    for (int cls = 0; cls < 2; ++cls) {
+    for (int cls = 0; cls < 3; ++cls)
+    for (int bpc = 1; bpc <= 8; ++bpc) {
       pafc_batch_s::Level L;
       L.level = l;
       L.cls = cls;
@@ -1341,6 +1374,7 @@ pafc_status pafc_batch_plan(pafc_batch_t* out, int count, const int64_t* sizes,
         const int f = b->fid[(size_t)i];
         auto it = didx.find({f, l});
         if (it == didx.end() || dcls[it->second] != cls) continue;
+        if (blocks_per_cu(dlds[it->second]) != bpc) continue;
         const PassArgs& a = descs[it->second];
         for (uint32_t t = 0; t < a.ntiles; ++t)
           tiles.push_back(BatchTile{it->second, t, b->offsets[(size_t)i]});

@@ -25,7 +25,7 @@
 namespace pafc {
 
 template <typename T, int CLS>
-__global__ void __launch_bounds__(256) pass_kernel(const PassArgs* __restrict__ desc,
+__global__ void __launch_bounds__(class_max_threads<CLS>()) pass_kernel(const PassArgs* __restrict__ desc,
                                                    const void* in, void* out) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
@@ -35,7 +35,7 @@ __global__ void __launch_bounds__(256) pass_kernel(const PassArgs* __restrict__ 
 // Batched form: block b processes work item tiles[first + b]; the pass
 // descriptors of all size classes sit in device memory.
 template <typename T, int CLS>
-__global__ void __launch_bounds__(256) batch_kernel(const PassArgs* __restrict__ descs,
+__global__ void __launch_bounds__(class_max_threads<CLS>()) batch_kernel(const PassArgs* __restrict__ descs,
                                                     const BatchTile* __restrict__ tiles,
                                                     uint32_t first, const void* in, void* out) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -199,11 +199,11 @@ static hipError_t launch_pass_t(const PassArgs* d_desc, uint32_t ntiles, const v
 
 hipError_t launch_pass(bool dbl, int cls, const PassArgs* d_desc, uint32_t ntiles, const void* in,
                        void* out, uint32_t threads, size_t lds_bytes, hipStream_t s) {
-  if (dbl)
-    return cls ? launch_pass_t<double, 1>(d_desc, ntiles, in, out, threads, lds_bytes, s)
-               : launch_pass_t<double, 0>(d_desc, ntiles, in, out, threads, lds_bytes, s);
-  return cls ? launch_pass_t<float, 1>(d_desc, ntiles, in, out, threads, lds_bytes, s)
-             : launch_pass_t<float, 0>(d_desc, ntiles, in, out, threads, lds_bytes, s);
+  if (cls < 0 || cls > 2 || threads > (cls == 2 ? 1024u : 256u)) return hipErrorInvalidValue;
+#define PAFC_LP(TT, CC) launch_pass_t<TT, CC>(d_desc, ntiles, in, out, threads, lds_bytes, s)
+  if (dbl) return cls == 0 ? PAFC_LP(double, 0) : cls == 1 ? PAFC_LP(double, 1) : PAFC_LP(double, 2);
+  return cls == 0 ? PAFC_LP(float, 0) : cls == 1 ? PAFC_LP(float, 1) : PAFC_LP(float, 2);
+#undef PAFC_LP
 }
 
 template <typename T, int CLS>
@@ -225,11 +225,12 @@ hipError_t launch_batch(bool dbl, int cls, const PassArgs* descs, const BatchTil
                         uint32_t first, uint32_t count, const void* in, void* out,
                         uint32_t threads, size_t lds_bytes, hipStream_t s) {
   if (count == 0) return hipSuccess;
-  if (dbl)
-    return cls ? launch_batch_t<double, 1>(descs, tiles, first, count, in, out, threads, lds_bytes, s)
-               : launch_batch_t<double, 0>(descs, tiles, first, count, in, out, threads, lds_bytes, s);
-  return cls ? launch_batch_t<float, 1>(descs, tiles, first, count, in, out, threads, lds_bytes, s)
-             : launch_batch_t<float, 0>(descs, tiles, first, count, in, out, threads, lds_bytes, s);
+  if (cls < 0 || cls > 2 || threads > (cls == 2 ? 1024u : 256u)) return hipErrorInvalidValue;
+#define PAFC_LB(TT, CC) \
+  launch_batch_t<TT, CC>(descs, tiles, first, count, in, out, threads, lds_bytes, s)
+  if (dbl) return cls == 0 ? PAFC_LB(double, 0) : cls == 1 ? PAFC_LB(double, 1) : PAFC_LB(double, 2);
+  return cls == 0 ? PAFC_LB(float, 0) : cls == 1 ? PAFC_LB(float, 1) : PAFC_LB(float, 2);
+#undef PAFC_LB
 }
 
 static uint32_t grid_for(int64_t n) {

@@ -59,8 +59,16 @@ __device__ __forceinline__ Item item_of(uint32_t tid, uint32_t W, uint32_t logW,
   return it;
 }
 
+// Two-group forward passes fit two waves per SIMD without spilling and run
+// faster when compiled for it; the middle and inverse passes (and longer
+// forward ones) need more registers for their prefetch buffers, spill under
+// that bound, and keep the compiler's own choice.
+template <int KIND, int NG>
+constexpr int pipe_waves_per_eu() { return KIND == PIPE_FWD && NG == 2 ? 2 : 1; }
+
 template <typename T, int r, int g, int NG, int KIND, int MODE>
-__global__ void __launch_bounds__(256) pipe_kernel(const PassArgs* __restrict__ desc,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(pipe_waves_per_eu<KIND, NG>())))
+pipe_kernel(const PassArgs* __restrict__ desc,
                                                    const void* __restrict__ in,
                                                    void* __restrict__ out) {
   constexpr int R = ipow(r, g);
@@ -75,6 +83,12 @@ __global__ void __launch_bounds__(256) pipe_kernel(const PassArgs* __restrict__ 
   // forward (its last group has leg stride 1: store the tile linearly)
   constexpr bool LINEAR_STORE = (MODE == MODE_CONTIG && KIND == PIPE_FWD);
 
+  // Prefetch schedule.  FP64: the next tile's inputs are requested in the
+  // first op and the next tile's filter values in the middle op, so both are
+  // in flight for a whole tile.  FP32: this tile's filter values in the first
+  // op and the next tile's inputs in the last op, which keeps fewer prefetch
+  // registers live (measured faster in FP32, slower in FP64).
+  constexpr bool PF_LATE = sizeof(T) == 4;
   const PassArgs& a = *desc;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
@@ -91,11 +105,14 @@ __global__ void __launch_bounds__(256) pipe_kernel(const PassArgs* __restrict__ 
     for (uint32_t e = tid; e < (uint32_t)L; e += nthr) tw[e] = lo[e];
   }
 
-  auto tile_base = [&](uint32_t tile, uint32_t& col0) -> int64_t {
+  // every array this kernel touches is below 4 GiB (the planner checks), so
+  // element indices and byte offsets are 32-bit
+  const uint32_t S_i = (uint32_t)a.S_i, S_c = (uint32_t)a.S_c, S_o = (uint32_t)a.S_o;
+  auto tile_base = [&](uint32_t tile, uint32_t& col0) -> uint32_t {
     const uint32_t o = fdiv(tile, a.divTiles);
     const uint32_t cb = tile - o * a.tiles_per_slice;
     col0 = cb * W;
-    return (int64_t)o * a.S_o + (int64_t)col0 * a.S_c;
+    return o * S_o + col0 * S_c;
   };
 
   // prefetch registers: the first op's inputs (or this thread's share of the
@@ -106,12 +123,12 @@ __global__ void __launch_bounds__(256) pipe_kernel(const PassArgs* __restrict__ 
 
   auto fetch_x = [&](uint32_t tile) {
     uint32_t col0;
-    const int64_t base = tile_base(tile, col0);
+    const uint32_t base = tile_base(tile, col0);
     if constexpr (LINEAR_LOAD) {
       static_for<R>([&](auto q) {
         const uint32_t x = tid + nthr * q.value;
         const uint32_t c = x / (uint32_t)L, i = x - c * (uint32_t)L;
-        pre[q.value] = (col0 + c < a.ncols) ? ld_g<T>(in, base + (int64_t)i + (int64_t)c * a.S_c)
+        pre[q.value] = (col0 + c < a.ncols) ? ld_g32<T>(in, base + i + c * S_c)
                                             : cx<T>{(T)0, (T)0};
       });
     } else {
@@ -119,22 +136,22 @@ __global__ void __launch_bounds__(256) pipe_kernel(const PassArgs* __restrict__ 
       constexpr int K0 = L / ipow(R, k0);
       constexpr int S0 = K0 / R;
       const Item it = item_of<R, L, K0, MODE>(tid, W, logW, col0, a.ncols);
-      const int64_t gb = base + (int64_t)it.i0 * a.S_i + (int64_t)it.c * a.S_c;
+      const uint32_t gb = base + it.i0 * S_i + it.c * S_c;
       static_for<R>([&](auto s) {
         // DIF reads natural positions, DIT reads digit-reversed ones
         constexpr int p = Sh::type(0) == OP_DIT ? digrev<r, g>(s.value) : s.value;
-        pre[s.value] = it.valid ? ld_g<T>(in, gb + (int64_t)(p * S0) * a.S_i) : cx<T>{(T)0, (T)0};
+        pre[s.value] = it.valid ? ld_g32<T>(in, gb + (uint32_t)(p * S0) * S_i) : cx<T>{(T)0, (T)0};
       });
     }
   };
   auto fetch_h = [&](uint32_t tile) {
     if constexpr (KIND == PIPE_MID) {
       uint32_t col0;
-      const int64_t base = tile_base(tile, col0);
+      const uint32_t base = tile_base(tile, col0);
       const Item it = item_of<R, L, R, MODE>(tid, W, logW, col0, a.ncols);
-      const int64_t gb = base + (int64_t)it.i0 * a.S_i + (int64_t)it.c * a.S_c;
+      const uint32_t gb = base + it.i0 * S_i + it.c * S_c;
       static_for<R>([&](auto m) {
-        preh[m.value] = it.valid ? ld_g<T>(a.H, gb + (int64_t)digrev<r, g>(m.value) * a.S_i)
+        preh[m.value] = it.valid ? ld_g32<T>(a.H, gb + (uint32_t)digrev<r, g>(m.value) * S_i)
                                  : cx<T>{(T)0, (T)0};
       });
     }
@@ -143,17 +160,18 @@ __global__ void __launch_bounds__(256) pipe_kernel(const PassArgs* __restrict__ 
   uint32_t tile = blockIdx.x;
   if (tile < a.ntiles) {
     fetch_x(tile);
-    fetch_h(tile);
+    if constexpr (!PF_LATE) fetch_h(tile);
   }
   __syncthreads();  // twiddles visible
 
   while (tile < a.ntiles) {
     const uint32_t next = tile + gridDim.x;
     uint32_t col0;
-    const int64_t base = tile_base(tile, col0);
+    const uint32_t base = tile_base(tile, col0);
     if constexpr (LINEAR_LOAD) {
       static_for<R>([&](auto q) { lds[lds_phys(tid + nthr * q.value)] = pre[q.value]; });
-      if (next < a.ntiles) fetch_x(next);  // pre is free again
+      if constexpr (!PF_LATE)
+        if (next < a.ntiles) fetch_x(next);  // pre is free again
       __syncthreads();
     }
     static_for<NOPS>([&](auto opi) {
@@ -166,7 +184,7 @@ __global__ void __launch_bounds__(256) pipe_kernel(const PassArgs* __restrict__ 
       constexpr bool last = (i == NOPS - 1) && !LINEAR_STORE;
       const Item it = item_of<R, L, K, MODE>(tid, W, logW, col0, a.ncols);
       const uint32_t lbase = it.i0 * ls_i + it.c * ls_c;
-      const int64_t gb = base + (int64_t)it.i0 * a.S_i + (int64_t)it.c * a.S_c;
+      const uint32_t gb = base + it.i0 * S_i + it.c * S_c;
       cx<T> v[R];
       // inputs
       static_for<R>([&](auto s) {
@@ -176,7 +194,14 @@ __global__ void __launch_bounds__(256) pipe_kernel(const PassArgs* __restrict__ 
         else
           v[s.value] = lds[lds_phys(lbase + (uint32_t)(p * S) * ls_i)];
       });
-      if constexpr (i == 0 && !LINEAR_LOAD) {
+      if constexpr (PF_LATE) {
+        // this tile's filter values are loaded while its first ops run; the
+        // next tile's inputs while its last op runs.  Each prefetch buffer
+        // is live for part of the tile only.
+        if constexpr (i == 0) fetch_h(tile);
+        if constexpr (i == NOPS - 1)
+          if (next < a.ntiles) fetch_x(next);
+      } else if constexpr (i == 0 && !LINEAR_LOAD) {
         // the inputs are in registers: start loading the next tile now
         if (next < a.ntiles) fetch_x(next);
       }
@@ -203,7 +228,8 @@ __global__ void __launch_bounds__(256) pipe_kernel(const PassArgs* __restrict__ 
       } else {  // MID
         Dft<R, r, false, T>::run(v);
         static_for<R>([&](auto m) { v[m.value] = cmul(v[m.value], preh[m.value]); });
-        if (next < a.ntiles) fetch_h(next);
+        if constexpr (!PF_LATE)
+          if (next < a.ntiles) fetch_h(next);
         Dft<R, r, true, T>::run(v);
       }
       // outputs
@@ -211,7 +237,7 @@ __global__ void __launch_bounds__(256) pipe_kernel(const PassArgs* __restrict__ 
         // DIF writes frequency m at its digit-reversed position
         constexpr int p = type == OP_DIF ? digrev<r, g>(s.value) : s.value;
         if constexpr (last) {
-          if (it.valid) st_g<T>(out, gb + (int64_t)(p * S) * a.S_i, v[s.value]);
+          if (it.valid) st_g32<T>(out, gb + (uint32_t)(p * S) * S_i, v[s.value]);
         } else {
           lds[lds_phys(lbase + (uint32_t)(p * S) * ls_i)] = v[s.value];
         }
@@ -222,7 +248,7 @@ __global__ void __launch_bounds__(256) pipe_kernel(const PassArgs* __restrict__ 
       static_for<R>([&](auto q) {
         const uint32_t x = tid + nthr * q.value;
         const uint32_t c = x / (uint32_t)L, i = x - c * (uint32_t)L;
-        if (col0 + c < a.ncols) st_g<T>(out, base + (int64_t)i + (int64_t)c * a.S_c, lds[lds_phys(x)]);
+        if (col0 + c < a.ncols) st_g32<T>(out, base + i + c * S_c, lds[lds_phys(x)]);
       });
     }
     __syncthreads();  // LDS free for the next tile

@@ -172,11 +172,16 @@ __device__ __forceinline__ void run_op(const PassArgs& a, const OpDesc& op, cons
 }
 
 // Register class of a kernel instance: CLS 0 holds the groups with R <= 16,
-// CLS 1 every group (R <= 32).  A group's register footprint sets the VGPR
-// count of the whole kernel, so the small class keeps occupancy for the
-// common radix-2/4/8 plans.
+// CLS 1 every group (R <= 32), both in blocks of up to 256 threads; CLS 2
+// the groups with R <= 9 in blocks of up to 1024 threads (at most 128 VGPRs).
+// A group's register footprint sets the VGPR count of the whole kernel, so
+// the small classes keep occupancy for the common radix-2/4/8 plans, and the
+// wide class gives short radix-3/5 groups one item per thread.
 template <int R, int CLS>
-constexpr bool kind_in_class() { return CLS == 1 || R <= 16; }
+constexpr bool kind_in_class() { return CLS == 1 || (CLS == 0 && R <= 16) || R <= 9; }
+
+template <int CLS>
+constexpr int class_max_threads() { return CLS == 2 ? 1024 : 256; }
 
 template <typename T, int TYPE, int CLS>
 __device__ __forceinline__ void dispatch_op(const PassArgs& a, const OpDesc& op,

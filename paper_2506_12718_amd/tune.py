@@ -9,9 +9,11 @@ that change only the schedule -- never the result:
   an inner (contiguous) pass;
 * W / Wo: the tile widths of the inner and outer pieces.
 
-The search is greedy coordinate descent from the planner's defaults: each
-coordinate in turn takes the candidate with the lowest measured time (ties
-within 2 % keep the current value).  Times come from HIP events around the
+The search is greedy coordinate descent, started from the better of the
+planner's defaults and the existing table's entry: each coordinate in turn
+takes the candidate with the lowest measured time (ties within 2 % keep the
+current value).  A time is the median wall time of one repetition (all of
+its launches and the gaps between them), from HIP events around the
 library's own launches (`Batch.profile_levels` for batched size classes,
 `Plan.profile_passes` for whole grids).  The result is a table in the format
 of `pafc_set_tuning`, written to ``tuning/<device>.txt`` and loaded by the
@@ -64,9 +66,9 @@ class Timer:
         x = torch.ones(n * count, dtype=self.tdt, device="cuda")
         y = torch.empty_like(x)
         B.convolve(x, out=y)
-        ms, _, _ = B.profile_levels(x, y, reps=self.reps)
+        _, _, per = B.profile_levels(x, y, reps=self.reps)
         B.close()
-        return sum(ms)
+        return float(np.median(per))
 
     def grid(self, dims, radix):
         torch = self.torch
@@ -76,9 +78,9 @@ class Timer:
         x = torch.ones(dims, dtype=self.tdt, device="cuda")
         y = torch.empty_like(x)
         P.convolve(x, out=y)
-        ms, _, _ = P.profile_passes(x, y, reps=self.reps)
+        _, _, per = P.profile_passes(x, y, reps=self.reps)
         P.close()
-        return sum(ms)
+        return float(np.median(per))
 
 
 def candidates(pafc, dt, n, key, cfg):
@@ -109,11 +111,32 @@ def candidates(pafc, dt, n, key, cfg):
     return []
 
 
-def tune_one(pafc, timer, dt, n, measure):
+def read_table(path):
+    """(dtype, n) -> config of an existing table (empty if there is none)."""
+    out = {}
+    if not path or not os.path.exists(path):
+        return out
+    for raw in open(path):
+        f = raw.split("#")[0].split()
+        if len(f) == 7:
+            out[(f[0], int(f[1]))] = dict(zip(("split", "W", "Wo", "g3", "g5"), map(int, f[2:])))
+    return out
+
+
+def tune_one(pafc, timer, dt, n, measure, prev=None):
     cfg = {"split": 0, "W": 0, "Wo": 0, "g3": 0, "g5": 0}
     pafc.set_tuning(None)
     best = measure()
     log = [("default", best)]
+    if prev and any(prev.values()):
+        try:
+            pafc.set_tuning(line(dt, n, prev))
+            t = measure()
+            log.append((line(dt, n, prev), t))
+            if t < best:
+                best, cfg = t, dict(prev)
+        except Exception as e:  # the planner no longer accepts it
+            log.append((line(dt, n, prev), "rejected: %s" % e))
     for key in ("g3", "g5", "split", "W", "Wo"):
         pafc.set_tuning(line(dt, n, cfg) if any(cfg.values()) else None)
         cands = candidates(pafc, dt, n, key, cfg)
@@ -138,8 +161,11 @@ def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--dtypes", nargs="+", default=["c128", "c64"])
     ap.add_argument("--out", default=DEFAULT_TABLE)
-    ap.add_argument("--reps", type=int, default=5)
+    ap.add_argument("--reps", type=int, default=7)
+    ap.add_argument("--prev", default=DEFAULT_TABLE,
+                    help="existing table whose entries are tried as starting points ('' for none)")
     a = ap.parse_args(argv)
+    prev = read_table(a.prev)
     os.environ["PAFC_NO_TUNING_TABLE"] = "1"
     import torch
     import paper_2506_12718_amd as pafc
@@ -156,7 +182,7 @@ def main(argv=None):
         jobs += [(n, (lambda n=n: timer.batch(n))) for n in BATCH_SIZES
                  if n not in [d[0] for d, _ in GRIDS]]
         for n, measure in jobs:
-            cfg, t, log = tune_one(pafc, timer, dt, n, measure)
+            cfg, t, log = tune_one(pafc, timer, dt, n, measure, prev.get((dt, n)))
             default_t = log[0][1]
             print(json.dumps({"dtype": dt, "n": n, "cfg": cfg, "ms": round(t, 5),
                               "default_ms": round(default_t, 5),
