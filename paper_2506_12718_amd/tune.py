@@ -123,7 +123,7 @@ def read_table(path):
     return out
 
 
-def tune_one(pafc, timer, dt, n, measure, prev=None):
+def tune_one(pafc, timer, dt, n, measure, prev=None, keys=("g3", "g5", "split", "W", "Wo")):
     cfg = {"split": 0, "W": 0, "Wo": 0, "g3": 0, "g5": 0}
     pafc.set_tuning(None)
     best = measure()
@@ -137,7 +137,7 @@ def tune_one(pafc, timer, dt, n, measure, prev=None):
                 best, cfg = t, dict(prev)
         except Exception as e:  # the planner no longer accepts it
             log.append((line(dt, n, prev), "rejected: %s" % e))
-    for key in ("g3", "g5", "split", "W", "Wo"):
+    for key in keys:
         pafc.set_tuning(line(dt, n, cfg) if any(cfg.values()) else None)
         cands = candidates(pafc, dt, n, key, cfg)
         for v in cands:
@@ -177,12 +177,20 @@ def main(argv=None):
     for dt in a.dtypes:
         timer = Timer(pafc, torch, dt, reps=a.reps)
         # whole grids first; a batched size class with the same axis length
-        # keeps the grid's entry (the table is keyed by axis length)
-        jobs = [(dims[0], (lambda d=dims, r=radix: timer.grid(d, r))) for dims, radix in GRIDS]
-        jobs += [(n, (lambda n=n: timer.batch(n))) for n in BATCH_SIZES
+        # keeps the grid's entry (the table is keyed by axis length).  The
+        # split field acts on 1-D plans only and the width candidates come
+        # from the 1-D plan's pieces, so a grid of more than one axis
+        # searches the register grouping alone.
+        one_d = ("g3", "g5", "split", "W", "Wo")
+        jobs = [(dims[0], (lambda d=dims, r=radix: timer.grid(d, r)),
+                 one_d if len(dims) == 1 else ("g3", "g5")) for dims, radix in GRIDS]
+        jobs += [(n, (lambda n=n: timer.batch(n)), one_d) for n in BATCH_SIZES
                  if n not in [d[0] for d, _ in GRIDS]]
-        for n, measure in jobs:
-            cfg, t, log = tune_one(pafc, timer, dt, n, measure, prev.get((dt, n)))
+        for n, measure, keys in jobs:
+            start = prev.get((dt, n))
+            if start is not None and keys != one_d:
+                start = dict(start, split=0, W=0, Wo=0)
+            cfg, t, log = tune_one(pafc, timer, dt, n, measure, start, keys)
             default_t = log[0][1]
             print(json.dumps({"dtype": dt, "n": n, "cfg": cfg, "ms": round(t, 5),
                               "default_ms": round(default_t, 5),
