@@ -110,8 +110,33 @@ def wl_serving(dtype_name):
                         "sides_3d": [32, 64, 81, 128, 243, 256]})
 
 
+def wl_aniso2d(dtype_name):
+    from paper_2506_12718_amd import inputs
+    shape = inputs.ANISO_2D
+    x, h = inputs.anisotropic_case(41, shape)
+    t = shape[0].bit_length() - 1
+    return dict(name="aniso2d_2p%d_%s" % (t, dtype_name), x=x, h=h, radix=[4, 2],
+                domain="spatial", rhos=[[4] * (t // 2), [2]],
+                config={"workload": "anisotropic 2-D convolution 2^%dx2, radix 4 on the long "
+                                    "axis, radix 2 on the short one" % t,
+                        "dims": list(shape), "radix": [4, 2]})
+
+
+def wl_aniso3d(dtype_name):
+    from paper_2506_12718_amd import inputs
+    shape = inputs.ANISO_3D
+    x, h = inputs.anisotropic_case(42, shape)
+    t = shape[0].bit_length() - 1
+    return dict(name="aniso3d_2p%d_%s" % (t, dtype_name), x=x, h=h, radix=[4, 2, 2],
+                domain="spatial", rhos=[[4] * (t // 2), [2], [2]],
+                config={"workload": "anisotropic 3-D convolution 2^%dx2x2, radix 4 on the long "
+                                    "axis, radix 2 on the short ones" % t,
+                        "dims": list(shape), "radix": [4, 2, 2]})
+
+
 WORKLOADS = {"conv3d": wl_conv3d, "conv1d": wl_conv1d, "conv2d": wl_conv2d, "conv1d5": wl_conv1d5,
-             "batched": wl_batched, "serving": wl_serving}
+             "batched": wl_batched, "serving": wl_serving, "aniso2d": wl_aniso2d,
+             "aniso3d": wl_aniso3d}
 
 
 def bench_serving(pafc, torch, wl, tdtype, args):
@@ -264,22 +289,54 @@ def bench_batched(pafc, torch, wl, tdtype, args):
     print(json.dumps(out), flush=True)
 
 
-def measure(pafc, torch, wl, tdtype, variant, steps, warmup):
+def conv_bytes(desc, filter_per_call):
+    """Algorithmic HBM bytes of one convolution; with the filter transformed
+    in the call, its forward passes (and, for the explicit variant, its
+    reversal) count too."""
+    b = desc["hbm_bytes_conv"]
+    if filter_per_call:
+        b += desc["hbm_bytes_forward"]
+        if desc.get("variant") == 1:  # explicit: the filter's reversal pass
+            b += 2 * desc["N"] * (16 if desc["dtype"] == "c128" else 8)
+    return b
+
+
+def measure(pafc, torch, wl, tdtype, variant, steps, warmup, filter_per_call=False):
     """Plan, set the filter, warm up, then time `steps` convolutions with a
-    HIP event around every kernel launch.  Returns a dict of results."""
+    HIP event around every kernel launch.  With `filter_per_call` the timed
+    calls are pafc_convolve_with_filter (the filter transformed in every
+    call, wall clock over the stream), and the per-launch events come from a
+    second run of the convolution passes alone.  Returns a dict of results."""
     plan = pafc.Plan(wl["x"].shape, tdtype, radix=wl["radix"], variant=variant)
     xd = torch.from_numpy(wl["x"]).to(tdtype).cuda()
     hd = torch.from_numpy(wl["h"]).to(tdtype).cuda()
     yd = torch.empty_like(xd)
     plan.set_filter(hd, domain=wl["domain"])
+    if filter_per_call:
+        for _ in range(warmup):
+            plan.convolve_with_filter(xd, hd, out=yd)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+        starts[0].record()
+        for k in range(steps):
+            plan.convolve_with_filter(xd, hd, out=yd)
+            starts[k + 1].record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        fpc_rep = [starts[k].elapsed_time(starts[k + 1]) for k in range(steps)]
+        ms_pass, bytes_pass, _ = plan.profile_passes(xd, yd, reps=max(5, steps // 2))
+        ms_rep = fpc_rep
+        plan.convolve_with_filter(xd, hd, out=yd)
+    else:
+        for _ in range(warmup):
+            plan.convolve(xd, out=yd)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ms_pass, bytes_pass, ms_rep = plan.profile_passes(xd, yd, reps=steps)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
     del hd
-    for _ in range(warmup):
-        plan.convolve(xd, out=yd)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ms_pass, bytes_pass, ms_rep = plan.profile_passes(xd, yd, reps=steps)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
     desc = pafc.describe(wl["x"].shape, "c128" if tdtype == torch.complex128 else "c64",
                          wl["radix"], variant)
     y = yd.cpu().numpy()
@@ -299,6 +356,9 @@ def main():
     ap.add_argument("--dtype", default="c128", choices=["c128", "c64"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing and error check")
     ap.add_argument("--no-compare", action="store_true", help="skip the comparison variants")
+    ap.add_argument("--filter-per-call", action="store_true",
+                    help="transform the filter inside every timed call (three transforms per "
+                         "convolution, as the paper times it)")
     ap.add_argument("--calibrate", action="store_true",
                     help="run only the plain streaming copy of 256 MiB (counter calibration)")
     args = ap.parse_args()
@@ -341,7 +401,11 @@ def main():
 
     print("bench: %s steps=%d warmup=%d" % (wl["name"], args.steps, args.warmup),
           file=sys.stderr, flush=True)
-    main_r = measure(pafc, torch, wl, tdtype, "perm_free", args.steps, args.warmup)
+    fpc = args.filter_per_call
+    if fpc and wl["domain"] != "spatial":
+        print("--filter-per-call needs a workload with a spatial filter", file=sys.stderr)
+        sys.exit(2)
+    main_r = measure(pafc, torch, wl, tdtype, "perm_free", args.steps, args.warmup, fpc)
     total_s = sum(main_r["ms_rep"]) / 1e3
     value = args.steps / main_r["wall"]
     ms_step = main_r["wall"] * 1e3 / args.steps
@@ -363,7 +427,7 @@ def main():
             "all_passes": {"launches": len(kern), "alg_bytes": all_bytes,
                            "ms": round(all_ms, 5),
                            "achieved": round(all_bytes / (all_ms * 1e-3) / 1e9, 1)}}
-    alg_bytes = main_r["desc"]["hbm_bytes_conv"]
+    alg_bytes = conv_bytes(main_r["desc"], fpc)
     out = {
         "metric": "convolutions/s + HBM GB/s (% roofline), perm-free vs explicit-perm; p99 latency",
         "value": round(value, 3),
@@ -378,7 +442,7 @@ def main():
         "dtype": "f64" if args.dtype == "c128" else "f32",
         "data": "synthetic",
         "config": dict(wl["config"], variant="perm_free", dtype=args.dtype,
-                       passes=main_r["labels"]),
+                       passes=main_r["labels"], filter_per_call=fpc),
         "hbm_gbps_alg": round(alg_bytes * value / 1e9, 1),
         "hbm_frac_alg": round(alg_bytes * value / 1e9 / HBM_PEAK_GBS, 4),
         "alg_bytes_per_conv": alg_bytes,
@@ -392,14 +456,14 @@ def main():
         comp = {}
         for variant in ("explicit_perm", "perm_free_unfused"):
             print("bench: comparison variant %s" % variant, file=sys.stderr, flush=True)
-            r = measure(pafc, torch, wl, tdtype, variant, max(5, args.steps // 2), 2)
+            r = measure(pafc, torch, wl, tdtype, variant, max(5, args.steps // 2), 2, fpc)
             v = len(r["ms_rep"]) / r["wall"]
             comp[variant] = {
                 "conv_per_s": round(v, 3),
                 "ms_per_conv": round(1e3 / v, 5),
                 "p99_ms": round(pct(r["ms_rep"], 99), 5),
-                "alg_bytes_per_conv": r["desc"]["hbm_bytes_conv"],
-                "hbm_gbps_alg": round(r["desc"]["hbm_bytes_conv"] * v / 1e9, 1),
+                "alg_bytes_per_conv": conv_bytes(r["desc"], fpc),
+                "hbm_gbps_alg": round(conv_bytes(r["desc"], fpc) * v / 1e9, 1),
                 "ms_per_pass": [round(t, 5) for t in r["ms_pass"]],
                 "passes": r["labels"],
                 "max_abs_diff_vs_perm_free": float(np.abs(r["y"] - main_r["y"]).max()),

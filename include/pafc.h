@@ -19,9 +19,10 @@
  *
  * where A_i^T is a decimation-in-frequency transform that leaves its output
  * in digit-reversed order, Hdr = (A_1^T (x) ... (x) A_d^T) vec(H) / N is the
- * filter spectrum held in that same order on the device, and conj A_i is a
- * decimation-in-time inverse that takes digit-reversed input and returns
- * natural order.  N = n_1 ... n_d.
+ * filter spectrum held in that same order on the device (kept as A^T h; the
+ * 1/N is applied with the product), and conj A_i is a decimation-in-time
+ * inverse that takes digit-reversed input and returns natural order.
+ * N = n_1 ... n_d.
  *
  * Conventions for every call:
  *   - Complex data are interleaved (re, im): PAFC_C64 = 2 x float (8 bytes
@@ -129,9 +130,10 @@ pafc_status pafc_plan(pafc_plan_t* out, int ndim, const int64_t* dims,
  *        natural frequency order.  The library copies what it needs (h is
  *        read only by work enqueued on hip_stream, so the caller may free or
  *        overwrite it once the stream has passed this call).
- * The plan keeps the spectrum scaled by 1/N -- the single normalisation of
- * the inverse transform -- in the digit-reversed order of its forward
- * transform (PAFC_EXPLICIT_PERM plans keep natural order).  The spatial
+ * The plan keeps the unscaled spectrum in the digit-reversed order of its
+ * forward transform (PAFC_EXPLICIT_PERM plans keep natural order); the single
+ * normalisation 1/N of the inverse transform is applied in the product with
+ * it, so setting a filter costs exactly one forward transform.  The spatial
  * filter is transformed with the plan's own forward passes
  * (Alg. alg:permutation-avoiding-convolution, first step); a natural-order
  * spectrum is reordered once, here, and never again.  Replaces any previous
@@ -156,6 +158,22 @@ pafc_status pafc_set_filter(pafc_plan_t p, const void* h_dev,
  */
 pafc_status pafc_convolve(pafc_plan_t p, const void* x_dev, void* y_dev,
                           void* hip_stream);
+
+/*
+ * pafc_convolve_with_filter -- y = x * h with the filter transformed inside
+ * the call: the evaluation of Alg. alg:permutation-avoiding-convolution as
+ * the paper times it, three transforms per call (forward of h, forward of
+ * x, inverse), for callers whose filter changes every call.  Equivalent to
+ * pafc_set_filter(p, h_dev, SPATIAL) followed by pafc_convolve, and leaves
+ * h as the plan's filter.
+ * h_dev: spatial filter, N elements, read only; x_dev, y_dev as for
+ * pafc_convolve (h_dev may not overlap y_dev).  Writes the plan's spectrum,
+ * so it must not overlap other work on the same plan.
+ * Errors: INVALID_VALUE (NULL or misaligned pointers), DEVICE.
+ */
+pafc_status pafc_convolve_with_filter(pafc_plan_t p, const void* x_dev,
+                                      const void* h_dev, void* y_dev,
+                                      void* hip_stream);
 
 /*
  * pafc_forward -- z = (A_1^T (x) ... (x) A_d^T) x: the forward transform

@@ -41,7 +41,8 @@ EXPORTS = ("pafc_plan", "pafc_set_filter", "pafc_convolve", "pafc_forward",
            "pafc_batch_plan", "pafc_batch_set_filter", "pafc_batch_convolve",
            "pafc_batch_destroy", "pafc_batch_device_bytes",
            "pafc_batch_describe", "pafc_set_tuning", "pafc_profile_passes",
-           "pafc_stream_copy", "pafc_batch_profile", "pafc_twiddle")
+           "pafc_stream_copy", "pafc_batch_profile", "pafc_twiddle",
+           "pafc_convolve_with_filter")
 
 
 class PafcError(RuntimeError):
@@ -69,6 +70,7 @@ def lib():
             "pafc_plan": [ctypes.POINTER(vp), ctypes.c_int, i64p, ip, ctypes.c_int, ctypes.c_int, vp],
             "pafc_set_filter": [vp, vp, ctypes.c_int, vp],
             "pafc_convolve": [vp, vp, vp, vp],
+            "pafc_convolve_with_filter": [vp, vp, vp, vp, vp],
             "pafc_forward": [vp, vp, vp, vp],
             "pafc_inverse": [vp, vp, vp, vp],
             "pafc_destroy": [vp],
@@ -263,6 +265,24 @@ class Plan:
     def convolve(self, x, out=None, stream=None):
         """y = x (*) h; ``out`` may be ``x`` (in place)."""
         return self._run(lib().pafc_convolve, x, out, stream, "pafc_convolve")
+
+    def convolve_with_filter(self, x, h, out=None, stream=None):
+        """y = x (*) h with h transformed inside the call (three transforms
+        per call); h becomes the plan's filter."""
+        import torch
+        self._check_tensor(x, "x")
+        self._check_tensor(h, "h")
+        if out is None:
+            out = torch.empty_like(x)
+        else:
+            self._check_tensor(out, "out")
+        if out.data_ptr() == h.data_ptr():
+            raise ValueError("out may not alias h")
+        _check(lib().pafc_convolve_with_filter(self._h, ctypes.c_void_p(x.data_ptr()),
+                                               ctypes.c_void_p(h.data_ptr()),
+                                               ctypes.c_void_p(out.data_ptr()), _stream(stream)),
+               "pafc_convolve_with_filter")
+        return out
 
     def profile_passes(self, x, out, reps=10, stream=None):
         """Run `reps` convolutions with a HIP event around every kernel launch

@@ -38,18 +38,19 @@ int pipe_blocks_per_cu(bool dbl, int r, int g, int ng, int kind, int mode, uint3
 hipError_t launch_pipe(bool dbl, int r, int g, int ng, int kind, int mode, const PassArgs* d,
                        uint32_t grid, uint32_t threads, size_t lds, const void* in, void* out,
                        hipStream_t s);
-hipError_t launch_mul(bool dbl, const void* x, const void* h, void* y, int64_t n, hipStream_t st);
+hipError_t launch_mul(bool dbl, const void* x, const void* h, void* y, int64_t n, double s,
+                      hipStream_t st);
 hipError_t launch_stream_copy(const void* src, void* dst, int64_t n16, hipStream_t st);
 hipError_t launch_permute_rows(bool dbl, const void* in, void* out, const void* h,
                                const int32_t* m0, const int32_t* m1, const int32_t* mlast,
                                uint32_t n0, uint32_t n1, uint32_t nlast, uint32_t rows_per_block,
-                               hipStream_t st);
+                               double s, hipStream_t st);
 hipError_t launch_permute_gather(bool dbl, const void* in, void* out, const void* h,
                                  const int32_t* m0, const int32_t* m1, const int32_t* m2,
-                                 uint32_t n0, uint32_t n1, uint32_t n2, hipStream_t st);
+                                 uint32_t n0, uint32_t n1, uint32_t n2, double s, hipStream_t st);
 hipError_t launch_permute_tile(bool dbl, const void* in, void* out, const void* h,
                                const int32_t* m0, const int32_t* m1, const int32_t* mlast,
-                               uint32_t n0, uint32_t n1, uint32_t log_nl, hipStream_t st);
+                               uint32_t n0, uint32_t n1, uint32_t log_nl, double s, hipStream_t st);
 }  // namespace pafc
 
 using namespace pafc;
@@ -64,6 +65,7 @@ constexpr size_t kLdsBudget = 160 * 1024;  // LDS per CU on gfx950
 //   PAFC_TUNE_WC / PAFC_TUNE_WS  tile width of contiguous / strided tiles
 //   PAFC_TUNE_MID  axis that carries the fused product (default 0, the slowest)
 //   PAFC_WIDE      0 disables the wide (1024-thread) register class
+//   PAFC_FOLD      0 keeps short faster axes in passes of their own
 int env_int(const char* name, int dflt) {
   const char* v = getenv(name);
   return v && *v ? atoi(v) : dflt;
@@ -218,6 +220,7 @@ struct Seg {  // one pass-sized piece of an axis transform
   uint32_t ncols = 1, nouter = 1, jmul = 1, col_in_j = 0;
   uint32_t jcdiv = 1;  // column -> inner position of an outer piece
   int64_t n_tw = 0;
+  bool tw_global = false;  // twiddles from the global table, no LDS copy
   std::vector<int> rho;  // this piece's stages, innermost first
   GroupCaps caps;
 };
@@ -312,22 +315,42 @@ void choose_width(Seg& s, size_t elem, int tuneW) {
   // ~4096 elements per tile; strided tiles also want >= 256 B row segments
   uint32_t W = pow2_floor(std::max<uint64_t>(1, 4096 / std::max<uint32_t>(1, s.L)));
   if (s.mode == MODE_STRIDED) W = std::max<uint32_t>(W, 16);
-  W = std::min<uint32_t>(W, 256);
+  // contiguous tiles of very short axes take more pencils (whole 4096-element
+  // tiles); other tiles stay within 256 columns
+  W = std::min<uint32_t>(W, s.mode == MODE_CONTIG && s.L < 16 ? 4096u : 256u);
   W = std::min<uint32_t>(W, pow2_floor(std::max<uint64_t>(1, s.ncols)));
   if (tuneW > 0) W = pow2_floor((uint64_t)tuneW);
   const int envW = env_int(s.mode == MODE_STRIDED ? "PAFC_TUNE_WS" : "PAFC_TUNE_WC", 0);
   if (envW > 0) W = std::min<uint32_t>(pow2_floor((uint64_t)envW),
                                        pow2_floor(std::max<uint64_t>(1, s.ncols)));
-  while (W > 1 && tile_lds_bytes((uint64_t)s.L * W, elem) + twl_bytes(s.n_tw, elem) > kLdsBudget)
-    W /= 2;
+  const size_t tw = s.tw_global ? 0 : twl_bytes(s.n_tw, elem);
+  while (W > 1 && tile_lds_bytes((uint64_t)s.L * W, elem) + tw > kLdsBudget) W /= 2;
   s.W = W;
 }
 
 bool fits_lds(int64_t L, size_t elem) { return tile_lds_bytes((uint64_t)L, elem) <= kLdsBudget; }
 
+// A piece reads its twiddles from the global (L2-resident) table instead of
+// an LDS copy when the copy would not fit beside a one-column tile, or when
+// it is larger than 64 KB (PAFC_TUNE_TWG bytes): staging it would cost more
+// than the tile's own data (measured: 2^24-long axes twice as fast with
+// global reads, the 48 KB tables of 5^9 faster in LDS).
+bool twiddles_global(int64_t L, int64_t n_tw, size_t elem) {
+  const size_t tw = twl_bytes(n_tw, elem);
+  const int lim = env_int("PAFC_TUNE_TWG", 64 * 1024);
+  return tile_lds_bytes((uint64_t)L, elem) + tw > kLdsBudget || (lim > 0 && tw > (size_t)lim);
+}
+
 // Build the op list of one pass over segment s.  kind: 0 = DIF only,
 // 1 = DIT only, 2 = DIF..., MID, ...DIT.
-bool build_ops(const Seg& s, int kind, PassArgs& a, int* cls) {
+// A short axis folded into a strided pass as a column op (see OpDesc).
+struct CrossAxis {
+  int r, g;     // its one register group: R = r^g = its length
+  uint32_t cs;  // its column stride within a tile row
+};
+
+bool build_ops(const Seg& s, int kind, PassArgs& a, int* cls,
+               const std::vector<CrossAxis>* cross = nullptr) {
   auto groups = group_runs(s.rho, s.caps);
   struct G { int r, g, R; uint32_t K, S; };
   std::vector<G> gs;
@@ -357,7 +380,31 @@ bool build_ops(const Seg& s, int kind, PassArgs& a, int* cls) {
     if (g.R > 16) *cls = 1;
     return op;
   };
+  auto mkx = [&](const CrossAxis& x, int type) {
+    OpDesc op;
+    memset(&op, 0, sizeof(op));
+    op.type = type;
+    op.kind = kind_of(x.r, x.g);
+    op.R = (int32_t)ipow64(x.r, x.g);
+    op.K = (uint32_t)op.R;
+    op.S = 1;
+    op.tw = 0;
+    op.nitems = s.L * (s.W / (uint32_t)op.R);
+    op.divS = make_fastdiv(1);
+    op.divNB = make_fastdiv(1);
+    op.cross = 1;
+    op.cs = x.cs;
+    op.divQ = make_fastdiv(s.W / (uint32_t)op.R);
+    op.divCs = make_fastdiv(x.cs);
+    if (op.R > 16) *cls = 1;
+    return op;
+  };
   std::vector<OpDesc> ops;
+  const bool folded = cross && !cross->empty();
+  if (folded) {
+    if (kind != 2 || s.mode != MODE_STRIDED || s.W != s.ncols) return false;
+    for (auto& x : *cross) ops.push_back(mkx(x, OP_DIF));
+  }
   if (kind == 0) {
     for (auto& g : gs) ops.push_back(mk(g, OP_DIF));
   } else if (kind == 1) {
@@ -367,6 +414,8 @@ bool build_ops(const Seg& s, int kind, PassArgs& a, int* cls) {
     ops.push_back(mk(gs.back(), OP_MID));
     for (size_t i = gs.size() - 1; i-- > 0;) ops.push_back(mk(gs[i], OP_DIT));
   }
+  if (folded)
+    for (auto it = cross->rbegin(); it != cross->rend(); ++it) ops.push_back(mkx(*it, OP_DIT));
   if ((int)ops.size() > kMaxOps) return false;
   for (auto& op : ops)
     if (op.kind < 0) return false;
@@ -378,8 +427,8 @@ bool build_ops(const Seg& s, int kind, PassArgs& a, int* cls) {
   const int io = env_int("PAFC_TUNE_IO", 13);
   const bool ld = s.mode == MODE_STRIDED ? (io & 4) : (io & 1);
   const bool st = s.mode == MODE_STRIDED ? (io & 8) : (io & 2);
-  ops.front().src_g = (ld && coalesced(ops.front())) ? 1 : 0;
-  ops.back().dst_g = (st && coalesced(ops.back())) ? 1 : 0;
+  ops.front().src_g = (ld && !ops.front().cross && coalesced(ops.front())) ? 1 : 0;
+  ops.back().dst_g = (st && !ops.back().cross && coalesced(ops.back())) ? 1 : 0;
   a.nops = (uint32_t)ops.size();
   for (size_t i = 0; i < ops.size(); ++i) a.ops[i] = ops[i];
   return true;
@@ -402,12 +451,22 @@ bool validate_pass(const PassArgs& a, int64_t extent, int64_t n_tw) {
   if (a.nops == 0 || a.nops > (uint32_t)kMaxOps) return false;
   // LDS twiddle tables: lo has 2^b entries, hi covers every exponent < n_tw,
   // and the flat source table is read at e << b < n_tw only
-  if (((int64_t)a.twl_nhi << a.twl_bits) < n_tw || (((int64_t)a.twl_nhi - 1) << a.twl_bits) >= n_tw)
-    return false;
-  if (((int64_t)1 << a.twl_bits) > n_tw && n_tw > 1) return false;
+  if (!a.twl_global) {
+    if (((int64_t)a.twl_nhi << a.twl_bits) < n_tw || (((int64_t)a.twl_nhi - 1) << a.twl_bits) >= n_tw)
+      return false;
+    if (((int64_t)1 << a.twl_bits) > n_tw && n_tw > 1) return false;
+  }
   uint32_t K = a.L;
   for (uint32_t k = 0; k < a.nops; ++k) {
     const OpDesc& op = a.ops[k];
+    if (op.cross) {  // legs hi*R*cs + p*cs + lo < W of one full tile row
+      if (a.mode != MODE_STRIDED || a.W != a.ncols || a.tiles_per_slice != 1) return false;
+      if (op.R < 2 || op.tw || op.src_g || op.dst_g || op.cs == 0) return false;
+      if (a.W % ((uint32_t)op.R * op.cs) != 0 || op.divCs.d != op.cs) return false;
+      if (op.divQ.d != a.W / (uint32_t)op.R || op.nitems != a.L * (a.W / (uint32_t)op.R)) return false;
+      if (op.type == OP_MID) return false;
+      continue;
+    }
     if (op.K == 0 || op.R < 2 || op.S * (uint32_t)op.R != op.K || a.L % op.K != 0) return false;
     if (op.nitems != (a.L / (uint32_t)op.R) * a.W) return false;
     if (op.Kf != op.K * a.jmul || (int64_t)op.Kf * op.escale != n_tw) return false;
@@ -419,7 +478,8 @@ bool validate_pass(const PassArgs& a, int64_t extent, int64_t n_tw) {
   return true;
 }
 
-bool make_pass(const Seg& s, int kind, size_t elem, Pass* p) {
+bool make_pass(const Seg& s, int kind, size_t elem, Pass* p,
+               const std::vector<CrossAxis>* cross = nullptr) {
   PassArgs& a = p->a;
   memset(&a, 0, sizeof(a));
   a.mode = s.mode;
@@ -438,13 +498,15 @@ bool make_pass(const Seg& s, int kind, size_t elem, Pass* p) {
   a.divL = make_fastdiv(s.L);
   a.divTiles = make_fastdiv(a.tiles_per_slice);
   a.divJc = make_fastdiv(s.jcdiv);
-  if (!build_ops(s, kind, a, &p->cls)) return false;
+  if (!build_ops(s, kind, a, &p->cls, cross)) return false;
   uint32_t maxitems = 0;
   for (uint32_t i = 0; i < a.nops; ++i) maxitems = std::max(maxitems, a.ops[i].nitems);
   uint32_t th = std::min<uint32_t>(kMaxThreads, ((maxitems + 63) / 64) * 64);
   p->threads = std::max<uint32_t>(64, th);
   // LDS copy of the twiddles, two-level with ~sqrt(n_tw) entries per level
-  // (the same split rule as the global table when that one is two-level)
+  // (the same split rule as the global table when that one is two-level),
+  // unless the piece reads the global table
+  a.twl_global = s.tw_global ? 1u : 0u;
   {
     uint32_t b = 0;
     while (((int64_t)1 << (2 * b)) < s.n_tw) ++b;
@@ -453,7 +515,7 @@ bool make_pass(const Seg& s, int kind, size_t elem, Pass* p) {
     const uint64_t LW = a.LW;
     a.twl_off = (uint32_t)((LW + (LW >> 4) + 2) & ~1ull);
   }
-  p->lds = (size_t)(a.twl_off + (1u << a.twl_bits) + a.twl_nhi) * elem;
+  p->lds = (size_t)(a.twl_off + (s.tw_global ? 0u : (1u << a.twl_bits) + a.twl_nhi)) * elem;
   if (p->lds > kLdsBudget) return false;
   p->tw_n = s.n_tw;
   p->mid = (kind == 2);
@@ -471,7 +533,8 @@ bool make_pass(const Seg& s, int kind, size_t elem, Pass* p) {
                           (uint64_t)(s.L - 1) * (uint64_t)s.S_i +
                           (uint64_t)(s.ncols - 1) * (uint64_t)s.S_c + 1;
     bool ok = env_int("PAFC_PIPE", 1) != 0 && uni && pipe_supported(groups[0].first, groups[0].second, ng) &&
-              s.col_in_j == 0 && s.jmul == 1 && s.n_tw == (int64_t)s.L &&
+              s.col_in_j == 0 && s.jmul == 1 && s.n_tw == (int64_t)s.L && !s.tw_global &&
+              !(cross && !cross->empty()) &&
               span * elem <= 0xFFFFFFFFull;
     for (uint32_t i = 0; ok && i < a.nops; ++i) ok = a.ops[i].nitems == p->threads;
     if (ok) {
@@ -505,13 +568,14 @@ bool make_pass(const Seg& s, int kind, size_t elem, Pass* p) {
   std::string ops;
   for (uint32_t i = 0; i < a.nops; ++i) {
     const OpDesc& o = a.ops[i];
-    snprintf(buf, sizeof(buf), "%s%s%d", i ? "," : "",
+    snprintf(buf, sizeof(buf), "%s%s%s%d", i ? "," : "", o.cross ? "X" : "",
              o.type == OP_DIF ? "DIF" : o.type == OP_DIT ? "DIT" : "MID", o.R);
     ops += buf;
   }
   snprintf(buf, sizeof(buf), "%s L=%u W=%u tiles=%u thr=%u [", s.mode == MODE_STRIDED ? "strided" : "contig",
            s.L, s.W, a.ntiles, p->threads);
   p->label = std::string(buf) + ops + "]";
+  if (s.tw_global) p->label += " twg";
 
   if (p->pipe) {
     char nm[96];
@@ -520,6 +584,104 @@ bool make_pass(const Seg& s, int kind, size_t elem, Pass* p) {
     p->label += nm;
   }
   return true;
+}
+
+// Pieces of one (sub-)axis of length n (stages rho, innermost first) at
+// element stride st, repeated over `outer` blocks spaced n*st apart.  Appends
+// the pieces outermost first; false if some piece cannot fit LDS.
+bool split_axis(int64_t n, const std::vector<int>& rho, int64_t st, int64_t outer, size_t elem,
+                const GroupCaps& caps, const TuneVal* tv, const TuneVal* tsplit,
+                std::vector<Seg>& segs) {
+  const int t = (int)rho.size();
+  auto tile16 = [&](int64_t L) { return tile_lds_bytes((uint64_t)L * 16, elem); };
+  int ti = 0;
+  int64_t ni = 1;
+  if (tsplit) {
+    while (ti < t && ni < tsplit->split) ni *= rho[ti++];
+    if (ni != tsplit->split) return false;
+  } else if (!fits_lds(n, elem) && st == 1) {
+    const size_t cap = elem == 16 ? 4096 : 8192;
+    while (ti < t - 1 && ni * rho[ti] <= (int64_t)cap) ni *= rho[ti++];
+  } else if (st > 1 && tile16(n) > 72 * 1024) {
+    while (ti < t - 1 && tile16(ni * rho[ti]) <= 72 * 1024) ni *= rho[ti++];
+    if (n / ni < 2) ti = 0, ni = 1;
+  }
+  // an outer piece that does not fit LDS, or whose tile would be narrower
+  // than 8 columns (row segments under 8 elements), takes fewer stages: the
+  // inner length grows, and is cut again below
+  auto outer_width = [&](int64_t L) {
+    Seg o;
+    o.mode = MODE_STRIDED;
+    o.L = (uint32_t)L;
+    o.ncols = (uint32_t)std::min<int64_t>(n / L * st, UINT32_MAX);
+    o.n_tw = n;
+    o.tw_global = twiddles_global(L, n, elem);
+    choose_width(o, elem, 0);
+    return o.W;
+  };
+  if (ti > 0 && !tsplit) {
+    if (!fits_lds(n / ni, elem)) {
+      // far too long for one outer piece: 16-column outer tiles within
+      // 72 KB, like every other strided pass
+      while (ti < t - 1 && tile16(n / ni) > 72 * 1024) ni *= rho[ti++];
+    } else {
+      while (ti < t - 1 && outer_width(n / ni) < 8) ni *= rho[ti++];
+    }
+  }
+  if (ti == 0) {
+    if (!fits_lds(n, elem)) return false;
+    Seg s;
+    s.L = (uint32_t)n;
+    s.rho = rho;
+    s.n_tw = n;
+    s.caps = caps;
+    if (st == 1) {
+      s.mode = MODE_CONTIG;
+      s.S_i = 1;
+      s.S_c = n;
+      s.ncols = (uint32_t)outer;
+      s.S_o = 0;
+      s.nouter = 1;
+    } else {
+      s.mode = MODE_STRIDED;
+      s.S_i = st;
+      s.S_c = 1;
+      s.ncols = (uint32_t)st;
+      s.S_o = n * st;
+      s.nouter = (uint32_t)outer;
+    }
+    if ((uint64_t)outer >= (1ull << 32) || (uint64_t)st >= (1ull << 32)) return false;
+    s.tw_global = twiddles_global(s.L, s.n_tw, elem);
+    choose_width(s, elem, tv ? tv->W : 0);
+    if (tile_lds_bytes(s.L * (uint64_t)s.W, elem) > kLdsBudget) return false;
+    segs.push_back(s);
+    return true;
+  }
+  const int64_t no = n / ni;
+  if (!fits_lds(no, elem) || ti == t) return false;
+  if ((uint64_t)ni * st >= (1ull << 32) || (uint64_t)outer * no >= (1ull << 32)) return false;
+  // element (o, i_o, i_i, f) of the sub-axis sits at
+  // o*n*st + i_o*ni*st + i_i*st + f
+  Seg so;  // outer: positions i_o < no at stride ni*st, columns (i_i, f)
+  so.mode = MODE_STRIDED;
+  so.L = (uint32_t)no;
+  so.S_i = ni * st;
+  so.S_c = 1;
+  so.ncols = (uint32_t)(ni * st);
+  so.S_o = n * st;
+  so.nouter = (uint32_t)outer;
+  so.jmul = (uint32_t)ni;
+  so.col_in_j = 1;
+  so.jcdiv = (uint32_t)st;
+  so.n_tw = n;
+  so.rho.assign(rho.begin() + ti, rho.end());
+  so.caps = caps;
+  so.tw_global = twiddles_global(so.L, so.n_tw, elem);
+  choose_width(so, elem, tv ? tv->Wo : 0);
+  segs.push_back(so);
+  // inner: an axis of length ni at stride st, one block per (o, i_o)
+  const std::vector<int> rin(rho.begin(), rho.begin() + ti);
+  return split_axis(ni, rin, st, outer * no, elem, caps, tv, nullptr, segs);
 }
 
 pafc_status plan_core(PlanCore& P, int ndim, const int64_t* dims, const int* radix, int dtype,
@@ -558,9 +720,7 @@ pafc_status plan_core(PlanCore& P, int ndim, const int64_t* dims, const int* rad
     ax.posinv.assign((size_t)ax.n, 0);
     for (int64_t k = 0; k < ax.n; ++k) ax.posinv[(size_t)ax.pos[(size_t)k]] = (int32_t)k;
   }
-  // Segments: every axis of a 2-D/3-D grid is one pass; a 1-D transform too
-  // long for LDS is cut into an outer piece (its outermost stages, strided
-  // over the inner length) and an inner piece (contiguous blocks).
+  // Segments: every axis is one pass unless it is cut into pieces (below).
   for (int a = 0; a < ndim; ++a) {
     AxisInfo& ax = P.axes[a];
     int64_t st = 1, outer = 1;
@@ -571,95 +731,16 @@ pafc_status plan_core(PlanCore& P, int ndim, const int64_t* dims, const int* rad
     GroupCaps caps;
     caps.g3 = tuned && tv.gmax3 > 0 ? tv.gmax3 : env_int("PAFC_TUNE_GMAX3", 3);
     caps.g5 = tuned && tv.gmax5 > 0 ? tv.gmax5 : env_int("PAFC_TUNE_GMAX5", 2);
-    // Cut the axis into an outer piece (its outermost stages, strided over
-    // the inner length) and an inner piece when its whole-axis tile would not
-    // fit LDS, when a strided tile 16 columns wide would leave the CU with a
-    // single resident block, or when the tuning table says so (1-D only: the
-    // table is measured on 1-D transforms).
-    const int t = (int)ax.rho.size();
-    auto tile16 = [&](int64_t L) { return tile_lds_bytes((uint64_t)L * 16, P.elem); };
-    int ti = 0;
-    int64_t ni = 1;
-    if (tuned && tv.split > 0 && tv.split < ax.n && ndim == 1) {
-      while (ti < t && ni < tv.split) ni *= ax.rho[ti++];
-      if (ni != tv.split) return PAFC_ERROR_INVALID_VALUE;
-    } else if (!fits_lds(ax.n, P.elem) && st == 1) {
-      const size_t cap = P.elem == 16 ? 4096 : 8192;
-      while (ti < t - 1 && ni * ax.rho[ti] <= (int64_t)cap) ni *= ax.rho[ti++];
-    } else if (st > 1 && tile16(ax.n) > 72 * 1024) {
-      while (ti < t - 1 && tile16(ni * ax.rho[ti]) <= 72 * 1024) ni *= ax.rho[ti++];
-      if (ax.n / ni < 2) ti = 0, ni = 1;
-    }
-    if (ti == 0) {
-      Seg s;
-      s.L = (uint32_t)ax.n;
-      s.rho = ax.rho;
-      s.n_tw = ax.n;
-      s.caps = caps;
-      if (st == 1) {
-        s.mode = MODE_CONTIG;
-        s.S_i = 1;
-        s.S_c = ax.n;
-        s.ncols = (uint32_t)outer;
-        s.S_o = 0;
-        s.nouter = 1;
-      } else {
-        s.mode = MODE_STRIDED;
-        s.S_i = st;
-        s.S_c = 1;
-        s.ncols = (uint32_t)st;
-        s.S_o = ax.n * st;
-        s.nouter = (uint32_t)outer;
-      }
-      choose_width(s, P.elem, tuned ? tv.W : 0);
-      if (tile_lds_bytes(s.L * (uint64_t)s.W, P.elem) > kLdsBudget) return PAFC_ERROR_UNSUPPORTED_SIZE;
-      ax.segs.push_back(s);
-    } else {
-      const int64_t no = ax.n / ni;
-      if (!fits_lds(no, P.elem) || !fits_lds(ni, P.elem) || ti == t) return PAFC_ERROR_UNSUPPORTED_SIZE;
-      if ((uint64_t)ni * st >= (1ull << 32) || (uint64_t)outer * no >= (1ull << 32))
-        return PAFC_ERROR_UNSUPPORTED_SIZE;
-      // element (o, i_o, i_i, f) of the axis sits at
-      // o*n*st + i_o*ni*st + i_i*st + f
-      Seg so;  // outer: positions i_o < no at stride ni*st, columns (i_i, f)
-      so.mode = MODE_STRIDED;
-      so.L = (uint32_t)no;
-      so.S_i = ni * st;
-      so.S_c = 1;
-      so.ncols = (uint32_t)(ni * st);
-      so.S_o = ax.n * st;
-      so.nouter = (uint32_t)outer;
-      so.jmul = (uint32_t)ni;
-      so.col_in_j = 1;
-      so.jcdiv = (uint32_t)st;
-      so.n_tw = ax.n;
-      so.rho.assign(ax.rho.begin() + ti, ax.rho.end());
-      so.caps = caps;
-      choose_width(so, P.elem, tuned ? tv.Wo : 0);
-      Seg si;  // inner: positions i_i < ni, one block per (o, i_o)
-      si.L = (uint32_t)ni;
-      si.n_tw = ni;
-      si.rho.assign(ax.rho.begin(), ax.rho.begin() + ti);
-      si.caps = caps;
-      if (st == 1) {
-        si.mode = MODE_CONTIG;
-        si.S_i = 1;
-        si.S_c = ni;
-        si.ncols = (uint32_t)(outer * no);
-        si.S_o = 0;
-        si.nouter = 1;
-      } else {
-        si.mode = MODE_STRIDED;
-        si.S_i = st;
-        si.S_c = 1;
-        si.ncols = (uint32_t)st;
-        si.S_o = ni * st;
-        si.nouter = (uint32_t)(outer * no);
-      }
-      choose_width(si, P.elem, tuned ? tv.W : 0);
-      ax.segs.push_back(so);
-      ax.segs.push_back(si);
-    }
+    // Cut the axis into pieces (G2): an outer piece takes its outermost
+    // stages, strided over the inner length; the inner length is again an
+    // axis of its own and is cut the same way while it is too long.  A piece
+    // is cut when its whole-axis tile does not fit LDS (contiguous), when a
+    // strided tile 16 columns wide would leave the CU with a single resident
+    // block, or at the top level of a 1-D transform when the tuning table
+    // says so (the table is measured on 1-D transforms).
+    const TuneVal* tvp = tuned && tv.split > 0 && tv.split < ax.n && ndim == 1 ? &tv : nullptr;
+    if (!split_axis(ax.n, ax.rho, st, outer, P.elem, caps, tuned ? &tv : nullptr, tvp, ax.segs))
+      return PAFC_ERROR_UNSUPPORTED_SIZE;
   }
   // twiddle tables, one per distinct n_tw
   for (auto& ax : P.axes)
@@ -701,20 +782,52 @@ pafc_status plan_core(PlanCore& P, int ndim, const int64_t* dims, const int* rad
   for (int a = 0; a < ndim; ++a)
     for (auto it = P.axes[a].segs.rbegin(); it != P.axes[a].segs.rend(); ++it)
       if (!add(P.inv, *it, 1)) return PAFC_ERROR_UNSUPPORTED_SIZE;
+  // Short faster axes folded into the fused middle pass as column ops: the
+  // middle axis is the slowest, so its innermost piece is strided over all
+  // the other axes; when each of them is one register group and together
+  // they form a tile row of at most 64 power-of-two columns, the tile holds
+  // whole rows and their DFTs run inside that pass (the anisotropic grids
+  // n x 2, n x 2 x 2 then move 5 and 5 passes instead of 7 and 9).
+  std::vector<CrossAxis> fold;
+  Seg mseg = P.axes[mid].segs.back();
+  if (variant == PAFC_PERM_FREE && mid == 0 && ndim > 1 && env_int("PAFC_FOLD", 1) != 0) {
+    bool ok = mseg.mode == MODE_STRIDED;
+    int64_t cs = 1;
+    for (int a = ndim - 1; a >= 1 && ok; --a) {
+      const AxisInfo& ax = P.axes[a];
+      const auto groups = group_runs(ax.rho, ax.segs[0].caps);
+      ok = ax.segs.size() == 1 && groups.size() == 1;
+      if (ok) fold.push_back(CrossAxis{groups[0].first, groups[0].second, (uint32_t)cs});
+      cs *= ax.n;
+    }
+    ok = ok && cs == (int64_t)mseg.ncols && (cs & (cs - 1)) == 0 && cs <= 64;
+    if (ok) {
+      mseg.W = (uint32_t)cs;
+      const size_t tw = mseg.tw_global ? 0 : twl_bytes(mseg.n_tw, P.elem);
+      ok = tile_lds_bytes((uint64_t)mseg.L * mseg.W, P.elem) + tw <= kLdsBudget;
+    }
+    if (!ok) fold.clear();
+  }
   if (variant == PAFC_PERM_FREE) {
     for (int a = ndim - 1; a >= 0; --a) {
-      if (a == mid) continue;
+      if (a == mid || !fold.empty()) continue;
       for (auto& s : P.axes[a].segs)
         if (!add(P.conv, s, 0)) return PAFC_ERROR_UNSUPPORTED_SIZE;
     }
     auto& ms = P.axes[mid].segs;
     for (size_t i = 0; i + 1 < ms.size(); ++i)
       if (!add(P.conv, ms[i], 0)) return PAFC_ERROR_UNSUPPORTED_SIZE;
-    if (!add(P.conv, ms.back(), 2)) return PAFC_ERROR_UNSUPPORTED_SIZE;
+    if (fold.empty()) {
+      if (!add(P.conv, ms.back(), 2)) return PAFC_ERROR_UNSUPPORTED_SIZE;
+    } else {
+      Pass p;
+      if (!make_pass(mseg, 2, P.elem, &p, &fold)) return PAFC_ERROR_UNSUPPORTED_SIZE;
+      P.conv.push_back(p);
+    }
     for (size_t i = ms.size() - 1; i-- > 0;)
       if (!add(P.conv, ms[i], 1)) return PAFC_ERROR_UNSUPPORTED_SIZE;
     for (int a = 0; a < ndim; ++a) {
-      if (a == mid) continue;
+      if (a == mid || !fold.empty()) continue;
       for (auto it = P.axes[a].segs.rbegin(); it != P.axes[a].segs.rend(); ++it)
         if (!add(P.conv, *it, 1)) return PAFC_ERROR_UNSUPPORTED_SIZE;
     }
@@ -855,6 +968,7 @@ void finalize_args(const PlanCore& P, const void* d_tw, const void* H, const Pas
                    PassArgs* a) {
   *a = ps.a;
   a->H = H;
+  a->hscale = 1.0 / (double)P.N;  // the single 1/N, applied with the spectrum
   const TwTable& t = P.tw.at(ps.tw_n);
   const char* base = (const char*)d_tw;
   a->tw_lo = base + t.lo_off * (int64_t)P.elem;
@@ -876,10 +990,11 @@ pafc_status run_pass(pafc_plan_t p, const Pass& ps, const void* in, void* out, h
 }
 
 // Index-reversal permutation pass of the explicit variant:
-// dir 1: out[k] = in[pos(k)] (* H),  dir 2: out[p] = in[posinv(p)].
+// dir 1: out[k] = in[pos(k)] (* H / N),  dir 2: out[p] = in[posinv(p)].
 pafc_status run_permute(pafc_plan_t p, int dir, const void* in, void* out, const void* h,
                         hipStream_t s) {
   const PlanCore& P = p->P;
+  const double hs = 1.0 / (double)P.N;
   const bool dbl = P.dtype == PAFC_C128;
   const bool inv = dir == 2;
   uint32_t n0 = 1, n1 = 1, nl = (uint32_t)P.dims[P.ndim - 1];
@@ -898,14 +1013,14 @@ pafc_status run_permute(pafc_plan_t p, int dir, const void* in, void* out, const
   const bool pow2 = (nl & (nl - 1)) == 0;
   if (pow2 && nl <= 4096 && ((uint64_t)n0 * n1 * nl) % 4096 == 0) {
     const uint32_t log_nl = ilog2u(nl);
-    return from_hip(launch_permute_tile(dbl, in, out, h, m0, m1, ml, n0, n1, log_nl, s));
+    return from_hip(launch_permute_tile(dbl, in, out, h, m0, m1, ml, n0, n1, log_nl, hs, s));
   }
   if (tile_lds_bytes(nl, P.elem) <= kLdsBudget) {
     uint32_t rows = std::max<uint32_t>(1, 2048 / nl);
     while (rows > 1 && tile_lds_bytes((uint64_t)rows * nl, P.elem) > 64 * 1024) rows /= 2;
-    return from_hip(launch_permute_rows(dbl, in, out, h, m0, m1, ml, n0, n1, nl, rows, s));
+    return from_hip(launch_permute_rows(dbl, in, out, h, m0, m1, ml, n0, n1, nl, rows, hs, s));
   }
-  return from_hip(launch_permute_gather(dbl, in, out, h, m0, m1, ml, n0, n1, nl, s));
+  return from_hip(launch_permute_gather(dbl, in, out, h, m0, m1, ml, n0, n1, nl, hs, s));
 }
 
 pafc_status run_sequence(pafc_plan_t p, const std::vector<Pass>& seq, const void* x, void* y,
@@ -920,7 +1035,7 @@ pafc_status run_sequence(pafc_plan_t p, const std::vector<Pass>& seq, const void
       PAFC_TRY(run_pass(p, ps, cur, y, s));
       cur = y;
     } else if (ps.kind == 1) {
-      PAFC_TRY(from_hip(launch_mul(dbl, cur, p->d_H, y, P.N, s)));
+      PAFC_TRY(from_hip(launch_mul(dbl, cur, p->d_H, y, P.N, 1.0 / (double)P.N, s)));
       cur = y;
     } else if (ps.kind == 2) {
       if (ps.perm_dir == 1) {
@@ -1104,35 +1219,53 @@ pafc_status pafc_plan_radices(pafc_plan_t p, int axis, int* rho, int* len) {
   return PAFC_SUCCESS;
 }
 
+// The plan's spectrum from a filter: spatial h -> A^T h by the plan's own
+// forward passes; natural-order spectrum -> one reversal pass.  Kept
+// unscaled (the 1/N is applied with the product); the explicit variant keeps
+// it in natural order, the reversal done here once.
+pafc_status load_filter(pafc_plan_t p, const void* h_dev, pafc_filter_domain domain,
+                        hipStream_t s) {
+  const PlanCore& P = p->P;
+  const size_t nbytes = (size_t)P.N * P.elem;
+  const bool natural = P.variant == PAFC_EXPLICIT_PERM;
+  if (domain == PAFC_FILTER_SPATIAL) {
+    if (natural) {
+      PAFC_TRY(run_sequence(p, P.fwd, h_dev, p->d_scratch, s));
+      PAFC_TRY(run_permute(p, 1, p->d_scratch, p->d_H, nullptr, s));
+    } else {
+      PAFC_TRY(run_sequence(p, P.fwd, h_dev, p->d_H, s));
+    }
+  } else if (natural) {
+    PAFC_TRY(from_hip(hipMemcpyAsync(p->d_H, h_dev, nbytes, hipMemcpyDeviceToDevice, s)));
+  } else {  // natural -> digit-reversed, once
+    PAFC_TRY(run_permute(p, 2, h_dev, p->d_H, nullptr, s));
+  }
+  return PAFC_SUCCESS;
+}
+
 pafc_status pafc_set_filter(pafc_plan_t p, const void* h_dev, pafc_filter_domain domain,
                             void* hip_stream) {
   if (!p || !h_dev || !aligned_for(h_dev, p->P.dtype)) return PAFC_ERROR_INVALID_VALUE;
   if (domain != PAFC_FILTER_SPATIAL && domain != PAFC_FILTER_SPECTRAL_NATURAL)
     return PAFC_ERROR_INVALID_VALUE;
   hipStream_t s = (hipStream_t)hip_stream;
-  const PlanCore& P = p->P;
-  const bool dbl = P.dtype == PAFC_C128;
-  const size_t nbytes = (size_t)P.N * P.elem;
   p->filter_set = false;
-  const bool natural = P.variant == PAFC_EXPLICIT_PERM;
-  if (domain == PAFC_FILTER_SPATIAL) {
-    // Hdr = (A^T (x) ... (x) A^T) h: the plan's own forward passes
-    PAFC_TRY(run_sequence(p, P.fwd, h_dev, p->d_H, s));
-    if (natural) {  // the one reversal of the spectrum, done here once
-      PAFC_TRY(run_permute(p, 1, p->d_H, p->d_scratch, nullptr, s));
-      PAFC_TRY(from_hip(hipMemcpyAsync(p->d_H, p->d_scratch, nbytes, hipMemcpyDeviceToDevice, s)));
-    }
-  } else {
-    if (natural) {
-      PAFC_TRY(from_hip(hipMemcpyAsync(p->d_H, h_dev, nbytes, hipMemcpyDeviceToDevice, s)));
-    } else {  // natural -> digit-reversed, once
-      PAFC_TRY(run_permute(p, 2, h_dev, p->d_H, nullptr, s));
-    }
-  }
-  // the single 1/N of the inverse transform
-  PAFC_TRY(from_hip(launch_scale(dbl, p->d_H, P.N, 1.0 / (double)P.N, s)));
+  PAFC_TRY(load_filter(p, h_dev, domain, s));
   p->filter_set = true;
   return PAFC_SUCCESS;
+}
+
+pafc_status pafc_convolve_with_filter(pafc_plan_t p, const void* x_dev, const void* h_dev,
+                                      void* y_dev, void* hip_stream) {
+  if (!p || !x_dev || !h_dev || !y_dev) return PAFC_ERROR_INVALID_VALUE;
+  if (!aligned_for(x_dev, p->P.dtype) || !aligned_for(y_dev, p->P.dtype) ||
+      !aligned_for(h_dev, p->P.dtype))
+    return PAFC_ERROR_INVALID_VALUE;
+  hipStream_t s = (hipStream_t)hip_stream;
+  p->filter_set = false;
+  PAFC_TRY(load_filter(p, h_dev, PAFC_FILTER_SPATIAL, s));
+  p->filter_set = true;
+  return run_sequence(p, p->P.conv, x_dev, y_dev, s);
 }
 
 pafc_status pafc_convolve(pafc_plan_t p, const void* x_dev, void* y_dev, void* hip_stream) {
@@ -1457,7 +1590,7 @@ pafc_status pafc_batch_set_filter(pafc_batch_t b, int filter_id, const void* h_d
   } else {
     return PAFC_ERROR_INVALID_VALUE;
   }
-  PAFC_TRY(from_hip(launch_scale(b->dtype == PAFC_C128, dst, n, 1.0 / (double)n, s)));
+  // kept unscaled: the middle op of the size class applies its 1/n
   b->fset[(size_t)filter_id] = true;
   return PAFC_SUCCESS;
 }

@@ -80,10 +80,20 @@ struct OpDesc {
   uint16_t dst_g;   // 1: the op writes its outputs straight to global memory
   FastDiv divS;     // division by S
   FastDiv divNB;    // division by L / K (blocks per column)
+  // Column op: the whole DFT of a short axis folded into a strided pass,
+  // whose tile row holds every column (W == ncols, row-major columns of the
+  // faster axes).  Its legs are columns p*cs + lo within a block of R*cs
+  // columns; no twiddles, LDS in and out.
+  uint32_t cross;   // 1 for a column op
+  uint32_t cs;      // column stride of the folded axis within a row
+  FastDiv divQ;     // division by W / R (column groups per row)
+  FastDiv divCs;    // division by cs
 };
 
 struct PassArgs {
   const void* H;       // filter spectrum for OP_MID (same layout as the data)
+  double hscale;       // OP_MID multiplies by H * hscale (1/N: the spectrum is
+                       // kept unscaled)
   const void* tw_lo;   // twiddle table(s): w_{n_tw}^E
   const void* tw_hi;   // second level (NULL for a flat table)
   uint32_t tw_bits;    // E = lo + (hi << tw_bits) when two-level
@@ -108,6 +118,8 @@ struct PassArgs {
   uint32_t twl_bits;   // LDS copy of the twiddles: w^E = lo[E & (2^b - 1)] * hi[E >> b]
   uint32_t twl_nhi;    // entries of the hi table (the lo table has 2^twl_bits)
   uint32_t twl_off;    // element offset of the LDS tables after the tile
+  uint32_t twl_global; // 1: no LDS copy (it would not fit beside the tile);
+                       // twiddles are read from the global table
   OpDesc ops[kMaxOps];
 };
 

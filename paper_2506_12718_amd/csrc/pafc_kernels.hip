@@ -65,15 +65,15 @@ __global__ void stream_copy_kernel(const double2* __restrict__ a, double2* __res
 
 template <typename T>
 __global__ void mul_kernel(const cx<T>* __restrict__ x, const cx<T>* __restrict__ h,
-                           cx<T>* __restrict__ y, int64_t n) {
+                           cx<T>* __restrict__ y, int64_t n, T s) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
-    y[i] = cmul(x[i], h[i]);
+    y[i] = cscale(cmul(x[i], h[i]), s);
 }
 
 // Per-axis index-reversal permutation as one HBM pass (the explicit variant's
 // Alg. alg:index-reversal-permutation), with an optional product:
-//   out[k_1..k_d] = in[map_1[k_1], ..., map_d[k_d]] (* h[k_1..k_d]).
+//   out[k_1..k_d] = in[map_1[k_1], ..., map_d[k_d]] (* h[k_1..k_d] * s).
 // One block handles `rows` output rows of the last axis; a source row is
 // staged through LDS so that both the global read and the global write are
 // contiguous; the within-row reversal happens on the LDS read.
@@ -82,7 +82,7 @@ __global__ void __launch_bounds__(256) permute_rows_kernel(
     const cx<T>* __restrict__ in, cx<T>* __restrict__ out, const cx<T>* __restrict__ h,
     const int32_t* __restrict__ map0, const int32_t* __restrict__ map1,
     const int32_t* __restrict__ map_last, uint32_t n0, uint32_t n1, uint32_t nlast,
-    uint32_t rows_per_block, uint32_t nrows) {
+    uint32_t rows_per_block, uint32_t nrows, T s) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
   const uint32_t row0 = blockIdx.x * rows_per_block;
@@ -100,7 +100,7 @@ __global__ void __launch_bounds__(256) permute_rows_kernel(
     const uint32_t rr = x / nlast, k = x - rr * nlast;
     const int64_t o = (int64_t)(row0 + rr) * nlast + k;
     cx<T> v = lds[lds_phys(rr * nlast + (uint32_t)map_last[k])];
-    if (h) v = cmul(v, h[o]);
+    if (h) v = cscale(cmul(v, h[o]), s);
     out[o] = v;
   }
 }
@@ -113,7 +113,7 @@ __global__ void __launch_bounds__(256) permute_tile_kernel(
     const cx<T>* __restrict__ in, cx<T>* __restrict__ out, const cx<T>* __restrict__ h,
     const int32_t* __restrict__ map0, const int32_t* __restrict__ map1,
     const int32_t* __restrict__ map_last, uint32_t n0, uint32_t n1, uint32_t log_nl,
-    FastDiv div_n1) {
+    FastDiv div_n1, T s) {
   constexpr int EPT = 16;
   constexpr uint32_t TILE = 256 * EPT;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -146,7 +146,7 @@ __global__ void __launch_bounds__(256) permute_tile_kernel(
     const uint32_t x = tid + 256u * q;
     const uint32_t rr = x >> log_nl, k = x & (nl - 1u);
     cx<T> w = lds[lds_phys((rr << log_nl) + (uint32_t)lmap[k])];
-    if (h) w = cmul(w, h[base + x]);
+    if (h) w = cscale(cmul(w, h[base + x]), s);
     out[base + x] = w;
   }
 }
@@ -158,7 +158,7 @@ __global__ void permute_gather_kernel(const cx<T>* __restrict__ in, cx<T>* __res
                                       const cx<T>* __restrict__ h,
                                       const int32_t* __restrict__ m0, const int32_t* __restrict__ m1,
                                       const int32_t* __restrict__ m2, uint32_t n0, uint32_t n1,
-                                      uint32_t n2, int64_t n) {
+                                      uint32_t n2, int64_t n, T sc) {
   for (int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; o < n;
        o += (int64_t)gridDim.x * blockDim.x) {
     const uint32_t k2 = (uint32_t)(o % n2);
@@ -167,7 +167,7 @@ __global__ void permute_gather_kernel(const cx<T>* __restrict__ in, cx<T>* __res
     const uint32_t k0 = (uint32_t)(q / n1);
     const int64_t s = ((int64_t)(n0 > 1 ? m0[k0] : 0) * n1 + (n1 > 1 ? m1[k1] : 0)) * n2 + m2[k2];
     cx<T> v = in[s];
-    if (h) v = cmul(v, h[o]);
+    if (h) v = cscale(cmul(v, h[o]), sc);
     out[o] = v;
   }
 }
@@ -256,20 +256,21 @@ hipError_t launch_stream_copy(const void* src, void* dst, int64_t n16, hipStream
   return hipGetLastError();
 }
 
-hipError_t launch_mul(bool dbl, const void* x, const void* h, void* y, int64_t n, hipStream_t st) {
+hipError_t launch_mul(bool dbl, const void* x, const void* h, void* y, int64_t n, double s,
+                      hipStream_t st) {
   if (dbl)
     hipLaunchKernelGGL(mul_kernel<double>, dim3(grid_for(n)), dim3(256), 0, st,
-                       (const cx<double>*)x, (const cx<double>*)h, (cx<double>*)y, n);
+                       (const cx<double>*)x, (const cx<double>*)h, (cx<double>*)y, n, s);
   else
     hipLaunchKernelGGL(mul_kernel<float>, dim3(grid_for(n)), dim3(256), 0, st,
-                       (const cx<float>*)x, (const cx<float>*)h, (cx<float>*)y, n);
+                       (const cx<float>*)x, (const cx<float>*)h, (cx<float>*)y, n, (float)s);
   return hipGetLastError();
 }
 
 hipError_t launch_permute_rows(bool dbl, const void* in, void* out, const void* h,
                                const int32_t* m0, const int32_t* m1, const int32_t* mlast,
                                uint32_t n0, uint32_t n1, uint32_t nlast, uint32_t rows_per_block,
-                               hipStream_t st) {
+                               double s, hipStream_t st) {
   static bool init_d = false, init_f = false;
   const uint32_t nrows = n0 * n1;
   const uint32_t blocks = (nrows + rows_per_block - 1) / rows_per_block;
@@ -284,7 +285,7 @@ hipError_t launch_permute_rows(bool dbl, const void* in, void* out, const void* 
     }
     hipLaunchKernelGGL(permute_rows_kernel<double>, dim3(blocks), dim3(256), lds, st,
                        (const cx<double>*)in, (cx<double>*)out, (const cx<double>*)h, m0, m1,
-                       mlast, n0, n1, nlast, rows_per_block, nrows);
+                       mlast, n0, n1, nlast, rows_per_block, nrows, s);
   } else {
     if (!init_f) {
       hipError_t e = set_lds_limit<float>((const void*)permute_rows_kernel<float>);
@@ -293,14 +294,14 @@ hipError_t launch_permute_rows(bool dbl, const void* in, void* out, const void* 
     }
     hipLaunchKernelGGL(permute_rows_kernel<float>, dim3(blocks), dim3(256), lds, st,
                        (const cx<float>*)in, (cx<float>*)out, (const cx<float>*)h, m0, m1, mlast,
-                       n0, n1, nlast, rows_per_block, nrows);
+                       n0, n1, nlast, rows_per_block, nrows, (float)s);
   }
   return hipGetLastError();
 }
 
 hipError_t launch_permute_tile(bool dbl, const void* in, void* out, const void* h,
                                const int32_t* m0, const int32_t* m1, const int32_t* mlast,
-                               uint32_t n0, uint32_t n1, uint32_t log_nl, hipStream_t st) {
+                               uint32_t n0, uint32_t n1, uint32_t log_nl, double s, hipStream_t st) {
   const uint32_t tile = 4096;
   const uint64_t total = (uint64_t)n0 * n1 << log_nl;
   if ((1u << log_nl) > tile || total % tile != 0) return hipErrorInvalidValue;
@@ -318,26 +319,26 @@ hipError_t launch_permute_tile(bool dbl, const void* in, void* out, const void* 
   if (dbl)
     hipLaunchKernelGGL(permute_tile_kernel<double>, dim3(ntiles), dim3(256), lds, st,
                        (const cx<double>*)in, (cx<double>*)out, (const cx<double>*)h, m0, m1,
-                       mlast, n0, n1, log_nl, dn1);
+                       mlast, n0, n1, log_nl, dn1, s);
   else
     hipLaunchKernelGGL(permute_tile_kernel<float>, dim3(ntiles), dim3(256), lds, st,
                        (const cx<float>*)in, (cx<float>*)out, (const cx<float>*)h, m0, m1, mlast,
-                       n0, n1, log_nl, dn1);
+                       n0, n1, log_nl, dn1, (float)s);
   return hipGetLastError();
 }
 
 hipError_t launch_permute_gather(bool dbl, const void* in, void* out, const void* h,
                                  const int32_t* m0, const int32_t* m1, const int32_t* m2,
-                                 uint32_t n0, uint32_t n1, uint32_t n2, hipStream_t st) {
+                                 uint32_t n0, uint32_t n1, uint32_t n2, double s, hipStream_t st) {
   const int64_t n = (int64_t)n0 * n1 * n2;
   if (dbl)
     hipLaunchKernelGGL(permute_gather_kernel<double>, dim3(grid_for(n)), dim3(256), 0, st,
                        (const cx<double>*)in, (cx<double>*)out, (const cx<double>*)h, m0, m1, m2,
-                       n0, n1, n2, n);
+                       n0, n1, n2, n, s);
   else
     hipLaunchKernelGGL(permute_gather_kernel<float>, dim3(grid_for(n)), dim3(256), 0, st,
                        (const cx<float>*)in, (cx<float>*)out, (const cx<float>*)h, m0, m1, m2,
-                       n0, n1, n2, n);
+                       n0, n1, n2, n, (float)s);
   return hipGetLastError();
 }
 

@@ -227,7 +227,8 @@ pipe_kernel(const PassArgs* __restrict__ desc,
         Dft<R, r, true, T>::run(v);
       } else {  // MID
         Dft<R, r, false, T>::run(v);
-        static_for<R>([&](auto m) { v[m.value] = cmul(v[m.value], preh[m.value]); });
+        const T hs = (T)a.hscale;
+        static_for<R>([&](auto m) { v[m.value] = cscale(cmul(v[m.value], preh[m.value]), hs); });
         if constexpr (!PF_LATE)
           if (next < a.ntiles) fetch_h(next);
         Dft<R, r, true, T>::run(v);

@@ -16,10 +16,18 @@ __device__ __forceinline__ cx<T> twiddle_lds(const PassArgs& a, const cx<T>* lds
   return cmul(lo[E & ((1u << a.twl_bits) - 1u)], hi[E >> a.twl_bits]);
 }
 
+// Twiddle w^E of a pass: from the LDS copy, or from the global table when
+// the pass has none.
+template <typename T>
+__device__ __forceinline__ cx<T> pass_twiddle(const PassArgs& a, const cx<T>* lds, uint32_t E) {
+  return a.twl_global ? twiddle<T>(a, E) : twiddle_lds<T>(a, lds, E);
+}
+
 // Stage the two-level twiddle table in LDS (from the flat or two-level
 // global table); the caller synchronises before the first op.
 template <typename T>
 __device__ __forceinline__ void stage_twiddles(const PassArgs& a, cx<T>* lds) {
+  if (a.twl_global) return;
   cx<T>* lo = lds + a.twl_off;
   cx<T>* hi = lo + (1u << a.twl_bits);
   const cx<T>* glo = reinterpret_cast<const cx<T>*>(a.tw_lo);
@@ -67,6 +75,22 @@ struct OpItem {
 
 __device__ __forceinline__ OpItem op_item(const PassArgs& a, const OpDesc& op, const TileCtx& t,
                                           uint32_t it) {
+  if (op.cross) {  // legs along the columns of one tile row
+    const uint32_t i = fdiv(it, op.divQ);
+    const uint32_t q = it - i * op.divQ.d;
+    const uint32_t hi = fdiv(q, op.divCs);
+    const uint32_t lo = q - hi * op.divCs.d;
+    OpItem m;
+    m.c = 0;
+    m.j = 0;
+    m.gcol = t.col0;
+    m.valid = true;
+    m.lbase = i * t.ls_i + (hi * (uint32_t)op.R * op.cs + lo) * t.ls_c;
+    m.lstep = op.cs * t.ls_c;
+    m.gbase = 0;
+    m.gstep = 0;
+    return m;
+  }
   const uint32_t S = op.S, K = op.K;
   uint32_t c, b, j;
   if (a.mode == MODE_STRIDED) {
@@ -140,7 +164,7 @@ __device__ __forceinline__ void run_op(const PassArgs& a, const OpDesc& op, cons
         static_for<R - 1>([&](auto mm) {
           E += jf;
           if (E >= op.Kf) E -= op.Kf;
-          v[mm.value + 1] = cmul(v[mm.value + 1], twiddle_lds<T>(a, lds, E * op.escale));
+          v[mm.value + 1] = cmul(v[mm.value + 1], pass_twiddle<T>(a, lds, E * op.escale));
         });
       }
       static_for<R>([&](auto mm) { put(digrev<r, g>(mm.value), v[mm.value]); });
@@ -151,7 +175,7 @@ __device__ __forceinline__ void run_op(const PassArgs& a, const OpDesc& op, cons
         static_for<R - 1>([&](auto mm) {
           E += jf;
           if (E >= op.Kf) E -= op.Kf;
-          v[mm.value + 1] = cmulc(v[mm.value + 1], twiddle_lds<T>(a, lds, E * op.escale));
+          v[mm.value + 1] = cmulc(v[mm.value + 1], pass_twiddle<T>(a, lds, E * op.escale));
         });
       }
       Dft<R, r, true, T>::run(v);
@@ -160,9 +184,10 @@ __device__ __forceinline__ void run_op(const PassArgs& a, const OpDesc& op, cons
       Dft<R, r, false, T>::run(v);
       if (m.valid) {
         const int64_t hb = m.gbase - t.off;
+        const T hs = (T)a.hscale;
         static_for<R>([&](auto mm) {
           const cx<T> h = ld_g<T>(a.H, hb + (int64_t)digrev<r, g>(mm.value) * a.S_i);
-          v[mm.value] = cmul(v[mm.value], h);
+          v[mm.value] = cscale(cmul(v[mm.value], h), hs);
         });
       }
       Dft<R, r, true, T>::run(v);

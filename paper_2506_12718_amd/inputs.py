@@ -81,6 +81,21 @@ def spectral_filter_case(seed, shape):
     return x, hhat
 
 
+ANISO_2D = (2 ** 24, 2)
+ANISO_3D = (2 ** 22, 2, 2)
+"""Anisotropic grids of the paper's n_1 >> n_2 (= n_3) tables, at the sizes
+measured here: one long axis that does not fit any cache level, and short
+axes of length 2."""
+
+
+def anisotropic_case(seed, shape):
+    """x and h re/im iid U[-1, 1] (x first)."""
+    rng = np.random.default_rng(seed)
+    x = complex_uniform(rng, shape)
+    h = complex_uniform(rng, shape)
+    return x, h
+
+
 BATCH_SIZES = tuple([2 ** e for e in range(8, 17)]
                     + [3 ** e for e in range(6, 11)]
                     + [5 ** e for e in range(4, 8)])

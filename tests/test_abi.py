@@ -85,8 +85,13 @@ def test_describe_errors():
     with pytest.raises(pafc.PafcError) as e:
         pafc.describe((2, 2, 2, 2), "c128")
     assert e.value.status == 1
-    with pytest.raises(pafc.PafcError):
-        pafc.describe((5 ** 9, 2), "c128")
+    # a long strided axis is cut into as many pieces as its tiles need
+    d = pafc.describe((5 ** 9, 2), "c128")
+    assert len(d["axes"][0]["pieces"]) == 3
+    L = 1
+    for p in d["axes"][0]["pieces"]:
+        L *= p["L"]
+    assert L == 5 ** 9
 
 
 def test_tuning_override_changes_split():

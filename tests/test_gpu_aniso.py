@@ -1,0 +1,180 @@
+"""GPU parity for the anisotropic grids of the paper's n_1 >> n_2 tables, for
+axes cut into three or more pieces, for twiddles read from the global table,
+and for the filter-per-call entry point (pafc_convolve_with_filter).
+
+Tolerances as everywhere: relative L2 <= 1e-12 (complex128), <= 1e-5
+(complex64, oracle on the same rounded inputs).
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2506_12718_amd import inputs
+from gpu_util import TOL, rel_l2, rounded, to_dev, to_host, torch
+
+pytestmark = pytest.mark.gpu
+
+C128, C64 = torch.complex128, torch.complex64
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2506_12718_amd as pafc
+    pafc.lib()
+    yield
+
+
+def pafc():
+    import paper_2506_12718_amd as m
+    return m
+
+
+def conv_gpu(x, h, dtype, radix):
+    P = pafc().Plan(x.shape, dtype, radix=radix)
+    P.set_filter(to_dev(h, dtype))
+    y = to_host(P.convolve(to_dev(x, dtype)))
+    P.close()
+    return y
+
+
+def ref_conv(x, h, dtype):
+    return oracle.conv_fft(rounded(x, dtype), rounded(h, dtype))
+
+
+def pieces(dims, dt, radix):
+    d = pafc().describe(dims, dt, radix=radix)
+    return [len(a["pieces"]) for a in d["axes"]], d["conv_passes"]
+
+
+# shapes of the paper's anisotropic tables at sizes the oracle handles in
+# seconds, and long axes cut into three pieces (checked below)
+ANISO = [
+    ((2 ** 20, 2), [4, 2], C128, 3),
+    ((2 ** 16, 2, 2), [4, 2, 2], C128, 2),
+    ((2 ** 18, 2), [2, 2], C64, 2),
+    ((3 ** 12, 2), [3, 2], C128, 3),
+    ((5 ** 8, 2), [5, 2], C64, 3),
+    ((2 ** 22,), [4], C128, 3),
+]
+
+
+@pytest.mark.parametrize("dims,radix,dtype,npieces", ANISO)
+def test_anisotropic_and_multilevel(dims, radix, dtype, npieces):
+    dt = "c128" if dtype == C128 else "c64"
+    got_pieces, labels = pieces(dims, dt, radix)
+    say("aniso", dims, radix, dt, got_pieces, len(labels), "passes")
+    assert got_pieces[0] == npieces
+    rng = np.random.default_rng([len(dims), dims[0] % 100003, 1 if dt == "c128" else 2])
+    x = inputs.complex_uniform(rng, dims)
+    h = inputs.complex_uniform(rng, dims)
+    y = conv_gpu(x, h, dtype, radix)
+    err = rel_l2(y, ref_conv(x, h, dtype))
+    say("  rel_l2", err)
+    assert err <= TOL[dtype]
+
+
+GLOBAL_TW = [
+    ((4096, 64), [4, 4]),
+    ((2187, 12), None),
+    ((5 ** 6,), None),
+    ((729, 100), None),
+    ((2 ** 18, 2), [2, 2]),
+]
+
+
+@pytest.mark.parametrize("dims,radix", GLOBAL_TW)
+@pytest.mark.parametrize("dtype", [C128, C64])
+def test_global_table_twiddles(dims, radix, dtype, monkeypatch):
+    """Every pass reading its twiddles from the global table instead of an
+    LDS copy (the planner's fallback for very long axes, forced here)."""
+    monkeypatch.setenv("PAFC_TUNE_TWG", "1")
+    dt = "c128" if dtype == C128 else "c64"
+    _, labels = pieces(dims, dt, radix)
+    assert all(l.endswith(" twg") for l in labels), labels
+    say("twg", dims, dt, len(labels), "passes")
+    rng = np.random.default_rng(7)
+    x = inputs.complex_uniform(rng, dims)
+    h = inputs.complex_uniform(rng, dims)
+    y = conv_gpu(x, h, dtype, radix)
+    err = rel_l2(y, ref_conv(x, h, dtype))
+    say("  rel_l2", err)
+    assert err <= TOL[dtype]
+
+
+FPC = [((32, 27, 20), None), ((4096,), [4]), ((729, 100), None), ((64, 64, 64), [4, 4, 4])]
+
+
+@pytest.mark.parametrize("dims,radix", FPC)
+@pytest.mark.parametrize("variant", ["perm_free", "explicit_perm", "perm_free_unfused"])
+@pytest.mark.parametrize("dtype", [C128, C64])
+def test_filter_per_call(dims, radix, variant, dtype):
+    """pafc_convolve_with_filter equals pafc_set_filter + pafc_convolve bit
+    for bit, matches the oracle, and leaves h as the plan's filter."""
+    say("fpc", dims, variant, dtype)
+    rng = np.random.default_rng(11)
+    x = inputs.complex_uniform(rng, dims)
+    h = inputs.complex_uniform(rng, dims)
+    x2 = inputs.complex_uniform(rng, dims)
+    h0 = inputs.complex_uniform(rng, dims)
+    P = pafc().Plan(dims, dtype, radix=radix, variant=variant)
+    xd, hd, x2d = to_dev(x, dtype), to_dev(h, dtype), to_dev(x2, dtype)
+    P.set_filter(to_dev(h0, dtype))  # a different filter first
+    y_fpc = to_host(P.convolve_with_filter(xd, hd))
+    y_after = to_host(P.convolve(x2d))  # h is now the plan's filter
+    P.set_filter(hd)
+    y_set = to_host(P.convolve(xd))
+    P.close()
+    assert np.array_equal(y_fpc, y_set)
+    assert rel_l2(y_fpc, ref_conv(x, h, dtype)) <= TOL[dtype]
+    assert rel_l2(y_after, ref_conv(x2, h, dtype)) <= TOL[dtype]
+
+
+def test_filter_per_call_rejects_aliasing():
+    P = pafc().Plan((64,), C128)
+    a = torch.zeros(64, dtype=C128, device="cuda")
+    with pytest.raises(ValueError):
+        P.convolve_with_filter(a, a, out=a)
+    P.close()
+
+
+FOLD = [
+    ((64, 16), None, C128),
+    ((4096, 8, 4), None, C128),
+    ((1000, 2), None, C64),
+    ((2 ** 16, 2), [4, 2], C128),
+    ((2 ** 14, 2, 2), [4, 2, 2], C64),
+    ((81, 8, 8), None, C128),
+]
+
+
+@pytest.mark.parametrize("dims,radix,dtype", FOLD)
+def test_short_axes_folded_into_middle_pass(dims, radix, dtype, monkeypatch):
+    """Short faster axes run as column ops inside the fused middle pass (one
+    pass fewer each way per axis); same result as the plan that keeps them in
+    passes of their own, and as the oracle."""
+    dt = "c128" if dtype == C128 else "c64"
+    _, labels = pieces(dims, dt, radix)
+    say("fold", dims, dt, labels)
+    assert any("XDIF" in l for l in labels)
+    assert len(labels) == 2 * len(pafc().describe(dims, dt, radix=radix)["axes"][0]["pieces"]) - 1
+    rng = np.random.default_rng([len(dims), dims[0], 3])
+    x = inputs.complex_uniform(rng, dims)
+    h = inputs.complex_uniform(rng, dims)
+    y = conv_gpu(x, h, dtype, radix)
+    ref = ref_conv(x, h, dtype)
+    assert rel_l2(y, ref) <= TOL[dtype]
+    monkeypatch.setenv("PAFC_FOLD", "0")
+    _, labels0 = pieces(dims, dt, radix)
+    assert not any("XDIF" in l for l in labels0)
+    y0 = conv_gpu(x, h, dtype, radix)
+    assert rel_l2(y, y0) <= TOL[dtype]
