@@ -594,6 +594,10 @@ bool split_axis(int64_t n, const std::vector<int>& rho, int64_t st, int64_t oute
                 std::vector<Seg>& segs) {
   const int t = (int)rho.size();
   auto tile16 = [&](int64_t L) { return tile_lds_bytes((uint64_t)L * 16, elem); };
+  // a strided piece's tile is at most 16 columns wide, and no wider than
+  // the stride (its column count)
+  const uint64_t wcap = pow2_floor((uint64_t)std::min<int64_t>(st, 16));
+  auto tilew = [&](int64_t L) { return tile_lds_bytes((uint64_t)L * wcap, elem); };
   int ti = 0;
   int64_t ni = 1;
   if (tsplit) {
@@ -602,13 +606,13 @@ bool split_axis(int64_t n, const std::vector<int>& rho, int64_t st, int64_t oute
   } else if (!fits_lds(n, elem) && st == 1) {
     const size_t cap = elem == 16 ? 4096 : 8192;
     while (ti < t - 1 && ni * rho[ti] <= (int64_t)cap) ni *= rho[ti++];
-  } else if (st > 1 && tile16(n) > 72 * 1024) {
-    while (ti < t - 1 && tile16(ni * rho[ti]) <= 72 * 1024) ni *= rho[ti++];
+  } else if (st > 1 && tilew(n) > 72 * 1024) {
+    while (ti < t - 1 && tilew(ni * rho[ti]) <= 72 * 1024) ni *= rho[ti++];
     if (n / ni < 2) ti = 0, ni = 1;
   }
-  // an outer piece that does not fit LDS, or whose tile would be narrower
-  // than 8 columns (row segments under 8 elements), takes fewer stages: the
-  // inner length grows, and is cut again below
+  // an outer piece that does not fit LDS, or whose tile would be too narrow
+  // (short row segments), takes fewer stages: the inner length grows, and is
+  // cut again below
   auto outer_width = [&](int64_t L) {
     Seg o;
     o.mode = MODE_STRIDED;
@@ -625,7 +629,12 @@ bool split_axis(int64_t n, const std::vector<int>& rho, int64_t st, int64_t oute
       // 72 KB, like every other strided pass
       while (ti < t - 1 && tile16(n / ni) > 72 * 1024) ni *= rho[ti++];
     } else {
-      while (ti < t - 1 && outer_width(n / ni) < 8) ni *= rho[ti++];
+      // 8 columns at least; an axis of a grid (stride > 1) is held to the
+      // 16-column tiles within 72 KB of every other strided pass (the 1-D
+      // pieces keep 8 columns: the tuned 1-D plans were measured so)
+      while (ti < t - 1 &&
+             (outer_width(n / ni) < 8 || (st > 1 && tile16(n / ni) > 72 * 1024)))
+        ni *= rho[ti++];
     }
   }
   if (ti == 0) {

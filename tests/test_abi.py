@@ -180,3 +180,26 @@ def test_twiddles_exact_points_and_rounding():
                 abs(w.imag - s) <= math.ulp(max(abs(s), 1e-300)), (n, e)
             wc = pafc.twiddle(n, n - int(e))
             assert wc.real == w.real and wc.imag == -w.imag or e == 0
+
+
+def test_anisotropic_plans():
+    """Host-only plans of the GPU anisotropic cases: the long axis is cut
+    into the expected number of pieces, and the short faster axes fold into
+    the fused middle pass (2 passes fewer per folded grid)."""
+    import importlib.util, os
+    spec = importlib.util.spec_from_file_location(
+        "gpu_aniso_cases", os.path.join(os.path.dirname(__file__), "test_gpu_aniso.py"))
+    # the case lists only; importing the module needs torch, which is present
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    for dims, radix, dtype, npieces in mod.ANISO:
+        dt = "c128" if dtype == mod.C128 else "c64"
+        d = pafc.describe(dims, dt, radix=radix)
+        assert len(d["axes"][0]["pieces"]) == npieces, (dims, dt)
+        if len(dims) > 1:
+            assert any("XDIF" in l for l in d["conv_passes"]), (dims, dt)
+            assert len(d["conv_passes"]) == 2 * npieces - 1, (dims, dt)
+    for dims, radix, dtype in mod.FOLD:
+        dt = "c128" if dtype == mod.C128 else "c64"
+        d = pafc.describe(dims, dt, radix=radix)
+        assert any("XDIF" in l for l in d["conv_passes"]), (dims, dt)
