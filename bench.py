@@ -134,7 +134,19 @@ def wl_aniso3d(dtype_name):
                         "dims": list(shape), "radix": [4, 2, 2]})
 
 
-WORKLOADS = {"conv3d": wl_conv3d, "conv1d": wl_conv1d, "conv2d": wl_conv2d, "conv1d5": wl_conv1d5,
+def wl_poisson3d(dtype_name):
+    from paper_2506_12718_amd import inputs
+    rng = np.random.default_rng(43)
+    f = inputs.complex_normal(rng, (256, 256, 256))
+    return dict(name="poisson3d_256_%s_r4" % dtype_name, x=f, h=None, radix=[4, 4, 4],
+                domain="symbol", symbol=("inv_laplacian_fd", ()), rhos=[[4] * 4] * 3,
+                config={"workload": "periodic Poisson solve on 256x256x256 (inverse of the "
+                                    "7-point Laplacian as a frequency symbol), radix 4 per axis, "
+                                    "right-hand side iid N(0,1)",
+                        "dims": [256, 256, 256], "radix": 4, "symbol": "inv_laplacian_fd"})
+
+
+WORKLOADS = {"conv3d": wl_conv3d, "poisson3d": wl_poisson3d, "conv1d": wl_conv1d, "conv2d": wl_conv2d, "conv1d5": wl_conv1d5,
              "batched": wl_batched, "serving": wl_serving, "aniso2d": wl_aniso2d,
              "aniso3d": wl_aniso3d}
 
@@ -309,9 +321,13 @@ def measure(pafc, torch, wl, tdtype, variant, steps, warmup, filter_per_call=Fal
     second run of the convolution passes alone.  Returns a dict of results."""
     plan = pafc.Plan(wl["x"].shape, tdtype, radix=wl["radix"], variant=variant)
     xd = torch.from_numpy(wl["x"]).to(tdtype).cuda()
-    hd = torch.from_numpy(wl["h"]).to(tdtype).cuda()
     yd = torch.empty_like(xd)
-    plan.set_filter(hd, domain=wl["domain"])
+    if wl["domain"] == "symbol":
+        plan.set_symbol(wl["symbol"][0], *wl["symbol"][1])
+        hd = None
+    else:
+        hd = torch.from_numpy(wl["h"]).to(tdtype).cuda()
+        plan.set_filter(hd, domain=wl["domain"])
     if filter_per_call:
         for _ in range(warmup):
             plan.convolve_with_filter(xd, hd, out=yd)
@@ -478,10 +494,16 @@ def main():
         h = wl["h"]
         if args.dtype == "c64":
             x = x.astype(np.complex64).astype(np.complex128)
-            h = h.astype(np.complex64).astype(np.complex128)
+            if h is not None:
+                h = h.astype(np.complex64).astype(np.complex128)
         t0 = time.perf_counter()
         if wl["domain"] == "spatial":
             ref = oracle.conv_fft(x, h, wl["rhos"])
+        elif wl["domain"] == "symbol":
+            from oracle import symbols
+            kind, params = wl["symbol"]
+            sym = getattr(symbols, kind)(x.shape, *params)
+            ref = symbols.apply(x, sym)
         else:
             ref = oracle.fft(h * oracle.fft(x, wl["rhos"]), wl["rhos"], inverse=True)
         t_cpu = time.perf_counter() - t0

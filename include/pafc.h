@@ -160,6 +160,45 @@ pafc_status pafc_convolve(pafc_plan_t p, const void* x_dev, void* y_dev,
                           void* hip_stream);
 
 /*
+ * Diagonal operators of the DFT for pafc_set_symbol.  S(k) is evaluated at
+ * the signed frequency kt_i = k_i (2 k_i <= n_i) or k_i - n_i of each axis,
+ * with w_i = 2 pi kt_i / n_i (unit grid spacing, period n_i):
+ *   INV_LAPLACIAN     -1 / sum_i w_i^2, 0 at k = 0: the periodic Poisson
+ *                     solve of the spectral Laplacian (mean removed)
+ *   INV_LAPLACIAN_FD  -1 / sum_i 4 sin^2(pi k_i / n_i), 0 at k = 0: the
+ *                     inverse of the (2d+1)-point finite-difference Laplacian
+ *   HEAT              exp(-t sum_i w_i^2), params[0] = t >= 0
+ *   DERIVATIVE        i w_a along axis a = params[0] (0 at the Nyquist
+ *                     frequency of an even axis): the spectral derivative
+ */
+typedef enum pafc_symbol {
+  PAFC_SYMBOL_INV_LAPLACIAN = 0,
+  PAFC_SYMBOL_INV_LAPLACIAN_FD = 1,
+  PAFC_SYMBOL_HEAT = 2,
+  PAFC_SYMBOL_DERIVATIVE = 3
+} pafc_symbol;
+
+/*
+ * pafc_set_symbol -- make the plan's spectrum a diagonal operator given by
+ * its symbol, so that pafc_convolve computes y = DFT^{-1}(S o DFT(x)): the
+ * unordered transforms with a general diagonal operator between them.  The
+ * scheme of Sec. "Permutation-avoiding convolution" only needs that operator
+ * to be elementwise in the frequency basis, held in the same digit-reversed
+ * order as the data (fast Poisson solvers are among the applications the
+ * Introduction names).  No array is passed: the
+ * per-axis factors are tabulated on the host (long double, rounded once to
+ * FP64, at most sum n_i entries) and combined on the device, where each
+ * position of the plan's layout finds its frequency through the inverse
+ * digit-reversal map.  Replaces any filter.  Synchronises hip_stream once
+ * (the table upload).
+ * params / nparams: as the symbol requires (NULL and 0 when none).
+ * Errors: INVALID_VALUE (bad kind, parameter count or value: t < 0 or not
+ * finite, axis not an integer in [0, ndim)), DEVICE.
+ */
+pafc_status pafc_set_symbol(pafc_plan_t p, pafc_symbol kind, const double* params,
+                            int nparams, void* hip_stream);
+
+/*
  * pafc_convolve_with_filter -- y = x * h with the filter transformed inside
  * the call: the evaluation of Alg. alg:permutation-avoiding-convolution as
  * the paper times it, three transforms per call (forward of h, forward of

@@ -18,9 +18,8 @@ the identities the paper states, and can pin the C oracle against them:
                       R_{r,q,n} = I_{r^{q-1}} (x) R_{r,n/r^{q-1}}
                       (Sec. "General radix Cooley-Tukey framework").
 * ``pos(rho, k)``     where entry k of F x sits in A_rho^T x: mixed-radix digit
-                      reversal (a consequence of F = P_rho A_rho^T, derived in
-                      the accompanying design notes and checked against the
-                      matrices above in the tests).
+                      reversal (a consequence of F = P_rho A_rho^T; checked
+                      against the matrices above in the tests).
 """
 from __future__ import annotations
 

@@ -42,7 +42,7 @@ EXPORTS = ("pafc_plan", "pafc_set_filter", "pafc_convolve", "pafc_forward",
            "pafc_batch_destroy", "pafc_batch_device_bytes",
            "pafc_batch_describe", "pafc_set_tuning", "pafc_profile_passes",
            "pafc_stream_copy", "pafc_batch_profile", "pafc_twiddle",
-           "pafc_convolve_with_filter")
+           "pafc_convolve_with_filter", "pafc_set_symbol")
 
 
 class PafcError(RuntimeError):
@@ -71,6 +71,8 @@ def lib():
             "pafc_set_filter": [vp, vp, ctypes.c_int, vp],
             "pafc_convolve": [vp, vp, vp, vp],
             "pafc_convolve_with_filter": [vp, vp, vp, vp, vp],
+            "pafc_set_symbol": [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.c_int,
+                                vp],
             "pafc_forward": [vp, vp, vp, vp],
             "pafc_inverse": [vp, vp, vp, vp],
             "pafc_destroy": [vp],
@@ -265,6 +267,16 @@ class Plan:
     def convolve(self, x, out=None, stream=None):
         """y = x (*) h; ``out`` may be ``x`` (in place)."""
         return self._run(lib().pafc_convolve, x, out, stream, "pafc_convolve")
+
+    SYMBOLS = {"inv_laplacian": 0, "inv_laplacian_fd": 1, "heat": 2, "derivative": 3}
+
+    def set_symbol(self, kind, *params, stream=None):
+        """Make the plan's operator the diagonal symbol `kind` (see
+        pafc_set_symbol): 'inv_laplacian', 'inv_laplacian_fd', 'heat' (t),
+        'derivative' (axis).  convolve() then applies it."""
+        arr = (ctypes.c_double * max(1, len(params)))(*[float(v) for v in params])
+        _check(lib().pafc_set_symbol(self._h, self.SYMBOLS[kind], arr if params else None,
+                                     len(params), _stream(stream)), "pafc_set_symbol")
 
     def convolve_with_filter(self, x, h, out=None, stream=None):
         """y = x (*) h with h transformed inside the call (three transforms

@@ -41,6 +41,9 @@ hipError_t launch_pipe(bool dbl, int r, int g, int ng, int kind, int mode, const
 hipError_t launch_mul(bool dbl, const void* x, const void* h, void* y, int64_t n, double s,
                       hipStream_t st);
 hipError_t launch_stream_copy(const void* src, void* dst, int64_t n16, hipStream_t st);
+hipError_t launch_symbol(bool dbl, void* H, const void* g, const int32_t* m0, const int32_t* m1,
+                         const int32_t* m2, uint32_t n0, uint32_t n1, uint32_t n2, uint32_t off0,
+                         uint32_t off1, uint32_t off2, int mode, hipStream_t st);
 hipError_t launch_permute_rows(bool dbl, const void* in, void* out, const void* h,
                                const int32_t* m0, const int32_t* m1, const int32_t* mlast,
                                uint32_t n0, uint32_t n1, uint32_t nlast, uint32_t rows_per_block,
@@ -933,6 +936,7 @@ struct pafc_plan_s {
   void* d_H = nullptr;
   void* d_scratch = nullptr;
   int32_t* d_maps = nullptr;  // per axis: pos, posinv
+  void* d_symtab = nullptr;   // per-axis symbol tables (FP64 complex), 3 + sum n_i
   PassArgs* d_descs = nullptr;
   std::vector<int64_t> map_off;
   bool filter_set = false;
@@ -964,6 +968,7 @@ void free_plan(pafc_plan_t p) {
   if (p->d_H) (void)hipFree(p->d_H);
   if (p->d_scratch) (void)hipFree(p->d_scratch);
   if (p->d_maps) (void)hipFree(p->d_maps);
+  if (p->d_symtab) (void)hipFree(p->d_symtab);
   if (p->d_descs) (void)hipFree(p->d_descs);
   delete p;
 }
@@ -1152,6 +1157,10 @@ pafc_status pafc_plan(pafc_plan_t* out, int ndim, const int64_t* dims, const int
   hipError_t e = hipMalloc(&p->d_tw, std::max<size_t>(tw_bytes, 16));
   if (e == hipSuccess) e = hipMalloc((void**)&p->d_maps, maps.size() * sizeof(int32_t));
   if (e == hipSuccess) e = hipMalloc(&p->d_H, (size_t)P.N * P.elem);
+  size_t symtab_bytes = 3;
+  for (auto& ax : P.axes) symtab_bytes += (size_t)ax.n;
+  symtab_bytes *= 2 * sizeof(double);
+  if (e == hipSuccess) e = hipMalloc(&p->d_symtab, symtab_bytes);
   if (e == hipSuccess && P.variant == PAFC_EXPLICIT_PERM)
     e = hipMalloc(&p->d_scratch, (size_t)P.N * P.elem);
   // persistent grids of the pipelined passes: resident blocks per CU x CUs
@@ -1202,6 +1211,7 @@ pafc_status pafc_plan(pafc_plan_t* out, int ndim, const int64_t* dims, const int
     return from_hip(e);
   }
   p->bytes = tw_bytes + maps.size() * sizeof(int32_t) + descs.size() * sizeof(PassArgs) +
+             symtab_bytes +
              (P.variant == PAFC_EXPLICIT_PERM ? (size_t)P.N * P.elem : 0) + (size_t)P.N * P.elem;
   *out = p;
   return PAFC_SUCCESS;
@@ -1275,6 +1285,93 @@ pafc_status pafc_convolve_with_filter(pafc_plan_t p, const void* x_dev, const vo
   PAFC_TRY(load_filter(p, h_dev, PAFC_FILTER_SPATIAL, s));
   p->filter_set = true;
   return run_sequence(p, p->P.conv, x_dev, y_dev, s);
+}
+
+pafc_status pafc_set_symbol(pafc_plan_t p, pafc_symbol kind, const double* params, int nparams,
+                            void* hip_stream) {
+  if (!p) return PAFC_ERROR_INVALID_VALUE;
+  const PlanCore& P = p->P;
+  const int d = P.ndim;
+  double t = 0;
+  int axis = 0;
+  switch (kind) {
+    case PAFC_SYMBOL_INV_LAPLACIAN:
+    case PAFC_SYMBOL_INV_LAPLACIAN_FD:
+      if (nparams != 0) return PAFC_ERROR_INVALID_VALUE;
+      break;
+    case PAFC_SYMBOL_HEAT:
+      if (nparams != 1 || !params || !(params[0] >= 0.0) || !std::isfinite(params[0]))
+        return PAFC_ERROR_INVALID_VALUE;
+      t = params[0];
+      break;
+    case PAFC_SYMBOL_DERIVATIVE:
+      if (nparams != 1 || !params || params[0] != std::floor(params[0]) || params[0] < 0 ||
+          params[0] >= d)
+        return PAFC_ERROR_INVALID_VALUE;
+      axis = (int)params[0];
+      break;
+    default:
+      return PAFC_ERROR_INVALID_VALUE;
+  }
+  // Per-axis tables of the natural frequencies k < n_i, in long double,
+  // rounded once to FP64.  kt = k (k <= n/2) or k - n, w = 2 pi kt / n.
+  const long double pi = 3.141592653589793238462643383279502884L;
+  const int mode = (kind == PAFC_SYMBOL_INV_LAPLACIAN || kind == PAFC_SYMBOL_INV_LAPLACIAN_FD) ? 0 : 1;
+  std::vector<double> g;  // (re, im) pairs; axes padded to 3 with one neutral entry
+  std::vector<uint32_t> off(3, 0), len(3, 1);
+  for (int i = 0; i < 3; ++i) {
+    off[(size_t)i] = (uint32_t)(g.size() / 2);
+    if (i >= d) {  // a missing axis: one neutral entry
+      g.push_back(mode == 0 ? 0.0 : 1.0);
+      g.push_back(0.0);
+      continue;
+    }
+    const int64_t n = P.axes[(size_t)i].n;
+    len[(size_t)i] = (uint32_t)n;
+    for (int64_t k = 0; k < n; ++k) {
+      const int64_t kt = 2 * k <= n ? k : k - n;
+      const long double w = 2.0L * pi * (long double)kt / (long double)n;
+      long double re = 0, im = 0;
+      if (kind == PAFC_SYMBOL_INV_LAPLACIAN) {
+        re = w * w;
+      } else if (kind == PAFC_SYMBOL_INV_LAPLACIAN_FD) {
+        const int64_t km = std::min<int64_t>(k, n - k);  // sin(pi k / n) = sin(pi (n - k) / n)
+        const long double sv = sinl(pi * (long double)km / (long double)n);
+        re = 4.0L * sv * sv;
+      } else if (kind == PAFC_SYMBOL_HEAT) {
+        re = expl(-(long double)t * w * w);
+      } else {  // derivative: i w on its axis (0 at the Nyquist frequency), 1 elsewhere
+        if (i == axis) {
+          im = (2 * k == n) ? 0.0L : w;
+        } else {
+          re = 1.0L;
+        }
+      }
+      g.push_back((double)re);
+      g.push_back((double)im);
+    }
+  }
+  // shape as three axes (leading ones of length 1)
+  const int32_t* m[3] = {nullptr, nullptr, nullptr};
+  uint32_t nn[3] = {1, 1, 1}, oo[3] = {0, 0, 0};
+  const bool natural = P.variant == PAFC_EXPLICIT_PERM;
+  for (int i = 0; i < d; ++i) {
+    const int slot = 3 - d + i;
+    nn[slot] = len[(size_t)i];
+    oo[slot] = off[(size_t)i];
+    m[slot] = natural ? nullptr : map_ptr(p, i, true);  // position -> frequency
+  }
+  for (int slot = 0; slot < 3 - d; ++slot) oo[slot] = off[(size_t)(d + slot)];
+  hipStream_t s = (hipStream_t)hip_stream;
+  p->filter_set = false;
+  PAFC_TRY(from_hip(hipMemcpyAsync(p->d_symtab, g.data(), g.size() * sizeof(double),
+                                   hipMemcpyHostToDevice, s)));
+  PAFC_TRY(from_hip(launch_symbol(P.dtype == PAFC_C128, p->d_H, p->d_symtab, m[0], m[1], m[2],
+                                  nn[0], nn[1], nn[2], oo[0], oo[1], oo[2], mode, s)));
+  // the host table dies here: wait for its upload
+  PAFC_TRY(from_hip(hipStreamSynchronize(s)));
+  p->filter_set = true;
+  return PAFC_SUCCESS;
 }
 
 pafc_status pafc_convolve(pafc_plan_t p, const void* x_dev, void* y_dev, void* hip_stream) {

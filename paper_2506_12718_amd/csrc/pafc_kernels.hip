@@ -172,6 +172,40 @@ __global__ void permute_gather_kernel(const cx<T>* __restrict__ in, cx<T>* __res
   }
 }
 
+// A diagonal operator's spectrum written in the plan's layout: at position
+// (p_0, p_1, p_2) the natural frequency of axis i is k_i = map_i[p_i] (or
+// p_i when map_i is NULL; k_i < n_i), and the value combines the per-axis
+// entries g[off_i + k_i]: mode 0 -> -1 / (sum of their real parts), 0 where the sum
+// is 0; mode 1 -> the complex product.  Computed in FP64, rounded once.
+template <typename T>
+__global__ void symbol_kernel(cx<T>* __restrict__ H, const double2* __restrict__ g,
+                              const int32_t* __restrict__ m0, const int32_t* __restrict__ m1,
+                              const int32_t* __restrict__ m2, uint32_t n0, uint32_t n1,
+                              uint32_t n2, uint32_t off0, uint32_t off1, uint32_t off2, int mode,
+                              int64_t n) {
+  for (int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; o < n;
+       o += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t p2 = (uint32_t)(o % n2);
+    const int64_t q = o / n2;
+    const uint32_t p1 = (uint32_t)(q % n1);
+    const uint32_t p0 = (uint32_t)(q / n1);
+    const double2 a = g[off0 + (m0 ? m0[p0] : p0)];
+    const double2 b = g[off1 + (m1 ? m1[p1] : p1)];
+    const double2 c = g[off2 + (m2 ? m2[p2] : p2)];
+    double re, im;
+    if (mode == 0) {
+      const double s = a.x + b.x + c.x;
+      re = s == 0.0 ? 0.0 : -1.0 / s;
+      im = 0.0;
+    } else {
+      const double abr = a.x * b.x - a.y * b.y, abi = a.x * b.y + a.y * b.x;
+      re = abr * c.x - abi * c.y;
+      im = abr * c.y + abi * c.x;
+    }
+    H[o] = cx<T>{(T)re, (T)im};
+  }
+}
+
 }  // namespace pafc
 
 // ----------------------------------------------------------------- launches
@@ -247,6 +281,21 @@ hipError_t launch_scale(bool dbl, void* p, int64_t n, double s, hipStream_t st) 
   else
     hipLaunchKernelGGL(scale_kernel<float>, dim3(grid_for(n)), dim3(256), 0, st,
                        (cx<float>*)p, n, (float)s);
+  return hipGetLastError();
+}
+
+hipError_t launch_symbol(bool dbl, void* H, const void* g, const int32_t* m0, const int32_t* m1,
+                         const int32_t* m2, uint32_t n0, uint32_t n1, uint32_t n2, uint32_t off0,
+                         uint32_t off1, uint32_t off2, int mode, hipStream_t st) {
+  const int64_t n = (int64_t)n0 * n1 * n2;
+  if (dbl)
+    hipLaunchKernelGGL(symbol_kernel<double>, dim3(grid_for(n)), dim3(256), 0, st,
+                       (cx<double>*)H, (const double2*)g, m0, m1, m2, n0, n1, n2, off0, off1,
+                       off2, mode, n);
+  else
+    hipLaunchKernelGGL(symbol_kernel<float>, dim3(grid_for(n)), dim3(256), 0, st,
+                       (cx<float>*)H, (const double2*)g, m0, m1, m2, n0, n1, n2, off0, off1,
+                       off2, mode, n);
   return hipGetLastError();
 }
 
