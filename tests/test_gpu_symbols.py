@@ -69,6 +69,12 @@ def test_symbols_match_oracle(shape, radix, variant, dtype):
         P.set_symbol(kind, *params)
         y = to_host(P.convolve(xd))
         ref = symbols.apply(rounded(x, dtype), ref_symbol(shape, kind, params))
+        if not np.any(ref_symbol(shape, kind, params)):
+            # e.g. the derivative along a length-2 axis: only k = 0 and the
+            # dropped Nyquist frequency -- the zero operator
+            say("  ", kind, params, "zero operator")
+            assert not np.any(y)
+            continue
         err = rel_l2(y, ref)
         say("  ", kind, params, err)
         assert err <= TOL[dtype], (kind, params, err)
