@@ -146,7 +146,20 @@ def wl_poisson3d(dtype_name):
                         "dims": [256, 256, 256], "radix": 4, "symbol": "inv_laplacian_fd"})
 
 
-WORKLOADS = {"conv3d": wl_conv3d, "poisson3d": wl_poisson3d, "conv1d": wl_conv1d, "conv2d": wl_conv2d, "conv1d5": wl_conv1d5,
+def wl_pfa1d(dtype_name):
+    from paper_2506_12718_amd import inputs
+    n = 2 ** 8 * 3 ** 5 * 5 ** 3
+    x, h = inputs.anisotropic_case(44, (n,))
+    return dict(name="pfa1d_7776000_%s" % dtype_name, x=x, h=h, radix=None, domain="spatial",
+                rhos=None, variant="prime_factor",
+                compare=["prime_factor_explicit", "perm_free"],
+                config={"workload": "1-D convolution n = 2^8 3^5 5^3 = 7776000 by the prime-factor "
+                                    "route (Chinese-remainder reindexing onto the 256x243x125 "
+                                    "grid), x and h re/im iid U[-1,1]",
+                        "dims": [n], "grid": [125, 243, 256]})
+
+
+WORKLOADS = {"conv3d": wl_conv3d, "poisson3d": wl_poisson3d, "pfa1d": wl_pfa1d, "conv1d": wl_conv1d, "conv2d": wl_conv2d, "conv1d5": wl_conv1d5,
              "batched": wl_batched, "serving": wl_serving, "aniso2d": wl_aniso2d,
              "aniso3d": wl_aniso3d}
 
@@ -421,7 +434,8 @@ def main():
     if fpc and wl["domain"] != "spatial":
         print("--filter-per-call needs a workload with a spatial filter", file=sys.stderr)
         sys.exit(2)
-    main_r = measure(pafc, torch, wl, tdtype, "perm_free", args.steps, args.warmup, fpc)
+    main_variant = wl.get("variant", "perm_free")
+    main_r = measure(pafc, torch, wl, tdtype, main_variant, args.steps, args.warmup, fpc)
     total_s = sum(main_r["ms_rep"]) / 1e3
     value = args.steps / main_r["wall"]
     ms_step = main_r["wall"] * 1e3 / args.steps
@@ -457,7 +471,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if args.dtype == "c128" else "f32",
         "data": "synthetic",
-        "config": dict(wl["config"], variant="perm_free", dtype=args.dtype,
+        "config": dict(wl["config"], variant=main_variant, dtype=args.dtype,
                        passes=main_r["labels"], filter_per_call=fpc),
         "hbm_gbps_alg": round(alg_bytes * value / 1e9, 1),
         "hbm_frac_alg": round(alg_bytes * value / 1e9 / HBM_PEAK_GBS, 4),
@@ -470,7 +484,8 @@ def main():
     }
     if not args.no_compare:
         comp = {}
-        for variant in ("explicit_perm", "perm_free_unfused"):
+        compare = wl.get("compare", ["explicit_perm", "perm_free_unfused"])
+        for variant in compare:
             print("bench: comparison variant %s" % variant, file=sys.stderr, flush=True)
             r = measure(pafc, torch, wl, tdtype, variant, max(5, args.steps // 2), 2, fpc)
             v = len(r["ms_rep"]) / r["wall"]
@@ -485,7 +500,7 @@ def main():
                 "max_abs_diff_vs_perm_free": float(np.abs(r["y"] - main_r["y"]).max()),
             }
         comp["speedup_perm_free_over_explicit"] = round(
-            value / comp["explicit_perm"]["conv_per_s"], 3)
+            value / comp[compare[0]]["conv_per_s"], 3)
         out["compare"] = comp
     if not args.no_cpu:
         import oracle

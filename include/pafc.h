@@ -82,7 +82,19 @@ typedef enum pafc_variant {
   PAFC_EXPLICIT_PERM = 1,
   /* Ablation: permutation-free, but every axis transform is its own pass and
      the product is a separate elementwise pass (no fusion). */
-  PAFC_PERM_FREE_UNFUSED = 2
+  PAFC_PERM_FREE_UNFUSED = 2,
+  /* Prime-factor route for a 1-D length n = N_1 N_2 (N_3) with pairwise
+     coprime factors (the powers of 2, 3 and 5 in n; at least two of them),
+     Sec. "Prime factor framework": the input map Gamma^T (Chinese-remainder
+     reindexing) turns the length-n circular convolution into one on the
+     N_1 x N_2 (x N_3) grid, which runs permutation-free; Gamma maps the
+     result back.  Three index permutations per evaluation counting the
+     filter's, which is done once at pafc_set_filter.  Radix: NULL or 0. */
+  PAFC_PRIME_FACTOR = 3,
+  /* Comparison: the same route with the grid convolution done by the
+     explicit-permutation variant (the standard prime-factor FFT
+     convolution, six permutations). */
+  PAFC_PRIME_FACTOR_EXPLICIT = 4
 } pafc_variant;
 
 typedef enum pafc_filter_domain {

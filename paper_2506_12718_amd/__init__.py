@@ -30,7 +30,8 @@ LIB_PATH = os.path.join(_HERE, "libpafc.so")
 
 PERM_FREE, EXPLICIT_PERM, PERM_FREE_UNFUSED = 0, 1, 2
 _VARIANTS = {"perm_free": PERM_FREE, "explicit_perm": EXPLICIT_PERM,
-             "perm_free_unfused": PERM_FREE_UNFUSED}
+             "perm_free_unfused": PERM_FREE_UNFUSED, "prime_factor": 3,
+             "prime_factor_explicit": 4}
 _C64, _C128 = 1, 2
 _DOMAINS = {"spatial": 0, "spectral_natural": 1}
 

@@ -41,6 +41,11 @@ hipError_t launch_pipe(bool dbl, int r, int g, int ng, int kind, int mode, const
 hipError_t launch_mul(bool dbl, const void* x, const void* h, void* y, int64_t n, double s,
                       hipStream_t st);
 hipError_t launch_stream_copy(const void* src, void* dst, int64_t n16, hipStream_t st);
+hipError_t launch_pfa_gather(bool dbl, const void* in, void* out, const uint32_t* t0,
+                             const uint32_t* t1, const uint32_t* t2, uint32_t N1, uint32_t N2,
+                             uint32_t n, hipStream_t st);
+hipError_t launch_pfa_scatter(bool dbl, const void* in, void* out, uint32_t N0, uint32_t N1,
+                              uint32_t N2, uint32_t n, hipStream_t st);
 hipError_t launch_symbol(bool dbl, void* H, const void* g, const int32_t* m0, const int32_t* m1,
                          const int32_t* m2, uint32_t n0, uint32_t n1, uint32_t n2, uint32_t off0,
                          uint32_t off1, uint32_t off2, int mode, hipStream_t st);
@@ -938,6 +943,12 @@ struct pafc_plan_s {
   int32_t* d_maps = nullptr;  // per axis: pos, posinv
   void* d_symtab = nullptr;   // per-axis symbol tables (FP64 complex), 3 + sum n_i
   PassArgs* d_descs = nullptr;
+  // prime-factor route: the grid plan, its factors N0 <= N1 <= N2 (N0 = 1
+  // for two factors) and the gather tables (CRT input map, then the
+  // output map of the spectrum), N0 + N1 + N2 entries each
+  pafc_plan_s* inner = nullptr;
+  uint32_t pfa_N[3] = {1, 1, 1};
+  uint32_t* d_pfa_tab = nullptr;
   std::vector<int64_t> map_off;
   bool filter_set = false;
   size_t bytes = 0;
@@ -970,6 +981,8 @@ void free_plan(pafc_plan_t p) {
   if (p->d_maps) (void)hipFree(p->d_maps);
   if (p->d_symtab) (void)hipFree(p->d_symtab);
   if (p->d_descs) (void)hipFree(p->d_descs);
+  if (p->d_pfa_tab) (void)hipFree(p->d_pfa_tab);
+  if (p->inner) free_plan(p->inner);
   delete p;
 }
 
@@ -1077,6 +1090,210 @@ int64_t pass_bytes(const PlanCore& P, const Pass& ps) {
 
 }  // namespace
 
+namespace {
+
+// ---------------------------------------------------------------------------
+// Prime-factor route (Sec. "Prime factor framework").  For n with pairwise
+// coprime factors N_q, j -> (j mod N_q)_q is a ring isomorphism Z_n ->
+// prod Z_{N_q} (Chinese remainder theorem), so (j - k) mod n maps to the
+// componentwise differences and the length-n circular convolution is the
+// grid convolution of the reindexed arrays.
+
+// The powers of 2, 3 and 5 in n, ascending; false unless n is {2,3,5}-smooth
+// with at least two of them.
+bool pfa_factors(int64_t n, std::vector<int64_t>* f) {
+  f->clear();
+  for (int p : {2, 3, 5}) {
+    int64_t q = 1;
+    while (n % p == 0) {
+      n /= p;
+      q *= p;
+    }
+    if (q > 1) f->push_back(q);
+  }
+  std::sort(f->begin(), f->end());
+  return n == 1 && f->size() >= 2;
+}
+
+// a^-1 mod m for coprime a, m (m >= 1)
+int64_t inv_mod(int64_t a, int64_t m) {
+  int64_t g = m, x = 0, g1 = a % m, x1 = 1;
+  while (g1 != 0) {
+    const int64_t q = g / g1;
+    int64_t t = g - q * g1;
+    g = g1;
+    g1 = t;
+    t = x - q * x1;
+    x = x1;
+    x1 = t;
+  }
+  x %= m;
+  return x < 0 ? x + m : x;
+}
+
+// which 0: the CRT input map (x -> grid); 1: the output map of the spectrum
+pafc_status pfa_gather(pafc_plan_t p, const void* in, void* out, int which, hipStream_t s) {
+  const uint32_t* N = p->pfa_N;
+  const uint32_t* t = p->d_pfa_tab + (size_t)which * (N[0] + N[1] + N[2]);
+  return from_hip(launch_pfa_gather(p->P.dtype == PAFC_C128, in, out, t, t + N[0], t + N[0] + N[1],
+                                    N[1], N[2], (uint32_t)p->P.N, s));
+}
+
+pafc_status pfa_scatter(pafc_plan_t p, const void* in, void* out, hipStream_t s) {
+  const uint32_t* N = p->pfa_N;
+  return from_hip(launch_pfa_scatter(p->P.dtype == PAFC_C128, in, out, N[0], N[1], N[2],
+                                     (uint32_t)p->P.N, s));
+}
+
+// gather, the grid convolution in place, scatter; events (when given) before
+// the gather and after every launch
+pafc_status pfa_convolve(pafc_plan_t p, const void* x, void* y, hipStream_t s,
+                         hipEvent_t* ev = nullptr) {
+  if (ev) PAFC_TRY(from_hip(hipEventRecord(ev[0], s)));
+  PAFC_TRY(pfa_gather(p, x, p->d_scratch, 0, s));
+  PAFC_TRY(run_sequence(p->inner, p->inner->P.conv, p->d_scratch, p->d_scratch, s,
+                        ev ? ev + 1 : nullptr));
+  PAFC_TRY(pfa_scatter(p, p->d_scratch, y, s));
+  if (ev) PAFC_TRY(from_hip(hipEventRecord(ev[p->inner->P.conv.size() + 2], s)));
+  return PAFC_SUCCESS;
+}
+
+pafc_status plan_prime_factor(pafc_plan_t* out, int ndim, const int64_t* dims, const int* radix,
+                              pafc_dtype dtype, pafc_variant variant, void* hip_stream) {
+  if (ndim != 1 || !dims || (radix && radix[0] != 0)) return PAFC_ERROR_INVALID_VALUE;
+  if (dtype != PAFC_C64 && dtype != PAFC_C128) return PAFC_ERROR_INVALID_VALUE;
+  const int64_t n = dims[0];
+  if (n < 2) return PAFC_ERROR_INVALID_VALUE;
+  std::vector<int64_t> f;
+  if (n >= ((int64_t)1 << 31) || !pfa_factors(n, &f)) return PAFC_ERROR_UNSUPPORTED_SIZE;
+  pafc_plan_t p = new (std::nothrow) pafc_plan_s;
+  if (!p) return PAFC_ERROR_OUT_OF_MEMORY;
+  p->P.ndim = 1;
+  p->P.dims[0] = n;
+  p->P.N = n;
+  p->P.dtype = dtype;
+  p->P.variant = variant;
+  p->P.elem = dtype == PAFC_C128 ? 16 : 8;
+  if (hipGetDevice(&p->device) != hipSuccess) {
+    delete p;
+    return PAFC_ERROR_DEVICE;
+  }
+  pafc_status st = pafc_plan(&p->inner, (int)f.size(), f.data(), nullptr, dtype,
+                             variant == PAFC_PRIME_FACTOR ? PAFC_PERM_FREE : PAFC_EXPLICIT_PERM,
+                             hip_stream);
+  if (st != PAFC_SUCCESS) {
+    p->inner = nullptr;
+    free_plan(p);
+    return st;
+  }
+  const size_t nf = f.size();
+  for (size_t q = 0; q < nf; ++q) p->pfa_N[3 - nf + q] = (uint32_t)f[q];
+  // tables: t_q[j] = j c_q mod n, c_q = e_q (CRT basis: 1 mod N_q, 0 mod the
+  // others) for the input map, c_q = n / N_q for the spectrum's output map
+  const uint32_t tot = p->pfa_N[0] + p->pfa_N[1] + p->pfa_N[2];
+  std::vector<uint32_t> tab((size_t)2 * tot);
+  for (int which = 0; which < 2; ++which) {
+    size_t at = (size_t)which * tot;
+    for (int q = 0; q < 3; ++q) {
+      const int64_t Nq = p->pfa_N[q];
+      const int64_t m = n / Nq;
+      const int64_t c = Nq == 1 ? 0 : which == 0 ? (m % n) * inv_mod(m % Nq, Nq) % n : m;
+      for (int64_t j = 0; j < Nq; ++j) tab[at++] = (uint32_t)((j * c) % n);
+    }
+  }
+  hipStream_t s = (hipStream_t)hip_stream;
+  hipError_t e = hipMalloc((void**)&p->d_pfa_tab, tab.size() * sizeof(uint32_t));
+  if (e == hipSuccess) e = hipMalloc(&p->d_scratch, (size_t)n * p->P.elem);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(p->d_pfa_tab, tab.data(), tab.size() * sizeof(uint32_t),
+                       hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);  // the host table dies here
+  if (e != hipSuccess) {
+    free_plan(p);
+    return from_hip(e);
+  }
+  p->bytes = p->inner->bytes + tab.size() * sizeof(uint32_t) + (size_t)n * p->P.elem;
+  *out = p;
+  return PAFC_SUCCESS;
+}
+
+// Events around the gather, every grid pass and the scatter (see
+// pafc_profile_passes).
+pafc_status profile_prime_factor(pafc_plan_t p, const void* x, void* y, hipStream_t s, int reps,
+                                 double* ms_per_pass, int64_t* bytes_per_pass, double* ms_per_rep,
+                                 int* npass) {
+  const auto& seq = p->inner->P.conv;
+  const int n = (int)seq.size() + 2;
+  const int cap = *npass;
+  *npass = n;
+  if (cap < n || !ms_per_pass) return PAFC_ERROR_INVALID_VALUE;
+  std::vector<hipEvent_t> ev((size_t)(n + 1) * reps, nullptr);
+  pafc_status st = PAFC_SUCCESS;
+  for (auto& e : ev)
+    if (st == PAFC_SUCCESS) st = from_hip(hipEventCreate(&e));
+  for (int r = 0; r < reps && st == PAFC_SUCCESS; ++r)
+    st = pfa_convolve(p, x, y, s, ev.data() + (size_t)r * (n + 1));
+  if (st == PAFC_SUCCESS) st = from_hip(hipStreamSynchronize(s));
+  const int64_t perm_bytes = 2 * p->P.N * (int64_t)p->P.elem;
+  for (int k = 0; k < n && st == PAFC_SUCCESS; ++k) {
+    double tot = 0;
+    for (int r = 0; r < reps && st == PAFC_SUCCESS; ++r) {
+      float ms = 0;
+      st = from_hip(hipEventElapsedTime(&ms, ev[(size_t)r * (n + 1) + k], ev[(size_t)r * (n + 1) + k + 1]));
+      tot += ms;
+    }
+    ms_per_pass[k] = tot / reps;
+    if (bytes_per_pass)
+      bytes_per_pass[k] = (k == 0 || k == n - 1) ? perm_bytes : pass_bytes(p->inner->P, seq[(size_t)k - 1]);
+  }
+  for (int r = 0; r < reps && ms_per_rep && st == PAFC_SUCCESS; ++r) {
+    float ms = 0;
+    st = from_hip(hipEventElapsedTime(&ms, ev[(size_t)r * (n + 1)], ev[(size_t)r * (n + 1) + n]));
+    ms_per_rep[r] = ms;
+  }
+  for (auto& e : ev)
+    if (e) (void)hipEventDestroy(e);
+  return st;
+}
+
+std::string describe_prime_factor(int64_t n, pafc_dtype dtype, pafc_variant variant,
+                                  pafc_status* st) {
+  std::vector<int64_t> f;
+  *st = PAFC_SUCCESS;
+  if (n < 2) {
+    *st = PAFC_ERROR_INVALID_VALUE;
+    return "";
+  }
+  if (n >= ((int64_t)1 << 31) || !pfa_factors(n, &f)) {
+    *st = PAFC_ERROR_UNSUPPORTED_SIZE;
+    return "";
+  }
+  PlanCore G;
+  *st = plan_core(G, (int)f.size(), f.data(), nullptr, dtype,
+                  variant == PAFC_PRIME_FACTOR ? PAFC_PERM_FREE : PAFC_EXPLICIT_PERM);
+  if (*st != PAFC_SUCCESS) return "";
+  const int64_t elem = dtype == PAFC_C128 ? 16 : 8;
+  char b[256];
+  std::string s = "{";
+  snprintf(b, sizeof(b), "\"ndim\": 1, \"dims\": [%lld], \"dtype\": \"%s\", \"variant\": %d, "
+           "\"prime_factor_grid\": [", (long long)n, dtype == PAFC_C128 ? "c128" : "c64", (int)variant);
+  s += b;
+  for (size_t q = 0; q < f.size(); ++q) {
+    snprintf(b, sizeof(b), "%s%lld", q ? ", " : "", (long long)f[q]);
+    s += b;
+  }
+  s += "], \"conv_passes\": [\"pfa gather (CRT input map)\"";
+  for (auto& ps : G.conv) s += ", \"" + ps.label + "\"";
+  snprintf(b, sizeof(b), ", \"pfa scatter\"], \"hbm_bytes_conv\": %lld, \"hbm_bytes_forward\": %lld, "
+           "\"N\": %lld, \"grid\": ",
+           (long long)(G.hbm_conv + 4 * n * elem), (long long)(G.hbm_fwd + 2 * n * elem), (long long)n);
+  s += b;
+  s += describe_core(G) + "}";
+  return s;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* pafc_status_string(pafc_status s) {
@@ -1093,9 +1310,18 @@ const char* pafc_status_string(pafc_status s) {
 
 pafc_status pafc_describe(int ndim, const int64_t* dims, const int* radix, pafc_dtype dtype,
                           pafc_variant variant, char* buf, size_t cap, size_t* needed) {
-  PlanCore P;
-  PAFC_TRY(plan_core(P, ndim, dims, radix, dtype, variant));
-  std::string s = describe_core(P);
+  std::string s;
+  if (variant == PAFC_PRIME_FACTOR || variant == PAFC_PRIME_FACTOR_EXPLICIT) {
+    if (ndim != 1 || !dims || (radix && radix[0] != 0)) return PAFC_ERROR_INVALID_VALUE;
+    if (dtype != PAFC_C64 && dtype != PAFC_C128) return PAFC_ERROR_INVALID_VALUE;
+    pafc_status st;
+    s = describe_prime_factor(dims[0], dtype, variant, &st);
+    PAFC_TRY(st);
+  } else {
+    PlanCore P;
+    PAFC_TRY(plan_core(P, ndim, dims, radix, dtype, variant));
+    s = describe_core(P);
+  }
   if (needed) *needed = s.size() + 1;
   if (buf && cap > 0) {
     size_t n = std::min(cap - 1, s.size());
@@ -1109,6 +1335,8 @@ pafc_status pafc_plan(pafc_plan_t* out, int ndim, const int64_t* dims, const int
                       pafc_dtype dtype, pafc_variant variant, void* hip_stream) {
   if (!out) return PAFC_ERROR_INVALID_VALUE;
   *out = nullptr;
+  if (variant == PAFC_PRIME_FACTOR || variant == PAFC_PRIME_FACTOR_EXPLICIT)
+    return plan_prime_factor(out, ndim, dims, radix, dtype, variant, hip_stream);
   pafc_plan_t p = new (std::nothrow) pafc_plan_s;
   if (!p) return PAFC_ERROR_OUT_OF_MEMORY;
   pafc_status st = plan_core(p->P, ndim, dims, radix, dtype, variant);
@@ -1229,7 +1457,7 @@ pafc_status pafc_plan_device_bytes(pafc_plan_t p, size_t* bytes) {
 }
 
 pafc_status pafc_plan_radices(pafc_plan_t p, int axis, int* rho, int* len) {
-  if (!p || !rho || !len || axis < 0 || axis >= p->P.ndim) return PAFC_ERROR_INVALID_VALUE;
+  if (!p || !rho || !len || axis < 0 || axis >= p->P.ndim || p->inner) return PAFC_ERROR_INVALID_VALUE;
   const auto& r = p->P.axes[(size_t)axis].rho;
   const int cap = *len;
   *len = (int)r.size();
@@ -1269,7 +1497,12 @@ pafc_status pafc_set_filter(pafc_plan_t p, const void* h_dev, pafc_filter_domain
     return PAFC_ERROR_INVALID_VALUE;
   hipStream_t s = (hipStream_t)hip_stream;
   p->filter_set = false;
-  PAFC_TRY(load_filter(p, h_dev, domain, s));
+  if (p->inner) {  // reindexed to the grid, then the grid plan's own filter
+    PAFC_TRY(pfa_gather(p, h_dev, p->d_scratch, domain == PAFC_FILTER_SPATIAL ? 0 : 1, s));
+    PAFC_TRY(pafc_set_filter(p->inner, p->d_scratch, domain, hip_stream));
+  } else {
+    PAFC_TRY(load_filter(p, h_dev, domain, s));
+  }
   p->filter_set = true;
   return PAFC_SUCCESS;
 }
@@ -1281,6 +1514,10 @@ pafc_status pafc_convolve_with_filter(pafc_plan_t p, const void* x_dev, const vo
       !aligned_for(h_dev, p->P.dtype))
     return PAFC_ERROR_INVALID_VALUE;
   hipStream_t s = (hipStream_t)hip_stream;
+  if (p->inner) {
+    PAFC_TRY(pafc_set_filter(p, h_dev, PAFC_FILTER_SPATIAL, hip_stream));
+    return pfa_convolve(p, x_dev, y_dev, s);
+  }
   p->filter_set = false;
   PAFC_TRY(load_filter(p, h_dev, PAFC_FILTER_SPATIAL, s));
   p->filter_set = true;
@@ -1289,7 +1526,7 @@ pafc_status pafc_convolve_with_filter(pafc_plan_t p, const void* x_dev, const vo
 
 pafc_status pafc_set_symbol(pafc_plan_t p, pafc_symbol kind, const double* params, int nparams,
                             void* hip_stream) {
-  if (!p) return PAFC_ERROR_INVALID_VALUE;
+  if (!p || p->inner) return PAFC_ERROR_INVALID_VALUE;  // not for the prime-factor route
   const PlanCore& P = p->P;
   const int d = P.ndim;
   double t = 0;
@@ -1379,6 +1616,7 @@ pafc_status pafc_convolve(pafc_plan_t p, const void* x_dev, void* y_dev, void* h
   if (!aligned_for(x_dev, p->P.dtype) || !aligned_for(y_dev, p->P.dtype))
     return PAFC_ERROR_INVALID_VALUE;
   if (!p->filter_set) return PAFC_ERROR_FILTER_NOT_SET;
+  if (p->inner) return pfa_convolve(p, x_dev, y_dev, (hipStream_t)hip_stream);
   return run_sequence(p, p->P.conv, x_dev, y_dev, (hipStream_t)hip_stream);
 }
 
@@ -1387,6 +1625,8 @@ pafc_status pafc_profile_passes(pafc_plan_t p, const void* x_dev, void* y_dev, v
                                 double* ms_per_rep, int* npass) {
   if (!p || !x_dev || !y_dev || !npass || reps < 1) return PAFC_ERROR_INVALID_VALUE;
   if (!p->filter_set) return PAFC_ERROR_FILTER_NOT_SET;
+  if (p->inner) return profile_prime_factor(p, x_dev, y_dev, (hipStream_t)hip_stream, reps,
+                                            ms_per_pass, bytes_per_pass, ms_per_rep, npass);
   const auto& seq = p->P.conv;
   const int n = (int)seq.size();
   const int cap = *npass;
@@ -1421,14 +1661,14 @@ pafc_status pafc_profile_passes(pafc_plan_t p, const void* x_dev, void* y_dev, v
 }
 
 pafc_status pafc_forward(pafc_plan_t p, const void* x_dev, void* z_dev, void* hip_stream) {
-  if (!p || !x_dev || !z_dev) return PAFC_ERROR_INVALID_VALUE;
+  if (!p || !x_dev || !z_dev || p->inner) return PAFC_ERROR_INVALID_VALUE;
   if (!aligned_for(x_dev, p->P.dtype) || !aligned_for(z_dev, p->P.dtype))
     return PAFC_ERROR_INVALID_VALUE;
   return run_sequence(p, p->P.fwd, x_dev, z_dev, (hipStream_t)hip_stream);
 }
 
 pafc_status pafc_inverse(pafc_plan_t p, const void* z_dev, void* y_dev, void* hip_stream) {
-  if (!p || !z_dev || !y_dev) return PAFC_ERROR_INVALID_VALUE;
+  if (!p || p->inner || !z_dev || !y_dev) return PAFC_ERROR_INVALID_VALUE;
   if (!aligned_for(z_dev, p->P.dtype) || !aligned_for(y_dev, p->P.dtype))
     return PAFC_ERROR_INVALID_VALUE;
   hipStream_t s = (hipStream_t)hip_stream;

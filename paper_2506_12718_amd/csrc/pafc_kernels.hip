@@ -206,6 +206,43 @@ __global__ void symbol_kernel(cx<T>* __restrict__ H, const double2* __restrict__
   }
 }
 
+// Index maps of the prime-factor route (Sec. "Prime factor framework"): a
+// 1-D array of length n = N0 N1 N2 (pairwise coprime factors) and the
+// N0 x N1 x N2 grid it is reindexed to.
+//   gather:  out[(j0 N1 + j1) N2 + j2] = in[(t0[j0] + t1[j1] + t2[j2]) mod n]
+//            (t_q[j] = j e_q mod n: with the CRT basis e_q this is the input
+//            map Gamma^T; with e_q = n / N_q the output map of the spectrum)
+//   scatter: out[j] = in[((j mod N0) N1 + j mod N1) N2 + j mod N2]
+//            (Gamma: grid position (j mod N_q)_q back to j)
+// n < 2^31; every table entry is below n.
+template <typename T>
+__global__ void pfa_gather_kernel(const cx<T>* __restrict__ in, cx<T>* __restrict__ out,
+                                  const uint32_t* __restrict__ t0, const uint32_t* __restrict__ t1,
+                                  const uint32_t* __restrict__ t2, FastDiv d1, FastDiv d2,
+                                  uint32_t n) {
+  for (uint32_t o = blockIdx.x * blockDim.x + threadIdx.x; o < n; o += gridDim.x * blockDim.x) {
+    const uint32_t q = fdiv(o, d2);
+    const uint32_t j2 = o - q * d2.d;
+    const uint32_t j0 = fdiv(q, d1);
+    const uint32_t j1 = q - j0 * d1.d;
+    uint64_t s = (uint64_t)t0[j0] + t1[j1] + t2[j2];
+    if (s >= n) s -= n;
+    if (s >= n) s -= n;
+    out[o] = in[s];
+  }
+}
+
+template <typename T>
+__global__ void pfa_scatter_kernel(const cx<T>* __restrict__ in, cx<T>* __restrict__ out,
+                                   FastDiv d0, FastDiv d1, FastDiv d2, uint32_t n) {
+  for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
+    const uint32_t r0 = j - fdiv(j, d0) * d0.d;
+    const uint32_t r1 = j - fdiv(j, d1) * d1.d;
+    const uint32_t r2 = j - fdiv(j, d2) * d2.d;
+    out[j] = in[((uint64_t)r0 * d1.d + r1) * d2.d + r2];
+  }
+}
+
 }  // namespace pafc
 
 // ----------------------------------------------------------------- launches
@@ -296,6 +333,31 @@ hipError_t launch_symbol(bool dbl, void* H, const void* g, const int32_t* m0, co
     hipLaunchKernelGGL(symbol_kernel<float>, dim3(grid_for(n)), dim3(256), 0, st,
                        (cx<float>*)H, (const double2*)g, m0, m1, m2, n0, n1, n2, off0, off1,
                        off2, mode, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_pfa_gather(bool dbl, const void* in, void* out, const uint32_t* t0,
+                             const uint32_t* t1, const uint32_t* t2, uint32_t N1, uint32_t N2,
+                             uint32_t n, hipStream_t st) {
+  const FastDiv d1 = make_fastdiv(N1), d2 = make_fastdiv(N2);
+  if (dbl)
+    hipLaunchKernelGGL(pfa_gather_kernel<double>, dim3(grid_for(n)), dim3(256), 0, st,
+                       (const cx<double>*)in, (cx<double>*)out, t0, t1, t2, d1, d2, n);
+  else
+    hipLaunchKernelGGL(pfa_gather_kernel<float>, dim3(grid_for(n)), dim3(256), 0, st,
+                       (const cx<float>*)in, (cx<float>*)out, t0, t1, t2, d1, d2, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_pfa_scatter(bool dbl, const void* in, void* out, uint32_t N0, uint32_t N1,
+                              uint32_t N2, uint32_t n, hipStream_t st) {
+  const FastDiv d0 = make_fastdiv(N0), d1 = make_fastdiv(N1), d2 = make_fastdiv(N2);
+  if (dbl)
+    hipLaunchKernelGGL(pfa_scatter_kernel<double>, dim3(grid_for(n)), dim3(256), 0, st,
+                       (const cx<double>*)in, (cx<double>*)out, d0, d1, d2, n);
+  else
+    hipLaunchKernelGGL(pfa_scatter_kernel<float>, dim3(grid_for(n)), dim3(256), 0, st,
+                       (const cx<float>*)in, (cx<float>*)out, d0, d1, d2, n);
   return hipGetLastError();
 }
 

@@ -310,3 +310,25 @@ def test_numpy_fft_corroboration_medium():
     x, h = crand(4096), crand(4096)
     y = oracle.conv_fft(x, h, [[4] * 6])
     assert rel_l2(y, np.fft.ifft(np.fft.fft(x) * np.fft.fft(h))) < 1e-14
+
+
+@pytest.mark.parametrize("factors", [(2, 3), (4, 5), (3, 8), (2, 3, 5), (4, 9, 5)])
+def test_prime_factor_reindexing_is_an_isomorphism_of_convolutions(factors):
+    """Sec. "Prime factor framework": for pairwise coprime N_q and n = prod
+    N_q, j -> (j mod N_q)_q maps the length-n circular convolution onto the
+    grid convolution (Chinese remainder theorem), so the prime-factor route
+    reindexes x and h, convolves on the grid and maps back.  Checked with the
+    direct sum on both sides."""
+    n = int(np.prod(factors))
+    rng = np.random.default_rng(n)
+    x = inputs.complex_uniform(rng, (n,))
+    h = inputs.complex_uniform(rng, (n,))
+    j = np.arange(n)
+    grid_index = tuple(j % N for N in factors)
+    xg = np.zeros(factors, dtype=np.complex128)
+    hg = np.zeros(factors, dtype=np.complex128)
+    xg[grid_index] = x
+    hg[grid_index] = h
+    yg = oracle.conv_direct(xg, hg)
+    y = yg[grid_index]
+    assert np.allclose(y, oracle.conv_direct(x, h), atol=1e-12 * n)
