@@ -159,9 +159,23 @@ def wl_pfa1d(dtype_name):
                         "dims": [n], "grid": [125, 243, 256]})
 
 
-WORKLOADS = {"conv3d": wl_conv3d, "poisson3d": wl_poisson3d, "pfa1d": wl_pfa1d, "conv1d": wl_conv1d, "conv2d": wl_conv2d, "conv1d5": wl_conv1d5,
-             "batched": wl_batched, "serving": wl_serving, "aniso2d": wl_aniso2d,
-             "aniso3d": wl_aniso3d}
+def wl_bluestein1d(dtype_name):
+    from paper_2506_12718_amd import inputs
+    n = 1000003  # prime
+    x, h = inputs.anisotropic_case(45, (n,))
+    return dict(name="bluestein1d_1000003_%s" % dtype_name, x=x, h=h, radix=None,
+                domain="spatial", rhos=None, oracle="direct_sampled",
+                compare=["explicit_perm", "perm_free_unfused"],
+                config={"workload": "1-D convolution of prime length n = 1000003 by Bluestein's "
+                                    "method (inner convolution of length 2025000 = 2^3 3^4 5^5), "
+                                    "x and h re/im iid U[-1,1]",
+                        "dims": [n], "inner_length": 2025000})
+
+
+WORKLOADS = {"conv3d": wl_conv3d, "poisson3d": wl_poisson3d, "pfa1d": wl_pfa1d,
+             "bluestein1d": wl_bluestein1d, "conv1d": wl_conv1d, "conv2d": wl_conv2d,
+             "conv1d5": wl_conv1d5, "batched": wl_batched, "serving": wl_serving,
+             "aniso2d": wl_aniso2d, "aniso3d": wl_aniso3d}
 
 
 def bench_serving(pafc, torch, wl, tdtype, args):
@@ -512,6 +526,22 @@ def main():
             if h is not None:
                 h = h.astype(np.complex64).astype(np.complex128)
         t0 = time.perf_counter()
+        if wl.get("oracle") == "direct_sampled":
+            # the oracle's FFT has no route for a prime length: the direct
+            # sum at a bounded sample of outputs, scaled to whole convolutions
+            idx = np.random.default_rng(46).integers(0, N, 16384)
+            ref = oracle.conv_direct_at(x, h, idx)
+            t_cpu = time.perf_counter() - t0
+            got = main_r["y"].reshape(-1)[idx]
+            out["rel_l2_vs_fp64_oracle_sampled"] = float(
+                np.linalg.norm(got - ref) / np.linalg.norm(ref))
+            out["cpu_baseline"] = {
+                "value": round(idx.size / N / t_cpu, 8), "unit": "conv/s",
+                "cores": oracle.num_threads(), "kind": "oracle",
+                "sample": "%d of the %d outputs by the direct sum (long double, OpenMP over "
+                          "outputs), scaled to one convolution; %.2f s" % (idx.size, N, t_cpu)}
+            print(json.dumps(out), flush=True)
+            return
         if wl["domain"] == "spatial":
             ref = oracle.conv_fft(x, h, wl["rhos"])
         elif wl["domain"] == "symbol":

@@ -56,7 +56,8 @@ extern "C" {
 typedef enum pafc_status {
   PAFC_SUCCESS = 0,
   PAFC_ERROR_INVALID_VALUE = 1,    /* null/misaligned pointer, bad ndim, n_i < 2, bad enum */
-  PAFC_ERROR_UNSUPPORTED_SIZE = 2, /* prime factor outside {2,3,5}, or n_i != r^t for an explicit uniform radix */
+  PAFC_ERROR_UNSUPPORTED_SIZE = 2, /* prime factor outside {2,3,5} in a 2-D/3-D shape, a 1-D length above 2^29
+                                      with such a factor, or n_i != r^t for an explicit uniform radix */
   PAFC_ERROR_OUT_OF_MEMORY = 3,    /* device allocation failed */
   PAFC_ERROR_DEVICE = 4,           /* HIP runtime or launch error */
   PAFC_ERROR_FILTER_NOT_SET = 5    /* pafc_convolve before pafc_set_filter */
@@ -109,7 +110,22 @@ typedef struct pafc_plan_s* pafc_plan_t;
  *
  * ndim:   1, 2 or 3.
  * dims:   host array of ndim sizes n_1..n_d (n_d is the fastest axis); each
- *         n_i >= 2 and a product of factors in {2, 3, 5}.
+ *         n_i >= 2 and a product of factors in {2, 3, 5}, except for ndim = 1:
+ *         a length n with a prime factor above 5 (n <= 2^29) is planned by
+ *         Bluestein's method (Sec. "Rader's and Bluestein's frameworks"): the
+ *         length-n DFT becomes a circular convolution of length m, the
+ *         smallest {2,3,5}-smooth m >= 2n - 1, run on an inner plan of length
+ *         m with the requested variant (PAFC_PERM_FREE, PAFC_EXPLICIT_PERM or
+ *         PAFC_PERM_FREE_UNFUSED; radix NULL or 0).  One convolution is then
+ *         two inner convolutions (the forward DFT of x, the inverse DFT through
+ *         conjugation) between elementwise chirp products; the filter's
+ *         natural-order spectrum is taken once, at pafc_set_filter.  The plan
+ *         owns two further m-element arrays (the chirp filter's spectrum in the
+ *         inner plan and a scratch array), the n-element chirp and the
+ *         n-element filter spectrum.  pafc_forward, pafc_inverse,
+ *         pafc_set_symbol and pafc_plan_radices return INVALID_VALUE for such
+ *         a plan (its spectrum has no digit-reversed layout of its own); so
+ *         they do for a PAFC_PRIME_FACTOR(_EXPLICIT) plan.
  * radix:  NULL, or host array of ndim entries.  radix[i] = 0 lets the
  *         planner choose the radix sequence of axis i (over {2,3,4,5,8});
  *         radix[i] = r in {2,3,4,5,8} requests the uniform radix-r

@@ -46,6 +46,8 @@ hipError_t launch_pfa_gather(bool dbl, const void* in, void* out, const uint32_t
                              uint32_t n, hipStream_t st);
 hipError_t launch_pfa_scatter(bool dbl, const void* in, void* out, uint32_t N0, uint32_t N1,
                               uint32_t N2, uint32_t n, hipStream_t st);
+hipError_t launch_bluestein(bool dbl, int stage, const void* src, const void* c, void* dst,
+                            const void* hn, int64_t n, int64_t m, double s, hipStream_t st);
 hipError_t launch_symbol(bool dbl, void* H, const void* g, const int32_t* m0, const int32_t* m1,
                          const int32_t* m2, uint32_t n0, uint32_t n1, uint32_t n2, uint32_t off0,
                          uint32_t off1, uint32_t off2, int mode, hipStream_t st);
@@ -949,6 +951,11 @@ struct pafc_plan_s {
   pafc_plan_s* inner = nullptr;
   uint32_t pfa_N[3] = {1, 1, 1};
   uint32_t* d_pfa_tab = nullptr;
+  // Bluestein route (blue_m > 0): the inner plan has length blue_m; chirp
+  // c_j (n entries) and the filter's natural-order spectrum (n entries)
+  int64_t blue_m = 0;
+  void* d_chirp = nullptr;
+  void* d_hn = nullptr;
   std::vector<int64_t> map_off;
   bool filter_set = false;
   size_t bytes = 0;
@@ -982,6 +989,8 @@ void free_plan(pafc_plan_t p) {
   if (p->d_symtab) (void)hipFree(p->d_symtab);
   if (p->d_descs) (void)hipFree(p->d_descs);
   if (p->d_pfa_tab) (void)hipFree(p->d_pfa_tab);
+  if (p->d_chirp) (void)hipFree(p->d_chirp);
+  if (p->d_hn) (void)hipFree(p->d_hn);
   if (p->inner) free_plan(p->inner);
   delete p;
 }
@@ -1217,6 +1226,212 @@ pafc_status plan_prime_factor(pafc_plan_t* out, int ndim, const int64_t* dims, c
   return PAFC_SUCCESS;
 }
 
+// ---------------------------------------------------------------------------
+// Bluestein route (Sec. "Rader's and Bluestein's frameworks") for a 1-D
+// length with a prime factor above 5: the length-n DFT as a length-m
+// circular convolution, m the smallest {2,3,5}-smooth length >= 2n - 1,
+// which runs on a permutation-avoiding inner plan (or the comparison
+// variants).  A convolution: chirp-in, inner convolution, chirp product with
+// the spectrum, inner convolution (the inverse DFT through conjugation),
+// chirp-out.
+
+bool smooth235(int64_t n) {
+  for (int p : {2, 3, 5})
+    while (n % p == 0) n /= p;
+  return n == 1;
+}
+
+int64_t smooth_at_least(int64_t v) {
+  for (int64_t m = v;; ++m)
+    if (smooth235(m)) return m;
+}
+
+bool is_bluestein_case(int ndim, const int64_t* dims, const int* radix, int variant) {
+  return ndim == 1 && dims && dims[0] >= 2 && !smooth235(dims[0]) && (!radix || radix[0] == 0) &&
+         variant >= PAFC_PERM_FREE && variant <= PAFC_PERM_FREE_UNFUSED;
+}
+
+bool is_bluestein(pafc_plan_t p) { return p->blue_m > 0; }
+bool is_prime_factor(pafc_plan_t p) { return p->inner && p->blue_m == 0; }
+
+pafc_status blue_stage(pafc_plan_t p, int stage, const void* src, void* dst, hipStream_t s) {
+  return from_hip(launch_bluestein(p->P.dtype == PAFC_C128, stage, src, p->d_chirp, dst, p->d_hn,
+                                   p->P.N, p->blue_m, 1.0 / (double)p->P.N, s));
+}
+
+// events (when given) before the first launch and after every launch
+pafc_status blue_convolve(pafc_plan_t p, const void* x, void* y, hipStream_t s,
+                          hipEvent_t* ev = nullptr) {
+  const size_t k = p->inner->P.conv.size();
+  void* b = p->d_scratch;
+  if (ev) PAFC_TRY(from_hip(hipEventRecord(ev[0], s)));
+  PAFC_TRY(blue_stage(p, 0, x, b, s));
+  PAFC_TRY(run_sequence(p->inner, p->inner->P.conv, b, b, s, ev ? ev + 1 : nullptr));
+  PAFC_TRY(blue_stage(p, 2, b, b, s));
+  if (ev) PAFC_TRY(from_hip(hipEventRecord(ev[k + 2], s)));
+  PAFC_TRY(run_sequence(p->inner, p->inner->P.conv, b, b, s, ev ? ev + k + 2 : nullptr));
+  PAFC_TRY(blue_stage(p, 3, b, y, s));
+  if (ev) PAFC_TRY(from_hip(hipEventRecord(ev[2 * k + 3], s)));
+  return PAFC_SUCCESS;
+}
+
+// the filter's natural-order spectrum by the forward Bluestein DFT
+pafc_status blue_set_filter(pafc_plan_t p, const void* h, pafc_filter_domain domain,
+                            hipStream_t s) {
+  if (domain == PAFC_FILTER_SPECTRAL_NATURAL)
+    return from_hip(hipMemcpyAsync(p->d_hn, h, (size_t)p->P.N * p->P.elem,
+                                   hipMemcpyDeviceToDevice, s));
+  void* b = p->d_scratch;
+  PAFC_TRY(blue_stage(p, 0, h, b, s));
+  PAFC_TRY(run_sequence(p->inner, p->inner->P.conv, b, b, s));
+  return blue_stage(p, 1, b, p->d_hn, s);
+}
+
+pafc_status plan_bluestein(pafc_plan_t* out, int64_t n, pafc_dtype dtype, pafc_variant variant,
+                           void* hip_stream) {
+  if (dtype != PAFC_C64 && dtype != PAFC_C128) return PAFC_ERROR_INVALID_VALUE;
+  if (n > ((int64_t)1 << 29)) return PAFC_ERROR_UNSUPPORTED_SIZE;
+  const int64_t m = smooth_at_least(2 * n - 1);
+  pafc_plan_t p = new (std::nothrow) pafc_plan_s;
+  if (!p) return PAFC_ERROR_OUT_OF_MEMORY;
+  p->P.ndim = 1;
+  p->P.dims[0] = n;
+  p->P.N = n;
+  p->P.dtype = dtype;
+  p->P.variant = variant;
+  p->P.elem = dtype == PAFC_C128 ? 16 : 8;
+  p->blue_m = m;
+  if (hipGetDevice(&p->device) != hipSuccess) {
+    delete p;
+    return PAFC_ERROR_DEVICE;
+  }
+  pafc_status st = pafc_plan(&p->inner, 1, &m, nullptr, dtype, variant, hip_stream);
+  if (st != PAFC_SUCCESS) {
+    p->inner = nullptr;
+    free_plan(p);
+    return st;
+  }
+  // chirp c_j = w_{2n}^{j^2 mod 2n} (FP64 with exact octant reduction, FP32
+  // plans round it once) and the inner filter g: conj(c_d) at offsets d and
+  // m - d for 0 <= d < n, zero elsewhere
+  std::vector<double> c64((size_t)n * 2), g64((size_t)m * 2, 0.0);
+  for (int64_t j = 0; j < n; ++j) {
+    const int64_t e = (int64_t)(((unsigned __int128)j * (unsigned __int128)j) % (unsigned __int128)(2 * n));
+    omega64(2 * n, e, &c64[(size_t)j * 2], &c64[(size_t)j * 2 + 1]);
+    g64[(size_t)j * 2] = c64[(size_t)j * 2];
+    g64[(size_t)j * 2 + 1] = -c64[(size_t)j * 2 + 1];
+    if (j > 0) {
+      g64[(size_t)(m - j) * 2] = c64[(size_t)j * 2];
+      g64[(size_t)(m - j) * 2 + 1] = -c64[(size_t)j * 2 + 1];
+    }
+  }
+  std::vector<float> c32, g32;
+  const void* ch = c64.data();
+  const void* gh = g64.data();
+  if (dtype == PAFC_C64) {
+    c32.assign(c64.begin(), c64.end());
+    g32.assign(g64.begin(), g64.end());
+    ch = c32.data();
+    gh = g32.data();
+  }
+  hipStream_t s = (hipStream_t)hip_stream;
+  const size_t eb = p->P.elem;
+  hipError_t e = hipMalloc(&p->d_chirp, (size_t)n * eb);
+  if (e == hipSuccess) e = hipMalloc(&p->d_hn, (size_t)n * eb);
+  if (e == hipSuccess) e = hipMalloc(&p->d_scratch, (size_t)m * eb);
+  if (e == hipSuccess) e = hipMemcpyAsync(p->d_chirp, ch, (size_t)n * eb, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(p->d_scratch, gh, (size_t)m * eb, hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) {
+    free_plan(p);
+    return from_hip(e);
+  }
+  st = pafc_set_filter(p->inner, p->d_scratch, PAFC_FILTER_SPATIAL, hip_stream);
+  if (st == PAFC_SUCCESS) st = from_hip(hipStreamSynchronize(s));  // host tables die here
+  if (st != PAFC_SUCCESS) {
+    free_plan(p);
+    return st;
+  }
+  p->bytes = p->inner->bytes + (2 * (size_t)n + (size_t)m) * eb;
+  *out = p;
+  return PAFC_SUCCESS;
+}
+
+pafc_status profile_bluestein(pafc_plan_t p, const void* x, void* y, hipStream_t s, int reps,
+                              double* ms_per_pass, int64_t* bytes_per_pass, double* ms_per_rep,
+                              int* npass) {
+  const auto& seq = p->inner->P.conv;
+  const int k = (int)seq.size();
+  const int n = 2 * k + 3;
+  const int cap = *npass;
+  *npass = n;
+  if (cap < n || !ms_per_pass) return PAFC_ERROR_INVALID_VALUE;
+  std::vector<hipEvent_t> ev((size_t)(n + 1) * reps, nullptr);
+  pafc_status st = PAFC_SUCCESS;
+  for (auto& e : ev)
+    if (st == PAFC_SUCCESS) st = from_hip(hipEventCreate(&e));
+  for (int r = 0; r < reps && st == PAFC_SUCCESS; ++r)
+    st = blue_convolve(p, x, y, s, ev.data() + (size_t)r * (n + 1));
+  if (st == PAFC_SUCCESS) st = from_hip(hipStreamSynchronize(s));
+  const int64_t eb = p->P.elem, N = p->P.N, m = p->blue_m;
+  for (int i = 0; i < n && st == PAFC_SUCCESS; ++i) {
+    double tot = 0;
+    for (int r = 0; r < reps && st == PAFC_SUCCESS; ++r) {
+      float ms = 0;
+      st = from_hip(hipEventElapsedTime(&ms, ev[(size_t)r * (n + 1) + i], ev[(size_t)r * (n + 1) + i + 1]));
+      tot += ms;
+    }
+    ms_per_pass[i] = tot / reps;
+    if (bytes_per_pass) {
+      if (i == 0) bytes_per_pass[i] = (2 * N + m) * eb;             // chirp-in
+      else if (i == k + 1) bytes_per_pass[i] = (2 * m + 2 * N) * eb;  // chirp product
+      else if (i == n - 1) bytes_per_pass[i] = (m + 2 * N) * eb;     // chirp-out
+      else bytes_per_pass[i] = pass_bytes(p->inner->P, seq[(size_t)((i - 1) % (k + 1))]);
+    }
+  }
+  for (int r = 0; r < reps && ms_per_rep && st == PAFC_SUCCESS; ++r) {
+    float ms = 0;
+    st = from_hip(hipEventElapsedTime(&ms, ev[(size_t)r * (n + 1)], ev[(size_t)r * (n + 1) + n]));
+    ms_per_rep[r] = ms;
+  }
+  for (auto& e : ev)
+    if (e) (void)hipEventDestroy(e);
+  return st;
+}
+
+std::string describe_bluestein(int64_t n, pafc_dtype dtype, pafc_variant variant,
+                               pafc_status* st) {
+  *st = PAFC_SUCCESS;
+  if (dtype != PAFC_C64 && dtype != PAFC_C128) {
+    *st = PAFC_ERROR_INVALID_VALUE;
+    return "";
+  }
+  if (n > ((int64_t)1 << 29)) {
+    *st = PAFC_ERROR_UNSUPPORTED_SIZE;
+    return "";
+  }
+  const int64_t m = smooth_at_least(2 * n - 1);
+  PlanCore G;
+  *st = plan_core(G, 1, &m, nullptr, dtype, variant);
+  if (*st != PAFC_SUCCESS) return "";
+  const int64_t eb = dtype == PAFC_C128 ? 16 : 8;
+  char b[256];
+  std::string s = "{";
+  snprintf(b, sizeof(b), "\"ndim\": 1, \"dims\": [%lld], \"dtype\": \"%s\", \"variant\": %d, "
+           "\"bluestein_m\": %lld, \"conv_passes\": [\"bluestein chirp-in\"",
+           (long long)n, dtype == PAFC_C128 ? "c128" : "c64", (int)variant, (long long)m);
+  s += b;
+  for (auto& ps : G.conv) s += ", \"" + ps.label + "\"";
+  s += ", \"bluestein chirp product\"";
+  for (auto& ps : G.conv) s += ", \"" + ps.label + "\"";
+  snprintf(b, sizeof(b), ", \"bluestein chirp-out\"], \"hbm_bytes_conv\": %lld, "
+           "\"hbm_bytes_forward\": %lld, \"N\": %lld, \"inner\": ",
+           (long long)(2 * G.hbm_conv + ((2 * n + m) + (2 * m + 2 * n) + (m + 2 * n)) * eb), (long long)(G.hbm_conv + (2 * n + m) * eb + 2 * n * eb),
+           (long long)n);
+  s += b;
+  s += describe_core(G) + "}";
+  return s;
+}
+
 // Events around the gather, every grid pass and the scatter (see
 // pafc_profile_passes).
 pafc_status profile_prime_factor(pafc_plan_t p, const void* x, void* y, hipStream_t s, int reps,
@@ -1311,7 +1526,11 @@ const char* pafc_status_string(pafc_status s) {
 pafc_status pafc_describe(int ndim, const int64_t* dims, const int* radix, pafc_dtype dtype,
                           pafc_variant variant, char* buf, size_t cap, size_t* needed) {
   std::string s;
-  if (variant == PAFC_PRIME_FACTOR || variant == PAFC_PRIME_FACTOR_EXPLICIT) {
+  if (is_bluestein_case(ndim, dims, radix, variant)) {
+    pafc_status st;
+    s = describe_bluestein(dims[0], dtype, variant, &st);
+    PAFC_TRY(st);
+  } else if (variant == PAFC_PRIME_FACTOR || variant == PAFC_PRIME_FACTOR_EXPLICIT) {
     if (ndim != 1 || !dims || (radix && radix[0] != 0)) return PAFC_ERROR_INVALID_VALUE;
     if (dtype != PAFC_C64 && dtype != PAFC_C128) return PAFC_ERROR_INVALID_VALUE;
     pafc_status st;
@@ -1337,6 +1556,8 @@ pafc_status pafc_plan(pafc_plan_t* out, int ndim, const int64_t* dims, const int
   *out = nullptr;
   if (variant == PAFC_PRIME_FACTOR || variant == PAFC_PRIME_FACTOR_EXPLICIT)
     return plan_prime_factor(out, ndim, dims, radix, dtype, variant, hip_stream);
+  if (is_bluestein_case(ndim, dims, radix, variant))
+    return plan_bluestein(out, dims[0], dtype, variant, hip_stream);
   pafc_plan_t p = new (std::nothrow) pafc_plan_s;
   if (!p) return PAFC_ERROR_OUT_OF_MEMORY;
   pafc_status st = plan_core(p->P, ndim, dims, radix, dtype, variant);
@@ -1497,7 +1718,9 @@ pafc_status pafc_set_filter(pafc_plan_t p, const void* h_dev, pafc_filter_domain
     return PAFC_ERROR_INVALID_VALUE;
   hipStream_t s = (hipStream_t)hip_stream;
   p->filter_set = false;
-  if (p->inner) {  // reindexed to the grid, then the grid plan's own filter
+  if (is_bluestein(p)) {
+    PAFC_TRY(blue_set_filter(p, h_dev, domain, s));
+  } else if (p->inner) {  // reindexed to the grid, then the grid plan's own filter
     PAFC_TRY(pfa_gather(p, h_dev, p->d_scratch, domain == PAFC_FILTER_SPATIAL ? 0 : 1, s));
     PAFC_TRY(pafc_set_filter(p->inner, p->d_scratch, domain, hip_stream));
   } else {
@@ -1516,7 +1739,7 @@ pafc_status pafc_convolve_with_filter(pafc_plan_t p, const void* x_dev, const vo
   hipStream_t s = (hipStream_t)hip_stream;
   if (p->inner) {
     PAFC_TRY(pafc_set_filter(p, h_dev, PAFC_FILTER_SPATIAL, hip_stream));
-    return pfa_convolve(p, x_dev, y_dev, s);
+    return is_bluestein(p) ? blue_convolve(p, x_dev, y_dev, s) : pfa_convolve(p, x_dev, y_dev, s);
   }
   p->filter_set = false;
   PAFC_TRY(load_filter(p, h_dev, PAFC_FILTER_SPATIAL, s));
@@ -1526,7 +1749,7 @@ pafc_status pafc_convolve_with_filter(pafc_plan_t p, const void* x_dev, const vo
 
 pafc_status pafc_set_symbol(pafc_plan_t p, pafc_symbol kind, const double* params, int nparams,
                             void* hip_stream) {
-  if (!p || p->inner) return PAFC_ERROR_INVALID_VALUE;  // not for the prime-factor route
+  if (!p || p->inner) return PAFC_ERROR_INVALID_VALUE;  // not for the prime-factor or Bluestein routes
   const PlanCore& P = p->P;
   const int d = P.ndim;
   double t = 0;
@@ -1616,6 +1839,7 @@ pafc_status pafc_convolve(pafc_plan_t p, const void* x_dev, void* y_dev, void* h
   if (!aligned_for(x_dev, p->P.dtype) || !aligned_for(y_dev, p->P.dtype))
     return PAFC_ERROR_INVALID_VALUE;
   if (!p->filter_set) return PAFC_ERROR_FILTER_NOT_SET;
+  if (is_bluestein(p)) return blue_convolve(p, x_dev, y_dev, (hipStream_t)hip_stream);
   if (p->inner) return pfa_convolve(p, x_dev, y_dev, (hipStream_t)hip_stream);
   return run_sequence(p, p->P.conv, x_dev, y_dev, (hipStream_t)hip_stream);
 }
@@ -1625,6 +1849,9 @@ pafc_status pafc_profile_passes(pafc_plan_t p, const void* x_dev, void* y_dev, v
                                 double* ms_per_rep, int* npass) {
   if (!p || !x_dev || !y_dev || !npass || reps < 1) return PAFC_ERROR_INVALID_VALUE;
   if (!p->filter_set) return PAFC_ERROR_FILTER_NOT_SET;
+  if (is_bluestein(p))
+    return profile_bluestein(p, x_dev, y_dev, (hipStream_t)hip_stream, reps, ms_per_pass,
+                             bytes_per_pass, ms_per_rep, npass);
   if (p->inner) return profile_prime_factor(p, x_dev, y_dev, (hipStream_t)hip_stream, reps,
                                             ms_per_pass, bytes_per_pass, ms_per_rep, npass);
   const auto& seq = p->P.conv;

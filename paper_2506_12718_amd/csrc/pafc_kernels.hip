@@ -243,6 +243,55 @@ __global__ void pfa_scatter_kernel(const cx<T>* __restrict__ in, cx<T>* __restri
   }
 }
 
+// Bluestein's method (Sec. "Rader's and Bluestein's frameworks"): the
+// length-n DFT as a length-m circular convolution (m >= 2n - 1) with the
+// chirp c_j = w_{2n}^{j^2}:  DFT(x)_k = c_k [ (x o c, padded) (*) g ]_k, with
+// g the filter of the inner plan (conj(c) on offsets |d| < n).  The inverse
+// DFT reuses the same convolution through conjugation.
+//   in:   a_j = x_j c_j (j < n), 0 (n <= j < m)
+//   spec: Hn_k = c_k b_k (k < n)                 (a filter's spectrum)
+//   mid:  b_k = conj(c_k b_k Hn_k) c_k (k < n), 0 (k >= n)
+//   out:  y_j = conj(c_j b_j) s
+template <typename T>
+__global__ void blue_in_kernel(const cx<T>* __restrict__ x, const cx<T>* __restrict__ c,
+                               cx<T>* __restrict__ a, int64_t n, int64_t m) {
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < m;
+       j += (int64_t)gridDim.x * blockDim.x)
+    a[j] = j < n ? cmul(x[j], c[j]) : cx<T>{(T)0, (T)0};
+}
+
+template <typename T>
+__global__ void blue_spec_kernel(const cx<T>* __restrict__ b, const cx<T>* __restrict__ c,
+                                 cx<T>* __restrict__ hn, int64_t n) {
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+       k += (int64_t)gridDim.x * blockDim.x)
+    hn[k] = cmul(c[k], b[k]);
+}
+
+template <typename T>
+__global__ void blue_mid_kernel(cx<T>* __restrict__ b, const cx<T>* __restrict__ c,
+                                const cx<T>* __restrict__ hn, int64_t n, int64_t m) {
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < m;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    cx<T> v = {(T)0, (T)0};
+    if (k < n) {
+      const cx<T> z = cmul(cmul(c[k], b[k]), hn[k]);
+      v = cmul(cx<T>{z.re, -z.im}, c[k]);
+    }
+    b[k] = v;
+  }
+}
+
+template <typename T>
+__global__ void blue_out_kernel(const cx<T>* __restrict__ b, const cx<T>* __restrict__ c,
+                                cx<T>* __restrict__ y, int64_t n, T s) {
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n;
+       j += (int64_t)gridDim.x * blockDim.x) {
+    const cx<T> z = cmul(c[j], b[j]);
+    y[j] = cx<T>{z.re * s, -z.im * s};
+  }
+}
+
 }  // namespace pafc
 
 // ----------------------------------------------------------------- launches
@@ -358,6 +407,40 @@ hipError_t launch_pfa_scatter(bool dbl, const void* in, void* out, uint32_t N0, 
   else
     hipLaunchKernelGGL(pfa_scatter_kernel<float>, dim3(grid_for(n)), dim3(256), 0, st,
                        (const cx<float>*)in, (cx<float>*)out, d0, d1, d2, n);
+  return hipGetLastError();
+}
+
+// stage 0 in, 1 spec, 2 mid, 3 out (see blue_*_kernel)
+hipError_t launch_bluestein(bool dbl, int stage, const void* src, const void* c, void* dst,
+                            const void* hn, int64_t n, int64_t m, double s, hipStream_t st) {
+  const uint32_t g = grid_for(stage == 0 || stage == 2 ? m : n);
+#define PAFC_BL(TT)                                                                              \
+  switch (stage) {                                                                               \
+    case 0:                                                                                      \
+      hipLaunchKernelGGL(blue_in_kernel<TT>, dim3(g), dim3(256), 0, st, (const cx<TT>*)src,      \
+                         (const cx<TT>*)c, (cx<TT>*)dst, n, m);                                  \
+      break;                                                                                     \
+    case 1:                                                                                      \
+      hipLaunchKernelGGL(blue_spec_kernel<TT>, dim3(g), dim3(256), 0, st, (const cx<TT>*)src,    \
+                         (const cx<TT>*)c, (cx<TT>*)dst, n);                                     \
+      break;                                                                                     \
+    case 2:                                                                                      \
+      hipLaunchKernelGGL(blue_mid_kernel<TT>, dim3(g), dim3(256), 0, st, (cx<TT>*)dst,           \
+                         (const cx<TT>*)c, (const cx<TT>*)hn, n, m);                             \
+      break;                                                                                     \
+    case 3:                                                                                      \
+      hipLaunchKernelGGL(blue_out_kernel<TT>, dim3(g), dim3(256), 0, st, (const cx<TT>*)src,     \
+                         (const cx<TT>*)c, (cx<TT>*)dst, n, (TT)s);                              \
+      break;                                                                                     \
+    default:                                                                                     \
+      return hipErrorInvalidValue;                                                               \
+  }
+  if (dbl) {
+    PAFC_BL(double)
+  } else {
+    PAFC_BL(float)
+  }
+#undef PAFC_BL
   return hipGetLastError();
 }
 

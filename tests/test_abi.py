@@ -73,8 +73,8 @@ def test_auto_radix_factorizes(n):
 
 
 def test_describe_errors():
-    with pytest.raises(pafc.PafcError) as e:
-        pafc.describe((7,), "c128")
+    with pytest.raises(pafc.PafcError) as e:  # Bluestein is 1-D only
+        pafc.describe((7, 4), "c128")
     assert e.value.status == 2
     with pytest.raises(pafc.PafcError) as e:
         pafc.describe((1,), "c128")
@@ -203,3 +203,26 @@ def test_anisotropic_plans():
         dt = "c128" if dtype == mod.C128 else "c64"
         d = pafc.describe(dims, dt, radix=radix)
         assert any("XDIF" in l for l in d["conv_passes"]), (dims, dt)
+
+
+def test_bluestein_plans():
+    """A 1-D length with a prime factor above 5 runs by Bluestein's method on
+    an inner convolution of the smallest {2,3,5}-smooth length >= 2n - 1."""
+    for n in (7, 97, 1009, 4099, 1000003, 1001):
+        d = pafc.describe((n,), "c128")
+        m = d["bluestein_m"]
+        assert m >= 2 * n - 1
+        k = m
+        for p in (2, 3, 5):
+            while k % p == 0:
+                k //= p
+        assert k == 1
+        for c in range(2 * n - 1, m):  # m is the smallest such length
+            for p in (2, 3, 5):
+                while c % p == 0:
+                    c //= p
+            assert c != 1
+        inner = len(d["inner"]["conv_passes"])
+        assert len(d["conv_passes"]) == 2 * inner + 3
+    with pytest.raises(pafc.PafcError):
+        pafc.describe((7, 7), "c128")
