@@ -172,8 +172,21 @@ def wl_bluestein1d(dtype_name):
                         "dims": [n], "inner_length": 2025000})
 
 
+def wl_rader1d(dtype_name):
+    from paper_2506_12718_amd import inputs
+    n = 995329  # prime, n - 1 = 2^12 3^5
+    x, h = inputs.anisotropic_case(47, (n,))
+    return dict(name="rader1d_995329_%s" % dtype_name, x=x, h=h, radix=None,
+                domain="spatial", rhos=None, oracle="direct_sampled",
+                compare=["explicit_perm", "perm_free_unfused", "bluestein"],
+                config={"workload": "1-D convolution of prime length n = 995329 by Rader's "
+                                    "method (inner convolution of length n - 1 = 2^12 3^5), "
+                                    "x and h re/im iid U[-1,1]",
+                        "dims": [n], "inner_length": n - 1})
+
+
 WORKLOADS = {"conv3d": wl_conv3d, "poisson3d": wl_poisson3d, "pfa1d": wl_pfa1d,
-             "bluestein1d": wl_bluestein1d, "conv1d": wl_conv1d, "conv2d": wl_conv2d,
+             "bluestein1d": wl_bluestein1d, "rader1d": wl_rader1d, "conv1d": wl_conv1d, "conv2d": wl_conv2d,
              "conv1d5": wl_conv1d5, "batched": wl_batched, "serving": wl_serving,
              "aniso2d": wl_aniso2d, "aniso3d": wl_aniso3d}
 
@@ -345,7 +358,14 @@ def measure(pafc, torch, wl, tdtype, variant, steps, warmup, filter_per_call=Fal
     HIP event around every kernel launch.  With `filter_per_call` the timed
     calls are pafc_convolve_with_filter (the filter transformed in every
     call, wall clock over the stream), and the per-launch events come from a
-    second run of the convolution passes alone.  Returns a dict of results."""
+    second run of the convolution passes alone.  Variant "bluestein" is the
+    permutation-avoiding variant with a prime length planned by Bluestein's
+    method (PAFC_BLUESTEIN=1) where Rader's would apply.  Returns a dict of
+    results."""
+    force_bluestein = variant == "bluestein"
+    if force_bluestein:
+        os.environ["PAFC_BLUESTEIN"] = "1"
+        variant = "perm_free"
     plan = pafc.Plan(wl["x"].shape, tdtype, radix=wl["radix"], variant=variant)
     xd = torch.from_numpy(wl["x"]).to(tdtype).cuda()
     yd = torch.empty_like(xd)
@@ -382,6 +402,8 @@ def measure(pafc, torch, wl, tdtype, variant, steps, warmup, filter_per_call=Fal
     del hd
     desc = pafc.describe(wl["x"].shape, "c128" if tdtype == torch.complex128 else "c64",
                          wl["radix"], variant)
+    if force_bluestein:
+        del os.environ["PAFC_BLUESTEIN"]
     y = yd.cpu().numpy()
     plan.close()
     del xd, yd

@@ -48,6 +48,9 @@ hipError_t launch_pfa_scatter(bool dbl, const void* in, void* out, uint32_t N0, 
                               uint32_t N2, uint32_t n, hipStream_t st);
 hipError_t launch_bluestein(bool dbl, int stage, const void* src, const void* c, void* dst,
                             const void* hn, int64_t n, int64_t m, double s, hipStream_t st);
+hipError_t launch_rader(bool dbl, int stage, int mode, const void* src, const void* x, void* dst,
+                        void* hq, const uint32_t* pw, const uint32_t* lg, double* part,
+                        void* consts, uint32_t p, double s, hipStream_t st);
 hipError_t launch_symbol(bool dbl, void* H, const void* g, const int32_t* m0, const int32_t* m1,
                          const int32_t* m2, uint32_t n0, uint32_t n1, uint32_t n2, uint32_t off0,
                          uint32_t off1, uint32_t off2, int mode, hipStream_t st);
@@ -76,6 +79,8 @@ constexpr size_t kLdsBudget = 160 * 1024;  // LDS per CU on gfx950
 //   PAFC_TUNE_MID  axis that carries the fused product (default 0, the slowest)
 //   PAFC_WIDE      0 disables the wide (1024-thread) register class
 //   PAFC_FOLD      0 keeps short faster axes in passes of their own
+//   PAFC_BLUESTEIN 1 plans a prime length by Bluestein's method even where
+//                  Rader's applies (p - 1 {2,3,5}-smooth)
 int env_int(const char* name, int dflt) {
   const char* v = getenv(name);
   return v && *v ? atoi(v) : dflt;
@@ -956,6 +961,13 @@ struct pafc_plan_s {
   int64_t blue_m = 0;
   void* d_chirp = nullptr;
   void* d_hn = nullptr;
+  // Rader route (rader_g > 0, the generator): the inner plan has length
+  // n - 1; d_hn holds the spectrum in generator order (n entries);
+  // d_rader_tab the powers g^m (n - 1 entries) then -log_g j (n entries);
+  // d_rader_acc the block sums (kRaderBlocks x 4 doubles) then two constants
+  int64_t rader_g = 0;
+  uint32_t* d_rader_tab = nullptr;
+  double* d_rader_acc = nullptr;
   std::vector<int64_t> map_off;
   bool filter_set = false;
   size_t bytes = 0;
@@ -991,6 +1003,8 @@ void free_plan(pafc_plan_t p) {
   if (p->d_pfa_tab) (void)hipFree(p->d_pfa_tab);
   if (p->d_chirp) (void)hipFree(p->d_chirp);
   if (p->d_hn) (void)hipFree(p->d_hn);
+  if (p->d_rader_tab) (void)hipFree(p->d_rader_tab);
+  if (p->d_rader_acc) (void)hipFree(p->d_rader_acc);
   if (p->inner) free_plan(p->inner);
   delete p;
 }
@@ -1246,13 +1260,29 @@ int64_t smooth_at_least(int64_t v) {
     if (smooth235(m)) return m;
 }
 
+bool is_prime(int64_t n) {
+  if (n < 2) return false;
+  for (int64_t d = 2; d * d <= n; ++d)
+    if (n % d == 0) return false;
+  return true;
+}
+
+bool is_rader_case(int ndim, const int64_t* dims, const int* radix, int variant) {
+  return ndim == 1 && dims && dims[0] >= 7 && dims[0] <= ((int64_t)1 << 30) &&
+         (!radix || radix[0] == 0) && variant >= PAFC_PERM_FREE &&
+         variant <= PAFC_PERM_FREE_UNFUSED && !smooth235(dims[0]) && smooth235(dims[0] - 1) &&
+         is_prime(dims[0]) && env_int("PAFC_BLUESTEIN", 0) == 0;
+}
+
 bool is_bluestein_case(int ndim, const int64_t* dims, const int* radix, int variant) {
   return ndim == 1 && dims && dims[0] >= 2 && !smooth235(dims[0]) && (!radix || radix[0] == 0) &&
-         variant >= PAFC_PERM_FREE && variant <= PAFC_PERM_FREE_UNFUSED;
+         variant >= PAFC_PERM_FREE && variant <= PAFC_PERM_FREE_UNFUSED &&
+         !is_rader_case(ndim, dims, radix, variant);
 }
 
 bool is_bluestein(pafc_plan_t p) { return p->blue_m > 0; }
-bool is_prime_factor(pafc_plan_t p) { return p->inner && p->blue_m == 0; }
+bool is_rader(pafc_plan_t p) { return p->rader_g > 0; }
+bool is_prime_factor(pafc_plan_t p) { return p->inner && p->blue_m == 0 && p->rader_g == 0; }
 
 pafc_status blue_stage(pafc_plan_t p, int stage, const void* src, void* dst, hipStream_t s) {
   return from_hip(launch_bluestein(p->P.dtype == PAFC_C128, stage, src, p->d_chirp, dst, p->d_hn,
@@ -1432,6 +1462,240 @@ std::string describe_bluestein(int64_t n, pafc_dtype dtype, pafc_variant variant
   return s;
 }
 
+// ---------------------------------------------------------------------------
+// Rader route (Sec. "Rader's and Bluestein's frameworks") for a prime length
+// p whose p - 1 is {2,3,5}-smooth: the DFT at the nonzero frequencies is a
+// length p - 1 circular convolution after reindexing by powers of a
+// generator g; that convolution runs on a permutation-avoiding inner plan.
+// The spectrum stays in generator order between the two inner convolutions,
+// so one evaluation permutes twice (gather in, scatter out) where undoing
+// each reindexing would take four.  A convolution: gather, inner
+// convolution, product with the spectrum (+ block sums), the two DC
+// constants, inner convolution (the inverse DFT through conjugation),
+// scatter.
+
+uint64_t mulmod(uint64_t a, uint64_t b, uint64_t m) {
+  return (uint64_t)((unsigned __int128)a * b % m);
+}
+
+uint64_t powmod(uint64_t b, uint64_t e, uint64_t m) {
+  uint64_t r = 1 % m;
+  for (b %= m; e; e >>= 1, b = mulmod(b, b, m))
+    if (e & 1) r = mulmod(r, b, m);
+  return r;
+}
+
+// smallest generator of the multiplicative group mod the prime p (p - 1
+// has prime factors in {2, 3, 5} only)
+int64_t primitive_root(int64_t p) {
+  for (int64_t g = 2; g < p; ++g) {
+    bool ok = true;
+    for (int q : {2, 3, 5})
+      if ((p - 1) % q == 0 && powmod((uint64_t)g, (uint64_t)((p - 1) / q), (uint64_t)p) == 1)
+        ok = false;
+    if (ok) return g;
+  }
+  return 0;
+}
+
+pafc_status rader_stage(pafc_plan_t p, int stage, int mode, const void* src, const void* x,
+                        void* dst, hipStream_t s) {
+  const uint32_t n = (uint32_t)p->P.N;
+  const double* acc = p->d_rader_acc;
+  return from_hip(launch_rader(p->P.dtype == PAFC_C128, stage, mode, src, x, dst, p->d_hn,
+                               p->d_rader_tab, p->d_rader_tab + (n - 1), p->d_rader_acc,
+                               (void*)(acc + 4 * (size_t)kRaderBlocks), n, 1.0 / (double)n, s));
+}
+
+// events (when given) before the first launch and after every launch
+pafc_status rader_convolve(pafc_plan_t p, const void* x, void* y, hipStream_t s,
+                           hipEvent_t* ev = nullptr) {
+  const size_t k = p->inner->P.conv.size();
+  void* b = p->d_scratch;
+  if (ev) PAFC_TRY(from_hip(hipEventRecord(ev[0], s)));
+  PAFC_TRY(rader_stage(p, 0, 0, x, nullptr, b, s));
+  PAFC_TRY(run_sequence(p->inner, p->inner->P.conv, b, b, s, ev ? ev + 1 : nullptr));
+  PAFC_TRY(rader_stage(p, 1, 1, nullptr, x, b, s));
+  if (ev) PAFC_TRY(from_hip(hipEventRecord(ev[k + 2], s)));
+  PAFC_TRY(rader_stage(p, 2, 1, nullptr, x, nullptr, s));
+  if (ev) PAFC_TRY(from_hip(hipEventRecord(ev[k + 3], s)));
+  PAFC_TRY(run_sequence(p->inner, p->inner->P.conv, b, b, s, ev ? ev + k + 3 : nullptr));
+  PAFC_TRY(rader_stage(p, 3, 0, b, nullptr, y, s));
+  if (ev) PAFC_TRY(from_hip(hipEventRecord(ev[2 * k + 4], s)));
+  return PAFC_SUCCESS;
+}
+
+// the filter's spectrum in generator order: by the forward Rader DFT, or
+// reordered from a natural-order spectrum
+pafc_status rader_set_filter(pafc_plan_t p, const void* h, pafc_filter_domain domain,
+                             hipStream_t s) {
+  if (domain == PAFC_FILTER_SPECTRAL_NATURAL) return rader_stage(p, 4, 0, h, nullptr, nullptr, s);
+  void* b = p->d_scratch;
+  PAFC_TRY(rader_stage(p, 0, 0, h, nullptr, b, s));
+  PAFC_TRY(run_sequence(p->inner, p->inner->P.conv, b, b, s));
+  PAFC_TRY(rader_stage(p, 1, 0, nullptr, h, b, s));
+  return rader_stage(p, 2, 0, nullptr, h, nullptr, s);
+}
+
+pafc_status plan_rader(pafc_plan_t* out, int64_t n, pafc_dtype dtype, pafc_variant variant,
+                       void* hip_stream) {
+  if (dtype != PAFC_C64 && dtype != PAFC_C128) return PAFC_ERROR_INVALID_VALUE;
+  const int64_t P1 = n - 1;
+  const int64_t g = primitive_root(n);
+  if (g == 0) return PAFC_ERROR_UNSUPPORTED_SIZE;
+  pafc_plan_t p = new (std::nothrow) pafc_plan_s;
+  if (!p) return PAFC_ERROR_OUT_OF_MEMORY;
+  p->P.ndim = 1;
+  p->P.dims[0] = n;
+  p->P.N = n;
+  p->P.dtype = dtype;
+  p->P.variant = variant;
+  p->P.elem = dtype == PAFC_C128 ? 16 : 8;
+  p->rader_g = g;
+  if (hipGetDevice(&p->device) != hipSuccess) {
+    delete p;
+    return PAFC_ERROR_DEVICE;
+  }
+  pafc_status st = pafc_plan(&p->inner, 1, &P1, nullptr, dtype, variant, hip_stream);
+  if (st != PAFC_SUCCESS) {
+    p->inner = nullptr;
+    free_plan(p);
+    return st;
+  }
+  // tables and the inner filter b_l = w_n^{g^{-l}} (FP64 with exact octant
+  // reduction; FP32 plans round it once)
+  std::vector<uint32_t> tab((size_t)(P1 + n), 0);
+  uint64_t gm = 1;
+  for (int64_t m = 0; m < P1; ++m, gm = mulmod(gm, (uint64_t)g, (uint64_t)n)) {
+    tab[(size_t)m] = (uint32_t)gm;
+    tab[(size_t)(P1 + (int64_t)gm)] = (uint32_t)((P1 - m) % P1);
+  }
+  std::vector<double> b64((size_t)P1 * 2);
+  for (int64_t l = 0; l < P1; ++l) {
+    const int64_t e = tab[(size_t)((P1 - l) % P1)];
+    omega64(n, e, &b64[(size_t)l * 2], &b64[(size_t)l * 2 + 1]);
+  }
+  std::vector<float> b32;
+  const void* bh = b64.data();
+  if (dtype == PAFC_C64) {
+    b32.assign(b64.begin(), b64.end());
+    bh = b32.data();
+  }
+  hipStream_t s = (hipStream_t)hip_stream;
+  const size_t eb = p->P.elem;
+  hipError_t e = hipMalloc(&p->d_hn, (size_t)n * eb);
+  if (e == hipSuccess) e = hipMalloc(&p->d_scratch, (size_t)P1 * eb);
+  if (e == hipSuccess) e = hipMalloc((void**)&p->d_rader_tab, tab.size() * sizeof(uint32_t));
+  if (e == hipSuccess) e = hipMalloc((void**)&p->d_rader_acc, (4 * (size_t)kRaderBlocks + 8) * sizeof(double));
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(p->d_rader_tab, tab.data(), tab.size() * sizeof(uint32_t),
+                       hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(p->d_scratch, bh, (size_t)P1 * eb, hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) {
+    free_plan(p);
+    return from_hip(e);
+  }
+  st = pafc_set_filter(p->inner, p->d_scratch, PAFC_FILTER_SPATIAL, hip_stream);
+  if (st == PAFC_SUCCESS) st = from_hip(hipStreamSynchronize(s));  // host tables die here
+  if (st != PAFC_SUCCESS) {
+    free_plan(p);
+    return st;
+  }
+  p->bytes = p->inner->bytes + ((size_t)n + (size_t)P1) * eb +
+             tab.size() * sizeof(uint32_t) + (4 * (size_t)kRaderBlocks + 8) * sizeof(double);
+  *out = p;
+  return PAFC_SUCCESS;
+}
+
+// algorithmic bytes of the Rader stages: gather (x, table, a), product
+// (u, spectrum, w), constants (block sums), scatter (v, table, y)
+void rader_stage_bytes(int64_t n, int64_t eb, int64_t* gather, int64_t* product,
+                       int64_t* fin, int64_t* scatter) {
+  const int64_t P1 = n - 1;
+  *gather = (2 * eb + 4) * P1;
+  *product = 3 * eb * P1;
+  *fin = 4 * 8 * ((P1 / 2 + 1 + 255) / 256 < (int64_t)kRaderBlocks ? (P1 / 2 + 1 + 255) / 256
+                                                                    : (int64_t)kRaderBlocks);
+  *scatter = (2 * eb + 4) * n;
+}
+
+pafc_status profile_rader(pafc_plan_t p, const void* x, void* y, hipStream_t s, int reps,
+                          double* ms_per_pass, int64_t* bytes_per_pass, double* ms_per_rep,
+                          int* npass) {
+  const auto& seq = p->inner->P.conv;
+  const int k = (int)seq.size();
+  const int n = 2 * k + 4;
+  const int cap = *npass;
+  *npass = n;
+  if (cap < n || !ms_per_pass) return PAFC_ERROR_INVALID_VALUE;
+  std::vector<hipEvent_t> ev((size_t)(n + 1) * reps, nullptr);
+  pafc_status st = PAFC_SUCCESS;
+  for (auto& e : ev)
+    if (st == PAFC_SUCCESS) st = from_hip(hipEventCreate(&e));
+  for (int r = 0; r < reps && st == PAFC_SUCCESS; ++r)
+    st = rader_convolve(p, x, y, s, ev.data() + (size_t)r * (n + 1));
+  if (st == PAFC_SUCCESS) st = from_hip(hipStreamSynchronize(s));
+  int64_t bg, bp, bf, bs;
+  rader_stage_bytes(p->P.N, p->P.elem, &bg, &bp, &bf, &bs);
+  for (int i = 0; i < n && st == PAFC_SUCCESS; ++i) {
+    double tot = 0;
+    for (int r = 0; r < reps && st == PAFC_SUCCESS; ++r) {
+      float ms = 0;
+      st = from_hip(hipEventElapsedTime(&ms, ev[(size_t)r * (n + 1) + i], ev[(size_t)r * (n + 1) + i + 1]));
+      tot += ms;
+    }
+    ms_per_pass[i] = tot / reps;
+    if (bytes_per_pass) {
+      if (i == 0) bytes_per_pass[i] = bg;
+      else if (i == k + 1) bytes_per_pass[i] = bp;
+      else if (i == k + 2) bytes_per_pass[i] = bf;
+      else if (i == n - 1) bytes_per_pass[i] = bs;
+      else bytes_per_pass[i] = pass_bytes(p->inner->P, seq[(size_t)(i <= k ? i - 1 : i - k - 3)]);
+    }
+  }
+  for (int r = 0; r < reps && ms_per_rep && st == PAFC_SUCCESS; ++r) {
+    float ms = 0;
+    st = from_hip(hipEventElapsedTime(&ms, ev[(size_t)r * (n + 1)], ev[(size_t)r * (n + 1) + n]));
+    ms_per_rep[r] = ms;
+  }
+  for (auto& e : ev)
+    if (e) (void)hipEventDestroy(e);
+  return st;
+}
+
+std::string describe_rader(int64_t n, pafc_dtype dtype, pafc_variant variant, pafc_status* st) {
+  *st = PAFC_SUCCESS;
+  if (dtype != PAFC_C64 && dtype != PAFC_C128) {
+    *st = PAFC_ERROR_INVALID_VALUE;
+    return "";
+  }
+  const int64_t P1 = n - 1;
+  PlanCore G;
+  *st = plan_core(G, 1, &P1, nullptr, dtype, variant);
+  if (*st != PAFC_SUCCESS) return "";
+  const int64_t eb = dtype == PAFC_C128 ? 16 : 8;
+  int64_t bg, bp, bf, bs;
+  rader_stage_bytes(n, eb, &bg, &bp, &bf, &bs);
+  char b[320];
+  std::string s = "{";
+  snprintf(b, sizeof(b), "\"ndim\": 1, \"dims\": [%lld], \"dtype\": \"%s\", \"variant\": %d, "
+           "\"rader_generator\": %lld, \"rader_inner\": %lld, \"conv_passes\": [\"rader gather\"",
+           (long long)n, dtype == PAFC_C128 ? "c128" : "c64", (int)variant,
+           (long long)primitive_root(n), (long long)P1);
+  s += b;
+  for (auto& ps : G.conv) s += ", \"" + ps.label + "\"";
+  s += ", \"rader product\", \"rader constants\"";
+  for (auto& ps : G.conv) s += ", \"" + ps.label + "\"";
+  // filter per call: gather, inner convolution, spectrum (u in, spectrum out)
+  snprintf(b, sizeof(b), ", \"rader scatter\"], \"hbm_bytes_conv\": %lld, "
+           "\"hbm_bytes_forward\": %lld, \"N\": %lld, \"inner\": ",
+           (long long)(2 * G.hbm_conv + bg + bp + bf + bs),
+           (long long)(G.hbm_conv + bg + 2 * eb * P1 + bf), (long long)n);
+  s += b;
+  s += describe_core(G) + "}";
+  return s;
+}
+
 // Events around the gather, every grid pass and the scatter (see
 // pafc_profile_passes).
 pafc_status profile_prime_factor(pafc_plan_t p, const void* x, void* y, hipStream_t s, int reps,
@@ -1526,7 +1790,11 @@ const char* pafc_status_string(pafc_status s) {
 pafc_status pafc_describe(int ndim, const int64_t* dims, const int* radix, pafc_dtype dtype,
                           pafc_variant variant, char* buf, size_t cap, size_t* needed) {
   std::string s;
-  if (is_bluestein_case(ndim, dims, radix, variant)) {
+  if (is_rader_case(ndim, dims, radix, variant)) {
+    pafc_status st;
+    s = describe_rader(dims[0], dtype, variant, &st);
+    PAFC_TRY(st);
+  } else if (is_bluestein_case(ndim, dims, radix, variant)) {
     pafc_status st;
     s = describe_bluestein(dims[0], dtype, variant, &st);
     PAFC_TRY(st);
@@ -1556,6 +1824,8 @@ pafc_status pafc_plan(pafc_plan_t* out, int ndim, const int64_t* dims, const int
   *out = nullptr;
   if (variant == PAFC_PRIME_FACTOR || variant == PAFC_PRIME_FACTOR_EXPLICIT)
     return plan_prime_factor(out, ndim, dims, radix, dtype, variant, hip_stream);
+  if (is_rader_case(ndim, dims, radix, variant))
+    return plan_rader(out, dims[0], dtype, variant, hip_stream);
   if (is_bluestein_case(ndim, dims, radix, variant))
     return plan_bluestein(out, dims[0], dtype, variant, hip_stream);
   pafc_plan_t p = new (std::nothrow) pafc_plan_s;
@@ -1720,6 +1990,8 @@ pafc_status pafc_set_filter(pafc_plan_t p, const void* h_dev, pafc_filter_domain
   p->filter_set = false;
   if (is_bluestein(p)) {
     PAFC_TRY(blue_set_filter(p, h_dev, domain, s));
+  } else if (is_rader(p)) {
+    PAFC_TRY(rader_set_filter(p, h_dev, domain, s));
   } else if (p->inner) {  // reindexed to the grid, then the grid plan's own filter
     PAFC_TRY(pfa_gather(p, h_dev, p->d_scratch, domain == PAFC_FILTER_SPATIAL ? 0 : 1, s));
     PAFC_TRY(pafc_set_filter(p->inner, p->d_scratch, domain, hip_stream));
@@ -1739,7 +2011,9 @@ pafc_status pafc_convolve_with_filter(pafc_plan_t p, const void* x_dev, const vo
   hipStream_t s = (hipStream_t)hip_stream;
   if (p->inner) {
     PAFC_TRY(pafc_set_filter(p, h_dev, PAFC_FILTER_SPATIAL, hip_stream));
-    return is_bluestein(p) ? blue_convolve(p, x_dev, y_dev, s) : pfa_convolve(p, x_dev, y_dev, s);
+    return is_bluestein(p) ? blue_convolve(p, x_dev, y_dev, s)
+           : is_rader(p)   ? rader_convolve(p, x_dev, y_dev, s)
+                           : pfa_convolve(p, x_dev, y_dev, s);
   }
   p->filter_set = false;
   PAFC_TRY(load_filter(p, h_dev, PAFC_FILTER_SPATIAL, s));
@@ -1840,6 +2114,7 @@ pafc_status pafc_convolve(pafc_plan_t p, const void* x_dev, void* y_dev, void* h
     return PAFC_ERROR_INVALID_VALUE;
   if (!p->filter_set) return PAFC_ERROR_FILTER_NOT_SET;
   if (is_bluestein(p)) return blue_convolve(p, x_dev, y_dev, (hipStream_t)hip_stream);
+  if (is_rader(p)) return rader_convolve(p, x_dev, y_dev, (hipStream_t)hip_stream);
   if (p->inner) return pfa_convolve(p, x_dev, y_dev, (hipStream_t)hip_stream);
   return run_sequence(p, p->P.conv, x_dev, y_dev, (hipStream_t)hip_stream);
 }
@@ -1852,6 +2127,9 @@ pafc_status pafc_profile_passes(pafc_plan_t p, const void* x_dev, void* y_dev, v
   if (is_bluestein(p))
     return profile_bluestein(p, x_dev, y_dev, (hipStream_t)hip_stream, reps, ms_per_pass,
                              bytes_per_pass, ms_per_rep, npass);
+  if (is_rader(p))
+    return profile_rader(p, x_dev, y_dev, (hipStream_t)hip_stream, reps, ms_per_pass,
+                         bytes_per_pass, ms_per_rep, npass);
   if (p->inner) return profile_prime_factor(p, x_dev, y_dev, (hipStream_t)hip_stream, reps,
                                             ms_per_pass, bytes_per_pass, ms_per_rep, npass);
   const auto& seq = p->P.conv;

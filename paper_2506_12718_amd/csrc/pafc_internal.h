@@ -46,6 +46,8 @@ enum { OP_DIF = 0, OP_DIT = 1, OP_MID = 2 };
 
 constexpr int kNumKinds = 13;
 constexpr int kMaxOps = 12;
+// most blocks of the Rader route's sum kernel (its partial-sum buffer)
+constexpr unsigned kRaderBlocks = 1024;
 
 // Unsigned 32-bit division by an invariant divisor d >= 1 (Granlund and
 // Montgomery's multiply-high method): q = (umulhi(x, m) + x) >> l with

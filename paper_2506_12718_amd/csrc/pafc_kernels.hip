@@ -292,6 +292,135 @@ __global__ void blue_out_kernel(const cx<T>* __restrict__ b, const cx<T>* __rest
   }
 }
 
+
+// Rader's algorithm (Sec. "Rader's and Bluestein's frameworks") for a prime
+// length p with a generator g of the multiplicative group mod p, P1 = p - 1.
+// With a_m = x[g^m] and the inner filter b_l = w_p^{g^{-l}}, the DFT at the
+// nonzero frequencies is X[g^{-q}] = x_0 + (a (*) b)_q, a length-P1 circular
+// convolution; X_0 = x_0 - sum_q (a (*) b)_q since sum_l b_l = -1.  The
+// spectrum is kept in this q order (Hq[q] = H[g^{-q}], Hq[P1] = H_0), so the
+// product needs no reordering, and the inverse DFT is the same convolution
+// through conjugation: with w_m = conj(Y[g^m]) = conj(Yq[-m]),
+// y[g^{-r}] = (Y_0 + conj((w (*) b)_r)) / p and y_0 = (Y_0 + sum_q Yq[q]) / p.
+// Tables: pw[m] = g^m mod p (m < P1); lg[j] = -log_g(j) mod P1 (0 < j < p).
+//   in:   a_m = x[pw[m]]
+//   sums: mode 0 (filter): hq[q] = x_0 + u_q, block sums of u
+//         mode 1 (product): u <- w in place, pairs (m, P1 - m) per thread,
+//         block sums of u and of Yq
+//   fin:  mode 0: hq[P1] = x_0 - sum u;  mode 1: consts = {Y_0, Y_0 + sum Yq}
+//   out:  y_0 = s consts[1], y_j = s (consts[0] + conj(v[lg[j]]))
+//   nat:  hq[q] = hn[pw[-q mod P1]], hq[P1] = hn[0]   (natural-order spectrum)
+// Block sums are double, four per block (sum u re/im, sum Yq re/im), added
+// in a fixed order, so results do not depend on scheduling.
+template <typename T>
+__global__ void rader_in_kernel(const cx<T>* __restrict__ x, const uint32_t* __restrict__ pw,
+                                cx<T>* __restrict__ a, uint32_t P1) {
+  for (uint32_t m = blockIdx.x * blockDim.x + threadIdx.x; m < P1; m += gridDim.x * blockDim.x)
+    a[m] = x[pw[m]];
+}
+
+__device__ inline void block_sum4(double v[4], double* __restrict__ out) {
+  __shared__ double red[4][256];
+  for (int c = 0; c < 4; ++c) red[c][threadIdx.x] = v[c];
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w)
+      for (int c = 0; c < 4; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+    for (int c = 0; c < 4; ++c) out[c] = red[c][0];
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void rader_sums_kernel(cx<T>* __restrict__ u,
+                                                          const cx<T>* __restrict__ x,
+                                                          cx<T>* __restrict__ hq,
+                                                          double* __restrict__ part, uint32_t P1,
+                                                          int mode) {
+  const cx<T> x0 = x[0];
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  if (mode == 0) {
+    for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < P1; q += gridDim.x * blockDim.x) {
+      const cx<T> v = u[q];
+      acc[0] += (double)v.re;
+      acc[1] += (double)v.im;
+      hq[q] = cx<T>{x0.re + v.re, x0.im + v.im};
+    }
+  } else {
+    const uint32_t half = P1 / 2;  // P1 is even
+    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t <= half;
+         t += gridDim.x * blockDim.x) {
+      const uint32_t tn = t == 0 ? 0 : P1 - t;
+      const cx<T> ua = u[t], ub = u[tn];
+      const cx<T> ya = cmul(cx<T>{x0.re + ua.re, x0.im + ua.im}, hq[t]);
+      const cx<T> yb = cmul(cx<T>{x0.re + ub.re, x0.im + ub.im}, hq[tn]);
+      u[t] = cx<T>{yb.re, -yb.im};
+      acc[0] += (double)ua.re;
+      acc[1] += (double)ua.im;
+      acc[2] += (double)ya.re;
+      acc[3] += (double)ya.im;
+      if (tn != t) {
+        u[tn] = cx<T>{ya.re, -ya.im};
+        acc[0] += (double)ub.re;
+        acc[1] += (double)ub.im;
+        acc[2] += (double)yb.re;
+        acc[3] += (double)yb.im;
+      }
+    }
+  }
+  block_sum4(acc, part + (size_t)blockIdx.x * 4);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void rader_fin_kernel(const double* __restrict__ part,
+                                                         uint32_t nb, const cx<T>* __restrict__ x,
+                                                         cx<T>* __restrict__ hq,
+                                                         cx<T>* __restrict__ consts, uint32_t P1,
+                                                         int mode) {
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (uint32_t b = threadIdx.x; b < nb; b += blockDim.x)
+    for (int c = 0; c < 4; ++c) acc[c] += part[(size_t)b * 4 + c];
+  __shared__ double tot[4];
+  block_sum4(acc, tot);
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  const double x0r = (double)x[0].re, x0i = (double)x[0].im;
+  const double X0r = x0r - tot[0], X0i = x0i - tot[1];
+  if (mode == 0) {
+    hq[P1] = cx<T>{(T)X0r, (T)X0i};
+    return;
+  }
+  const cx<T> h0 = hq[P1];
+  const double Y0r = X0r * (double)h0.re - X0i * (double)h0.im;
+  const double Y0i = X0r * (double)h0.im + X0i * (double)h0.re;
+  consts[0] = cx<T>{(T)Y0r, (T)Y0i};
+  consts[1] = cx<T>{(T)(Y0r + tot[2]), (T)(Y0i + tot[3])};
+}
+
+template <typename T>
+__global__ void rader_out_kernel(const cx<T>* __restrict__ v, const uint32_t* __restrict__ lg,
+                                 const cx<T>* __restrict__ consts, cx<T>* __restrict__ y,
+                                 uint32_t p, T s) {
+  const cx<T> y0 = consts[0];
+  for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < p; j += gridDim.x * blockDim.x) {
+    if (j == 0) {
+      const cx<T> c1 = consts[1];
+      y[0] = cx<T>{c1.re * s, c1.im * s};
+    } else {
+      const cx<T> w = v[lg[j]];
+      y[j] = cx<T>{(y0.re + w.re) * s, (y0.im - w.im) * s};
+    }
+  }
+}
+
+template <typename T>
+__global__ void rader_nat_kernel(const cx<T>* __restrict__ hn, const uint32_t* __restrict__ pw,
+                                 cx<T>* __restrict__ hq, uint32_t P1) {
+  for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q <= P1; q += gridDim.x * blockDim.x)
+    hq[q] = q == P1 ? hn[0] : hn[pw[q == 0 ? 0 : P1 - q]];
+}
+
 }  // namespace pafc
 
 // ----------------------------------------------------------------- launches
@@ -441,6 +570,48 @@ hipError_t launch_bluestein(bool dbl, int stage, const void* src, const void* c,
     PAFC_BL(float)
   }
 #undef PAFC_BL
+  return hipGetLastError();
+}
+
+// stage 0 in, 1 sums (mode 0/1), 2 fin (mode 0/1), 3 out, 4 natural spectrum
+// (see rader_*_kernel); the sums stage uses at most kRaderBlocks blocks.
+hipError_t launch_rader(bool dbl, int stage, int mode, const void* src, const void* x, void* dst,
+                        void* hq, const uint32_t* pw, const uint32_t* lg, double* part,
+                        void* consts, uint32_t p, double s, hipStream_t st) {
+  const uint32_t P1 = p - 1;
+  uint32_t nb = (P1 / 2 + 1 + 255) / 256;
+  if (nb > kRaderBlocks) nb = kRaderBlocks;
+#define PAFC_RD(TT)                                                                              \
+  switch (stage) {                                                                               \
+    case 0:                                                                                      \
+      hipLaunchKernelGGL(rader_in_kernel<TT>, dim3(grid_for(P1)), dim3(256), 0, st,              \
+                         (const cx<TT>*)src, pw, (cx<TT>*)dst, P1);                              \
+      break;                                                                                     \
+    case 1:                                                                                      \
+      hipLaunchKernelGGL(rader_sums_kernel<TT>, dim3(nb), dim3(256), 0, st, (cx<TT>*)dst,        \
+                         (const cx<TT>*)x, (cx<TT>*)hq, part, P1, mode);                         \
+      break;                                                                                     \
+    case 2:                                                                                      \
+      hipLaunchKernelGGL(rader_fin_kernel<TT>, dim3(1), dim3(256), 0, st, part, nb,              \
+                         (const cx<TT>*)x, (cx<TT>*)hq, (cx<TT>*)consts, P1, mode);              \
+      break;                                                                                     \
+    case 3:                                                                                      \
+      hipLaunchKernelGGL(rader_out_kernel<TT>, dim3(grid_for(p)), dim3(256), 0, st,              \
+                         (const cx<TT>*)src, lg, (const cx<TT>*)consts, (cx<TT>*)dst, p, (TT)s); \
+      break;                                                                                     \
+    case 4:                                                                                      \
+      hipLaunchKernelGGL(rader_nat_kernel<TT>, dim3(grid_for(p)), dim3(256), 0, st,              \
+                         (const cx<TT>*)src, pw, (cx<TT>*)hq, P1);                               \
+      break;                                                                                     \
+    default:                                                                                     \
+      return hipErrorInvalidValue;                                                               \
+  }
+  if (dbl) {
+    PAFC_RD(double)
+  } else {
+    PAFC_RD(float)
+  }
+#undef PAFC_RD
   return hipGetLastError();
 }
 

@@ -206,9 +206,10 @@ def test_anisotropic_plans():
 
 
 def test_bluestein_plans():
-    """A 1-D length with a prime factor above 5 runs by Bluestein's method on
-    an inner convolution of the smallest {2,3,5}-smooth length >= 2n - 1."""
-    for n in (7, 97, 1009, 4099, 1000003, 1001):
+    """A 1-D length with a prime factor above 5 (other than a prime that
+    Rader's method takes) runs by Bluestein's method on an inner convolution
+    of the smallest {2,3,5}-smooth length >= 2n - 1."""
+    for n in (23, 1009, 4099, 1000003, 1001, 14):
         d = pafc.describe((n,), "c128")
         m = d["bluestein_m"]
         assert m >= 2 * n - 1
@@ -226,3 +227,25 @@ def test_bluestein_plans():
         assert len(d["conv_passes"]) == 2 * inner + 3
     with pytest.raises(pafc.PafcError):
         pafc.describe((7, 7), "c128")
+
+
+def test_rader_plans(monkeypatch):
+    """A prime p with p - 1 {2,3,5}-smooth runs by Rader's method: the
+    reported generator generates the multiplicative group mod p, the inner
+    convolution has length p - 1; PAFC_BLUESTEIN=1 switches to Bluestein."""
+    for n in (7, 11, 13, 17, 97, 257, 769, 65537, 786433, 995329):
+        d = pafc.describe((n,), "c128")
+        g = d["rader_generator"]
+        assert d["rader_inner"] == n - 1
+        for q in (2, 3, 5):
+            if (n - 1) % q == 0:
+                assert pow(g, (n - 1) // q, n) != 1
+        # the smallest generator: every smaller candidate has a proper order
+        for c in range(2, g):
+            assert any(pow(c, (n - 1) // q, n) == 1 for q in (2, 3, 5) if (n - 1) % q == 0)
+        k = len(d["inner"]["conv_passes"])
+        assert len(d["conv_passes"]) == 2 * k + 4
+    for n in (23, 1009, 1000003):  # p - 1 not smooth
+        assert "bluestein_m" in pafc.describe((n,), "c128")
+    monkeypatch.setenv("PAFC_BLUESTEIN", "1")
+    assert "bluestein_m" in pafc.describe((97,), "c128")
