@@ -56,8 +56,9 @@ extern "C" {
 typedef enum pafc_status {
   PAFC_SUCCESS = 0,
   PAFC_ERROR_INVALID_VALUE = 1,    /* null/misaligned pointer, bad ndim, n_i < 2, bad enum */
-  PAFC_ERROR_UNSUPPORTED_SIZE = 2, /* prime factor outside {2,3,5} in a 2-D/3-D shape, a 1-D length above 2^29
-                                      with such a factor, or n_i != r^t for an explicit uniform radix */
+  PAFC_ERROR_UNSUPPORTED_SIZE = 2, /* prime factor outside {2,3,5} in a 2-D/3-D shape or with an explicit radix,
+                                      a 1-D length above 2^29 with such a factor (Rader's primes: 2^30), or
+                                      n_i != r^t for an explicit uniform radix */
   PAFC_ERROR_OUT_OF_MEMORY = 3,    /* device allocation failed */
   PAFC_ERROR_DEVICE = 4,           /* HIP runtime or launch error */
   PAFC_ERROR_FILTER_NOT_SET = 5    /* pafc_convolve before pafc_set_filter */
@@ -111,21 +112,31 @@ typedef struct pafc_plan_s* pafc_plan_t;
  * ndim:   1, 2 or 3.
  * dims:   host array of ndim sizes n_1..n_d (n_d is the fastest axis); each
  *         n_i >= 2 and a product of factors in {2, 3, 5}, except for ndim = 1:
- *         a length n with a prime factor above 5 (n <= 2^29) is planned by
- *         Bluestein's method (Sec. "Rader's and Bluestein's frameworks"): the
- *         length-n DFT becomes a circular convolution of length m, the
- *         smallest {2,3,5}-smooth m >= 2n - 1, run on an inner plan of length
- *         m with the requested variant (PAFC_PERM_FREE, PAFC_EXPLICIT_PERM or
- *         PAFC_PERM_FREE_UNFUSED; radix NULL or 0).  One convolution is then
- *         two inner convolutions (the forward DFT of x, the inverse DFT through
- *         conjugation) between elementwise chirp products; the filter's
- *         natural-order spectrum is taken once, at pafc_set_filter.  The plan
- *         owns two further m-element arrays (the chirp filter's spectrum in the
- *         inner plan and a scratch array), the n-element chirp and the
- *         n-element filter spectrum.  pafc_forward, pafc_inverse,
- *         pafc_set_symbol and pafc_plan_radices return INVALID_VALUE for such
- *         a plan (its spectrum has no digit-reversed layout of its own); so
- *         they do for a PAFC_PRIME_FACTOR(_EXPLICIT) plan.
+ *         a length n with a prime factor above 5 is planned on an inner
+ *         plan of smooth length with the requested variant (PAFC_PERM_FREE,
+ *         PAFC_EXPLICIT_PERM or PAFC_PERM_FREE_UNFUSED; radix NULL or 0),
+ *         Sec. "Rader's and Bluestein's frameworks":
+ *         - a prime n <= 2^30 with n - 1 {2,3,5}-smooth by Rader's method:
+ *           the DFT at the nonzero frequencies, reindexed by powers of a
+ *           generator g, is a circular convolution of length n - 1.  The
+ *           filter's spectrum is kept in generator order, so one evaluation
+ *           permutes twice (gather, scatter).  The plan owns an inner plan of
+ *           length n - 1, an (n - 1)-element scratch array, the n-element
+ *           spectrum, 8n bytes of index tables and 32 KiB of block sums;
+ *         - any other such n <= 2^29 by Bluestein's method: the DFT is a
+ *           circular convolution of length m, the smallest {2,3,5}-smooth
+ *           m >= 2n - 1, between elementwise chirp products.  The plan owns
+ *           an inner plan of length m, an m-element scratch array, the
+ *           n-element chirp and the n-element natural-order spectrum.
+ *         The environment variable PAFC_BLUESTEIN=1, read at planning, sends
+ *         Rader's primes to Bluestein's method too.  Either way one
+ *         convolution is two inner convolutions (the forward DFT of x, and
+ *         the inverse DFT through conjugation on the same inner filter); the
+ *         filter's spectrum is taken once, at pafc_set_filter.
+ *         pafc_forward, pafc_inverse, pafc_set_symbol and pafc_plan_radices
+ *         return INVALID_VALUE for such a plan (its spectrum has no
+ *         digit-reversed layout of its own); so they do for a
+ *         PAFC_PRIME_FACTOR(_EXPLICIT) plan.
  * radix:  NULL, or host array of ndim entries.  radix[i] = 0 lets the
  *         planner choose the radix sequence of axis i (over {2,3,4,5,8});
  *         radix[i] = r in {2,3,4,5,8} requests the uniform radix-r
@@ -300,7 +311,9 @@ pafc_status pafc_describe(int ndim, const int64_t* dims, const int* radix,
 
 /*
  * pafc_profile_passes -- run pafc_convolve `reps` times on hip_stream with a
- * hipEvent recorded around every kernel the convolution launches, synchronise,
+ * hipEvent recorded around every kernel the convolution launches (timing-only
+ * events, created with hipEventDisableSystemFence so that recording them
+ * writes back and invalidates no cache), synchronise,
  * and report the mean duration of each launch position in ms_per_pass[]
  * (capacity *npass on entry; the number of launches per convolution on
  * exit) and the algorithmic HBM bytes of each launch in bytes_per_pass[]
@@ -314,6 +327,23 @@ pafc_status pafc_profile_passes(pafc_plan_t p, const void* x_dev, void* y_dev,
                                 void* hip_stream, int reps, double* ms_per_pass,
                                 int64_t* bytes_per_pass, double* ms_per_rep,
                                 int* npass);
+
+/*
+ * pafc_profile_launch -- the same measurement with fewer events: run
+ * pafc_convolve `reps` times on hip_stream, recording timing-only events at
+ * the start of every repetition and around launch `launch` only (its
+ * position in pafc_profile_passes' order, 0 <= launch < *npass there), so
+ * that a throughput measurement carries two or three event packets per
+ * convolution instead of one per launch.  *ms_launch receives the mean
+ * duration of that launch; ms_per_rep[0..reps-1] (may be NULL) the time from
+ * the start of each repetition to the start of the next (the end, for the
+ * last).  Same buffer rules as pafc_convolve.  Blocks the host.
+ * Errors: INVALID_VALUE (NULL pointers, reps < 1, launch out of range),
+ * FILTER_NOT_SET, DEVICE.
+ */
+pafc_status pafc_profile_launch(pafc_plan_t p, const void* x_dev, void* y_dev,
+                                void* hip_stream, int reps, int launch,
+                                double* ms_launch, double* ms_per_rep);
 
 /*
  * pafc_twiddle -- the FP64 twiddle the planner uploads for w_n^e =

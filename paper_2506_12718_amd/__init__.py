@@ -43,7 +43,7 @@ EXPORTS = ("pafc_plan", "pafc_set_filter", "pafc_convolve", "pafc_forward",
            "pafc_batch_destroy", "pafc_batch_device_bytes",
            "pafc_batch_describe", "pafc_set_tuning", "pafc_profile_passes",
            "pafc_stream_copy", "pafc_batch_profile", "pafc_twiddle",
-           "pafc_convolve_with_filter", "pafc_set_symbol")
+           "pafc_convolve_with_filter", "pafc_set_symbol", "pafc_profile_launch")
 
 
 class PafcError(RuntimeError):
@@ -98,6 +98,9 @@ def lib():
             "pafc_profile_passes": [vp, vp, vp, vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
                                     ctypes.POINTER(ctypes.c_int64),
                                     ctypes.POINTER(ctypes.c_double), ip],
+            "pafc_profile_launch": [vp, vp, vp, vp, ctypes.c_int, ctypes.c_int,
+                                    ctypes.POINTER(ctypes.c_double),
+                                    ctypes.POINTER(ctypes.c_double)],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -313,6 +316,20 @@ class Plan:
                "pafc_profile_passes")
         return ([ms[i] for i in range(n.value)], [by[i] for i in range(n.value)],
                 [per[i] for i in range(int(reps))])
+
+    def profile_launch(self, x, out, launch, reps=10, stream=None):
+        """Run `reps` convolutions with HIP events at the start of every
+        repetition and around launch `launch` only.  Returns (mean ms of that
+        launch, ms of every repetition)."""
+        self._check_tensor(x, "x")
+        self._check_tensor(out, "out")
+        ms = ctypes.c_double(0.0)
+        per = (ctypes.c_double * int(reps))()
+        _check(lib().pafc_profile_launch(self._h, ctypes.c_void_p(x.data_ptr()),
+                                         ctypes.c_void_p(out.data_ptr()), _stream(stream),
+                                         int(reps), int(launch), ctypes.byref(ms), per),
+               "pafc_profile_launch")
+        return ms.value, [per[i] for i in range(int(reps))]
 
     def describe(self):
         """The planner's JSON for this plan's problem (host only)."""

@@ -987,6 +987,20 @@ pafc_status from_hip(hipError_t e) {
     if (st_ != PAFC_SUCCESS) return st_;       \
   } while (0)
 
+// Events that only time launches: no system-scope fence (cache writeback
+// and invalidate) when they are recorded, which would slow the launches they
+// bracket; their times are read after a stream synchronisation.
+hipError_t timing_event(hipEvent_t* e) {
+  return hipEventCreateWithFlags(e, hipEventDisableSystemFence);
+}
+
+// Record event k of an event array, if there is an array and that entry
+// exists (profiling runs may time a few launch positions only).
+pafc_status rec(hipEvent_t* ev, size_t k, hipStream_t s) {
+  if (!ev || !ev[k]) return PAFC_SUCCESS;
+  return from_hip(hipEventRecord(ev[k], s));
+}
+
 bool aligned_for(const void* p, int dtype) {
   const uintptr_t m = dtype == PAFC_C128 ? 15 : 7;
   return ((uintptr_t)p & m) == 0;
@@ -1079,7 +1093,7 @@ pafc_status run_sequence(pafc_plan_t p, const std::vector<Pass>& seq, const void
   const bool dbl = P.dtype == PAFC_C128;
   const void* cur = x;
   size_t k = 0;
-  if (ev) PAFC_TRY(from_hip(hipEventRecord(ev[0], s)));
+  PAFC_TRY(rec(ev, 0, s));
   for (const Pass& ps : seq) {
     if (ps.kind == 0) {
       PAFC_TRY(run_pass(p, ps, cur, y, s));
@@ -1097,7 +1111,7 @@ pafc_status run_sequence(pafc_plan_t p, const std::vector<Pass>& seq, const void
       }
     }
     ++k;
-    if (ev) PAFC_TRY(from_hip(hipEventRecord(ev[k], s)));
+    PAFC_TRY(rec(ev, k, s));
   }
   if (cur != y) return PAFC_ERROR_DEVICE;
   return PAFC_SUCCESS;
@@ -1172,12 +1186,12 @@ pafc_status pfa_scatter(pafc_plan_t p, const void* in, void* out, hipStream_t s)
 // the gather and after every launch
 pafc_status pfa_convolve(pafc_plan_t p, const void* x, void* y, hipStream_t s,
                          hipEvent_t* ev = nullptr) {
-  if (ev) PAFC_TRY(from_hip(hipEventRecord(ev[0], s)));
+  PAFC_TRY(rec(ev, 0, s));
   PAFC_TRY(pfa_gather(p, x, p->d_scratch, 0, s));
   PAFC_TRY(run_sequence(p->inner, p->inner->P.conv, p->d_scratch, p->d_scratch, s,
                         ev ? ev + 1 : nullptr));
   PAFC_TRY(pfa_scatter(p, p->d_scratch, y, s));
-  if (ev) PAFC_TRY(from_hip(hipEventRecord(ev[p->inner->P.conv.size() + 2], s)));
+  PAFC_TRY(rec(ev, p->inner->P.conv.size() + 2, s));
   return PAFC_SUCCESS;
 }
 
@@ -1294,14 +1308,14 @@ pafc_status blue_convolve(pafc_plan_t p, const void* x, void* y, hipStream_t s,
                           hipEvent_t* ev = nullptr) {
   const size_t k = p->inner->P.conv.size();
   void* b = p->d_scratch;
-  if (ev) PAFC_TRY(from_hip(hipEventRecord(ev[0], s)));
+  PAFC_TRY(rec(ev, 0, s));
   PAFC_TRY(blue_stage(p, 0, x, b, s));
   PAFC_TRY(run_sequence(p->inner, p->inner->P.conv, b, b, s, ev ? ev + 1 : nullptr));
   PAFC_TRY(blue_stage(p, 2, b, b, s));
-  if (ev) PAFC_TRY(from_hip(hipEventRecord(ev[k + 2], s)));
+  PAFC_TRY(rec(ev, k + 2, s));
   PAFC_TRY(run_sequence(p->inner, p->inner->P.conv, b, b, s, ev ? ev + k + 2 : nullptr));
   PAFC_TRY(blue_stage(p, 3, b, y, s));
-  if (ev) PAFC_TRY(from_hip(hipEventRecord(ev[2 * k + 3], s)));
+  PAFC_TRY(rec(ev, 2 * k + 3, s));
   return PAFC_SUCCESS;
 }
 
@@ -1384,48 +1398,6 @@ pafc_status plan_bluestein(pafc_plan_t* out, int64_t n, pafc_dtype dtype, pafc_v
   p->bytes = p->inner->bytes + (2 * (size_t)n + (size_t)m) * eb;
   *out = p;
   return PAFC_SUCCESS;
-}
-
-pafc_status profile_bluestein(pafc_plan_t p, const void* x, void* y, hipStream_t s, int reps,
-                              double* ms_per_pass, int64_t* bytes_per_pass, double* ms_per_rep,
-                              int* npass) {
-  const auto& seq = p->inner->P.conv;
-  const int k = (int)seq.size();
-  const int n = 2 * k + 3;
-  const int cap = *npass;
-  *npass = n;
-  if (cap < n || !ms_per_pass) return PAFC_ERROR_INVALID_VALUE;
-  std::vector<hipEvent_t> ev((size_t)(n + 1) * reps, nullptr);
-  pafc_status st = PAFC_SUCCESS;
-  for (auto& e : ev)
-    if (st == PAFC_SUCCESS) st = from_hip(hipEventCreate(&e));
-  for (int r = 0; r < reps && st == PAFC_SUCCESS; ++r)
-    st = blue_convolve(p, x, y, s, ev.data() + (size_t)r * (n + 1));
-  if (st == PAFC_SUCCESS) st = from_hip(hipStreamSynchronize(s));
-  const int64_t eb = p->P.elem, N = p->P.N, m = p->blue_m;
-  for (int i = 0; i < n && st == PAFC_SUCCESS; ++i) {
-    double tot = 0;
-    for (int r = 0; r < reps && st == PAFC_SUCCESS; ++r) {
-      float ms = 0;
-      st = from_hip(hipEventElapsedTime(&ms, ev[(size_t)r * (n + 1) + i], ev[(size_t)r * (n + 1) + i + 1]));
-      tot += ms;
-    }
-    ms_per_pass[i] = tot / reps;
-    if (bytes_per_pass) {
-      if (i == 0) bytes_per_pass[i] = (2 * N + m) * eb;             // chirp-in
-      else if (i == k + 1) bytes_per_pass[i] = (2 * m + 2 * N) * eb;  // chirp product
-      else if (i == n - 1) bytes_per_pass[i] = (m + 2 * N) * eb;     // chirp-out
-      else bytes_per_pass[i] = pass_bytes(p->inner->P, seq[(size_t)((i - 1) % (k + 1))]);
-    }
-  }
-  for (int r = 0; r < reps && ms_per_rep && st == PAFC_SUCCESS; ++r) {
-    float ms = 0;
-    st = from_hip(hipEventElapsedTime(&ms, ev[(size_t)r * (n + 1)], ev[(size_t)r * (n + 1) + n]));
-    ms_per_rep[r] = ms;
-  }
-  for (auto& e : ev)
-    if (e) (void)hipEventDestroy(e);
-  return st;
 }
 
 std::string describe_bluestein(int64_t n, pafc_dtype dtype, pafc_variant variant,
@@ -1512,16 +1484,16 @@ pafc_status rader_convolve(pafc_plan_t p, const void* x, void* y, hipStream_t s,
                            hipEvent_t* ev = nullptr) {
   const size_t k = p->inner->P.conv.size();
   void* b = p->d_scratch;
-  if (ev) PAFC_TRY(from_hip(hipEventRecord(ev[0], s)));
+  PAFC_TRY(rec(ev, 0, s));
   PAFC_TRY(rader_stage(p, 0, 0, x, nullptr, b, s));
   PAFC_TRY(run_sequence(p->inner, p->inner->P.conv, b, b, s, ev ? ev + 1 : nullptr));
   PAFC_TRY(rader_stage(p, 1, 1, nullptr, x, b, s));
-  if (ev) PAFC_TRY(from_hip(hipEventRecord(ev[k + 2], s)));
+  PAFC_TRY(rec(ev, k + 2, s));
   PAFC_TRY(rader_stage(p, 2, 1, nullptr, x, nullptr, s));
-  if (ev) PAFC_TRY(from_hip(hipEventRecord(ev[k + 3], s)));
+  PAFC_TRY(rec(ev, k + 3, s));
   PAFC_TRY(run_sequence(p->inner, p->inner->P.conv, b, b, s, ev ? ev + k + 3 : nullptr));
   PAFC_TRY(rader_stage(p, 3, 0, b, nullptr, y, s));
-  if (ev) PAFC_TRY(from_hip(hipEventRecord(ev[2 * k + 4], s)));
+  PAFC_TRY(rec(ev, 2 * k + 4, s));
   return PAFC_SUCCESS;
 }
 
@@ -1619,50 +1591,6 @@ void rader_stage_bytes(int64_t n, int64_t eb, int64_t* gather, int64_t* product,
   *scatter = (2 * eb + 4) * n;
 }
 
-pafc_status profile_rader(pafc_plan_t p, const void* x, void* y, hipStream_t s, int reps,
-                          double* ms_per_pass, int64_t* bytes_per_pass, double* ms_per_rep,
-                          int* npass) {
-  const auto& seq = p->inner->P.conv;
-  const int k = (int)seq.size();
-  const int n = 2 * k + 4;
-  const int cap = *npass;
-  *npass = n;
-  if (cap < n || !ms_per_pass) return PAFC_ERROR_INVALID_VALUE;
-  std::vector<hipEvent_t> ev((size_t)(n + 1) * reps, nullptr);
-  pafc_status st = PAFC_SUCCESS;
-  for (auto& e : ev)
-    if (st == PAFC_SUCCESS) st = from_hip(hipEventCreate(&e));
-  for (int r = 0; r < reps && st == PAFC_SUCCESS; ++r)
-    st = rader_convolve(p, x, y, s, ev.data() + (size_t)r * (n + 1));
-  if (st == PAFC_SUCCESS) st = from_hip(hipStreamSynchronize(s));
-  int64_t bg, bp, bf, bs;
-  rader_stage_bytes(p->P.N, p->P.elem, &bg, &bp, &bf, &bs);
-  for (int i = 0; i < n && st == PAFC_SUCCESS; ++i) {
-    double tot = 0;
-    for (int r = 0; r < reps && st == PAFC_SUCCESS; ++r) {
-      float ms = 0;
-      st = from_hip(hipEventElapsedTime(&ms, ev[(size_t)r * (n + 1) + i], ev[(size_t)r * (n + 1) + i + 1]));
-      tot += ms;
-    }
-    ms_per_pass[i] = tot / reps;
-    if (bytes_per_pass) {
-      if (i == 0) bytes_per_pass[i] = bg;
-      else if (i == k + 1) bytes_per_pass[i] = bp;
-      else if (i == k + 2) bytes_per_pass[i] = bf;
-      else if (i == n - 1) bytes_per_pass[i] = bs;
-      else bytes_per_pass[i] = pass_bytes(p->inner->P, seq[(size_t)(i <= k ? i - 1 : i - k - 3)]);
-    }
-  }
-  for (int r = 0; r < reps && ms_per_rep && st == PAFC_SUCCESS; ++r) {
-    float ms = 0;
-    st = from_hip(hipEventElapsedTime(&ms, ev[(size_t)r * (n + 1)], ev[(size_t)r * (n + 1) + n]));
-    ms_per_rep[r] = ms;
-  }
-  for (auto& e : ev)
-    if (e) (void)hipEventDestroy(e);
-  return st;
-}
-
 std::string describe_rader(int64_t n, pafc_dtype dtype, pafc_variant variant, pafc_status* st) {
   *st = PAFC_SUCCESS;
   if (dtype != PAFC_C64 && dtype != PAFC_C128) {
@@ -1696,39 +1624,95 @@ std::string describe_rader(int64_t n, pafc_dtype dtype, pafc_variant variant, pa
   return s;
 }
 
-// Events around the gather, every grid pass and the scatter (see
-// pafc_profile_passes).
-pafc_status profile_prime_factor(pafc_plan_t p, const void* x, void* y, hipStream_t s, int reps,
-                                 double* ms_per_pass, int64_t* bytes_per_pass, double* ms_per_rep,
-                                 int* npass) {
-  const auto& seq = p->inner->P.conv;
-  const int n = (int)seq.size() + 2;
-  const int cap = *npass;
-  *npass = n;
-  if (cap < n || !ms_per_pass) return PAFC_ERROR_INVALID_VALUE;
-  std::vector<hipEvent_t> ev((size_t)(n + 1) * reps, nullptr);
+// ------------------------------------------------------------ profiling
+
+// launches of one convolution, in the order the profiling calls report them
+int route_launches(pafc_plan_t p) {
+  if (is_bluestein(p)) return 2 * (int)p->inner->P.conv.size() + 3;
+  if (is_rader(p)) return 2 * (int)p->inner->P.conv.size() + 4;
+  if (p->inner) return (int)p->inner->P.conv.size() + 2;
+  return (int)p->P.conv.size();
+}
+
+pafc_status route_convolve(pafc_plan_t p, const void* x, void* y, hipStream_t s,
+                           hipEvent_t* ev) {
+  if (is_bluestein(p)) return blue_convolve(p, x, y, s, ev);
+  if (is_rader(p)) return rader_convolve(p, x, y, s, ev);
+  if (p->inner) return pfa_convolve(p, x, y, s, ev);
+  return run_sequence(p, p->P.conv, x, y, s, ev);
+}
+
+// algorithmic HBM bytes of launch i of one convolution
+int64_t route_pass_bytes(pafc_plan_t p, int i) {
+  const int64_t eb = p->P.elem, N = p->P.N;
+  if (is_bluestein(p)) {
+    const auto& seq = p->inner->P.conv;
+    const int k = (int)seq.size(), n = 2 * k + 3;
+    const int64_t m = p->blue_m;
+    if (i == 0) return (2 * N + m) * eb;              // chirp-in
+    if (i == k + 1) return (2 * m + 2 * N) * eb;      // chirp product
+    if (i == n - 1) return (m + 2 * N) * eb;          // chirp-out
+    return pass_bytes(p->inner->P, seq[(size_t)((i - 1) % (k + 1))]);
+  }
+  if (is_rader(p)) {
+    const auto& seq = p->inner->P.conv;
+    const int k = (int)seq.size(), n = 2 * k + 4;
+    int64_t bg, bp, bf, bs;
+    rader_stage_bytes(N, eb, &bg, &bp, &bf, &bs);
+    if (i == 0) return bg;
+    if (i == k + 1) return bp;
+    if (i == k + 2) return bf;
+    if (i == n - 1) return bs;
+    return pass_bytes(p->inner->P, seq[(size_t)(i <= k ? i - 1 : i - k - 3)]);
+  }
+  if (p->inner) {  // prime-factor: gather, grid passes, scatter
+    const int n = (int)p->inner->P.conv.size() + 2;
+    if (i == 0 || i == n - 1) return 2 * N * eb;
+    return pass_bytes(p->inner->P, p->inner->P.conv[(size_t)i - 1]);
+  }
+  return pass_bytes(p->P, p->P.conv[(size_t)i]);
+}
+
+// `reps` convolutions with timing events at launch boundaries.  sel < 0:
+// an event before every launch and after the last, and ms_per_pass[k] the
+// mean of launch k.  sel >= 0: events at the start of every repetition and
+// around launch sel only (fewer event packets in the stream), *ms_sel its
+// mean.  ms_per_rep[r] (may be NULL): start of repetition r to the start of
+// the next (to the end of the last).
+pafc_status profile_impl(pafc_plan_t p, const void* x, void* y, hipStream_t s, int reps, int sel,
+                         double* ms_per_pass, double* ms_per_rep, double* ms_sel) {
+  const int n = route_launches(p);
+  const size_t stride = (size_t)n + 1;
+  std::vector<hipEvent_t> ev(stride * (size_t)reps, nullptr);
+  auto want = [&](int r, int k) {
+    return sel < 0 || k == 0 || k == sel || k == sel + 1 || (k == n && r == reps - 1);
+  };
   pafc_status st = PAFC_SUCCESS;
-  for (auto& e : ev)
-    if (st == PAFC_SUCCESS) st = from_hip(hipEventCreate(&e));
+  for (int r = 0; r < reps; ++r)
+    for (int k = 0; k <= n && st == PAFC_SUCCESS; ++k)
+      if (want(r, k)) st = from_hip(timing_event(&ev[(size_t)r * stride + (size_t)k]));
   for (int r = 0; r < reps && st == PAFC_SUCCESS; ++r)
-    st = pfa_convolve(p, x, y, s, ev.data() + (size_t)r * (n + 1));
+    st = route_convolve(p, x, y, s, ev.data() + (size_t)r * stride);
   if (st == PAFC_SUCCESS) st = from_hip(hipStreamSynchronize(s));
-  const int64_t perm_bytes = 2 * p->P.N * (int64_t)p->P.elem;
+  auto elapsed = [&](hipEvent_t a, hipEvent_t b, double* out) {
+    float ms = 0;
+    if (st == PAFC_SUCCESS) st = from_hip(hipEventElapsedTime(&ms, a, b));
+    *out = ms;
+  };
   for (int k = 0; k < n && st == PAFC_SUCCESS; ++k) {
-    double tot = 0;
-    for (int r = 0; r < reps && st == PAFC_SUCCESS; ++r) {
-      float ms = 0;
-      st = from_hip(hipEventElapsedTime(&ms, ev[(size_t)r * (n + 1) + k], ev[(size_t)r * (n + 1) + k + 1]));
+    if (sel >= 0 && k != sel) continue;
+    double tot = 0, ms = 0;
+    for (int r = 0; r < reps; ++r) {
+      elapsed(ev[(size_t)r * stride + (size_t)k], ev[(size_t)r * stride + (size_t)k + 1], &ms);
       tot += ms;
     }
-    ms_per_pass[k] = tot / reps;
-    if (bytes_per_pass)
-      bytes_per_pass[k] = (k == 0 || k == n - 1) ? perm_bytes : pass_bytes(p->inner->P, seq[(size_t)k - 1]);
+    if (sel < 0) ms_per_pass[k] = tot / reps;
+    else *ms_sel = tot / reps;
   }
-  for (int r = 0; r < reps && ms_per_rep && st == PAFC_SUCCESS; ++r) {
-    float ms = 0;
-    st = from_hip(hipEventElapsedTime(&ms, ev[(size_t)r * (n + 1)], ev[(size_t)r * (n + 1) + n]));
-    ms_per_rep[r] = ms;
+  for (int r = 0; r < reps && ms_per_rep; ++r) {
+    hipEvent_t end = ev[(size_t)r * stride + (size_t)n];
+    if (!end) end = ev[(size_t)(r + 1) * stride];
+    elapsed(ev[(size_t)r * stride], end, &ms_per_rep[r]);
   }
   for (auto& e : ev)
     if (e) (void)hipEventDestroy(e);
@@ -2123,46 +2107,29 @@ pafc_status pafc_profile_passes(pafc_plan_t p, const void* x_dev, void* y_dev, v
                                 int reps, double* ms_per_pass, int64_t* bytes_per_pass,
                                 double* ms_per_rep, int* npass) {
   if (!p || !x_dev || !y_dev || !npass || reps < 1) return PAFC_ERROR_INVALID_VALUE;
+  if (!aligned_for(x_dev, p->P.dtype) || !aligned_for(y_dev, p->P.dtype))
+    return PAFC_ERROR_INVALID_VALUE;
   if (!p->filter_set) return PAFC_ERROR_FILTER_NOT_SET;
-  if (is_bluestein(p))
-    return profile_bluestein(p, x_dev, y_dev, (hipStream_t)hip_stream, reps, ms_per_pass,
-                             bytes_per_pass, ms_per_rep, npass);
-  if (is_rader(p))
-    return profile_rader(p, x_dev, y_dev, (hipStream_t)hip_stream, reps, ms_per_pass,
-                         bytes_per_pass, ms_per_rep, npass);
-  if (p->inner) return profile_prime_factor(p, x_dev, y_dev, (hipStream_t)hip_stream, reps,
-                                            ms_per_pass, bytes_per_pass, ms_per_rep, npass);
-  const auto& seq = p->P.conv;
-  const int n = (int)seq.size();
+  const int n = route_launches(p);
   const int cap = *npass;
   *npass = n;
   if (cap < n || !ms_per_pass) return PAFC_ERROR_INVALID_VALUE;
-  hipStream_t s = (hipStream_t)hip_stream;
-  std::vector<hipEvent_t> ev((size_t)(n + 1) * reps, nullptr);
-  pafc_status st = PAFC_SUCCESS;
-  for (auto& e : ev)
-    if (st == PAFC_SUCCESS) st = from_hip(hipEventCreate(&e));
-  for (int r = 0; r < reps && st == PAFC_SUCCESS; ++r)
-    st = run_sequence(p, seq, x_dev, y_dev, s, ev.data() + (size_t)r * (n + 1));
-  if (st == PAFC_SUCCESS) st = from_hip(hipStreamSynchronize(s));
-  for (int k = 0; k < n; ++k) {
-    double tot = 0;
-    for (int r = 0; r < reps && st == PAFC_SUCCESS; ++r) {
-      float ms = 0;
-      st = from_hip(hipEventElapsedTime(&ms, ev[(size_t)r * (n + 1) + k], ev[(size_t)r * (n + 1) + k + 1]));
-      tot += ms;
-    }
-    ms_per_pass[k] = tot / reps;
-    if (bytes_per_pass) bytes_per_pass[k] = pass_bytes(p->P, seq[(size_t)k]);
-  }
-  for (int r = 0; r < reps && ms_per_rep && st == PAFC_SUCCESS; ++r) {
-    float ms = 0;
-    st = from_hip(hipEventElapsedTime(&ms, ev[(size_t)r * (n + 1)], ev[(size_t)r * (n + 1) + n]));
-    ms_per_rep[r] = ms;
-  }
-  for (auto& e : ev)
-    if (e) (void)hipEventDestroy(e);
-  return st;
+  PAFC_TRY(profile_impl(p, x_dev, y_dev, (hipStream_t)hip_stream, reps, -1, ms_per_pass,
+                        ms_per_rep, nullptr));
+  if (bytes_per_pass)
+    for (int k = 0; k < n; ++k) bytes_per_pass[k] = route_pass_bytes(p, k);
+  return PAFC_SUCCESS;
+}
+
+pafc_status pafc_profile_launch(pafc_plan_t p, const void* x_dev, void* y_dev, void* hip_stream,
+                                int reps, int launch, double* ms_launch, double* ms_per_rep) {
+  if (!p || !x_dev || !y_dev || !ms_launch || reps < 1) return PAFC_ERROR_INVALID_VALUE;
+  if (!aligned_for(x_dev, p->P.dtype) || !aligned_for(y_dev, p->P.dtype))
+    return PAFC_ERROR_INVALID_VALUE;
+  if (!p->filter_set) return PAFC_ERROR_FILTER_NOT_SET;
+  if (launch < 0 || launch >= route_launches(p)) return PAFC_ERROR_INVALID_VALUE;
+  return profile_impl(p, x_dev, y_dev, (hipStream_t)hip_stream, reps, launch, nullptr,
+                      ms_per_rep, ms_launch);
 }
 
 pafc_status pafc_forward(pafc_plan_t p, const void* x_dev, void* z_dev, void* hip_stream) {
@@ -2478,7 +2445,7 @@ pafc_status pafc_batch_profile(pafc_batch_t b, const void* x_dev, void* y_dev, v
   std::vector<hipEvent_t> ev((size_t)(n + 1) * reps, nullptr);
   pafc_status st = PAFC_SUCCESS;
   for (auto& e : ev)
-    if (st == PAFC_SUCCESS) st = from_hip(hipEventCreate(&e));
+    if (st == PAFC_SUCCESS) st = from_hip(timing_event(&e));
   for (int r = 0; r < reps && st == PAFC_SUCCESS; ++r) {
     hipEvent_t* E = ev.data() + (size_t)r * (n + 1);
     st = from_hip(hipEventRecord(E[0], s));

@@ -37,6 +37,9 @@ DEFAULT_TABLE = os.path.join(HERE, "tuning", "mi355x.txt")
 BATCH_SIZES = [2 ** e for e in range(8, 17)] + [3 ** e for e in range(6, 11)] + \
               [5 ** e for e in range(4, 8)]
 GRIDS = [((2187, 2187), 3), ((5 ** 9,), 5)]
+# inner lengths of the prime-length routes' benchmark workloads (Rader at
+# n = 995329, Bluestein at n = 995329 and n = 1000003), tuned as 1-D plans
+INNER_1D = [995328, 2000000, 2025000]
 
 
 def _factors(n):
@@ -72,7 +75,7 @@ class Timer:
 
     def grid(self, dims, radix):
         torch = self.torch
-        P = self.pafc.Plan(dims, self.tdt, radix=[radix] * len(dims))
+        P = self.pafc.Plan(dims, self.tdt, radix=None if radix is None else [radix] * len(dims))
         h = torch.ones(dims, dtype=self.tdt, device="cuda")
         P.set_filter(h)
         x = torch.ones(dims, dtype=self.tdt, device="cuda")
@@ -111,15 +114,17 @@ def candidates(pafc, dt, n, key, cfg):
     return []
 
 
-def read_table(path):
-    """(dtype, n) -> config of an existing table (empty if there is none)."""
+def read_table(path, raw=False):
+    """(dtype, n) -> config of an existing table (empty if there is none);
+    with ``raw`` the table's lines themselves, comments included."""
     out = {}
     if not path or not os.path.exists(path):
         return out
-    for raw in open(path):
-        f = raw.split("#")[0].split()
+    for text in open(path):
+        f = text.split("#")[0].split()
         if len(f) == 7:
-            out[(f[0], int(f[1]))] = dict(zip(("split", "W", "Wo", "g3", "g5"), map(int, f[2:])))
+            out[(f[0], int(f[1]))] = text.rstrip("\n") if raw else \
+                dict(zip(("split", "W", "Wo", "g3", "g5"), map(int, f[2:])))
     return out
 
 
@@ -164,8 +169,11 @@ def main(argv=None):
     ap.add_argument("--reps", type=int, default=7)
     ap.add_argument("--prev", default=DEFAULT_TABLE,
                     help="existing table whose entries are tried as starting points ('' for none)")
+    ap.add_argument("--sizes", nargs="*", type=int, default=None,
+                    help="tune only these axis lengths; the other entries of --prev are kept")
     a = ap.parse_args(argv)
     prev = read_table(a.prev)
+    prev_lines = read_table(a.prev, raw=True)
     os.environ["PAFC_NO_TUNING_TABLE"] = "1"
     import torch
     import paper_2506_12718_amd as pafc
@@ -186,6 +194,12 @@ def main(argv=None):
                  one_d if len(dims) == 1 else ("g3", "g5")) for dims, radix in GRIDS]
         jobs += [(n, (lambda n=n: timer.batch(n)), one_d) for n in BATCH_SIZES
                  if n not in [d[0] for d, _ in GRIDS]]
+        jobs += [(n, (lambda n=n: timer.grid((n,), None)), one_d) for n in INNER_1D]
+        if a.sizes is not None:
+            jobs = [j for j in jobs if j[0] in a.sizes]
+            for (pdt, pn), pcfg in sorted(prev.items()):
+                if pdt == dt and pn not in a.sizes and any(pcfg.values()):
+                    lines.append(prev_lines[(pdt, pn)])
         for n, measure, keys in jobs:
             start = prev.get((dt, n))
             if start is not None and keys != one_d:

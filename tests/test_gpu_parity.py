@@ -244,12 +244,41 @@ def test_errors():
                                ctypes.c_void_p(x.data_ptr()), None)
     assert st == 1  # misaligned for complex128
     P.close()
-    with pytest.raises(m.PafcError) as e:
-        m.Plan((7,), C128)
+    with pytest.raises(m.PafcError) as e:  # 1-D lengths 7, 11, ... have their own routes
+        m.Plan((7, 4), C128)
     assert e.value.status == 2
     with pytest.raises(m.PafcError) as e:
         m.Plan((48,), C128, radix=[4])
     assert e.value.status == 2
+
+
+@pytest.mark.parametrize("shape", [(64, 64, 64), (4096,), (97,), (1009,), (2 ** 6 * 3 ** 3,)])
+def test_profile_launch(shape):
+    """pafc_profile_launch times one launch position with fewer events: its
+    mean agrees with the full per-launch profile, every repetition is
+    timed, the result is the convolution, and positions out of range are
+    rejected."""
+    m = pafc()
+    rng = np.random.default_rng(21)
+    x = inputs.complex_uniform(rng, shape)
+    h = inputs.complex_uniform(rng, shape)
+    P = m.Plan(shape, C128)
+    P.set_filter(to_dev(h, C128))
+    xd = to_dev(x, C128)
+    yd = torch.empty_like(xd)
+    ms, by, _ = P.profile_passes(xd, yd, reps=5)
+    for k in (0, len(ms) - 1, max(range(len(ms)), key=lambda i: ms[i])):
+        t, per = P.profile_launch(xd, yd, k, reps=6)
+        assert len(per) == 6 and min(per) > 0 and t > 0
+        assert t <= max(per)
+        say("launch", k, "of", len(ms), t, ms[k])
+    ref = oracle.conv_fft(x, h) if len(shape) > 1 or shape[0] in (4096, 1728) else \
+        oracle.conv_direct(x, h)
+    assert rel_l2(to_host(yd), ref) <= TOL[C128]
+    for bad in (-1, len(ms)):
+        with pytest.raises(m.PafcError):
+            P.profile_launch(xd, yd, bad, reps=2)
+    P.close()
 
 
 @pytest.mark.parametrize("shape", [(729, 100), (2187, 12), (512, 20, 6), (81, 729, 8), (1024, 3)])
