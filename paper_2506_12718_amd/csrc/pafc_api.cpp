@@ -79,6 +79,7 @@ constexpr size_t kLdsBudget = 160 * 1024;  // LDS per CU on gfx950
 //   PAFC_TUNE_MID  axis that carries the fused product (default 0, the slowest)
 //   PAFC_WIDE      0 disables the wide (1024-thread) register class
 //   PAFC_FOLD      0 keeps short faster axes in passes of their own
+//   PAFC_SNAKE     0 walks every pass's tiles in the same direction
 //   PAFC_BLUESTEIN 1 plans a prime length by Bluestein's method even where
 //                  Rader's applies (p - 1 {2,3,5}-smooth)
 int env_int(const char* name, int dflt) {
@@ -1884,16 +1885,24 @@ pafc_status pafc_plan(pafc_plan_t* out, int ndim, const int64_t* dims, const int
       }
 
   }
-  // pass descriptors of the three sequences, uploaded once
+  // pass descriptors of the three sequences, uploaded once.  Consecutive
+  // axis passes walk their tiles in opposite directions, so that a pass
+  // starts on the end of the array the previous pass wrote last, which is
+  // still in the device's last-level cache when the array is larger
+  // than it.
+  const bool snake = env_int("PAFC_SNAKE", 1) != 0;
   std::vector<PassArgs> descs;
-  for (auto* seq : {&p->P.conv, &p->P.fwd, &p->P.inv})
+  for (auto* seq : {&p->P.conv, &p->P.fwd, &p->P.inv}) {
+    int i = 0;
     for (Pass& ps : *seq) {
       if (ps.kind != 0) continue;
       ps.desc = (uint32_t)descs.size();
       PassArgs a;
       finalize_args(P, p->d_tw, p->d_H, ps, &a);
+      a.rev = snake && (i++ % 2 == 1) ? 1u : 0u;
       descs.push_back(a);
     }
+  }
   if (e == hipSuccess)
     e = hipMalloc((void**)&p->d_descs, std::max<size_t>(1, descs.size()) * sizeof(PassArgs));
   if (e != hipSuccess) {

@@ -122,6 +122,8 @@ struct PassArgs {
   uint32_t twl_off;    // element offset of the LDS tables after the tile
   uint32_t twl_global; // 1: no LDS copy (it would not fit beside the tile);
                        // twiddles are read from the global table
+  uint32_t rev;        // 1: tile t of the launch is tile ntiles - 1 - t (the
+                       // pass walks the array from its end)
   OpDesc ops[kMaxOps];
 };
 

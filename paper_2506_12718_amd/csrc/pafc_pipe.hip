@@ -109,6 +109,7 @@ pipe_kernel(const PassArgs* __restrict__ desc,
   // element indices and byte offsets are 32-bit
   const uint32_t S_i = (uint32_t)a.S_i, S_c = (uint32_t)a.S_c, S_o = (uint32_t)a.S_o;
   auto tile_base = [&](uint32_t tile, uint32_t& col0) -> uint32_t {
+    if (a.rev) tile = a.ntiles - 1u - tile;
     const uint32_t o = fdiv(tile, a.divTiles);
     const uint32_t cb = tile - o * a.tiles_per_slice;
     col0 = cb * W;

@@ -49,6 +49,7 @@ struct TileCtx {
 };
 
 __device__ __forceinline__ TileCtx make_ctx(const PassArgs& a, uint32_t tile, int64_t off) {
+  if (a.rev) tile = a.ntiles - 1u - tile;
   const uint32_t o = fdiv(tile, a.divTiles);
   const uint32_t cb = tile - o * a.tiles_per_slice;
   TileCtx t;
