@@ -417,9 +417,12 @@ bool build_ops(const Seg& s, int kind, PassArgs& a, int* cls,
   };
   std::vector<OpDesc> ops;
   const bool folded = cross && !cross->empty();
+  // folded short axes: their forward DFTs before the pass's own forward
+  // stages, their inverse DFTs after its inverse stages
   if (folded) {
-    if (kind != 2 || s.mode != MODE_STRIDED || s.W != s.ncols) return false;
-    for (auto& x : *cross) ops.push_back(mkx(x, OP_DIF));
+    if (s.mode != MODE_STRIDED || s.W != s.ncols) return false;
+    if (kind != 1)
+      for (auto& x : *cross) ops.push_back(mkx(x, OP_DIF));
   }
   if (kind == 0) {
     for (auto& g : gs) ops.push_back(mk(g, OP_DIF));
@@ -430,7 +433,7 @@ bool build_ops(const Seg& s, int kind, PassArgs& a, int* cls,
     ops.push_back(mk(gs.back(), OP_MID));
     for (size_t i = gs.size() - 1; i-- > 0;) ops.push_back(mk(gs[i], OP_DIT));
   }
-  if (folded)
+  if (folded && kind != 0)
     for (auto it = cross->rbegin(); it != cross->rend(); ++it) ops.push_back(mkx(*it, OP_DIT));
   if ((int)ops.size() > kMaxOps) return false;
   for (auto& op : ops)
@@ -799,23 +802,17 @@ pafc_status plan_core(PlanCore& P, int ndim, const int64_t* dims, const int* rad
     v.push_back(p);
     return true;
   };
-  // forward only: all axes, fastest first, outer piece before inner piece
-  for (int a = ndim - 1; a >= 0; --a)
-    for (auto& s : P.axes[a].segs)
-      if (!add(P.fwd, s, 0)) return PAFC_ERROR_UNSUPPORTED_SIZE;
-  // inverse only: the mirror image
-  for (int a = 0; a < ndim; ++a)
-    for (auto it = P.axes[a].segs.rbegin(); it != P.axes[a].segs.rend(); ++it)
-      if (!add(P.inv, *it, 1)) return PAFC_ERROR_UNSUPPORTED_SIZE;
-  // Short faster axes folded into the fused middle pass as column ops: the
-  // middle axis is the slowest, so its innermost piece is strided over all
-  // the other axes; when each of them is one register group and together
-  // they form a tile row of at most 64 power-of-two columns, the tile holds
-  // whole rows and their DFTs run inside that pass (the anisotropic grids
-  // n x 2, n x 2 x 2 then move 5 and 5 passes instead of 7 and 9).
+  // Short faster axes folded into a pass of the slowest axis as column ops:
+  // its innermost piece is strided over all the other axes; when each of
+  // them is one register group and together they form a tile row of at
+  // most 64 power-of-two columns, the tile holds whole rows and their DFTs
+  // run inside that pass -- the fused middle pass of the permutation-free
+  // convolution, and the innermost forward and inverse passes of the
+  // slowest axis in the transforms alone (the anisotropic grids n x 2,
+  // n x 2 x 2 then move 5 and 5 passes instead of 7 and 9).
   std::vector<CrossAxis> fold;
   Seg mseg = P.axes[mid].segs.back();
-  if (variant == PAFC_PERM_FREE && mid == 0 && ndim > 1 && env_int("PAFC_FOLD", 1) != 0) {
+  if (mid == 0 && ndim > 1 && env_int("PAFC_FOLD", 1) != 0) {
     bool ok = mseg.mode == MODE_STRIDED;
     int64_t cs = 1;
     for (int a = ndim - 1; a >= 1 && ok; --a) {
@@ -832,6 +829,32 @@ pafc_status plan_core(PlanCore& P, int ndim, const int64_t* dims, const int* rad
       ok = tile_lds_bytes((uint64_t)mseg.L * mseg.W, P.elem) + tw <= kLdsBudget;
     }
     if (!ok) fold.clear();
+  }
+  auto add_folded = [&](std::vector<Pass>& v, int kind) -> bool {
+    Pass p;
+    if (!make_pass(mseg, kind, P.elem, &p, &fold)) return false;
+    v.push_back(p);
+    return true;
+  };
+  // forward only: all axes, fastest first, outer piece before inner piece
+  // (folded: the slowest axis alone, its innermost piece with the others)
+  const auto& s0 = P.axes[0].segs;
+  for (int a = ndim - 1; a >= 0; --a) {
+    if (!fold.empty() && a != 0) continue;
+    for (size_t i = 0; i < P.axes[a].segs.size(); ++i) {
+      const bool f = !fold.empty() && i + 1 == s0.size();
+      if (!(f ? add_folded(P.fwd, 0) : add(P.fwd, P.axes[a].segs[i], 0)))
+        return PAFC_ERROR_UNSUPPORTED_SIZE;
+    }
+  }
+  // inverse only: the mirror image
+  for (int a = 0; a < ndim; ++a) {
+    if (!fold.empty() && a != 0) continue;
+    for (size_t i = P.axes[a].segs.size(); i-- > 0;) {
+      const bool f = !fold.empty() && i + 1 == s0.size();
+      if (!(f ? add_folded(P.inv, 1) : add(P.inv, P.axes[a].segs[i], 1)))
+        return PAFC_ERROR_UNSUPPORTED_SIZE;
+    }
   }
   if (variant == PAFC_PERM_FREE) {
     for (int a = ndim - 1; a >= 0; --a) {

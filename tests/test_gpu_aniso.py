@@ -178,3 +178,50 @@ def test_short_axes_folded_into_middle_pass(dims, radix, dtype, monkeypatch):
     assert not any("XDIF" in l for l in labels0)
     y0 = conv_gpu(x, h, dtype, radix)
     assert rel_l2(y, y0) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dims,radix,dtype", FOLD)
+@pytest.mark.parametrize("variant", ["explicit_perm", "perm_free_unfused"])
+def test_folded_transforms_in_comparison_variants(dims, radix, dtype, variant, monkeypatch):
+    """The comparison variants run the transforms alone, whose innermost
+    forward and inverse passes of the slowest axis carry the folded short
+    axes; same result as without folding, and as the oracle."""
+    dt = "c128" if dtype == C128 else "c64"
+    labels = pafc().describe(dims, dt, radix, variant)["conv_passes"]
+    say("fold", variant, dims, dt, labels)
+    assert any("XDIF" in l for l in labels) and any("XDIT" in l for l in labels)
+    rng = np.random.default_rng([len(dims), dims[0], 4])
+    x = inputs.complex_uniform(rng, dims)
+    h = inputs.complex_uniform(rng, dims)
+    P = pafc().Plan(dims, dtype, radix=radix, variant=variant)
+    P.set_filter(to_dev(h, dtype))
+    y = to_host(P.convolve(to_dev(x, dtype)))
+    P.close()
+    assert rel_l2(y, ref_conv(x, h, dtype)) <= TOL[dtype]
+    monkeypatch.setenv("PAFC_FOLD", "0")
+    assert not any("XDIF" in l for l in pafc().describe(dims, dt, radix, variant)["conv_passes"])
+    P = pafc().Plan(dims, dtype, radix=radix, variant=variant)
+    P.set_filter(to_dev(h, dtype))
+    y0 = to_host(P.convolve(to_dev(x, dtype)))
+    P.close()
+    assert rel_l2(y, y0) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dims,radix", [((64, 16), None), ((4096, 8, 4), None), ((2 ** 14, 2, 2), [4, 2, 2])])
+def test_folded_forward_layout(dims, radix, monkeypatch):
+    """pafc_forward with folded short axes writes the same digit-reversed
+    spectrum as the unfolded plan (to rounding: the same register groups per
+    axis, in other kernels), and pafc_inverse undoes it."""
+    rng = np.random.default_rng(5)
+    x = inputs.complex_uniform(rng, dims)
+    assert any("XDIF" in l for l in pafc().describe(dims, "c128", radix)["conv_passes"])
+    P = pafc().Plan(dims, C128, radix=radix)
+    z = to_host(P.forward(to_dev(x, C128)))
+    back = to_host(P.inverse(to_dev(z, C128)))
+    P.close()
+    assert rel_l2(back, x) <= 1e-13
+    monkeypatch.setenv("PAFC_FOLD", "0")
+    P = pafc().Plan(dims, C128, radix=radix)
+    z0 = to_host(P.forward(to_dev(x, C128)))
+    P.close()
+    assert rel_l2(z, z0) <= 1e-14
