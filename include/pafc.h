@@ -376,8 +376,12 @@ pafc_status pafc_stream_copy(const void* src_dev, void* dst_dev, size_t bytes,
  * by the planner, or from the table set by pafc_set_tuning) and a device
  * work list; pafc_batch_convolve enqueues, for each pass level in turn (at
  * most three), one launch per register class and LDS-bound occupancy
- * present, which a caller may capture in a hipGraph.
- * Errors: INVALID_VALUE, UNSUPPORTED_SIZE, OUT_OF_MEMORY, DEVICE.
+ * present, which a caller may capture in a hipGraph.  All arguments are
+ * checked before any device call.
+ * Errors: INVALID_VALUE (out, sizes or filter_ids NULL, count < 1,
+ * nfilters < 1, a length < 2, a filter id out of range, two lengths on one
+ * filter, bad dtype), UNSUPPORTED_SIZE (a length with a prime factor above
+ * 5), OUT_OF_MEMORY, DEVICE.
  */
 typedef struct pafc_batch_s* pafc_batch_t;
 

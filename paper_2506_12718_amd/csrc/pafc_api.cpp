@@ -2292,12 +2292,21 @@ pafc_status pafc_batch_plan(pafc_batch_t* out, int count, const int64_t* sizes,
     free_batch(b);
     return st;
   };
+  // every argument is checked before any device call; the batched form runs
+  // the pass plans of {2,3,5}-smooth lengths only (the prime-length routes
+  // have stages of their own)
   for (int i = 0; i < count; ++i) {
     const int64_t n = sizes[i];
     const int f = filter_ids[i];
     if (n < 2 || f < 0 || f >= nfilters) return fail(PAFC_ERROR_INVALID_VALUE);
     if (b->fsize[(size_t)f] != 0 && b->fsize[(size_t)f] != n) return fail(PAFC_ERROR_INVALID_VALUE);
     b->fsize[(size_t)f] = n;
+  }
+  for (int i = 0; i < count; ++i)
+    if (!smooth235(sizes[i])) return fail(PAFC_ERROR_UNSUPPORTED_SIZE);
+  for (int i = 0; i < count; ++i) {
+    const int64_t n = sizes[i];
+    const int f = filter_ids[i];
     b->sizes.push_back(n);
     b->fid.push_back(f);
     b->offsets.push_back(b->total);

@@ -249,3 +249,35 @@ def test_rader_plans(monkeypatch):
         assert "bluestein_m" in pafc.describe((n,), "c128")
     monkeypatch.setenv("PAFC_BLUESTEIN", "1")
     assert "bluestein_m" in pafc.describe((97,), "c128")
+
+
+def test_size_limits_and_batch_argument_errors():
+    """The planner's bounds on the host: up to 2^34 elements per array (the
+    pass kernels switch from 32-bit to 64-bit offsets above 4 GiB), and the
+    batched form's argument checks, which run before any device call."""
+    d = pafc.describe((2 ** 14, 2 ** 14), "c128")  # 4 GiB per array
+    assert not any("pipe_kernel" in l for l in d["conv_passes"])  # 64-bit engine
+    d = pafc.describe((2 ** 13, 2 ** 14), "c128")  # 2 GiB: 32-bit offsets suffice
+    assert any("pipe_kernel" in l for l in d["conv_passes"])
+    for dims in [(2 ** 18, 2 ** 17), (2 ** 12, 2 ** 12, 2 ** 11)]:
+        with pytest.raises(pafc.PafcError) as e:
+            pafc.describe(dims, "c128")
+        assert e.value.status == 2
+    L = pafc.lib()
+    h = ctypes.c_void_p()
+    I64, I32 = ctypes.c_int64, ctypes.c_int
+    cases = [
+        (0, [], [], 1),                    # no problems
+        (2, [64, 1], [0, 0], 1),           # a length below 2
+        (2, [64, 128], [0, 0], 1),         # one filter, two lengths
+        (2, [64, 64], [0, 1], 1),          # filter id out of range
+        (1, [64], [0], 0),                 # no filters
+    ]
+    for count, sizes, fids, nf in cases:
+        st = L.pafc_batch_plan(ctypes.byref(h), count, (I64 * max(1, count))(*sizes),
+                               (I32 * max(1, count))(*fids), nf, 2, None)
+        assert st == 1, (count, sizes, fids, nf)
+        assert not h.value
+    # a length with a prime factor above 5 (no pass plan), after a valid one
+    st = L.pafc_batch_plan(ctypes.byref(h), 2, (I64 * 2)(64, 97), (I32 * 2)(0, 1), 2, 2, None)
+    assert st == 2 and not h.value

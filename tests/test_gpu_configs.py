@@ -85,3 +85,32 @@ def test_conv1d_5pow9_radix5(dtype):
     y = to_host(P.convolve(to_dev(x, dtype)))
     P.close()
     assert rel_l2(y, ref) < TOL[dtype]
+
+
+def test_maximum_size_64bit_offsets():
+    """16384 x 16384 complex128: 4 GiB per array, beyond the pipelined
+    kernels' 32-bit byte offsets, so every pass runs on the general engine
+    with 64-bit offsets.  Sampled outputs (first, last, random) against the
+    oracle's direct sum."""
+    shape = (2 ** 14, 2 ** 14)
+    d = pafc().describe(shape, "c128")
+    assert not any("pipe_kernel" in l for l in d["conv_passes"])
+    rng = np.random.default_rng(77)
+    x = inputs.complex_uniform(rng, shape)
+    h = inputs.complex_uniform(rng, shape)
+    P = pafc().Plan(shape, torch.complex128)
+    hd = to_dev(h, torch.complex128)
+    P.set_filter(hd)
+    del hd
+    xd = to_dev(x, torch.complex128)
+    P.convolve(xd, out=xd)  # in place
+    y = to_host(xd).reshape(-1)
+    del xd
+    P.close()
+    torch.cuda.empty_cache()
+    idx = rng.integers(0, y.size, 8)
+    idx[0], idx[1] = 0, y.size - 1
+    ref = oracle.conv_direct_at(x, h, idx)
+    err = np.linalg.norm(y[idx] - ref) / np.linalg.norm(ref)
+    say("16384^2 c128 sampled rel_l2", err)
+    assert err <= TOL[torch.complex128]
