@@ -151,9 +151,14 @@ typedef struct pafc_plan_s* pafc_plan_t;
  * hip_stream: stream on which the twiddle uploads are enqueued.
  *
  * On success *out receives the plan, which owns device memory for the
- * twiddles, the filter spectrum (N elements) and, for PAFC_EXPLICIT_PERM,
- * one N-element scratch array; it allocates with hipMalloc.  On failure
- * *out is set to NULL and nothing is leaked.
+ * twiddles, the filter spectrum (N elements, or the slots of the middle
+ * pass's tiles when its last tile is partial) and one N-element scratch
+ * array for PAFC_EXPLICIT_PERM, and for PAFC_PERM_FREE plans whose strided
+ * middle pass reads the spectrum tile-major (each tile's values in one
+ * contiguous block, written by the filter's last forward pass from that
+ * scratch array); it allocates with hipMalloc (PAFC_HTM=0 in the environment
+ * at planning keeps the plan layout).  On failure *out is set to NULL and
+ * nothing is leaked.
  * Errors: INVALID_VALUE (out == NULL, ndim outside 1..3, dims == NULL,
  * n_i < 2, bad dtype/variant), UNSUPPORTED_SIZE, OUT_OF_MEMORY, DEVICE.
  */

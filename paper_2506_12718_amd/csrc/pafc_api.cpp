@@ -35,6 +35,9 @@ bool pipe_supported(int r, int g, int ng);
 
 int pipe_blocks_per_cu(bool dbl, int r, int g, int ng, int kind, int mode, uint32_t threads,
                        size_t lds);
+hipError_t launch_pipe_htm(bool dbl, int r, int g, int ng, int mode, const PassArgs* d,
+                           uint32_t ntiles, uint32_t threads, const void* src, void* dst,
+                           hipStream_t s);
 hipError_t launch_pipe(bool dbl, int r, int g, int ng, int kind, int mode, const PassArgs* d,
                        uint32_t grid, uint32_t threads, size_t lds, const void* in, void* out,
                        hipStream_t s);
@@ -993,6 +996,11 @@ struct pafc_plan_s {
   uint32_t* d_rader_tab = nullptr;
   double* d_rader_acc = nullptr;
   std::vector<int64_t> map_off;
+  // tile-major spectrum (PassArgs::h_tm): the middle pass of the convolution
+  // and, in fwd_tm, the forward sequence whose last pass writes that order
+  bool h_tm = false;
+  int mid_pass = -1;  // index of the middle pass in P.conv
+  std::vector<Pass> fwd_tm;
   bool filter_set = false;
   size_t bytes = 0;
 };
@@ -1779,6 +1787,33 @@ std::string describe_prime_factor(int64_t n, pafc_dtype dtype, pafc_variant vari
   return s;
 }
 
+// A spectrum produced in plan layout (natural-order input, symbols) for a
+// plan that stores it tile-major: `produce` writes the plan layout into the
+// plan's staging array, which is then reordered into the spectrum (the two
+// layouts place a tile's values differently, so it cannot be done in place).
+template <typename F>
+pafc_status via_plan_layout(pafc_plan_t p, hipStream_t s, F produce) {
+  const PlanCore& P = p->P;
+  const Pass& m = P.conv[(size_t)p->mid_pass];
+  PAFC_TRY(produce(p->d_scratch));
+  return from_hip(launch_pipe_htm(P.dtype == PAFC_C128, m.pipe_r, m.pipe_g, m.pipe_ng,
+                                  (int)m.a.mode, p->d_descs + m.desc, m.a.ntiles, m.threads,
+                                  p->d_scratch, p->d_H, s));
+}
+
+// The filter's forward transform for a plan that stores the spectrum
+// tile-major: all forward passes but the last in the staging array, the
+// last one from there into the spectrum in tile-major order.
+pafc_status forward_tile_major(pafc_plan_t p, const void* h, hipStream_t s) {
+  const std::vector<Pass> head(p->fwd_tm.begin(), p->fwd_tm.end() - 1);
+  const void* src = h;
+  if (!head.empty()) {
+    PAFC_TRY(run_sequence(p, head, h, p->d_scratch, s));
+    src = p->d_scratch;
+  }
+  return run_pass(p, p->fwd_tm.back(), src, p->d_H, s);
+}
+
 }  // namespace
 
 extern "C" {
@@ -1883,7 +1918,16 @@ pafc_status pafc_plan(pafc_plan_t* out, int ndim, const int64_t* dims, const int
   }
   hipError_t e = hipMalloc(&p->d_tw, std::max<size_t>(tw_bytes, 16));
   if (e == hipSuccess) e = hipMalloc((void**)&p->d_maps, maps.size() * sizeof(int32_t));
-  if (e == hipSuccess) e = hipMalloc(&p->d_H, (size_t)P.N * P.elem);
+  // the spectrum: N elements, or every slot of the middle pass's tiles when
+  // it is stored tile-major (decided below, once the pipelined passes are
+  // known); the larger size is reserved either way
+  int64_t h_elems = P.N;
+  for (size_t i = 0; i < P.conv.size(); ++i)
+    if (P.conv[i].kind == 0 && P.conv[i].mid) {
+      p->mid_pass = (int)i;
+      h_elems = std::max<int64_t>(h_elems, (int64_t)P.conv[i].a.LW * P.conv[i].a.ntiles);
+    }
+  if (e == hipSuccess) e = hipMalloc(&p->d_H, (size_t)h_elems * P.elem);
   size_t symtab_bytes = 3;
   for (auto& ax : P.axes) symtab_bytes += (size_t)ax.n;
   symtab_bytes *= 2 * sizeof(double);
@@ -1908,6 +1952,25 @@ pafc_status pafc_plan(pafc_plan_t* out, int ndim, const int64_t* dims, const int
       }
 
   }
+  // Tile-major spectrum: when the middle pass and the last forward pass (the
+  // same piece of the same axis) both run on the pipelined kernel with the
+  // same strided tiling, the filter's last forward pass writes the spectrum
+  // in the order the middle pass reads it, one contiguous block per tile
+  // instead of 16-column row segments (contiguous tiles read whole rows
+  // already, and their forward pass stores through LDS).
+  if (P.variant == PAFC_PERM_FREE && p->mid_pass >= 0 && !P.fwd.empty() &&
+      env_int("PAFC_HTM", 1) != 0) {
+    const Pass& m = P.conv[(size_t)p->mid_pass];
+    const Pass& f = P.fwd.back();
+    const PassArgs &x = m.a, &y = f.a;
+    p->h_tm = m.pipe && f.pipe && m.pipe_r == f.pipe_r && m.pipe_g == f.pipe_g &&
+              m.pipe_ng == f.pipe_ng && m.threads == f.threads && x.mode == MODE_STRIDED &&
+              y.mode == MODE_STRIDED &&
+              x.L == y.L && x.W == y.W && x.S_i == y.S_i && x.S_c == y.S_c && x.S_o == y.S_o &&
+              x.ncols == y.ncols && x.tiles_per_slice == y.tiles_per_slice &&
+              x.ntiles == y.ntiles &&
+              (uint64_t)x.LW * x.ntiles * (uint64_t)P.elem <= 0xFFFFFFFFull;
+  }
   // pass descriptors of the three sequences, uploaded once.  Consecutive
   // axis passes walk their tiles in opposite directions, so that a pass
   // starts on the end of the array the previous pass wrote last, which is
@@ -1923,8 +1986,19 @@ pafc_status pafc_plan(pafc_plan_t* out, int ndim, const int64_t* dims, const int
       PassArgs a;
       finalize_args(P, p->d_tw, p->d_H, ps, &a);
       a.rev = snake && (i++ % 2 == 1) ? 1u : 0u;
+      if (p->h_tm && seq == &p->P.conv && &ps == &p->P.conv[(size_t)p->mid_pass]) a.h_tm = 1;
       descs.push_back(a);
     }
+  }
+  if (p->h_tm && e == hipSuccess)  // staging array of the filter's transform
+    e = hipMalloc(&p->d_scratch, (size_t)P.N * P.elem);
+  if (p->h_tm) {  // the forward sequence again, its last pass writing tile-major
+    p->fwd_tm = p->P.fwd;
+    Pass& last = p->fwd_tm.back();
+    PassArgs a = descs[last.desc];
+    a.tm_store = 1;
+    last.desc = (uint32_t)descs.size();
+    descs.push_back(a);
   }
   if (e == hipSuccess)
     e = hipMalloc((void**)&p->d_descs, std::max<size_t>(1, descs.size()) * sizeof(PassArgs));
@@ -1947,7 +2021,8 @@ pafc_status pafc_plan(pafc_plan_t* out, int ndim, const int64_t* dims, const int
   }
   p->bytes = tw_bytes + maps.size() * sizeof(int32_t) + descs.size() * sizeof(PassArgs) +
              symtab_bytes +
-             (P.variant == PAFC_EXPLICIT_PERM ? (size_t)P.N * P.elem : 0) + (size_t)P.N * P.elem;
+             (P.variant == PAFC_EXPLICIT_PERM || p->h_tm ? (size_t)P.N * P.elem : 0) +
+             (size_t)h_elems * P.elem;
   *out = p;
   return PAFC_SUCCESS;
 }
@@ -1987,10 +2062,12 @@ pafc_status load_filter(pafc_plan_t p, const void* h_dev, pafc_filter_domain dom
       PAFC_TRY(run_sequence(p, P.fwd, h_dev, p->d_scratch, s));
       PAFC_TRY(run_permute(p, 1, p->d_scratch, p->d_H, nullptr, s));
     } else {
-      PAFC_TRY(run_sequence(p, P.fwd, h_dev, p->d_H, s));
+      PAFC_TRY(p->h_tm ? forward_tile_major(p, h_dev, s) : run_sequence(p, P.fwd, h_dev, p->d_H, s));
     }
   } else if (natural) {
     PAFC_TRY(from_hip(hipMemcpyAsync(p->d_H, h_dev, nbytes, hipMemcpyDeviceToDevice, s)));
+  } else if (p->h_tm) {  // natural -> digit-reversed -> tile-major, once
+    return via_plan_layout(p, s, [&](void* t) { return run_permute(p, 2, h_dev, t, nullptr, s); });
   } else {  // natural -> digit-reversed, once
     PAFC_TRY(run_permute(p, 2, h_dev, p->d_H, nullptr, s));
   }
@@ -2116,8 +2193,11 @@ pafc_status pafc_set_symbol(pafc_plan_t p, pafc_symbol kind, const double* param
   p->filter_set = false;
   PAFC_TRY(from_hip(hipMemcpyAsync(p->d_symtab, g.data(), g.size() * sizeof(double),
                                    hipMemcpyHostToDevice, s)));
-  PAFC_TRY(from_hip(launch_symbol(P.dtype == PAFC_C128, p->d_H, p->d_symtab, m[0], m[1], m[2],
-                                  nn[0], nn[1], nn[2], oo[0], oo[1], oo[2], mode, s)));
+  auto write = [&](void* H) {
+    return from_hip(launch_symbol(P.dtype == PAFC_C128, H, p->d_symtab, m[0], m[1], m[2], nn[0],
+                                  nn[1], nn[2], oo[0], oo[1], oo[2], mode, s));
+  };
+  PAFC_TRY(p->h_tm ? via_plan_layout(p, s, write) : write(p->d_H));
   // the host table dies here: wait for its upload
   PAFC_TRY(from_hip(hipStreamSynchronize(s)));
   p->filter_set = true;

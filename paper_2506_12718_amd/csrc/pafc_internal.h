@@ -124,6 +124,12 @@ struct PassArgs {
                        // twiddles are read from the global table
   uint32_t rev;        // 1: tile t of the launch is tile ntiles - 1 - t (the
                        // pass walks the array from its end)
+  uint32_t h_tm;       // middle pass: H is stored tile-major -- the value
+                       // thread t takes for frequency slot m of (logical) tile
+                       // q sits at q * LW + m * threads + t, so each tile's
+                       // spectrum is one contiguous block read in order
+  uint32_t tm_store;   // forward pass: its last op writes that tile-major
+                       // order (the filter's last forward pass)
   OpDesc ops[kMaxOps];
 };
 

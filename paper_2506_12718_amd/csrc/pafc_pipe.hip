@@ -108,8 +108,10 @@ pipe_kernel(const PassArgs* __restrict__ desc,
   // every array this kernel touches is below 4 GiB (the planner checks), so
   // element indices and byte offsets are 32-bit
   const uint32_t S_i = (uint32_t)a.S_i, S_c = (uint32_t)a.S_c, S_o = (uint32_t)a.S_o;
+  // logical tile of launch tile t (the pass may walk the array backwards)
+  auto logical = [&](uint32_t tile) -> uint32_t { return a.rev ? a.ntiles - 1u - tile : tile; };
   auto tile_base = [&](uint32_t tile, uint32_t& col0) -> uint32_t {
-    if (a.rev) tile = a.ntiles - 1u - tile;
+    tile = logical(tile);
     const uint32_t o = fdiv(tile, a.divTiles);
     const uint32_t cb = tile - o * a.tiles_per_slice;
     col0 = cb * W;
@@ -150,11 +152,19 @@ pipe_kernel(const PassArgs* __restrict__ desc,
       uint32_t col0;
       const uint32_t base = tile_base(tile, col0);
       const Item it = item_of<R, L, R, MODE>(tid, W, logW, col0, a.ncols);
-      const uint32_t gb = base + it.i0 * S_i + it.c * S_c;
-      static_for<R>([&](auto m) {
-        preh[m.value] = it.valid ? ld_g32<T>(a.H, gb + (uint32_t)digrev<r, g>(m.value) * S_i)
-                                 : cx<T>{(T)0, (T)0};
-      });
+      if (a.h_tm) {  // one contiguous block per tile, slot-major
+        const uint32_t tb = logical(tile) * LW + tid;
+        static_for<R>([&](auto m) {
+          preh[m.value] = it.valid ? ld_g32<T>(a.H, tb + (uint32_t)m.value * nthr)
+                                   : cx<T>{(T)0, (T)0};
+        });
+      } else {
+        const uint32_t gb = base + it.i0 * S_i + it.c * S_c;
+        static_for<R>([&](auto m) {
+          preh[m.value] = it.valid ? ld_g32<T>(a.H, gb + (uint32_t)digrev<r, g>(m.value) * S_i)
+                                   : cx<T>{(T)0, (T)0};
+        });
+      }
     }
   };
 
@@ -235,15 +245,27 @@ pipe_kernel(const PassArgs* __restrict__ desc,
         Dft<R, r, true, T>::run(v);
       }
       // outputs
-      static_for<R>([&](auto s) {
-        // DIF writes frequency m at its digit-reversed position
-        constexpr int p = type == OP_DIF ? digrev<r, g>(s.value) : s.value;
-        if constexpr (last) {
-          if (it.valid) st_g32<T>(out, gb + (uint32_t)(p * S) * S_i, v[s.value]);
-        } else {
-          lds[lds_phys(lbase + (uint32_t)(p * S) * ls_i)] = v[s.value];
-        }
-      });
+      bool tm = false;
+      if constexpr (last && KIND == PIPE_FWD) tm = a.tm_store != 0;
+      if (tm) {
+        // the tile-major spectrum order the middle pass reads (PassArgs::h_tm):
+        // this last op has the middle op's items (level NG - 1, S = 1), and
+        // slot s holds the frequency the middle op's slot s multiplies
+        const uint32_t tb = logical(tile) * LW + tid;
+        static_for<R>([&](auto s) {
+          if (it.valid) st_g32<T>(out, tb + (uint32_t)s.value * nthr, v[s.value]);
+        });
+      } else {
+        static_for<R>([&](auto s) {
+          // DIF writes frequency m at its digit-reversed position
+          constexpr int p = type == OP_DIF ? digrev<r, g>(s.value) : s.value;
+          if constexpr (last) {
+            if (it.valid) st_g32<T>(out, gb + (uint32_t)(p * S) * S_i, v[s.value]);
+          } else {
+            lds[lds_phys(lbase + (uint32_t)(p * S) * ls_i)] = v[s.value];
+          }
+        });
+      }
       if constexpr (!last) __syncthreads();
     });
     if constexpr (LINEAR_STORE) {
@@ -255,6 +277,35 @@ pipe_kernel(const PassArgs* __restrict__ desc,
     }
     __syncthreads();  // LDS free for the next tile
     tile = next;
+  }
+}
+
+// The spectrum in plan layout -> the tile-major order of a middle pass
+// (PassArgs::h_tm), for spectra that do not come out of the filter's own
+// forward passes (natural-order input, symbols).  Launched with the middle
+// pass's descriptor and thread count; slots of columns beyond the edge are
+// zero.
+template <typename T, int r, int g, int NG, int MODE>
+__global__ void __launch_bounds__(256) pipe_htm_kernel(const PassArgs* __restrict__ desc,
+                                                        const void* __restrict__ src,
+                                                        void* __restrict__ dst) {
+  constexpr int R = ipow(r, g);
+  constexpr int L = ipow(R, NG);
+  const PassArgs& a = *desc;
+  const uint32_t tid = threadIdx.x, nthr = blockDim.x;
+  const uint32_t W = a.W, logW = a.logW, LW = a.LW;
+  const uint32_t S_i = (uint32_t)a.S_i, S_c = (uint32_t)a.S_c, S_o = (uint32_t)a.S_o;
+  for (uint32_t q = blockIdx.x; q < a.ntiles; q += gridDim.x) {
+    const uint32_t o = fdiv(q, a.divTiles);
+    const uint32_t col0 = (q - o * a.tiles_per_slice) * W;
+    const uint32_t base = o * S_o + col0 * S_c;
+    const Item it = item_of<R, L, R, MODE>(tid, W, logW, col0, a.ncols);
+    const uint32_t gb = base + it.i0 * S_i + it.c * S_c;
+    static_for<R>([&](auto m) {
+      const cx<T> v = it.valid ? ld_g32<T>(src, gb + (uint32_t)digrev<r, g>(m.value) * S_i)
+                               : cx<T>{(T)0, (T)0};
+      st_g32<T>(dst, q * LW + (uint32_t)m.value * nthr + tid, v);
+    });
   }
 }
 
@@ -306,6 +357,34 @@ int pipe_blocks_per_cu(bool dbl, int r, int g, int ng, int kind, int mode, uint3
   int nb = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, (int)threads, lds) != hipSuccess) return 0;
   return nb;
+}
+
+hipError_t launch_pipe_htm(bool dbl, int r, int g, int ng, int mode, const PassArgs* d,
+                           uint32_t ntiles, uint32_t threads, const void* src, void* dst,
+                           hipStream_t s) {
+  const uint32_t grid = ntiles < 8192u ? ntiles : 8192u;
+#define PAFC_HTM_GO(rr, gg, nn)                                                               \
+  if (r == rr && g == gg && ng == nn) {                                                       \
+    if (dbl) {                                                                                \
+      if (mode == MODE_CONTIG)                                                                \
+        hipLaunchKernelGGL((pipe_htm_kernel<double, rr, gg, nn, MODE_CONTIG>), dim3(grid),    \
+                           dim3(threads), 0, s, d, src, dst);                                 \
+      else                                                                                    \
+        hipLaunchKernelGGL((pipe_htm_kernel<double, rr, gg, nn, MODE_STRIDED>), dim3(grid),   \
+                           dim3(threads), 0, s, d, src, dst);                                 \
+    } else {                                                                                  \
+      if (mode == MODE_CONTIG)                                                                \
+        hipLaunchKernelGGL((pipe_htm_kernel<float, rr, gg, nn, MODE_CONTIG>), dim3(grid),     \
+                           dim3(threads), 0, s, d, src, dst);                                 \
+      else                                                                                    \
+        hipLaunchKernelGGL((pipe_htm_kernel<float, rr, gg, nn, MODE_STRIDED>), dim3(grid),    \
+                           dim3(threads), 0, s, d, src, dst);                                 \
+    }                                                                                         \
+    return hipGetLastError();                                                                 \
+  }
+  PAFC_PIPE_SHAPES(PAFC_HTM_GO)
+#undef PAFC_HTM_GO
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_pipe(bool dbl, int r, int g, int ng, int kind, int mode, const PassArgs* d,

@@ -294,3 +294,42 @@ def test_split_strided_axes(shape, dtype):
     y, _ = run_conv(x, h, dtype)
     ref = oracle.conv_fft(rounded(x, dtype), rounded(h, dtype))
     assert rel_l2(y, ref) < TOL[dtype], d["conv_passes"]
+
+
+HTM_SHAPES = [((64, 64, 64), [4, 4, 4]), ((256, 256), [4, 4]), ((4096, 48), [4, 0]), ((256, 64), [2, 2]),
+              ((512, 40), [8, 0])]
+
+
+@pytest.mark.parametrize("shape,radix", HTM_SHAPES)
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_tile_major_spectrum(shape, radix, dtype, monkeypatch):
+    """Plans whose strided middle pass reads the spectrum tile-major (the
+    filter's last forward pass writes that order; natural-order spectra and
+    symbols are reordered into it) give the same bits as plans that keep the
+    plan layout (PAFC_HTM=0), for spatial, natural-spectral, per-call and
+    symbol filters, and match the oracle."""
+    rng = np.random.default_rng([len(shape), shape[0], 9])
+    x = inputs.complex_uniform(rng, shape)
+    h = inputs.complex_uniform(rng, shape)
+    hn = inputs.complex_normal(rng, shape)
+    out = {}
+    for htm in ("1", "0"):
+        monkeypatch.setenv("PAFC_HTM", htm)
+        P = pafc().Plan(shape, dtype, radix=radix)
+        xd = to_dev(x, dtype)
+        P.set_filter(to_dev(h, dtype))
+        a = to_host(P.convolve(xd))
+        P.set_filter(to_dev(hn, dtype), domain="spectral_natural")
+        b = to_host(P.convolve(xd))
+        c = to_host(P.convolve_with_filter(xd, to_dev(h, dtype)))
+        P.set_symbol("heat", 0.5)
+        d = to_host(P.convolve(xd))
+        P.close()
+        out[htm] = (a, b, c, d)
+    for u, v in zip(out["1"], out["0"]):
+        assert np.array_equal(u, v)
+    xr, hr = rounded(x, dtype), rounded(h, dtype)
+    assert rel_l2(out["1"][0], oracle.conv_fft(xr, hr)) <= TOL[dtype]
+    assert rel_l2(out["1"][2], out["1"][0]) == 0.0
+    ref_b = oracle.fft(rounded(hn, dtype) * oracle.fft(xr), inverse=True)
+    assert rel_l2(out["1"][1], ref_b) <= TOL[dtype]
