@@ -83,6 +83,8 @@ constexpr size_t kLdsBudget = 160 * 1024;  // LDS per CU on gfx950
 //   PAFC_WIDE      0 disables the wide (1024-thread) register class
 //   PAFC_FOLD      0 keeps short faster axes in passes of their own
 //   PAFC_SNAKE     0 walks every pass's tiles in the same direction
+//   PAFC_AXIS_ORDER 1 runs the other axes' forward passes slowest first
+//   PAFC_HTM       0 keeps the spectrum in plan layout (no tile-major order)
 //   PAFC_BLUESTEIN 1 plans a prime length by Bluestein's method even where
 //                  Rader's applies (p - 1 {2,3,5}-smooth)
 int env_int(const char* name, int dflt) {
@@ -860,11 +862,15 @@ pafc_status plan_core(PlanCore& P, int ndim, const int64_t* dims, const int* rad
     }
   }
   if (variant == PAFC_PERM_FREE) {
-    for (int a = ndim - 1; a >= 0; --a) {
-      if (a == mid || !fold.empty()) continue;
+    // the other axes' forward passes, fastest axis first (PAFC_AXIS_ORDER=1:
+    // slowest first), their inverse passes in the mirrored order
+    std::vector<int> order;
+    for (int a = ndim - 1; a >= 0; --a)
+      if (a != mid && fold.empty()) order.push_back(a);
+    if (env_int("PAFC_AXIS_ORDER", 0) == 1) std::reverse(order.begin(), order.end());
+    for (int a : order)
       for (auto& s : P.axes[a].segs)
         if (!add(P.conv, s, 0)) return PAFC_ERROR_UNSUPPORTED_SIZE;
-    }
     auto& ms = P.axes[mid].segs;
     for (size_t i = 0; i + 1 < ms.size(); ++i)
       if (!add(P.conv, ms[i], 0)) return PAFC_ERROR_UNSUPPORTED_SIZE;
@@ -877,11 +883,9 @@ pafc_status plan_core(PlanCore& P, int ndim, const int64_t* dims, const int* rad
     }
     for (size_t i = ms.size() - 1; i-- > 0;)
       if (!add(P.conv, ms[i], 1)) return PAFC_ERROR_UNSUPPORTED_SIZE;
-    for (int a = 0; a < ndim; ++a) {
-      if (a == mid || !fold.empty()) continue;
-      for (auto it = P.axes[a].segs.rbegin(); it != P.axes[a].segs.rend(); ++it)
+    for (auto a = order.rbegin(); a != order.rend(); ++a)
+      for (auto it = P.axes[*a].segs.rbegin(); it != P.axes[*a].segs.rend(); ++it)
         if (!add(P.conv, *it, 1)) return PAFC_ERROR_UNSUPPORTED_SIZE;
-    }
   } else {
     for (auto& p : P.fwd) P.conv.push_back(p);
     if (variant == PAFC_PERM_FREE_UNFUSED) {
