@@ -53,6 +53,11 @@
 extern "C" {
 #endif
 
+/* Every enum below ends in a *_MAX_ENUM member: it keeps each non-negative
+   int a value of the enum type, so an out-of-range value passed across the
+   C ABI is rejected by the library's checks (INVALID_VALUE) instead of being
+   undefined in its C++ implementation.  *_MAX_ENUM is never a valid
+   argument. */
 typedef enum pafc_status {
   PAFC_SUCCESS = 0,
   PAFC_ERROR_INVALID_VALUE = 1,    /* null/misaligned pointer, bad ndim, n_i < 2, bad enum */
@@ -61,12 +66,14 @@ typedef enum pafc_status {
                                       n_i != r^t for an explicit uniform radix */
   PAFC_ERROR_OUT_OF_MEMORY = 3,    /* device allocation failed */
   PAFC_ERROR_DEVICE = 4,           /* HIP runtime or launch error */
-  PAFC_ERROR_FILTER_NOT_SET = 5    /* pafc_convolve before pafc_set_filter */
+  PAFC_ERROR_FILTER_NOT_SET = 5,   /* pafc_convolve before pafc_set_filter */
+  PAFC_STATUS_MAX_ENUM = 0x7FFFFFFF
 } pafc_status;
 
 typedef enum pafc_dtype {
   PAFC_C64 = 1,  /* complex float32, interleaved */
-  PAFC_C128 = 2  /* complex float64, interleaved */
+  PAFC_C128 = 2, /* complex float64, interleaved */
+  PAFC_DTYPE_MAX_ENUM = 0x7FFFFFFF
 } pafc_dtype;
 
 typedef enum pafc_variant {
@@ -96,12 +103,14 @@ typedef enum pafc_variant {
   /* Comparison: the same route with the grid convolution done by the
      explicit-permutation variant (the standard prime-factor FFT
      convolution, six permutations). */
-  PAFC_PRIME_FACTOR_EXPLICIT = 4
+  PAFC_PRIME_FACTOR_EXPLICIT = 4,
+  PAFC_VARIANT_MAX_ENUM = 0x7FFFFFFF
 } pafc_variant;
 
 typedef enum pafc_filter_domain {
   PAFC_FILTER_SPATIAL = 0,          /* h given in the spatial domain, natural order */
-  PAFC_FILTER_SPECTRAL_NATURAL = 1  /* the DFT of h given, natural frequency order */
+  PAFC_FILTER_SPECTRAL_NATURAL = 1, /* the DFT of h given, natural frequency order */
+  PAFC_FILTER_DOMAIN_MAX_ENUM = 0x7FFFFFFF
 } pafc_filter_domain;
 
 typedef struct pafc_plan_s* pafc_plan_t;
@@ -219,7 +228,8 @@ typedef enum pafc_symbol {
   PAFC_SYMBOL_INV_LAPLACIAN = 0,
   PAFC_SYMBOL_INV_LAPLACIAN_FD = 1,
   PAFC_SYMBOL_HEAT = 2,
-  PAFC_SYMBOL_DERIVATIVE = 3
+  PAFC_SYMBOL_DERIVATIVE = 3,
+  PAFC_SYMBOL_MAX_ENUM = 0x7FFFFFFF
 } pafc_symbol;
 
 /*

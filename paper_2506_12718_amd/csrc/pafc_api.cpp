@@ -85,6 +85,7 @@ constexpr size_t kLdsBudget = 160 * 1024;  // LDS per CU on gfx950
 //   PAFC_SNAKE     0 walks every pass's tiles in the same direction
 //   PAFC_AXIS_ORDER 1 runs the other axes' forward passes slowest first
 //   PAFC_HTM       0 keeps the spectrum in plan layout (no tile-major order)
+//   PAFC_LDS_POISON 1 (debug) every pass fills its LDS tile with NaN first
 //   PAFC_BLUESTEIN 1 plans a prime length by Bluestein's method even where
 //                  Rader's applies (p - 1 {2,3,5}-smooth)
 int env_int(const char* name, int dflt) {
@@ -205,24 +206,44 @@ std::vector<int32_t> pos_table(int64_t n, const std::vector<int>& rho) {
 
 // ---------------------------------------------------------------- twiddles
 
-// w_n^E = exp(-2 pi i E / n) in FP64, from long double with exact octant
-// reduction, so that +-1, +-i and (+-1 +-i)/sqrt(2) are exact.
+// w_n^E = exp(-2 pi i E / n) in FP64, from long double.  The angle
+// theta = 2 pi E / n is reduced exactly in integers to an octant o and a
+// remainder r (8E = o n + r); cosl/sinl are only evaluated on [0, pi/4]
+// (phi = (pi/4) r / n, or its reflection (pi/4)(n - r)/n in the odd
+// octants), and the octant is applied by exact swaps and sign changes.  So
+// +-1 and +-i are exact, (+-1 +-i)/sqrt(2) correctly rounded, and
+// w_n^(n-E) is exactly the conjugate of w_n^E.
 void omega64(int64_t n, int64_t E, double* re, double* im) {
   E %= n;
   if (E < 0) E += n;
   const __int128 num = (__int128)8 * E;
-  const int oct = (int)(num / n);
-  const int64_t rem = (int64_t)(num - (__int128)oct * n);
-  const long double pi = 3.141592653589793238462643383279502884L;
-  const long double phi = (long double)rem / (long double)n * (pi / 4.0L);
-  long double c = cosl(phi), s = sinl(phi);
-  if (rem == 0) { c = 1.0L; s = 0.0L; }
-  const long double h = 0.707106781186547524400844362104849039L;
-  const long double bc[8] = {1, h, 0, -h, -1, -h, 0, h};
-  const long double bs[8] = {0, h, 1, h, 0, -h, -1, -h};
-  long double ct = bc[oct] * c - bs[oct] * s;
-  long double st = bs[oct] * c + bc[oct] * s;
-  if (rem == 0) { ct = bc[oct]; st = bs[oct]; }
+  const int o = (int)(num / n);
+  const int64_t r = (int64_t)(num - (__int128)o * n);
+  const long double pi4 = 0.785398163397448309615660845819875721L;
+  const int64_t rr = (o & 1) ? n - r : r;  // odd octants: reflected remainder
+  long double c, sn;
+  if (rr == 0) {
+    c = 1.0L;
+    sn = 0.0L;
+  } else if (rr == n) {
+    c = sn = 0.707106781186547524400844362104849039L;
+  } else {
+    const long double phi = (long double)rr / (long double)n * pi4;
+    c = cosl(phi);
+    sn = sinl(phi);
+  }
+  // (cos theta, sin theta) from (c, sn) = (cos, sin) of phi or its reflection
+  long double ct, st;
+  switch (o) {
+    case 0: ct = c; st = sn; break;
+    case 1: ct = sn; st = c; break;
+    case 2: ct = -sn; st = c; break;
+    case 3: ct = -c; st = sn; break;
+    case 4: ct = -c; st = -sn; break;
+    case 5: ct = -sn; st = -c; break;
+    case 6: ct = sn; st = -c; break;
+    default: ct = c; st = -sn; break;
+  }
   *re = (double)ct;
   *im = (double)(-st);
 }
@@ -1981,6 +2002,7 @@ pafc_status pafc_plan(pafc_plan_t* out, int ndim, const int64_t* dims, const int
   // still in the device's last-level cache when the array is larger
   // than it.
   const bool snake = env_int("PAFC_SNAKE", 1) != 0;
+  const bool poison = env_int("PAFC_LDS_POISON", 0) != 0;
   std::vector<PassArgs> descs;
   for (auto* seq : {&p->P.conv, &p->P.fwd, &p->P.inv}) {
     int i = 0;
@@ -1990,6 +2012,7 @@ pafc_status pafc_plan(pafc_plan_t* out, int ndim, const int64_t* dims, const int
       PassArgs a;
       finalize_args(P, p->d_tw, p->d_H, ps, &a);
       a.rev = snake && (i++ % 2 == 1) ? 1u : 0u;
+      a.poison = poison ? 1u : 0u;
       if (p->h_tm && seq == &p->P.conv && &ps == &p->P.conv[(size_t)p->mid_pass]) a.h_tm = 1;
       descs.push_back(a);
     }
@@ -2420,6 +2443,7 @@ pafc_status pafc_batch_plan(pafc_batch_t* out, int count, const int64_t* sizes,
     for (size_t l = 0; l < conv.size(); ++l) {
       PassArgs a;
       finalize_args(p->P, p->d_tw, b->d_spec[(size_t)f], conv[l], &a);
+      a.poison = env_int("PAFC_LDS_POISON", 0) != 0 ? 1u : 0u;
       didx[{f, (int)l}] = (uint32_t)descs.size();
       descs.push_back(a);
       dthreads.push_back(conv[l].threads);

@@ -176,6 +176,11 @@ pipe_kernel(const PassArgs* __restrict__ desc,
   __syncthreads();  // twiddles visible
 
   while (tile < a.ntiles) {
+    if (a.poison) {  // debug: the tile region (below the twiddles) is NaN
+      const T nan = __builtin_nan("");
+      for (uint32_t x = tid; x < (uint32_t)(tw - lds); x += nthr) lds[x] = cx<T>{nan, nan};
+      __syncthreads();
+    }
     const uint32_t next = tile + gridDim.x;
     uint32_t col0;
     const uint32_t base = tile_base(tile, col0);

@@ -279,6 +279,11 @@ __device__ __forceinline__ void do_tile(const PassArgs& a, const void* __restric
                                         void* __restrict__ out, uint32_t tile, int64_t off,
                                         cx<T>* lds) {
   const TileCtx t = make_ctx(a, tile, off);
+  if (a.poison) {  // debug: the tile region (below the twiddle copy) is NaN
+    const T nan = __builtin_nan("");
+    for (uint32_t x = threadIdx.x; x < a.twl_off; x += blockDim.x) lds[x] = cx<T>{nan, nan};
+    __syncthreads();
+  }
   stage_twiddles<T>(a, lds);
   // load (unless the first op reads global memory itself)
   if (!a.ops[0].src_g) load_tile<T>(a, t, in, lds);

@@ -333,3 +333,61 @@ def test_tile_major_spectrum(shape, radix, dtype, monkeypatch):
     assert rel_l2(out["1"][2], out["1"][0]) == 0.0
     ref_b = oracle.fft(rounded(hn, dtype) * oracle.fft(xr), inverse=True)
     assert rel_l2(out["1"][1], ref_b) <= TOL[dtype]
+
+
+POISON_CASES = [((256, 256), [4, 4]), ((4096,), [4]), ((4096, 48), [4, 0]), ((512, 40), [8, 0]),
+                ((2187, 12), None), ((5 ** 6,), None), ((81, 8, 8), None), ((729, 100), None),
+                ((1000, 2), None), ((2 ** 15 * 3,), None), ((97,), None), ((1001,), None),
+                ((360,), None)]
+
+
+@pytest.mark.parametrize("shape,radix", POISON_CASES)
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_lds_poison_leaves_results_unchanged(shape, radix, dtype, monkeypatch):
+    """LDS race guard: with PAFC_LDS_POISON=1 every pass fills its LDS tile
+    with NaN before each tile, so an op that read LDS no earlier op wrote (a
+    missing barrier, a wrong index) would turn results into NaN or change
+    them.  Every variant, pipelined and general passes, folded column ops,
+    split axes, partial tiles, the prime routes: bit-identical to the normal
+    run."""
+    rng = np.random.default_rng([len(shape), shape[0], 13])
+    x = inputs.complex_uniform(rng, shape)
+    h = inputs.complex_uniform(rng, shape)
+    variants = ["perm_free", "explicit_perm", "perm_free_unfused"]
+    if shape == (360,):
+        variants = ["prime_factor", "prime_factor_explicit"]
+    for variant in variants:
+        out = {}
+        for flag in ("0", "1"):
+            monkeypatch.setenv("PAFC_LDS_POISON", flag)
+            P = pafc().Plan(shape, dtype, radix=radix, variant=variant)
+            xd = to_dev(x, dtype)
+            P.set_filter(to_dev(h, dtype))
+            y = to_host(P.convolve(xd))
+            z = to_host(P.forward(xd)) if not P.describe().get("rader_inner") and \
+                "bluestein_m" not in P.describe() and not variant.startswith("prime") else None
+            P.close()
+            out[flag] = (y, z)
+        assert not np.isnan(out["1"][0]).any(), (shape, variant)
+        assert np.array_equal(out["0"][0], out["1"][0]), (shape, variant)
+        if out["0"][1] is not None:
+            assert np.array_equal(out["0"][1], out["1"][1]), (shape, variant)
+
+
+def test_lds_poison_batched(monkeypatch):
+    sizes = [256, 729, 625, 4096, 8192, 6561, 3125, 256, 15625, 2048]
+    classes = sorted(set(sizes))
+    fids = [classes.index(n) for n in sizes]
+    rng = np.random.default_rng(14)
+    xs = np.concatenate([inputs.complex_uniform(rng, (n,)) for n in sizes])
+    hs = {n: inputs.complex_uniform(rng, (n,)) for n in classes}
+    out = {}
+    for flag in ("0", "1"):
+        monkeypatch.setenv("PAFC_LDS_POISON", flag)
+        B = pafc().Batch(sizes, fids, len(classes), C128)
+        for n in classes:
+            B.set_filter(classes.index(n), to_dev(hs[n], C128))
+        out[flag] = to_host(B.convolve(to_dev(xs, C128)))
+        B.close()
+    assert not np.isnan(out["1"]).any()
+    assert np.array_equal(out["0"], out["1"])
