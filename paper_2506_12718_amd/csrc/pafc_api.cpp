@@ -86,6 +86,8 @@ constexpr size_t kLdsBudget = 160 * 1024;  // LDS per CU on gfx950
 //   PAFC_AXIS_ORDER 1 runs the other axes' forward passes slowest first
 //   PAFC_HTM       0 keeps the spectrum in plan layout (no tile-major order)
 //   PAFC_LDS_POISON 1 (debug) every pass fills its LDS tile with NaN first
+//   PAFC_FAULT_INJECT=oom  pafc_plan fails with OUT_OF_MEMORY after its first
+//                  allocations (tests of the cleanup path)
 //   PAFC_BLUESTEIN 1 plans a prime length by Bluestein's method even where
 //                  Rader's applies (p - 1 {2,3,5}-smooth)
 int env_int(const char* name, int dflt) {
@@ -1953,6 +1955,12 @@ pafc_status pafc_plan(pafc_plan_t* out, int ndim, const int64_t* dims, const int
       h_elems = std::max<int64_t>(h_elems, (int64_t)P.conv[i].a.LW * P.conv[i].a.ntiles);
     }
   if (e == hipSuccess) e = hipMalloc(&p->d_H, (size_t)h_elems * P.elem);
+  // fault injection (tests of the cleanup path): report the device as full
+  // once the first allocations succeeded
+  if (e == hipSuccess) {
+    const char* f = getenv("PAFC_FAULT_INJECT");
+    if (f && strcmp(f, "oom") == 0) e = hipErrorOutOfMemory;
+  }
   size_t symtab_bytes = 3;
   for (auto& ax : P.axes) symtab_bytes += (size_t)ax.n;
   symtab_bytes *= 2 * sizeof(double);

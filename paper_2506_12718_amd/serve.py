@@ -11,7 +11,12 @@ server
 * runs every admitted request on one of S HIP streams, so requests that
   arrive while others are on the GPU overlap with them on the device;
 * detects completions with stream events and records latency
-  (arrival -> completion) and throughput.
+  (arrival -> completion) and throughput;
+* fails a request whose preparation or launch raises, or that cannot fit
+  the budget even alone, records it in ``failed`` with the error, returns
+  its slot, memory reservation and cache reference, and carries on
+  (``GpuExecutor`` can inject such a failure: PAFC_FAULT_INJECT=prepare:N or
+  launch:N fails the N-th call).
 
 Results do not depend on what else runs: every convolution is the same
 deterministic kernel sequence on its own buffers (the plan state it shares
@@ -43,6 +48,7 @@ class Request:
     out: Any = None
     slot: int = -1
     meta: dict = field(default_factory=dict)
+    error: Optional[str] = None   # set when the request failed
 
 
 class PlanCache:
@@ -103,6 +109,7 @@ class Server:
         self.free_slots = list(range(slots))
         self.reserved = 0             # bytes of in-flight request buffers
         self.completed = []
+        self.failed = []
         self.max_inflight = 0
         self.lock = threading.Lock()
 
@@ -122,23 +129,43 @@ class Server:
         if not self.cache.can_fit(extra, self.reserved):
             if self.inflight:
                 return False  # wait for completions to free memory
-            if entry is None and need + self.ex.plan_bytes(req) > self.cache.budget:
-                raise MemoryError("request %d does not fit the HBM budget" % req.rid)
+            if need + (0 if entry is not None else self.ex.plan_bytes(req)) > self.cache.budget:
+                self.pending.popleft()
+                self._fail(req, "request %d does not fit the HBM budget" % req.rid)
+                return True
         self.pending.popleft()
         slot = self.free_slots.pop()
         if entry is None:
             self.cache.make_room(extra, self.reserved, self.ex.release_plan)
-            plan = self.ex.prepare(req, slot)
+            try:
+                plan = self.ex.prepare(req, slot)
+            except Exception as e:  # nothing was cached or reserved yet
+                self.free_slots.append(slot)
+                self._fail(req, "prepare: %s" % e)
+                return True
             entry = self.cache.put(key, plan, self.ex.plan_bytes(req))
         entry[2] += 1
         self.reserved += need
         req.slot = slot
         req.start = self.clock()
+        try:
+            self.ex.launch(req, entry[0], slot)
+        except Exception as e:
+            entry[2] -= 1
+            self.reserved -= need
+            self.free_slots.append(slot)
+            self._fail(req, "launch: %s" % e)
+            return True
         req.meta["entry"] = entry
-        self.ex.launch(req, entry[0], slot)
         self.inflight[slot] = req
         self.max_inflight = max(self.max_inflight, len(self.inflight))
         return True
+
+    def _fail(self, req: Request, msg: str):
+        req.error = msg
+        req.done = self.clock()
+        req.out = None
+        self.failed.append(req)
 
     def _reap(self) -> int:
         n = 0
@@ -239,6 +266,18 @@ class GpuExecutor:
         self.streams = [torch.cuda.Stream() for _ in range(slots)]
         self.sigma_of = sigma_of
         self.prepared = 0
+        # fault injection (tests of the server's failure handling):
+        # PAFC_FAULT_INJECT=prepare:N or launch:N fails the N-th such call
+        import os
+        spec = os.environ.get("PAFC_FAULT_INJECT", "")
+        kind, _, nth = spec.partition(":")
+        self.fault = (kind, int(nth)) if kind in ("prepare", "launch") and nth.isdigit() else None
+        self.calls = {"prepare": 0, "launch": 0}
+
+    def _maybe_fail(self, kind):
+        self.calls[kind] += 1
+        if self.fault == (kind, self.calls[kind]):
+            raise RuntimeError("injected %s failure (call %d)" % (kind, self.calls[kind]))
 
     def request_bytes(self, req):
         n = 1
@@ -263,6 +302,7 @@ class GpuExecutor:
         return h.to(self.dtype).contiguous()
 
     def prepare(self, req, slot):
+        self._maybe_fail("prepare")
         torch = self.torch
         s = self.streams[slot]
         with torch.cuda.stream(s):
@@ -281,6 +321,7 @@ class GpuExecutor:
         obj["plan"].close()
 
     def launch(self, req, obj, slot):
+        self._maybe_fail("launch")
         torch = self.torch
         s = self.streams[slot]
         s.wait_event(obj["ready"])

@@ -81,3 +81,46 @@ def test_tight_budget_evicts_and_agrees():
     assert srv_tight.cache.evictions > 0
     for rid in outs_free:
         assert np.array_equal(outs_free[rid], outs_tight[rid])
+
+
+def test_injected_failures_fail_one_request_each(monkeypatch):
+    """PAFC_FAULT_INJECT makes one preparation and one launch fail: those two
+    requests fail with the error, every other request is served with the
+    same bits as an undisturbed run, and the server ends with nothing held."""
+    reqs = make_requests(15, 24)
+    outs_ok, _ = serve(reqs, slots=3)
+    for spec in ("prepare:2", "launch:7"):
+        monkeypatch.setenv("PAFC_FAULT_INJECT", spec)
+        reqs2 = make_requests(15, 24)
+        from paper_2506_12718_amd.serve import GpuExecutor, Server, run_closed_loop
+        ex = GpuExecutor(dtype=torch.complex64, sigma_of=inputs.serving_sigma, slots=3)
+        srv = Server(ex, budget_bytes=8 << 30, slots=3)
+        done = run_closed_loop(srv, reqs2, make_input=device_input)
+        torch.cuda.synchronize()
+        say(spec, "failed", [(r.rid, r.error) for r in srv.failed])
+        assert len(srv.failed) == 1 and "injected" in srv.failed[0].error
+        assert len(done) == len(reqs2) - 1
+        for r in done:
+            assert np.array_equal(r.out.cpu().numpy(), outs_ok[r.rid])
+        assert srv.reserved == 0 and not srv.inflight
+        assert all(e[2] == 0 for e in srv.cache.entries.values())
+
+
+def test_injected_out_of_memory_leaks_nothing(monkeypatch):
+    """PAFC_FAULT_INJECT=oom: pafc_plan reports OUT_OF_MEMORY after its first
+    allocations and frees them; the device's free memory is unchanged after
+    many such failures of a 256^3 plan (about 300 MB each)."""
+    import paper_2506_12718_amd as pafc
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
+    monkeypatch.setenv("PAFC_FAULT_INJECT", "oom")
+    for _ in range(20):
+        with pytest.raises(pafc.PafcError) as e:
+            pafc.Plan((256, 256, 256), torch.complex128)
+        assert e.value.status == 3
+    monkeypatch.delenv("PAFC_FAULT_INJECT")
+    torch.cuda.synchronize()
+    free1 = torch.cuda.mem_get_info()[0]
+    assert abs(free1 - free0) < (64 << 20), (free0, free1)
+    P = pafc.Plan((64, 64), torch.complex128)  # planning works again
+    P.close()

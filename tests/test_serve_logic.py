@@ -108,12 +108,52 @@ def test_entries_in_use_are_never_evicted():
     assert len(s.completed) == 40
 
 
-def test_request_larger_than_budget_raises():
+def test_request_larger_than_budget_fails_alone():
+    """A request that cannot fit the budget even alone fails; the requests
+    around it are served."""
     ex = FakeExecutor()
-    s = Server(ex, budget_bytes=1000, slots=2, clock=FakeClock())
-    s.submit(Request(rid=0, dims=(64, 64), fid=0))
-    with pytest.raises(MemoryError):
-        s.drain()
+    s = Server(ex, budget_bytes=3 * 64 * 64 * 8, slots=2, clock=FakeClock())
+    reqs = [Request(rid=0, dims=(32, 32), fid=0), Request(rid=1, dims=(256, 256), fid=1),
+            Request(rid=2, dims=(32, 32), fid=0)]
+    run_closed_loop(s, reqs)
+    assert [r.rid for r in s.failed] == [1] and "budget" in s.failed[0].error
+    assert sorted(r.rid for r in s.completed) == [0, 2]
+    assert s.reserved == 0
+
+
+class FailingExecutor(FakeExecutor):
+    """prepare() or launch() raises on chosen requests (an allocation or a
+    launch that fails)."""
+
+    def __init__(self, fail_prepare=(), fail_launch=()):
+        super().__init__()
+        self.fail_prepare, self.fail_launch = set(fail_prepare), set(fail_launch)
+
+    def prepare(self, req, slot):
+        if req.rid in self.fail_prepare:
+            raise RuntimeError("out of device memory")
+        return super().prepare(req, slot)
+
+    def launch(self, req, obj, slot):
+        if req.rid in self.fail_launch:
+            raise RuntimeError("launch failed")
+        return super().launch(req, obj, slot)
+
+
+def test_failed_prepare_and_launch_do_not_stop_the_server():
+    ex = FailingExecutor(fail_prepare={3}, fail_launch={5, 6})
+    s = Server(ex, budget_bytes=1 << 30, slots=2, clock=FakeClock())
+    reqs = [Request(rid=i, dims=(16, 16 + (i % 4)), fid=i % 4) for i in range(20)]
+    run_closed_loop(s, reqs)
+    assert sorted(r.rid for r in s.failed) == [3, 5, 6]
+    assert all(r.error for r in s.failed) and all(r.out is None for r in s.failed)
+    assert sorted(r.rid for r in s.completed) == [i for i in range(20) if i not in (3, 5, 6)]
+    # nothing leaked: no reservation, no reference, every slot free
+    assert s.reserved == 0 and not s.inflight and sorted(s.free_slots) == [0, 1]
+    assert all(e[2] == 0 for e in s.cache.entries.values())
+    # the failed preparation left no cache entry behind; a later request of
+    # that shape prepared its plan again
+    assert ex.prepared.count(((16, 19), 3)) == 1
 
 
 def test_latency_stats():
