@@ -391,3 +391,44 @@ def test_lds_poison_batched(monkeypatch):
         B.close()
     assert not np.isnan(out["1"]).any()
     assert np.array_equal(out["0"], out["1"])
+
+
+SHAPE_CASES = [((256, 256), [4, 4]), ((2187, 12), None), ((5 ** 6,), None), ((64, 64, 64), [4, 4, 4]),
+               ((4096, 48), [4, 0])]
+KNOBS = [{"PAFC_TUNE_WS": "8"}, {"PAFC_TUNE_WS": "32"}, {"PAFC_TUNE_WC": "2"},
+         {"PAFC_TUNE_WC": "4"}, {"PAFC_PIPE": "0"}]
+
+
+@pytest.mark.parametrize("shape,radix", SHAPE_CASES)
+def test_tile_shapes_and_kernels_agree(shape, radix, monkeypatch):
+    """The same convolution planned with other tile widths, or with the
+    general pass engine instead of the pipelined kernel, agrees with the
+    default plan to a few ulps (the same arithmetic per column; kernels may
+    contract multiply-adds differently); walking every pass's tiles in one
+    direction (PAFC_SNAKE=0) gives the same bits."""
+    rng = np.random.default_rng([len(shape), shape[0], 17])
+    x = inputs.complex_uniform(rng, shape)
+    h = inputs.complex_uniform(rng, shape)
+
+    def run():
+        P = pafc().Plan(shape, C128, radix=radix)
+        P.set_filter(to_dev(h, C128))
+        y = to_host(P.convolve(to_dev(x, C128)))
+        labels = P.describe()["conv_passes"]
+        P.close()
+        return y, labels
+
+    y0, l0 = run()
+    assert rel_l2(y0, oracle.conv_fft(x, h)) <= TOL[C128]
+    monkeypatch.setenv("PAFC_SNAKE", "0")
+    y1, _ = run()
+    monkeypatch.delenv("PAFC_SNAKE")
+    assert np.array_equal(y0, y1)
+    for knob in KNOBS:
+        for k, v in knob.items():
+            monkeypatch.setenv(k, v)
+        y, labels = run()
+        for k in knob:
+            monkeypatch.delenv(k)
+        say(shape, knob, labels != l0)
+        assert rel_l2(y, y0) <= 2e-15, (shape, knob)
