@@ -14,6 +14,9 @@ __device__ __forceinline__ uint32_t fdiv(uint32_t x, const FastDiv& f) {
 }
 
 __device__ __forceinline__ uint32_t lds_phys(uint32_t x) { return x + (x >> 4); }
+// The same with the padding interval of a pass (PassArgs::lds_sh: one pad
+// element every 2^sh, or none for sh = 31).
+__device__ __forceinline__ uint32_t lds_phys(uint32_t x, uint32_t sh) { return x + (x >> sh); }
 
 template <typename T>
 __device__ __forceinline__ cx<T> ld_g(const void* p, int64_t idx) {

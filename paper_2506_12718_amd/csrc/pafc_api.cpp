@@ -86,6 +86,7 @@ constexpr size_t kLdsBudget = 160 * 1024;  // LDS per CU on gfx950
 //   PAFC_AXIS_ORDER 1 runs the other axes' forward passes slowest first
 //   PAFC_HTM       0 keeps the spectrum in plan layout (no tile-major order)
 //   PAFC_LDS_POISON 1 (debug) every pass fills its LDS tile with NaN first
+//   PAFC_LDS_PAD   1 pads the LDS tiles of odd-length contiguous passes too
 //   PAFC_FAULT_INJECT=oom  pafc_plan fails with OUT_OF_MEMORY after its first
 //                  allocations (tests of the cleanup path)
 //   PAFC_BLUESTEIN 1 plans a prime length by Bluestein's method even where
@@ -545,6 +546,7 @@ bool make_pass(const Seg& s, int kind, size_t elem, Pass* p,
   a.divL = make_fastdiv(s.L);
   a.divTiles = make_fastdiv(a.tiles_per_slice);
   a.divJc = make_fastdiv(s.jcdiv);
+  a.lds_sh = s.mode == MODE_CONTIG && (s.L & 1u) && env_int("PAFC_LDS_PAD", 0) == 0 ? 31u : 4u;
   if (!build_ops(s, kind, a, &p->cls, cross)) return false;
   uint32_t maxitems = 0;
   for (uint32_t i = 0; i < a.nops; ++i) maxitems = std::max(maxitems, a.ops[i].nitems);

@@ -130,6 +130,10 @@ struct PassArgs {
                        // spectrum is one contiguous block read in order
   uint32_t tm_store;   // forward pass: its last op writes that tile-major
                        // order (the filter's last forward pass)
+  uint32_t lds_sh;     // LDS padding of the general engine: one pad element
+                       // every 2^lds_sh (4: breaks power-of-two strides), or
+                       // none (31) for contiguous tiles of odd length, whose
+                       // strides are odd and conflict-free unpadded
   uint32_t poison;     // debug: fill the LDS tile with NaN before each tile,
                        // so a read of LDS that no op wrote shows in the result
   OpDesc ops[kMaxOps];

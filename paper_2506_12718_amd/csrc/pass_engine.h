@@ -145,7 +145,7 @@ __device__ __forceinline__ void run_op(const PassArgs& a, const OpDesc& op, cons
       if (op.dst_g) {
         if (m.valid) st_g<T>(out, m.gbase + k * m.gstep, val);
       } else {
-        lds[lds_phys(m.lbase + k * m.lstep)] = val;
+        lds[lds_phys(m.lbase + k * m.lstep, a.lds_sh)] = val;
       }
     };
     cx<T> v[R];
@@ -154,7 +154,7 @@ __device__ __forceinline__ void run_op(const PassArgs& a, const OpDesc& op, cons
     } else {
       static_for<R>([&](auto s) {
         constexpr int p = TYPE == OP_DIT ? digrev<r, g>(s.value) : s.value;
-        v[s.value] = lds[lds_phys(m.lbase + p * m.lstep)];
+        v[s.value] = lds[lds_phys(m.lbase + p * m.lstep, a.lds_sh)];
       });
     }
     if constexpr (TYPE == OP_DIF) {
@@ -257,7 +257,7 @@ __device__ __forceinline__ void load_tile(const PassArgs& a, const TileCtx& t,
     tile_pos(a, x, i, c);
     cx<T> v = {(T)0, (T)0};
     if (t.col0 + c < a.ncols) v = ld_g<T>(in, t.base + (int64_t)i * a.S_i + (int64_t)c * a.S_c);
-    lds[lds_phys(x)] = v;
+    lds[lds_phys(x, a.lds_sh)] = v;
   }
 }
 
@@ -268,7 +268,7 @@ __device__ __forceinline__ void store_tile(const PassArgs& a, const TileCtx& t,
     uint32_t i, c;
     tile_pos(a, x, i, c);
     if (t.col0 + c < a.ncols)
-      st_g<T>(out, t.base + (int64_t)i * a.S_i + (int64_t)c * a.S_c, lds[lds_phys(x)]);
+      st_g<T>(out, t.base + (int64_t)i * a.S_i + (int64_t)c * a.S_c, lds[lds_phys(x, a.lds_sh)]);
   }
 }
 
