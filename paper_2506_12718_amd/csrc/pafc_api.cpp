@@ -32,6 +32,7 @@ hipError_t launch_batch(bool dbl, int cls, const PassArgs* descs, const BatchTil
                         uint32_t threads, size_t lds_bytes, hipStream_t s);
 hipError_t launch_scale(bool dbl, void* p, int64_t n, double s, hipStream_t st);
 bool pipe_supported(int r, int g, int ng);
+int pipe_thread_limit(int r, int g);
 
 int pipe_blocks_per_cu(bool dbl, int r, int g, int ng, int kind, int mode, uint32_t threads,
                        size_t lds);
@@ -285,6 +286,7 @@ struct Pass {
   bool pipe = false;
   int pipe_r = 0, pipe_g = 0, pipe_ng = 0, pipe_kind = 0;
   uint32_t pipe_grid = 0;
+  uint32_t pipe_threads = 0;  // one per item (the general engine's count is `threads`)
   size_t pipe_lds = 0;
 
   std::string label;
@@ -526,8 +528,34 @@ bool validate_pass(const PassArgs& a, int64_t extent, int64_t n_tw) {
   return true;
 }
 
-bool make_pass(const Seg& s, int kind, size_t elem, Pass* p,
+// The pipelined kernel runs a piece whose register groups are all the same
+// (r, g), with flat twiddles of the piece's own length, one item per thread.
+bool pipe_shape(const Seg& s, const std::vector<CrossAxis>* cross, int* r, int* g, int* ng) {
+  if (env_int("PAFC_PIPE", 1) == 0 || (cross && !cross->empty()) || s.col_in_j != 0 ||
+      s.jmul != 1 || s.n_tw != (int64_t)s.L || s.tw_global)
+    return false;
+  const auto groups = group_runs(s.rho, s.caps);
+  if (groups.empty()) return false;
+  for (auto& gr : groups)
+    if (gr != groups[0]) return false;
+  *r = groups[0].first;
+  *g = groups[0].second;
+  *ng = (int)groups.size();
+  return pipe_supported(*r, *g, *ng);
+}
+
+bool make_pass(const Seg& s_in, int kind, size_t elem, Pass* p,
                const std::vector<CrossAxis>* cross = nullptr) {
+  // a piece of short groups (R <= 9) can take one item per thread in blocks
+  // of up to 1024 threads: narrow its tile until it holds that many items
+  Seg s = s_in;
+  {
+    int r = 0, g = 0, ng = 0;
+    if (pipe_shape(s, cross, &r, &g, &ng) && pipe_thread_limit(r, g) > 256) {
+      const uint32_t R = (uint32_t)ipow64(r, g);
+      while (s.W > 1 && (s.L / R) * s.W > (uint32_t)pipe_thread_limit(r, g)) s.W /= 2;
+    }
+  }
   PassArgs& a = p->a;
   memset(&a, 0, sizeof(a));
   a.mode = s.mode;
@@ -572,26 +600,27 @@ bool make_pass(const Seg& s, int kind, size_t elem, Pass* p,
   // pipelined kernel: every group of the piece has the same (r, g), each op
   // has one item per thread, flat twiddles of the piece's own length
   {
-    auto groups = group_runs(s.rho, s.caps);
-    bool uni = !groups.empty();
-    for (auto& gr : groups) uni = uni && gr == groups[0];
-    const int ng = (int)groups.size();
+    int r = 0, g = 0, ng = 0;
     // it also addresses with 32-bit byte offsets: the span of elements the
     // pass touches must stay below 4 GiB
     const uint64_t span = (uint64_t)(s.nouter - 1) * (uint64_t)s.S_o +
                           (uint64_t)(s.L - 1) * (uint64_t)s.S_i +
                           (uint64_t)(s.ncols - 1) * (uint64_t)s.S_c + 1;
-    bool ok = env_int("PAFC_PIPE", 1) != 0 && uni && pipe_supported(groups[0].first, groups[0].second, ng) &&
-              s.col_in_j == 0 && s.jmul == 1 && s.n_tw == (int64_t)s.L && !s.tw_global &&
-              !(cross && !cross->empty()) &&
-              span * elem <= 0xFFFFFFFFull;
-    for (uint32_t i = 0; ok && i < a.nops; ++i) ok = a.ops[i].nitems == p->threads;
+    bool ok = pipe_shape(s, cross, &r, &g, &ng) && span * elem <= 0xFFFFFFFFull;
+    // one item per thread: the radix-16 shapes in whole waves (as the
+    // general engine would size the block), the short ones in blocks of
+    // exactly one thread per item
+    const uint32_t items = a.nops ? a.ops[0].nitems : 0;
+    for (uint32_t i = 0; ok && i < a.nops; ++i) ok = a.ops[i].nitems == items;
+    const bool small = ok && pipe_thread_limit(r, g) > 256;
+    if (ok) ok = small ? items <= (uint32_t)pipe_thread_limit(r, g) : items == p->threads;
     if (ok) {
       p->pipe = true;
-      p->pipe_r = groups[0].first;
-      p->pipe_g = groups[0].second;
+      p->pipe_r = r;
+      p->pipe_g = g;
       p->pipe_ng = ng;
       p->pipe_kind = kind;
+      p->pipe_threads = items;
       const uint64_t LW = a.LW;
       p->pipe_lds = (size_t)(((LW + (LW >> 4) + 2) & ~1ull) + s.L) * elem;
     }
@@ -600,7 +629,8 @@ bool make_pass(const Seg& s, int kind, size_t elem, Pass* p,
   // rounds of a 256-thread block -> (nearly) one item per thread, up to 1024
   // threads.  Ops with fewer items would leave most of a wide block idle and
   // cost resident blocks (measured slower), so they stay in the small class.
-  if (!p->pipe) {
+  // (Decided for pipelined passes too: the general engine is their fallback.)
+  {
     int maxR = 0;
     uint32_t maxitems = 0, minitems = UINT32_MAX;
     for (uint32_t i = 0; i < a.nops; ++i) {
@@ -622,7 +652,7 @@ bool make_pass(const Seg& s, int kind, size_t elem, Pass* p,
     ops += buf;
   }
   snprintf(buf, sizeof(buf), "%s L=%u W=%u tiles=%u thr=%u [", s.mode == MODE_STRIDED ? "strided" : "contig",
-           s.L, s.W, a.ntiles, p->threads);
+           s.L, s.W, a.ntiles, p->pipe ? p->pipe_threads : p->threads);
   p->label = std::string(buf) + ops + "]";
   if (s.tw_global) p->label += " twg";
 
@@ -1107,8 +1137,8 @@ pafc_status run_pass(pafc_plan_t p, const Pass& ps, const void* in, void* out, h
   if (ps.kind != 0) return PAFC_ERROR_INVALID_VALUE;
   if (ps.pipe && ps.pipe_grid > 0)
     return from_hip(launch_pipe(dbl, ps.pipe_r, ps.pipe_g, ps.pipe_ng, ps.pipe_kind, ps.a.mode,
-                                p->d_descs + ps.desc, ps.pipe_grid, ps.threads, ps.pipe_lds, in,
-                                out, s));
+                                p->d_descs + ps.desc, ps.pipe_grid, ps.pipe_threads, ps.pipe_lds,
+                                in, out, s));
 
   return from_hip(launch_pass(dbl, ps.cls, p->d_descs + ps.desc, ps.a.ntiles, in, out, ps.threads,
                               ps.lds, s));
@@ -1826,7 +1856,7 @@ pafc_status via_plan_layout(pafc_plan_t p, hipStream_t s, F produce) {
   const Pass& m = P.conv[(size_t)p->mid_pass];
   PAFC_TRY(produce(p->d_scratch));
   return from_hip(launch_pipe_htm(P.dtype == PAFC_C128, m.pipe_r, m.pipe_g, m.pipe_ng,
-                                  (int)m.a.mode, p->d_descs + m.desc, m.a.ntiles, m.threads,
+                                  (int)m.a.mode, p->d_descs + m.desc, m.a.ntiles, m.pipe_threads,
                                   p->d_scratch, p->d_H, s));
 }
 
@@ -1979,7 +2009,7 @@ pafc_status pafc_plan(pafc_plan_t* out, int ndim, const int64_t* dims, const int
         if (!ps.pipe) continue;
         int nb = ncu > 0 ? pipe_blocks_per_cu(P.dtype == PAFC_C128, ps.pipe_r, ps.pipe_g,
                                               ps.pipe_ng, ps.pipe_kind, (int)ps.a.mode,
-                                              ps.threads, ps.pipe_lds)
+                                              ps.pipe_threads, ps.pipe_lds)
                          : 0;
         const int64_t want = (int64_t)nb * ncu;
         ps.pipe_grid = (uint32_t)std::min<int64_t>(want, ps.a.ntiles);
@@ -1999,7 +2029,8 @@ pafc_status pafc_plan(pafc_plan_t* out, int ndim, const int64_t* dims, const int
     const Pass& f = P.fwd.back();
     const PassArgs &x = m.a, &y = f.a;
     p->h_tm = m.pipe && f.pipe && m.pipe_r == f.pipe_r && m.pipe_g == f.pipe_g &&
-              m.pipe_ng == f.pipe_ng && m.threads == f.threads && x.mode == MODE_STRIDED &&
+              m.pipe_ng == f.pipe_ng && m.pipe_threads == f.pipe_threads &&
+              x.mode == MODE_STRIDED &&
               y.mode == MODE_STRIDED &&
               x.L == y.L && x.W == y.W && x.S_i == y.S_i && x.S_c == y.S_c && x.S_o == y.S_o &&
               x.ncols == y.ncols && x.tiles_per_slice == y.tiles_per_slice &&

@@ -66,8 +66,16 @@ __device__ __forceinline__ Item item_of(uint32_t tid, uint32_t W, uint32_t logW,
 template <int KIND, int NG>
 constexpr int pipe_waves_per_eu() { return KIND == PIPE_FWD && NG == 2 ? 2 : 1; }
 
+// Threads of one block: one per item, so L W / R of them -- up to 256 for
+// the power-of-two shapes, up to 1024 for single radix-3 and radix-5 stages
+// (whose items need few registers: a 1024-thread block leaves 128 VGPRs per
+// thread); the count need not be a multiple of the wave size.
+template <int r, int g>
+constexpr int pipe_max_threads() { return (r == 3 || r == 5) && g == 1 ? 1024 : 256; }
+
 template <typename T, int r, int g, int NG, int KIND, int MODE>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(pipe_waves_per_eu<KIND, NG>())))
+__global__ void __launch_bounds__((pipe_max_threads<r, g>()))
+__attribute__((amdgpu_waves_per_eu(pipe_waves_per_eu<KIND, NG>())))
 pipe_kernel(const PassArgs* __restrict__ desc,
                                                    const void* __restrict__ in,
                                                    void* __restrict__ out) {
@@ -291,7 +299,7 @@ pipe_kernel(const PassArgs* __restrict__ desc,
 // pass's descriptor and thread count; slots of columns beyond the edge are
 // zero.
 template <typename T, int r, int g, int NG, int MODE>
-__global__ void __launch_bounds__(256) pipe_htm_kernel(const PassArgs* __restrict__ desc,
+__global__ void __launch_bounds__((pipe_max_threads<r, g>())) pipe_htm_kernel(const PassArgs* __restrict__ desc,
                                                         const void* __restrict__ src,
                                                         void* __restrict__ dst) {
   constexpr int R = ipow(r, g);
@@ -323,7 +331,14 @@ __global__ void __launch_bounds__(256) pipe_htm_kernel(const PassArgs* __restric
   X(2, 4, 3) /* L = 4096 */   \
   X(8, 1, 2) /* L = 64 */     \
   X(8, 1, 3) /* L = 512 */    \
-  X(4, 2, 1) /* L = 16 */
+  X(4, 2, 1) /* L = 16 */     \
+  X(3, 1, 4) /* L = 81 */     \
+  X(3, 1, 5) /* L = 243 */    \
+  X(3, 1, 6) /* L = 729 */    \
+  X(3, 1, 7) /* L = 2187 */   \
+  X(5, 1, 3) /* L = 125 */    \
+  X(5, 1, 4) /* L = 625 */    \
+  X(5, 1, 5) /* L = 3125 */
 
 template <typename T, int r, int g, int NG>
 static const void* pipe_fn(int kind, int mode) {
@@ -351,6 +366,9 @@ static const void* pipe_lookup(bool dbl, int r, int g, int ng, int kind, int mod
 bool pipe_supported(int r, int g, int ng) {
   return pipe_lookup(true, r, g, ng, PIPE_FWD, MODE_CONTIG) != nullptr;
 }
+
+// Most threads a block of the pipelined kernel for groups r^g may have.
+int pipe_thread_limit(int r, int g) { return (r == 3 || r == 5) && g == 1 ? 1024 : 256; }
 
 // Resident blocks per CU of a pipelined kernel instance (0 on error).
 int pipe_blocks_per_cu(bool dbl, int r, int g, int ng, int kind, int mode, uint32_t threads,

@@ -89,7 +89,7 @@ class Timer:
 def candidates(pafc, dt, n, key, cfg):
     f = _factors(n)
     if key == "g3":
-        return [2, 3] if 3 in f else []
+        return [1, 2, 3] if 3 in f else []
     if key == "g5":
         return [1, 2] if 5 in f else []
     d = pafc.describe((n,), dt)

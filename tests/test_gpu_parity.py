@@ -432,3 +432,50 @@ def test_tile_shapes_and_kernels_agree(shape, radix, monkeypatch):
             monkeypatch.delenv(k)
         say(shape, knob, labels != l0)
         assert rel_l2(y, y0) <= 2e-15, (shape, knob)
+
+
+# (a length-2187 axis as the fused middle pass would need 15 single-stage
+# ops, more than a pass holds: those plans keep larger groups)
+SMALL_RADIX = [((3125,), None), ((243, 20), None), ((729, 12), None), ((625, 36), None),
+               ((24, 2187), None), ((4, 2187), None), ((10, 3125), None), ((81, 243), None),
+               ((5 ** 7,), None), ((2187, 2187), [3, 3])]
+
+
+@pytest.mark.parametrize("shape,radix", SMALL_RADIX)
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_small_radix_pipelined_passes(shape, radix, dtype, monkeypatch):
+    """Single radix-3 / radix-5 stages per op (PAFC_TUNE_GMAX3/5=1) make the
+    uniform pieces run on the pipelined kernel with up to 1024 threads, one
+    item per thread, the tile narrowed to fit; against the oracle, in every
+    variant, and against the general engine (PAFC_PIPE=0)."""
+    monkeypatch.setenv("PAFC_NO_TUNING_TABLE", "1")
+    monkeypatch.setenv("PAFC_TUNE_GMAX3", "1")
+    monkeypatch.setenv("PAFC_TUNE_GMAX5", "1")
+    import paper_2506_12718_amd as m
+    m.set_tuning(None)
+    try:
+        dt = "c128" if dtype == C128 else "c64"
+        labels = m.describe(shape, dt, radix)["conv_passes"]
+        say("small radix", shape, dt, labels)
+        assert any(("<double,3,1," in l or "<double,5,1," in l or "<float,3,1," in l or
+                    "<float,5,1," in l) for l in labels), labels
+        rng = np.random.default_rng([len(shape), shape[0], 19])
+        x = inputs.complex_uniform(rng, shape)
+        h = inputs.complex_uniform(rng, shape)
+        ref = oracle.conv_fft(rounded(x, dtype), rounded(h, dtype))
+        ys = {}
+        for variant in ("perm_free", "explicit_perm", "perm_free_unfused"):
+            P = m.Plan(shape, dtype, radix=radix, variant=variant)
+            P.set_filter(to_dev(h, dtype))
+            ys[variant] = to_host(P.convolve(to_dev(x, dtype)))
+            P.close()
+            assert rel_l2(ys[variant], ref) <= TOL[dtype], variant
+        monkeypatch.setenv("PAFC_PIPE", "0")
+        P = m.Plan(shape, dtype, radix=radix)
+        P.set_filter(to_dev(h, dtype))
+        y0 = to_host(P.convolve(to_dev(x, dtype)))
+        P.close()
+        assert rel_l2(ys["perm_free"], y0) <= (2e-15 if dtype == C128 else 1e-6)
+    finally:
+        monkeypatch.delenv("PAFC_NO_TUNING_TABLE")
+        m._load_tuning_table(m.lib())  # the table the other tests plan with

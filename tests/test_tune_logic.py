@@ -47,7 +47,7 @@ def test_line_and_table_roundtrip(tmp_path):
 def test_candidates_follow_the_factorisation():
     lib = FakeLib()
     base = {"split": 0, "W": 0, "Wo": 0, "g3": 0, "g5": 0}
-    assert tune.candidates(lib, "c128", 2187, "g3", base) == [2, 3]
+    assert tune.candidates(lib, "c128", 2187, "g3", base) == [1, 2, 3]
     assert tune.candidates(lib, "c128", 2187, "g5", base) == []
     assert tune.candidates(lib, "c128", 3125, "g5", base) == [1, 2]
     splits = tune.candidates(lib, "c128", 78125, "split", base)
