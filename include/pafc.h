@@ -450,7 +450,9 @@ pafc_status pafc_batch_describe(pafc_batch_t b, char* buf, size_t cap,
  *   g3, g5 largest number of radix-3 (<= 3) and radix-5 (<= 2) stages fused
  *          into one register group; 0 = default (3 and 2)
  * None of these changes the result, only the pass and register schedule.
- * NULL clears the table.  Errors: INVALID_VALUE (unparsable text; the
+ * An entry applies to every axis of length n; a plan that its choices make
+ * infeasible (more ops in one pass than a pass holds) is made with the
+ * planner defaults instead.  NULL clears the table.  Errors: INVALID_VALUE (unparsable text; the
  * previous table stays).
  */
 pafc_status pafc_set_tuning(const char* text);

@@ -772,8 +772,8 @@ bool split_axis(int64_t n, const std::vector<int>& rho, int64_t st, int64_t oute
   return split_axis(ni, rin, st, outer * no, elem, caps, tv, nullptr, segs);
 }
 
-pafc_status plan_core(PlanCore& P, int ndim, const int64_t* dims, const int* radix, int dtype,
-                      int variant) {
+pafc_status plan_once(PlanCore& P, int ndim, const int64_t* dims, const int* radix, int dtype,
+                      int variant, bool use_table) {
   if (ndim < 1 || ndim > 3 || !dims) return PAFC_ERROR_INVALID_VALUE;
   if (dtype != PAFC_C64 && dtype != PAFC_C128) return PAFC_ERROR_INVALID_VALUE;
   if (variant < PAFC_PERM_FREE || variant > PAFC_PERM_FREE_UNFUSED) return PAFC_ERROR_INVALID_VALUE;
@@ -815,7 +815,7 @@ pafc_status plan_core(PlanCore& P, int ndim, const int64_t* dims, const int* rad
     for (int b = a + 1; b < ndim; ++b) st *= dims[b];
     for (int b = 0; b < a; ++b) outer *= dims[b];
     TuneVal tv;
-    bool tuned = tune_lookup(dtype, ax.n, &tv);
+    bool tuned = use_table && tune_lookup(dtype, ax.n, &tv);
     GroupCaps caps;
     caps.g3 = tuned && tv.gmax3 > 0 ? tv.gmax3 : env_int("PAFC_TUNE_GMAX3", 3);
     caps.g5 = tuned && tv.gmax5 > 0 ? tv.gmax5 : env_int("PAFC_TUNE_GMAX5", 2);
@@ -980,6 +980,19 @@ pafc_status plan_core(PlanCore& P, int ndim, const int64_t* dims, const int* rad
   P.hbm_conv = bytes(P.conv);
   P.hbm_fwd = bytes(P.fwd);
   return PAFC_SUCCESS;
+}
+
+// A tuning entry is keyed by axis length alone, so a choice measured for an
+// axis of one shape can be infeasible for the same length in another (the
+// 2187 axis of a 2187 x 2187 grid is cut into pieces, a 2187-point 1-D
+// transform is one middle pass, which single radix-3 groups would give more
+// ops than a pass holds): the plan is then made with the planner defaults.
+pafc_status plan_core(PlanCore& P, int ndim, const int64_t* dims, const int* radix, int dtype,
+                      int variant) {
+  pafc_status st = plan_once(P, ndim, dims, radix, dtype, variant, true);
+  if (st != PAFC_ERROR_UNSUPPORTED_SIZE) return st;
+  P = PlanCore();
+  return plan_once(P, ndim, dims, radix, dtype, variant, false);
 }
 
 std::string describe_core(const PlanCore& P) {

@@ -107,6 +107,20 @@ def test_tuning_override_changes_split():
         pafc.set_tuning("garbage line")
 
 
+def test_infeasible_tuning_entry_falls_back_to_defaults():
+    # single radix-3 groups suit the 2187 axis of a 2187 x 2187 grid (cut
+    # into pieces) but would give a 2187-point 1-D middle pass 13 ops
+    try:
+        pafc.set_tuning("c128 2187 0 0 0 1 0\n")
+        grid = pafc.describe((2187, 2187), "c128")
+        assert any("DIF3,DIF3" in s for s in grid["conv_passes"])
+        one = pafc.describe((2187,), "c128")
+        assert not any("DIF3," in s for s in one["conv_passes"])
+    finally:
+        pafc.set_tuning(None)
+    assert pafc.describe((2187,), "c128")["conv_passes"] == one["conv_passes"]
+
+
 def _smooth(n):
     for q in (2, 3, 5):
         while n % q == 0:
