@@ -40,6 +40,11 @@ GRIDS = [((2187, 2187), 3), ((5 ** 9,), 5)]
 # inner lengths of the prime-length routes' benchmark workloads (Rader at
 # n = 995329, Bluestein at n = 995329 and n = 1000003), tuned as 1-D plans
 INNER_1D = [995328, 2000000, 2025000]
+# the radix-3 and radix-5 axes of the prime-factor route's benchmark
+# workload (n = 2^8 3^5 5^3 on the 125 x 243 x 256 grid), each tuned on the
+# whole route (register grouping only)
+PFA_N = 2 ** 8 * 3 ** 5 * 5 ** 3
+PFA_AXES = [243, 125]
 
 
 def _factors(n):
@@ -73,9 +78,10 @@ class Timer:
         B.close()
         return float(np.median(per))
 
-    def grid(self, dims, radix):
+    def grid(self, dims, radix, variant="perm_free"):
         torch = self.torch
-        P = self.pafc.Plan(dims, self.tdt, radix=None if radix is None else [radix] * len(dims))
+        P = self.pafc.Plan(dims, self.tdt, radix=None if radix is None else [radix] * len(dims),
+                           variant=variant)
         h = torch.ones(dims, dtype=self.tdt, device="cuda")
         P.set_filter(h)
         x = torch.ones(dims, dtype=self.tdt, device="cuda")
@@ -195,6 +201,8 @@ def main(argv=None):
         jobs += [(n, (lambda n=n: timer.batch(n)), one_d) for n in BATCH_SIZES
                  if n not in [d[0] for d, _ in GRIDS]]
         jobs += [(n, (lambda n=n: timer.grid((n,), None)), one_d) for n in INNER_1D]
+        jobs += [(n, (lambda: timer.grid((PFA_N,), None, "prime_factor")), ("g3", "g5"))
+                 for n in PFA_AXES]
         if a.sizes is not None:
             jobs = [j for j in jobs if j[0] in a.sizes]
             for (pdt, pn), pcfg in sorted(prev.items()):
