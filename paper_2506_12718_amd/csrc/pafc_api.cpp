@@ -48,8 +48,8 @@ hipError_t launch_stream_copy(const void* src, void* dst, int64_t n16, hipStream
 hipError_t launch_pfa_gather(bool dbl, const void* in, void* out, const uint32_t* t0,
                              const uint32_t* t1, const uint32_t* t2, uint32_t N1, uint32_t N2,
                              uint32_t n, hipStream_t st);
-hipError_t launch_pfa_scatter(bool dbl, const void* in, void* out, uint32_t N0, uint32_t N1,
-                              uint32_t N2, uint32_t n, hipStream_t st);
+hipError_t launch_pfa_map(bool dbl, int dir, const void* in, void* out, uint32_t N0, uint32_t N1,
+                          uint32_t N2, uint32_t uinv, hipStream_t st);
 hipError_t launch_bluestein(bool dbl, int stage, const void* src, const void* c, void* dst,
                             const void* hn, int64_t n, int64_t m, double s, hipStream_t st);
 hipError_t launch_rader(bool dbl, int stage, int mode, const void* src, const void* x, void* dst,
@@ -1054,6 +1054,7 @@ struct pafc_plan_s {
   // output map of the spectrum), N0 + N1 + N2 entries each
   pafc_plan_s* inner = nullptr;
   uint32_t pfa_N[3] = {1, 1, 1};
+  uint32_t pfa_uinv = 0;  // (N0 N1)^-1 mod N2, for the tiled CRT map
   uint32_t* d_pfa_tab = nullptr;
   // Bluestein route (blue_m > 0): the inner plan has length blue_m; chirp
   // c_j (n entries) and the filter's natural-order spectrum (n entries)
@@ -1275,6 +1276,9 @@ int64_t inv_mod(int64_t a, int64_t m) {
 // which 0: the CRT input map (x -> grid); 1: the output map of the spectrum
 pafc_status pfa_gather(pafc_plan_t p, const void* in, void* out, int which, hipStream_t s) {
   const uint32_t* N = p->pfa_N;
+  if (which == 0)
+    return from_hip(launch_pfa_map(p->P.dtype == PAFC_C128, 0, in, out, N[0], N[1], N[2],
+                                   p->pfa_uinv, s));
   const uint32_t* t = p->d_pfa_tab + (size_t)which * (N[0] + N[1] + N[2]);
   return from_hip(launch_pfa_gather(p->P.dtype == PAFC_C128, in, out, t, t + N[0], t + N[0] + N[1],
                                     N[1], N[2], (uint32_t)p->P.N, s));
@@ -1282,8 +1286,8 @@ pafc_status pfa_gather(pafc_plan_t p, const void* in, void* out, int which, hipS
 
 pafc_status pfa_scatter(pafc_plan_t p, const void* in, void* out, hipStream_t s) {
   const uint32_t* N = p->pfa_N;
-  return from_hip(launch_pfa_scatter(p->P.dtype == PAFC_C128, in, out, N[0], N[1], N[2],
-                                     (uint32_t)p->P.N, s));
+  return from_hip(launch_pfa_map(p->P.dtype == PAFC_C128, 1, in, out, N[0], N[1], N[2],
+                                 p->pfa_uinv, s));
 }
 
 // gather, the grid convolution in place, scatter; events (when given) before
@@ -1329,6 +1333,7 @@ pafc_status plan_prime_factor(pafc_plan_t* out, int ndim, const int64_t* dims, c
   }
   const size_t nf = f.size();
   for (size_t q = 0; q < nf; ++q) p->pfa_N[3 - nf + q] = (uint32_t)f[q];
+  p->pfa_uinv = (uint32_t)inv_mod((int64_t)p->pfa_N[0] * p->pfa_N[1] % p->pfa_N[2], p->pfa_N[2]);
   // tables: t_q[j] = j c_q mod n, c_q = e_q (CRT basis: 1 mod N_q, 0 mod the
   // others) for the input map, c_q = n / N_q for the spectrum's output map
   const uint32_t tot = p->pfa_N[0] + p->pfa_N[1] + p->pfa_N[2];

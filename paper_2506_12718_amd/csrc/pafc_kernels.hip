@@ -210,10 +210,8 @@ __global__ void symbol_kernel(cx<T>* __restrict__ H, const double2* __restrict__
 // 1-D array of length n = N0 N1 N2 (pairwise coprime factors) and the
 // N0 x N1 x N2 grid it is reindexed to.
 //   gather:  out[(j0 N1 + j1) N2 + j2] = in[(t0[j0] + t1[j1] + t2[j2]) mod n]
-//            (t_q[j] = j e_q mod n: with the CRT basis e_q this is the input
-//            map Gamma^T; with e_q = n / N_q the output map of the spectrum)
-//   scatter: out[j] = in[((j mod N0) N1 + j mod N1) N2 + j mod N2]
-//            (Gamma: grid position (j mod N_q)_q back to j)
+//            (t_q[j] = j e_q mod n; with e_q = n / N_q this is the output
+//            map of a filter's spectrum)
 // n < 2^31; every table entry is below n.
 template <typename T>
 __global__ void pfa_gather_kernel(const cx<T>* __restrict__ in, cx<T>* __restrict__ out,
@@ -232,15 +230,47 @@ __global__ void pfa_gather_kernel(const cx<T>* __restrict__ in, cx<T>* __restric
   }
 }
 
-template <typename T>
-__global__ void pfa_scatter_kernel(const cx<T>* __restrict__ in, cx<T>* __restrict__ out,
-                                   FastDiv d0, FastDiv d1, FastDiv d2, uint32_t n) {
-  for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
-    const uint32_t r0 = j - fdiv(j, d0) * d0.d;
-    const uint32_t r1 = j - fdiv(j, d1) * d1.d;
-    const uint32_t r2 = j - fdiv(j, d2) * d2.d;
-    out[j] = in[((uint64_t)r0 * d1.d + r1) * d2.d + r2];
-  }
+// The CRT map itself, j <-> grid position ((j mod N0) N1 + j mod N1) N2 +
+// j mod N2, in both directions (dir 0: grid[pos(j)] = in[j], the input map;
+// dir 1: out[j] = grid[pos(j)], its inverse).  Element by element, one side
+// of the map is read or written with a stride of about N1 N2 elements, one
+// cache line per element.  Tiled instead: with U = N0 N1, each j is the pair
+// (u, w) = (j mod U, j mod N2) and u + U k (k = (w - u) U^-1 mod N2) back.
+// Tile (u0, w0) holds the pairs u = u0 + a, w = (w0 + b + a) mod N2 for
+// a, b < 16: along a both u and w step by one, so j steps by one (16
+// consecutive j); along b only w steps, 16 consecutive grid positions (up to
+// a wrap of w).  The tiles u0, w0 in 16 Z cover every pair once (u < U,
+// w0 + b < N2), and each passes through LDS, so both sides move runs of 16
+// elements.  256 threads per tile; uinv = U^-1 mod N2.
+template <typename T, int DIR>
+__global__ void __launch_bounds__(256)
+pfa_map_kernel(const cx<T>* __restrict__ in, cx<T>* __restrict__ out, FastDiv d0, FastDiv d1,
+               FastDiv d2, uint32_t U, uint32_t uinv, FastDiv dtw) {
+  __shared__ cx<T> tile[16][17];
+  const uint32_t tu = fdiv(blockIdx.x, dtw);
+  const uint32_t u0 = tu * 16, w0 = (blockIdx.x - tu * dtw.d) * 16;
+  const uint32_t N2 = d2.d;
+  // element (a, b): false outside the tile's part of the index space
+  auto locate = [&](uint32_t a, uint32_t b, uint32_t* j, uint32_t* g) -> bool {
+    const uint32_t u = u0 + a, wb = w0 + b;
+    if (u >= U || wb >= N2) return false;
+    const uint32_t w = (wb + a) - fdiv(wb + a, d2) * N2;
+    const uint32_t r0 = u - fdiv(u, d0) * d0.d;
+    const uint32_t r1 = u - fdiv(u, d1) * d1.d;
+    *g = (r0 * d1.d + r1) * N2 + w;
+    const uint32_t um = u - fdiv(u, d2) * N2;
+    const uint32_t dw = w >= um ? w - um : w + N2 - um;
+    *j = u + U * (uint32_t)(((uint64_t)dw * uinv) % N2);
+    return true;
+  };
+  const uint32_t hi = threadIdx.x >> 4, lo = threadIdx.x & 15u;
+  uint32_t j, g;
+  // read along the contiguous side of the source: j for dir 0, grid for 1
+  const uint32_t ra = DIR == 0 ? lo : hi, rb = DIR == 0 ? hi : lo;
+  if (locate(ra, rb, &j, &g)) tile[ra][rb] = in[DIR == 0 ? j : g];
+  __syncthreads();
+  const uint32_t wa = DIR == 0 ? hi : lo, wb = DIR == 0 ? lo : hi;
+  if (locate(wa, wb, &j, &g)) out[DIR == 0 ? g : j] = tile[wa][wb];
 }
 
 // Bluestein's method (Sec. "Rader's and Bluestein's frameworks"): the
@@ -527,15 +557,24 @@ hipError_t launch_pfa_gather(bool dbl, const void* in, void* out, const uint32_t
   return hipGetLastError();
 }
 
-hipError_t launch_pfa_scatter(bool dbl, const void* in, void* out, uint32_t N0, uint32_t N1,
-                              uint32_t N2, uint32_t n, hipStream_t st) {
+hipError_t launch_pfa_map(bool dbl, int dir, const void* in, void* out, uint32_t N0, uint32_t N1,
+                          uint32_t N2, uint32_t uinv, hipStream_t st) {
   const FastDiv d0 = make_fastdiv(N0), d1 = make_fastdiv(N1), d2 = make_fastdiv(N2);
-  if (dbl)
-    hipLaunchKernelGGL(pfa_scatter_kernel<double>, dim3(grid_for(n)), dim3(256), 0, st,
-                       (const cx<double>*)in, (cx<double>*)out, d0, d1, d2, n);
-  else
-    hipLaunchKernelGGL(pfa_scatter_kernel<float>, dim3(grid_for(n)), dim3(256), 0, st,
-                       (const cx<float>*)in, (cx<float>*)out, d0, d1, d2, n);
+  const uint32_t U = N0 * N1;
+  const uint32_t tw = (N2 + 15) / 16;
+  const dim3 grid(((U + 15) / 16) * tw);
+  const FastDiv dtw = make_fastdiv(tw);
+#define PAFC_MAP_LAUNCH(T, D)                                                              \
+  hipLaunchKernelGGL((pfa_map_kernel<T, D>), grid, dim3(256), 0, st, (const cx<T>*)in,   \
+                     (cx<T>*)out, d0, d1, d2, U, uinv, dtw)
+  if (dbl) {
+    if (dir == 0) PAFC_MAP_LAUNCH(double, 0);
+    else PAFC_MAP_LAUNCH(double, 1);
+  } else {
+    if (dir == 0) PAFC_MAP_LAUNCH(float, 0);
+    else PAFC_MAP_LAUNCH(float, 1);
+  }
+#undef PAFC_MAP_LAUNCH
   return hipGetLastError();
 }
 
