@@ -32,6 +32,7 @@ hipError_t launch_batch(bool dbl, int cls, const PassArgs* descs, const BatchTil
                         uint32_t threads, size_t lds_bytes, hipStream_t s);
 hipError_t launch_scale(bool dbl, void* p, int64_t n, double s, hipStream_t st);
 bool pipe_supported(int r, int g, int ng);
+bool pipe_outer_supported(int r, int g, int ng);
 int pipe_thread_limit(int r, int g);
 
 int pipe_blocks_per_cu(bool dbl, int r, int g, int ng, int kind, int mode, uint32_t threads,
@@ -285,6 +286,7 @@ struct Pass {
   // pipelined persistent kernel (uniform-radix axis, one item per thread)
   bool pipe = false;
   int pipe_r = 0, pipe_g = 0, pipe_ng = 0, pipe_kind = 0;
+  int pipe_mode = 0;  // MODE_CONTIG, MODE_STRIDED, or MODE_OUTER (an outer piece)
   uint32_t pipe_grid = 0;
   uint32_t pipe_threads = 0;  // one per item (the general engine's count is `threads`)
   size_t pipe_lds = 0;
@@ -529,10 +531,14 @@ bool validate_pass(const PassArgs& a, int64_t extent, int64_t n_tw) {
 }
 
 // The pipelined kernel runs a piece whose register groups are all the same
-// (r, g), with flat twiddles of the piece's own length, one item per thread.
-bool pipe_shape(const Seg& s, const std::vector<CrossAxis>* cross, int* r, int* g, int* ng) {
-  if (env_int("PAFC_PIPE", 1) == 0 || (cross && !cross->empty()) || s.col_in_j != 0 ||
-      s.jmul != 1 || s.n_tw != (int64_t)s.L || s.tw_global)
+// (r, g), one item per thread: with flat twiddles of the piece's own length,
+// or (*outer) a strided outer piece of a cut axis with the whole axis's
+// twiddles from a two-level LDS copy (PAFC_PIPE_OUTER=0: general engine).
+bool pipe_shape(const Seg& s, const std::vector<CrossAxis>* cross, int* r, int* g, int* ng,
+                bool* outer = nullptr) {
+  if (env_int("PAFC_PIPE", 1) == 0 || (cross && !cross->empty()) || s.tw_global) return false;
+  const bool out = s.col_in_j != 0 && s.mode == MODE_STRIDED;
+  if (out ? env_int("PAFC_PIPE_OUTER", 1) == 0 : (s.jmul != 1 || s.n_tw != (int64_t)s.L))
     return false;
   const auto groups = group_runs(s.rho, s.caps);
   if (groups.empty()) return false;
@@ -541,7 +547,8 @@ bool pipe_shape(const Seg& s, const std::vector<CrossAxis>* cross, int* r, int* 
   *r = groups[0].first;
   *g = groups[0].second;
   *ng = (int)groups.size();
-  return pipe_supported(*r, *g, *ng);
+  if (outer) *outer = out;
+  return out ? pipe_outer_supported(*r, *g, *ng) : pipe_supported(*r, *g, *ng);
 }
 
 bool make_pass(const Seg& s_in, int kind, size_t elem, Pass* p,
@@ -601,12 +608,25 @@ bool make_pass(const Seg& s_in, int kind, size_t elem, Pass* p,
   // has one item per thread, flat twiddles of the piece's own length
   {
     int r = 0, g = 0, ng = 0;
+    bool outer = false;
     // it also addresses with 32-bit byte offsets: the span of elements the
     // pass touches must stay below 4 GiB
     const uint64_t span = (uint64_t)(s.nouter - 1) * (uint64_t)s.S_o +
                           (uint64_t)(s.L - 1) * (uint64_t)s.S_i +
                           (uint64_t)(s.ncols - 1) * (uint64_t)s.S_c + 1;
-    bool ok = pipe_shape(s, cross, &r, &g, &ng) && span * elem <= 0xFFFFFFFFull;
+    bool ok = pipe_shape(s, cross, &r, &g, &ng, &outer) && span * elem <= 0xFFFFFFFFull;
+    // an outer piece is never the middle pass (the product sits in the
+    // innermost piece)
+    if (outer && kind == 2) ok = false;
+    // the kernel takes each op's twiddle scale from the descriptor by its
+    // own op index, so the two op orders must agree (forward: K = L / R^i,
+    // inverse: K = R^(i+1)), every op with twiddles
+    if (ok && outer) {
+      const uint32_t R = (uint32_t)ipow64(r, g);
+      uint32_t Kd = s.L, Ku = R;
+      for (uint32_t i = 0; ok && i < a.nops; ++i, Kd /= R, Ku *= R)
+        ok = a.ops[i].K == (kind == 0 ? Kd : Ku) && a.ops[i].tw == 1;
+    }
     // one item per thread: the radix-16 shapes in whole waves (as the
     // general engine would size the block), the short ones in blocks of
     // exactly one thread per item
@@ -620,9 +640,12 @@ bool make_pass(const Seg& s_in, int kind, size_t elem, Pass* p,
       p->pipe_g = g;
       p->pipe_ng = ng;
       p->pipe_kind = kind;
+      p->pipe_mode = outer ? (int)MODE_OUTER : (int)s.mode;
       p->pipe_threads = items;
       const uint64_t LW = a.LW;
-      p->pipe_lds = (size_t)(((LW + (LW >> 4) + 2) & ~1ull) + s.L) * elem;
+      // tile, then the flat table of the piece (or, outer, the two-level
+      // table of the general engine's layout)
+      p->pipe_lds = outer ? p->lds : (size_t)(((LW + (LW >> 4) + 2) & ~1ull) + s.L) * elem;
     }
   }
   // wide register class: every group R <= 9 and every op at least two full
@@ -659,7 +682,7 @@ bool make_pass(const Seg& s_in, int kind, size_t elem, Pass* p,
   if (p->pipe) {
     char nm[96];
     snprintf(nm, sizeof(nm), " pipe_kernel<%s,%d,%d,%d,%d,%d>", elem == 16 ? "double" : "float",
-             p->pipe_r, p->pipe_g, p->pipe_ng, kind, (int)s.mode);
+             p->pipe_r, p->pipe_g, p->pipe_ng, kind, p->pipe_mode);
     p->label += nm;
   }
   return true;
@@ -1150,7 +1173,7 @@ pafc_status run_pass(pafc_plan_t p, const Pass& ps, const void* in, void* out, h
   const bool dbl = p->P.dtype == PAFC_C128;
   if (ps.kind != 0) return PAFC_ERROR_INVALID_VALUE;
   if (ps.pipe && ps.pipe_grid > 0)
-    return from_hip(launch_pipe(dbl, ps.pipe_r, ps.pipe_g, ps.pipe_ng, ps.pipe_kind, ps.a.mode,
+    return from_hip(launch_pipe(dbl, ps.pipe_r, ps.pipe_g, ps.pipe_ng, ps.pipe_kind, ps.pipe_mode,
                                 p->d_descs + ps.desc, ps.pipe_grid, ps.pipe_threads, ps.pipe_lds,
                                 in, out, s));
 
@@ -2026,7 +2049,7 @@ pafc_status pafc_plan(pafc_plan_t* out, int ndim, const int64_t* dims, const int
       for (Pass& ps : *seq) {
         if (!ps.pipe) continue;
         int nb = ncu > 0 ? pipe_blocks_per_cu(P.dtype == PAFC_C128, ps.pipe_r, ps.pipe_g,
-                                              ps.pipe_ng, ps.pipe_kind, (int)ps.a.mode,
+                                              ps.pipe_ng, ps.pipe_kind, ps.pipe_mode,
                                               ps.pipe_threads, ps.pipe_lds)
                          : 0;
         const int64_t want = (int64_t)nb * ncu;
@@ -2048,6 +2071,7 @@ pafc_status pafc_plan(pafc_plan_t* out, int ndim, const int64_t* dims, const int
     const PassArgs &x = m.a, &y = f.a;
     p->h_tm = m.pipe && f.pipe && m.pipe_r == f.pipe_r && m.pipe_g == f.pipe_g &&
               m.pipe_ng == f.pipe_ng && m.pipe_threads == f.pipe_threads &&
+              m.pipe_mode == MODE_STRIDED && f.pipe_mode == MODE_STRIDED &&
               x.mode == MODE_STRIDED &&
               y.mode == MODE_STRIDED &&
               x.L == y.L && x.W == y.W && x.S_i == y.S_i && x.S_c == y.S_c && x.S_o == y.S_o &&

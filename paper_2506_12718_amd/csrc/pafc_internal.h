@@ -26,6 +26,10 @@
 namespace pafc {
 
 enum { MODE_CONTIG = 0, MODE_STRIDED = 1 };
+// Pipelined kernel only: a strided outer piece of a cut axis, whose twiddles
+// are those of the whole axis (two-level LDS table, exponent with the
+// column's inner position); its PassArgs::mode stays MODE_STRIDED.
+enum { MODE_OUTER = 2 };
 enum { OP_DIF = 0, OP_DIT = 1, OP_MID = 2 };
 
 // Group kinds (r, g) instantiated in the kernels.

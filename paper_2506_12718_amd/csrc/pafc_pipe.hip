@@ -11,7 +11,9 @@
 // Twiddles are staged once per block in LDS, so no global load other than
 // the prefetch sits in the loop and the in-order vector-memory counter never
 // makes a group wait on the prefetch.
-#include "kernel_common.h"
+#include <type_traits>
+
+#include "pass_engine.h"
 
 namespace pafc {
 
@@ -73,12 +75,25 @@ constexpr int pipe_waves_per_eu() { return KIND == PIPE_FWD && NG == 2 ? 2 : 1; 
 template <int r, int g>
 constexpr int pipe_max_threads() { return (r == 3 || r == 5) && g == 1 ? 1024 : 256; }
 
-template <typename T, int r, int g, int NG, int KIND, int MODE>
+// Outer pieces of a cut axis (MODE_OUTER) are compiled for the shapes the
+// tuned 1-D plans cut off (243 = 3^5 and 625 = 5^4 positions) and the
+// shorter ones of cut grid axes (81 = 3^4, 125 = 5^3).
+template <int r, int g, int NG>
+constexpr bool pipe_outer_shape() {
+  return g == 1 && ((r == 3 && (NG == 4 || NG == 5)) || (r == 5 && (NG == 3 || NG == 4)));
+}
+
+template <typename T, int r, int g, int NG, int KIND, int MODE_ARG>
 __global__ void __launch_bounds__((pipe_max_threads<r, g>()))
 __attribute__((amdgpu_waves_per_eu(pipe_waves_per_eu<KIND, NG>())))
 pipe_kernel(const PassArgs* __restrict__ desc,
                                                    const void* __restrict__ in,
                                                    void* __restrict__ out) {
+  // an outer piece is a strided pass whose twiddles are those of the whole
+  // axis: w_{Kf}^{m jf}, Kf = K jmul, jf = j jmul + (inner position of the
+  // column), from the two-level LDS copy of the axis's table
+  constexpr bool OUTER = MODE_ARG == MODE_OUTER;
+  constexpr int MODE = OUTER ? MODE_STRIDED : MODE_ARG;
   constexpr int R = ipow(r, g);
   using Sh = PipeShape<R, NG, KIND>;
   constexpr int L = Sh::L;
@@ -108,10 +123,14 @@ pipe_kernel(const PassArgs* __restrict__ desc,
   const uint32_t ls_i = MODE == MODE_STRIDED ? W : 1u;
   const uint32_t ls_c = MODE == MODE_STRIDED ? 1u : (uint32_t)L;
 
-  {
+  if constexpr (OUTER) {
+    stage_twiddles<T>(a, lds);  // at a.twl_off == the offset of tw
+  } else {
     const cx<T>* lo = reinterpret_cast<const cx<T>*>(a.tw_lo);
     for (uint32_t e = tid; e < (uint32_t)L; e += nthr) tw[e] = lo[e];
   }
+  const uint32_t jmul = a.jmul;
+  const bool col_in_j = a.col_in_j != 0;
 
   // every array this kernel touches is below 4 GiB (the planner checks), so
   // element indices and byte offsets are 32-bit
@@ -229,9 +248,28 @@ pipe_kernel(const PassArgs* __restrict__ desc,
         // the inputs are in registers: start loading the next tile now
         if (next < a.ntiles) fetch_x(next);
       }
+      // the twiddles of an outer piece (every op has them: its column's
+      // inner position enters the exponent even where S == 1)
+      auto outer_tw = [&](auto conj_tag) {
+        const uint32_t Kf = (uint32_t)K * jmul;
+        const uint32_t esc = a.ops[i].escale;
+        const uint32_t jf = it.j * jmul + (col_in_j && it.valid ? fdiv(col0 + it.c, a.divJc) : 0u);
+        uint32_t E = 0;
+        static_for<R - 1>([&](auto mm) {
+          E += jf;
+          if (E >= Kf) E -= Kf;
+          const cx<T> w = twiddle_lds<T>(a, lds, E * esc);
+          if constexpr (decltype(conj_tag)::value)
+            v[mm.value + 1] = cmulc(v[mm.value + 1], w);
+          else
+            v[mm.value + 1] = cmul(v[mm.value + 1], w);
+        });
+      };
       if constexpr (type == OP_DIF) {
         Dft<R, r, false, T>::run(v);
-        if constexpr (S > 1) {
+        if constexpr (OUTER) {
+          outer_tw(std::false_type{});
+        } else if constexpr (S > 1) {
           uint32_t E = 0;
           static_for<R - 1>([&](auto mm) {
             E += it.j;
@@ -240,7 +278,9 @@ pipe_kernel(const PassArgs* __restrict__ desc,
           });
         }
       } else if constexpr (type == OP_DIT) {
-        if constexpr (S > 1) {
+        if constexpr (OUTER) {
+          outer_tw(std::true_type{});
+        } else if constexpr (S > 1) {
           uint32_t E = 0;
           static_for<R - 1>([&](auto mm) {
             E += it.j;
@@ -350,6 +390,10 @@ static const void* pipe_fn(int kind, int mode) {
   PAFC_PIPE_SEL(PIPE_INV, MODE_STRIDED)
   PAFC_PIPE_SEL(PIPE_MID, MODE_CONTIG)
   PAFC_PIPE_SEL(PIPE_MID, MODE_STRIDED)
+  if constexpr (pipe_outer_shape<r, g, NG>()) {
+    PAFC_PIPE_SEL(PIPE_FWD, MODE_OUTER)
+    PAFC_PIPE_SEL(PIPE_INV, MODE_OUTER)
+  }
 #undef PAFC_PIPE_SEL
   return nullptr;
 }
@@ -365,6 +409,10 @@ static const void* pipe_lookup(bool dbl, int r, int g, int ng, int kind, int mod
 
 bool pipe_supported(int r, int g, int ng) {
   return pipe_lookup(true, r, g, ng, PIPE_FWD, MODE_CONTIG) != nullptr;
+}
+
+bool pipe_outer_supported(int r, int g, int ng) {
+  return pipe_lookup(true, r, g, ng, PIPE_FWD, MODE_OUTER) != nullptr;
 }
 
 // Most threads a block of the pipelined kernel for groups r^g may have.

@@ -479,3 +479,51 @@ def test_small_radix_pipelined_passes(shape, radix, dtype, monkeypatch):
     finally:
         monkeypatch.delenv("PAFC_NO_TUNING_TABLE")
         m._load_tuning_table(m.lib())  # the table the other tests plan with
+
+
+# (shape, dtype, table): outer pieces of cut axes on the pipelined kernel
+# (MODE_OUTER): the tuned 1-D plans' 625- and 243-long outer pieces (tuning
+# table), and the 125-long outer pieces of cut grid axes, whose column's
+# inner position is the column divided by the axis stride (env caps)
+OUTER_PIECES = [((5 ** 9,), C128, True), ((995328,), C128, True), ((995328,), C64, True),
+                ((2025000,), C128, True), ((390625, 2), C128, False), ((390625, 2), C64, False),
+                ((78125, 8), C128, False)]
+
+
+@pytest.mark.parametrize("shape,dtype,table", OUTER_PIECES)
+def test_outer_pieces_pipelined(shape, dtype, table, monkeypatch):
+    """Outer pieces of a cut axis run on the pipelined kernel with the whole
+    axis's twiddles (two-level LDS table, exponent j*jmul + inner position);
+    against the oracle and against the general engine (PAFC_PIPE_OUTER=0)."""
+    import paper_2506_12718_amd as m
+    if not table:
+        monkeypatch.setenv("PAFC_NO_TUNING_TABLE", "1")
+        monkeypatch.setenv("PAFC_TUNE_GMAX3", "1")
+        monkeypatch.setenv("PAFC_TUNE_GMAX5", "1")
+        m.set_tuning(None)
+    try:
+        dt = "c128" if dtype == C128 else "c64"
+        labels = m.describe(shape, dt)["conv_passes"]
+        say("outer pieces", shape, dt, labels)
+        assert sum(l.endswith(",2>") for l in labels) == 2, labels
+        rng = np.random.default_rng([len(shape), shape[0], 23])
+        x = inputs.complex_uniform(rng, shape)
+        h = inputs.complex_uniform(rng, shape)
+        ref = oracle.conv_fft(rounded(x, dtype), rounded(h, dtype))
+        ys = {}
+        for flag in ("1", "0"):
+            monkeypatch.setenv("PAFC_PIPE_OUTER", flag)
+            P = m.Plan(shape, dtype)
+            if flag == "0":
+                assert not any(l.endswith(",2>") for l in m.describe(shape, dt)["conv_passes"])
+            P.set_filter(to_dev(h, dtype))
+            ys[flag] = to_host(P.convolve(to_dev(x, dtype)))
+            P.close()
+            err = rel_l2(ys[flag], ref)
+            say("  PAFC_PIPE_OUTER", flag, "rel_l2", err)
+            assert err <= TOL[dtype]
+        assert rel_l2(ys["1"], ys["0"]) <= (2e-15 if dtype == C128 else 1e-6)
+    finally:
+        if not table:
+            monkeypatch.delenv("PAFC_NO_TUNING_TABLE")
+            m._load_tuning_table(m.lib())
