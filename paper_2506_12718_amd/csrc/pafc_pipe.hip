@@ -77,10 +77,11 @@ constexpr int pipe_max_threads() { return (r == 3 || r == 5) && g == 1 ? 1024 : 
 
 // Outer pieces of a cut axis (MODE_OUTER) are compiled for the shapes the
 // tuned 1-D plans cut off (243 = 3^5 and 625 = 5^4 positions) and the
-// shorter ones of cut grid axes (81 = 3^4, 125 = 5^3).
+// shorter ones of cut grid axes (9 = 3^2, 81 = 3^4, 125 = 5^3).
 template <int r, int g, int NG>
 constexpr bool pipe_outer_shape() {
-  return g == 1 && ((r == 3 && (NG == 4 || NG == 5)) || (r == 5 && (NG == 3 || NG == 4)));
+  return g == 1 &&
+         ((r == 3 && (NG == 2 || NG == 4 || NG == 5)) || (r == 5 && (NG == 3 || NG == 4)));
 }
 
 template <typename T, int r, int g, int NG, int KIND, int MODE_ARG>
@@ -372,6 +373,7 @@ __global__ void __launch_bounds__((pipe_max_threads<r, g>())) pipe_htm_kernel(co
   X(8, 1, 2) /* L = 64 */     \
   X(8, 1, 3) /* L = 512 */    \
   X(4, 2, 1) /* L = 16 */     \
+  X(3, 1, 2) /* L = 9 */      \
   X(3, 1, 4) /* L = 81 */     \
   X(3, 1, 5) /* L = 243 */    \
   X(3, 1, 6) /* L = 729 */    \

@@ -483,9 +483,10 @@ def test_small_radix_pipelined_passes(shape, radix, dtype, monkeypatch):
 
 # (shape, dtype, table): outer pieces of cut axes on the pipelined kernel
 # (MODE_OUTER): the tuned 1-D plans' 625- and 243-long outer pieces (tuning
-# table), and the 125-long outer pieces of cut grid axes, whose column's
-# inner position is the column divided by the axis stride (env caps)
+# table), and the 9- and 125-long outer pieces of cut grid axes, whose
+# column's inner position is the column divided by the axis stride
 OUTER_PIECES = [((5 ** 9,), C128, True), ((995328,), C128, True), ((995328,), C64, True),
+                ((2187, 2187), C128, True), ((2187, 2187), C64, True),
                 ((2025000,), C128, True), ((390625, 2), C128, False), ((390625, 2), C64, False),
                 ((78125, 8), C128, False)]
 
