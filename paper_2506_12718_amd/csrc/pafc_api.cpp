@@ -87,6 +87,11 @@ constexpr size_t kLdsBudget = 160 * 1024;  // LDS per CU on gfx950
 //   PAFC_SNAKE     0 walks every pass's tiles in the same direction
 //   PAFC_AXIS_ORDER 1 runs the other axes' forward passes slowest first
 //   PAFC_HTM       0 keeps the spectrum in plan layout (no tile-major order)
+//   PAFC_PIPE      0 runs every pass on the general engine (no pipelined kernel)
+//   PAFC_PIPE_OUTER 0 keeps outer pieces of cut axes on the general engine
+//   PAFC_TUNE_GMAX3 / PAFC_TUNE_GMAX5  largest radix-3 / radix-5 register
+//                  group (stages) where the tuning table has no entry
+//   PAFC_NO_TUNING_TABLE 1 (binding) loads no tuning table
 //   PAFC_LDS_POISON 1 (debug) every pass fills its LDS tile with NaN first
 //   PAFC_LDS_PAD   1 pads the LDS tiles of odd-length contiguous passes too
 //   PAFC_FAULT_INJECT=oom  pafc_plan fails with OUT_OF_MEMORY after its first
