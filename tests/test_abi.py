@@ -121,6 +121,25 @@ def test_infeasible_tuning_entry_falls_back_to_defaults():
     assert pafc.describe((2187,), "c128")["conv_passes"] == one["conv_passes"]
 
 
+def test_outer_pieces_take_the_pipelined_kernel(monkeypatch):
+    # one-stage radix-5 groups: 5^9 is cut into 625 x 3125, and the 625-long
+    # outer pieces run the pipelined kernel in its outer-piece mode, one
+    # thread per item (125 items x 8 columns); the 2187^2 grid's 9-long
+    # outer pieces too; PAFC_PIPE_OUTER=0 keeps them on the general engine
+    try:
+        pafc.set_tuning("c128 1953125 0 0 0 0 1\nc128 2187 0 0 0 1 0\n")
+        one = pafc.describe((5 ** 9,), "c128")["conv_passes"]
+        outer = [l for l in one if l.endswith(",2>")]
+        assert len(outer) == 2 and all("L=625 W=8" in l and "thr=1000" in l for l in outer), one
+        grid = pafc.describe((2187, 2187), "c128")["conv_passes"]
+        assert sum(l.endswith(",2>") and "L=9 " in l for l in grid) == 2, grid
+        monkeypatch.setenv("PAFC_PIPE_OUTER", "0")
+        assert not any(l.endswith(",2>") for l in pafc.describe((5 ** 9,), "c128")["conv_passes"])
+        assert not any(l.endswith(",2>") for l in pafc.describe((2187, 2187), "c128")["conv_passes"])
+    finally:
+        pafc.set_tuning(None)
+
+
 def _smooth(n):
     for q in (2, 3, 5):
         while n % q == 0:
