@@ -16,13 +16,6 @@ __device__ __forceinline__ cx<T> twiddle_lds(const PassArgs& a, const cx<T>* lds
   return cmul(lo[E & ((1u << a.twl_bits) - 1u)], hi[E >> a.twl_bits]);
 }
 
-// Twiddle w^E of a pass: from the LDS copy, or from the global table when
-// the pass has none.
-template <typename T>
-__device__ __forceinline__ cx<T> pass_twiddle(const PassArgs& a, const cx<T>* lds, uint32_t E) {
-  return a.twl_global ? twiddle<T>(a, E) : twiddle_lds<T>(a, lds, E);
-}
-
 // Stage the two-level twiddle table in LDS (from the flat or two-level
 // global table); the caller synchronises before the first op.
 template <typename T>
@@ -161,23 +154,43 @@ __device__ __forceinline__ void run_op(const PassArgs& a, const OpDesc& op, cons
       Dft<R, r, false, T>::run(v);
       if (op.tw) {
         const uint32_t jf = m.j * a.jmul + (a.col_in_j && m.valid ? fdiv(m.gcol, a.divJc) : 0u);
-        uint32_t E = 0;
-        static_for<R - 1>([&](auto mm) {
-          E += jf;
-          if (E >= op.Kf) E -= op.Kf;
-          v[mm.value + 1] = cmul(v[mm.value + 1], pass_twiddle<T>(a, lds, E * op.escale));
-        });
+        if (a.twl_global) {
+          // no LDS copy: one read of the global table per item, the other
+          // twiddles as powers, w^(m jf) = (w^jf)^m (jf < Kf / R)
+          const cx<T> w1 = twiddle<T>(a, jf * op.escale);
+          cx<T> w = w1;
+          static_for<R - 1>([&](auto mm) {
+            v[mm.value + 1] = cmul(v[mm.value + 1], w);
+            w = cmul(w, w1);
+          });
+        } else {
+          uint32_t E = 0;
+          static_for<R - 1>([&](auto mm) {
+            E += jf;
+            if (E >= op.Kf) E -= op.Kf;
+            v[mm.value + 1] = cmul(v[mm.value + 1], twiddle_lds<T>(a, lds, E * op.escale));
+          });
+        }
       }
       static_for<R>([&](auto mm) { put(digrev<r, g>(mm.value), v[mm.value]); });
     } else if constexpr (TYPE == OP_DIT) {
       if (op.tw) {
         const uint32_t jf = m.j * a.jmul + (a.col_in_j && m.valid ? fdiv(m.gcol, a.divJc) : 0u);
-        uint32_t E = 0;
-        static_for<R - 1>([&](auto mm) {
-          E += jf;
-          if (E >= op.Kf) E -= op.Kf;
-          v[mm.value + 1] = cmulc(v[mm.value + 1], pass_twiddle<T>(a, lds, E * op.escale));
-        });
+        if (a.twl_global) {  // as in the DIF op
+          const cx<T> w1 = twiddle<T>(a, jf * op.escale);
+          cx<T> w = w1;
+          static_for<R - 1>([&](auto mm) {
+            v[mm.value + 1] = cmulc(v[mm.value + 1], w);
+            w = cmul(w, w1);
+          });
+        } else {
+          uint32_t E = 0;
+          static_for<R - 1>([&](auto mm) {
+            E += jf;
+            if (E >= op.Kf) E -= op.Kf;
+            v[mm.value + 1] = cmulc(v[mm.value + 1], twiddle_lds<T>(a, lds, E * op.escale));
+          });
+        }
       }
       Dft<R, r, true, T>::run(v);
       static_for<R>([&](auto s) { put(s.value, v[s.value]); });
