@@ -223,12 +223,22 @@ pafc_status pafc_convolve(pafc_plan_t p, const void* x_dev, void* y_dev,
  *   HEAT              exp(-t sum_i w_i^2), params[0] = t >= 0
  *   DERIVATIVE        i w_a along axis a = params[0] (0 at the Nyquist
  *                     frequency of an even axis): the spectral derivative
+ *   GAUSSIAN          the DFT of the unit-sum periodic Gaussian of width
+ *                     sigma = params[0] (0.05 <= sigma <= 1e6), whose spatial
+ *                     form is h_j = prod_i g_i(j_i) / sum_j g_i(j) with
+ *                     g_i(j) = sum_{p in Z} exp(-(j + p n_i)^2 / (2 sigma^2)):
+ *                     by Poisson summation its spectrum is the product over
+ *                     the axes of theta_i(kt_i) / theta_i(0), theta_i(kt) =
+ *                     sum_{m in Z} exp(-2 pi^2 sigma^2 (kt / n_i + m)^2), so
+ *                     pafc_convolve computes y = x * h without h ever being
+ *                     formed or transformed
  */
 typedef enum pafc_symbol {
   PAFC_SYMBOL_INV_LAPLACIAN = 0,
   PAFC_SYMBOL_INV_LAPLACIAN_FD = 1,
   PAFC_SYMBOL_HEAT = 2,
   PAFC_SYMBOL_DERIVATIVE = 3,
+  PAFC_SYMBOL_GAUSSIAN = 4,
   PAFC_SYMBOL_MAX_ENUM = 0x7FFFFFFF
 } pafc_symbol;
 
@@ -247,7 +257,8 @@ typedef enum pafc_symbol {
  * (the table upload).
  * params / nparams: as the symbol requires (NULL and 0 when none).
  * Errors: INVALID_VALUE (bad kind, parameter count or value: t < 0 or not
- * finite, axis not an integer in [0, ndim)), DEVICE.
+ * finite, axis not an integer in [0, ndim), sigma outside [0.05, 1e6]),
+ * DEVICE.
  */
 pafc_status pafc_set_symbol(pafc_plan_t p, pafc_symbol kind, const double* params,
                             int nparams, void* hip_stream);

@@ -272,12 +272,14 @@ class Plan:
         """y = x (*) h; ``out`` may be ``x`` (in place)."""
         return self._run(lib().pafc_convolve, x, out, stream, "pafc_convolve")
 
-    SYMBOLS = {"inv_laplacian": 0, "inv_laplacian_fd": 1, "heat": 2, "derivative": 3}
+    SYMBOLS = {"inv_laplacian": 0, "inv_laplacian_fd": 1, "heat": 2, "derivative": 3,
+               "gaussian": 4}
 
     def set_symbol(self, kind, *params, stream=None):
         """Make the plan's operator the diagonal symbol `kind` (see
         pafc_set_symbol): 'inv_laplacian', 'inv_laplacian_fd', 'heat' (t),
-        'derivative' (axis).  convolve() then applies it."""
+        'derivative' (axis), 'gaussian' (sigma: the spectrum of the unit-sum
+        periodic Gaussian filter).  convolve() then applies it."""
         arr = (ctypes.c_double * max(1, len(params)))(*[float(v) for v in params])
         _check(lib().pafc_set_symbol(self._h, self.SYMBOLS[kind], arr if params else None,
                                      len(params), _stream(stream)), "pafc_set_symbol")

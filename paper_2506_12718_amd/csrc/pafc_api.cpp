@@ -2252,6 +2252,11 @@ pafc_status pafc_set_symbol(pafc_plan_t p, pafc_symbol kind, const double* param
         return PAFC_ERROR_INVALID_VALUE;
       axis = (int)params[0];
       break;
+    case PAFC_SYMBOL_GAUSSIAN:
+      if (nparams != 1 || !params || !(params[0] >= 0.05) || !(params[0] <= 1e6))
+        return PAFC_ERROR_INVALID_VALUE;
+      t = params[0];  // sigma
+      break;
     default:
       return PAFC_ERROR_INVALID_VALUE;
   }
@@ -2270,6 +2275,25 @@ pafc_status pafc_set_symbol(pafc_plan_t p, pafc_symbol kind, const double* param
     }
     const int64_t n = P.axes[(size_t)i].n;
     len[(size_t)i] = (uint32_t)n;
+    // Gaussian: theta(kt) = sum_m exp(-2 pi^2 sigma^2 (kt/n + m)^2) for
+    // 0 <= kt <= n/2 (theta is even in kt), the images m and -m added as one
+    // pair in order of increasing |m|; terms beyond |m| = M are below
+    // exp(-100) of the largest
+    std::vector<long double> theta;
+    if (kind == PAFC_SYMBOL_GAUSSIAN) {
+      const long double c = 2.0L * pi * pi * (long double)t * (long double)t;
+      const int64_t M = 2 + (int64_t)std::ceil(std::sqrt(100.0 / (double)c));
+      theta.resize((size_t)(n / 2 + 1));
+      for (int64_t kt = 0; kt <= n / 2; ++kt) {
+        const long double xk = (long double)kt / (long double)n;
+        long double sum = expl(-c * xk * xk);
+        for (int64_t m = 1; m <= M; ++m) {
+          const long double a = xk + (long double)m, b = xk - (long double)m;
+          sum += expl(-c * a * a) + expl(-c * b * b);
+        }
+        theta[(size_t)kt] = sum;
+      }
+    }
     for (int64_t k = 0; k < n; ++k) {
       const int64_t kt = 2 * k <= n ? k : k - n;
       const long double w = 2.0L * pi * (long double)kt / (long double)n;
@@ -2282,6 +2306,8 @@ pafc_status pafc_set_symbol(pafc_plan_t p, pafc_symbol kind, const double* param
         re = 4.0L * sv * sv;
       } else if (kind == PAFC_SYMBOL_HEAT) {
         re = expl(-(long double)t * w * w);
+      } else if (kind == PAFC_SYMBOL_GAUSSIAN) {
+        re = theta[(size_t)(kt < 0 ? -kt : kt)] / theta[0];
       } else {  // derivative: i w on its axis (0 at the Nyquist frequency), 1 elsewhere
         if (i == axis) {
           im = (2 * k == n) ? 0.0L : w;
@@ -2550,7 +2576,11 @@ pafc_status pafc_batch_plan(pafc_batch_t* out, int count, const int64_t* sizes,
                    [&](int x, int y) { return b->sizes[(size_t)x] > b->sizes[(size_t)y]; });
   auto blocks_per_cu = [](size_t lds) { return (int)std::min<size_t>(8, kLdsBudget / std::max<size_t>(lds, 1)); };
   std::vector<BatchTile> tiles;
-  for (int l = 0; l < 3; ++l) {
+  // every pass level of the longest plan (a 1-D plan has 1, 3 or, for
+  // lengths cut twice, 5 passes)
+  int nlevels = 0;
+  for (auto& kv : b->plans) nlevels = std::max(nlevels, (int)kv.second->P.conv.size());
+  for (int l = 0; l < nlevels; ++l) {
     for (int cls = 0; cls < 3; ++cls)
     for (int bpc = 1; bpc <= 8; ++bpc) {
       pafc_batch_s::Level L;

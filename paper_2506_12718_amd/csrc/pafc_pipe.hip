@@ -87,9 +87,9 @@ constexpr bool pipe_outer_shape() {
 template <typename T, int r, int g, int NG, int KIND, int MODE_ARG>
 __global__ void __launch_bounds__((pipe_max_threads<r, g>()))
 __attribute__((amdgpu_waves_per_eu(pipe_waves_per_eu<KIND, NG>())))
-pipe_kernel(const PassArgs* __restrict__ desc,
-                                                   const void* __restrict__ in,
-                                                   void* __restrict__ out) {
+pipe_kernel(const PassArgs* __restrict__ desc, const void* in, void* out) {
+  // in and out may be the same array (every pass after the first runs in
+  // place), so neither is declared __restrict__
   // an outer piece is a strided pass whose twiddles are those of the whole
   // axis: w_{Kf}^{m jf}, Kf = K jmul, jf = j jmul + (inner position of the
   // column), from the two-level LDS copy of the axis's table

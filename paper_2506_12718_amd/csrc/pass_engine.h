@@ -114,7 +114,7 @@ __device__ __forceinline__ OpItem op_item(const PassArgs& a, const OpDesc& op, c
 // Global inputs of one item, in the order the op consumes them (DIF and MID
 // read natural positions, DIT digit-reversed ones).
 template <typename T, int r, int g, int TYPE, typename Dst>
-__device__ __forceinline__ void fetch_item(const OpItem& m, const void* __restrict__ in,
+__device__ __forceinline__ void fetch_item(const OpItem& m, const void* in,
                                            Dst& v) {
   constexpr int R = ipow(r, g);
   static_for<R>([&](auto s) {
@@ -129,8 +129,8 @@ __device__ __forceinline__ void fetch_item(const OpItem& m, const void* __restri
 // (op.dst_g, last op) straight to global memory.
 template <typename T, int r, int g, int TYPE>
 __device__ __forceinline__ void run_op(const PassArgs& a, const OpDesc& op, const TileCtx& t,
-                                       cx<T>* lds, const void* __restrict__ in,
-                                       void* __restrict__ out) {
+                                       cx<T>* lds, const void* in,
+                                       void* out) {
   constexpr int R = ipow(r, g);
   for (uint32_t it = threadIdx.x; it < op.nitems; it += blockDim.x) {
     const OpItem m = op_item(a, op, t, it);
@@ -225,7 +225,7 @@ constexpr int class_max_threads() { return CLS == 2 ? 1024 : 256; }
 template <typename T, int TYPE, int CLS>
 __device__ __forceinline__ void dispatch_op(const PassArgs& a, const OpDesc& op,
                                             const TileCtx& t, cx<T>* lds,
-                                            const void* __restrict__ in, void* __restrict__ out) {
+                                            const void* in, void* out) {
   switch (op.kind) {
 #define PAFC_CASE(id, r, g)                                                          \
   case id:                                                                           \
@@ -242,7 +242,7 @@ __device__ __forceinline__ void dispatch_op(const PassArgs& a, const OpDesc& op,
 template <typename T, int CLS>
 __device__ __forceinline__ void dispatch_any(const PassArgs& a, const OpDesc& op,
                                              const TileCtx& t, cx<T>* lds,
-                                             const void* __restrict__ in, void* __restrict__ out) {
+                                             const void* in, void* out) {
   if (op.type == OP_DIF)
     dispatch_op<T, OP_DIF, CLS>(a, op, t, lds, in, out);
   else if (op.type == OP_DIT)
@@ -264,7 +264,7 @@ __device__ __forceinline__ void tile_pos(const PassArgs& a, uint32_t x, uint32_t
 
 template <typename T>
 __device__ __forceinline__ void load_tile(const PassArgs& a, const TileCtx& t,
-                                          const void* __restrict__ in, cx<T>* lds) {
+                                          const void* in, cx<T>* lds) {
   for (uint32_t x = threadIdx.x; x < a.LW; x += blockDim.x) {
     uint32_t i, c;
     tile_pos(a, x, i, c);
@@ -276,7 +276,7 @@ __device__ __forceinline__ void load_tile(const PassArgs& a, const TileCtx& t,
 
 template <typename T>
 __device__ __forceinline__ void store_tile(const PassArgs& a, const TileCtx& t,
-                                           void* __restrict__ out, const cx<T>* lds) {
+                                           void* out, const cx<T>* lds) {
   for (uint32_t x = threadIdx.x; x < a.LW; x += blockDim.x) {
     uint32_t i, c;
     tile_pos(a, x, i, c);
@@ -288,8 +288,8 @@ __device__ __forceinline__ void store_tile(const PassArgs& a, const TileCtx& t,
 // Process tile `tile` of the pass described by `a`; `off` shifts in, out and H
 // (the packed offset of a problem in the batched form).
 template <typename T, int CLS>
-__device__ __forceinline__ void do_tile(const PassArgs& a, const void* __restrict__ in,
-                                        void* __restrict__ out, uint32_t tile, int64_t off,
+__device__ __forceinline__ void do_tile(const PassArgs& a, const void* in,
+                                        void* out, uint32_t tile, int64_t off,
                                         cx<T>* lds) {
   const TileCtx t = make_ctx(a, tile, off);
   if (a.poison) {  // debug: the tile region (below the twiddle copy) is NaN

@@ -63,20 +63,27 @@ class PlanCache:
         self.evictions = 0
 
     def get(self, key):
+        """The entry for `key` (moved to the most recently used end), or None."""
         e = self.entries.get(key)
         if e is None:
             return None
         self.entries.move_to_end(key)
-        self.hits += 1
         return e
 
     def can_fit(self, extra: int, reserved: int) -> bool:
-        """Can `extra` more bytes fit, evicting unused entries if needed?"""
+        """Can `extra` more bytes fit, evicting unused entries if needed?
+        Entries with a reference (in flight, or pinned by the admission
+        being decided) are not reclaimable."""
         free = self.budget - reserved - self.bytes
         if extra <= free:
             return True
         reclaim = sum(b for (o, b, r) in self.entries.values() if r == 0)
         return extra <= free + reclaim
+
+    def recharge(self, entry, nbytes: int):
+        """Set an entry's charge to the bytes its object really holds."""
+        self.bytes += int(nbytes) - entry[1]
+        entry[1] = int(nbytes)
 
     def make_room(self, extra: int, reserved: int, release: Callable):
         for key in list(self.entries.keys()):
@@ -125,18 +132,29 @@ class Server:
         key = (tuple(req.dims), req.fid)
         entry = self.cache.get(key)
         need = self.ex.request_bytes(req)
-        extra = need + (0 if entry is not None else self.ex.plan_bytes(req))
+        if entry is not None:
+            # pin the hit while deciding, so that it is not counted as
+            # memory that eviction could free for this very request
+            entry[2] += 1
+            extra, total = need, need + entry[1]
+        else:
+            est = self.ex.plan_bytes(req)
+            extra, total = need + est, need + est
         if not self.cache.can_fit(extra, self.reserved):
+            if entry is not None:
+                entry[2] -= 1
             if self.inflight:
                 return False  # wait for completions to free memory
-            if need + (0 if entry is not None else self.ex.plan_bytes(req)) > self.cache.budget:
-                self.pending.popleft()
-                self._fail(req, "request %d does not fit the HBM budget" % req.rid)
-                return True
+            # nothing in flight: every other entry could be evicted, so the
+            # request alone (with its plan) exceeds the budget
+            self.pending.popleft()
+            self._fail(req, "request %d (%d bytes with its plan) does not fit the HBM budget"
+                       % (req.rid, total))
+            return True
         self.pending.popleft()
         slot = self.free_slots.pop()
+        self.cache.make_room(extra, self.reserved, self.ex.release_plan)
         if entry is None:
-            self.cache.make_room(extra, self.reserved, self.ex.release_plan)
             try:
                 plan = self.ex.prepare(req, slot)
             except Exception as e:  # nothing was cached or reserved yet
@@ -144,7 +162,15 @@ class Server:
                 self._fail(req, "prepare: %s" % e)
                 return True
             entry = self.cache.put(key, plan, self.ex.plan_bytes(req))
-        entry[2] += 1
+            entry[2] += 1
+            # charge what the plan really holds (the estimate is an upper
+            # bound), then evict again in case it was not
+            held = getattr(self.ex, "held_bytes", None)
+            if held is not None:
+                self.cache.recharge(entry, held(plan))
+                self.cache.make_room(need, self.reserved, self.ex.release_plan)
+        else:
+            self.cache.hits += 1
         self.reserved += need
         req.slot = slot
         req.start = self.clock()
@@ -249,11 +275,12 @@ def latency_stats(reqs):
 class GpuExecutor:
     """Runs requests through the permutation-avoiding convolution library.
 
-    prepare(): plan for the request's shape + set_filter with the request's
-    Gaussian filter (built on the device from its separable 1-D factors),
-    enqueued on the slot's stream.  launch(): convolve on the slot's stream
-    into a fresh output buffer, after waiting for the plan's filter to be
-    ready.  finished(): the completion event has fired.
+    prepare(): plan for the request's shape, with the request's Gaussian
+    filter installed as its closed-form spectrum (pafc_set_symbol GAUSSIAN:
+    no filter array is formed or transformed), enqueued on the slot's
+    stream.  launch(): convolve on the slot's stream into a fresh output
+    buffer, ordered after the stream that produced the input and after the
+    plan's preparation.  finished(): the completion event has fired.
     """
 
     def __init__(self, dtype=None, sigma_of=None, slots=4):
@@ -286,35 +313,35 @@ class GpuExecutor:
         return n * self.elem  # the output buffer (the input is the caller's)
 
     def plan_bytes(self, req):
+        """Upper bound of a plan's device memory before it exists: the
+        spectrum (at most 1.25 N elements with the padding of ragged
+        tile-major tiles), one N-element staging array, and the twiddles,
+        index maps, symbol tables and descriptors (below 256 KiB for every
+        served grid; a GPU test checks the bound against
+        pafc_plan_device_bytes)."""
         n = 1
         for d in req.dims:
             n *= d
-        return n * self.elem + 64 * 1024  # spectrum + twiddles, descriptors
+        return (9 * n * self.elem) // 4 + (256 << 10)
 
-    def filter_tensor(self, dims, sigma):
-        torch = self.torch
-        from paper_2506_12718_amd import inputs
-        h = None
-        for n in dims:
-            g = inputs.wrapped_gaussian_1d(int(n), sigma)
-            g = torch.from_numpy(g / g.sum()).to(torch.float64).cuda()
-            h = g if h is None else torch.multiply(h.unsqueeze(-1), g)
-        return h.to(self.dtype).contiguous()
+    def held_bytes(self, obj):
+        """Device memory a prepared plan really holds (pafc_plan_device_bytes)."""
+        return obj["bytes"]
 
     def prepare(self, req, slot):
         self._maybe_fail("prepare")
         torch = self.torch
         s = self.streams[slot]
-        with torch.cuda.stream(s):
-            plan = self.pafc.Plan(req.dims, self.dtype, stream=s)
-            sigma = self.sigma_of(req.dims, req.fid)
-            h = self.filter_tensor(req.dims, sigma)
-            plan.set_filter(h, stream=s)
-            ev = torch.cuda.Event()
-            ev.record(s)
-            h.record_stream(s)
+        plan = self.pafc.Plan(req.dims, self.dtype, stream=s)
+        try:
+            plan.set_symbol("gaussian", self.sigma_of(req.dims, req.fid), stream=s)
+        except Exception:
+            plan.close()
+            raise
+        ev = torch.cuda.Event()
+        ev.record(s)
         self.prepared += 1
-        return {"plan": plan, "ready": ev}
+        return {"plan": plan, "ready": ev, "bytes": plan.device_bytes}
 
     def release_plan(self, obj):
         obj["ready"].synchronize()
@@ -325,6 +352,11 @@ class GpuExecutor:
         torch = self.torch
         s = self.streams[slot]
         s.wait_event(obj["ready"])
+        # the input was produced on this thread's current stream: order the
+        # convolution after it, and keep the allocator from reusing the
+        # input's memory before the convolution has read it
+        s.wait_stream(torch.cuda.current_stream())
+        req.x.record_stream(s)
         with torch.cuda.stream(s):
             out = torch.empty(req.dims, dtype=self.dtype, device="cuda")
             obj["plan"].convolve(req.x, out=out, stream=s)

@@ -8,7 +8,7 @@ import pytest
 
 import oracle
 from paper_2506_12718_amd import inputs
-from gpu_util import TOL, rel_l2, rounded, to_dev, to_host, torch
+from gpu_util import TOL, check_close, rel_l2, rounded, to_dev, to_host, torch
 
 pytestmark = pytest.mark.gpu
 
@@ -56,7 +56,7 @@ def check_batch(sizes, fids, filters, xs, dtype, spectral=False, sample=None):
             ref = oracle.fft(h * oracle.fft(x), inverse=True)
         else:
             ref = oracle.conv_fft(x, h)
-        assert rel_l2(ys[i], ref) < TOL[dtype], (i, sizes[i])
+        check_close(ys[i], ref, TOL[dtype], what=str((i, sizes[i])))
     B.close()
     return ys
 
@@ -144,3 +144,29 @@ def test_batch_errors():
         B.convolve(to_dev(np.zeros(128, complex), torch.complex128))
     assert e.value.status == 5
     B.close()
+
+
+def test_batch_with_five_pass_size():
+    """A length whose 1-D plan runs five passes (2^23 complex128: the axis is
+    cut twice) in a batch with one- and three-pass lengths: every pass level
+    runs.  The long problem is checked at sampled outputs (first, last,
+    random) against the oracle's direct sum, the short ones whole."""
+    m = pafc()
+    n = 2 ** 23
+    assert len(m.describe((n,), "c128")["conv_passes"]) == 5
+    rng = np.random.default_rng(9)
+    sizes = [256, n, 4096, 3 ** 9]
+    filters = {k: inputs.complex_uniform(rng, (s,)) for k, s in enumerate(sizes)}
+    xs = [inputs.complex_uniform(rng, (s,)) for s in sizes]
+    B = m.Batch(sizes, [0, 1, 2, 3], 4, torch.complex128)
+    for f, h in filters.items():
+        B.set_filter(f, to_dev(h, torch.complex128))
+    say("batch with a five-pass length", B.describe()["levels"])
+    ys = unpack(to_host(B.convolve(to_dev(pack(xs), torch.complex128))), sizes)
+    B.close()
+    for i in (0, 2, 3):
+        check_close(ys[i], oracle.conv_fft(xs[i], filters[i]), 1e-12, what=str(sizes[i]))
+    idx = rng.integers(0, n, 8)
+    idx[0], idx[1] = 0, n - 1
+    check_close(ys[1][idx], oracle.conv_direct_at(xs[1], filters[1], idx), 1e-12,
+                what="2^23 sampled")

@@ -8,7 +8,7 @@ import pytest
 
 import oracle
 from paper_2506_12718_amd import inputs
-from gpu_util import rel_l2, torch
+from gpu_util import check_close, rel_l2, torch
 
 pytestmark = pytest.mark.gpu
 
@@ -62,22 +62,63 @@ def test_alone_equals_mix():
     assert np.array_equal(outs_alone[target.rid], outs_mix[target.rid])
 
 
+def served_reference(dims, x_seed, sigma):
+    """The oracle's FP64 convolution of the FP32 input the server was given
+    with the unit-sum wrapped Gaussian of width sigma (formed in space)."""
+    x = inputs.serving_input({"dims": dims, "x_seed": x_seed}).astype(np.complex128)
+    h = inputs.wrapped_gaussian(dims, sigma)
+    return oracle.conv_fft(x, h)
+
+
 def test_served_results_match_oracle():
     reqs = make_requests(12, 12)
     outs, _ = serve(reqs, slots=4)
     for r in reqs[:8]:
-        x = inputs.serving_input({"dims": r.dims, "x_seed": r.meta["x_seed"]}).astype(np.complex128)
-        h = inputs.wrapped_gaussian(r.dims, inputs.serving_sigma(r.dims, r.fid))
-        h = h.astype(np.complex64).astype(np.complex128)
-        ref = oracle.conv_fft(x, h)
-        assert rel_l2(outs[r.rid], ref) < 1e-5, r.dims
+        ref = served_reference(r.dims, r.meta["x_seed"], inputs.serving_sigma(r.dims, r.fid))
+        check_close(outs[r.rid], ref, 1e-5, what=str(r.dims))
+
+
+SERVED_GRIDS = ([(s, s) for s in inputs.SERVE_SIDES_2D] +
+                [(s, s, s) for s in inputs.SERVE_SIDES_3D])
+
+
+@pytest.mark.parametrize("dims", SERVED_GRIDS, ids=lambda d: "x".join(map(str, d)))
+def test_every_served_grid_fp32(dims):
+    """Every grid the served workload draws, through the server's own plan
+    path (FP32 plan, Gaussian filter installed as its closed-form spectrum),
+    at the widest and narrowest filter widths of the pool of that grid,
+    against the FP64 oracle element by element; and the plan's device
+    memory stays within what admission charged for it beforehand."""
+    from paper_2506_12718_amd.serve import GpuExecutor, Request
+    ex = GpuExecutor(dtype=torch.complex64, sigma_of=inputs.serving_sigma, slots=1)
+    sig = {f: inputs.serving_sigma(dims, f) for f in range(8)}
+    for fid in (min(sig, key=sig.get), max(sig, key=sig.get)):
+        req = Request(rid=fid, dims=dims, fid=fid, meta={"x_seed": 7000 + fid})
+        say("served grid", dims, "sigma %.3f" % sig[fid])
+        req.x = device_input(req)
+        obj = ex.prepare(req, 0)
+        assert ex.held_bytes(obj) <= ex.plan_bytes(req), (ex.held_bytes(obj), ex.plan_bytes(req))
+        ex.launch(req, obj, 0)
+        torch.cuda.synchronize()
+        y = req.out.cpu().numpy()
+        ex.release_plan(obj)
+        check_close(y, served_reference(dims, req.meta["x_seed"], sig[fid]), 1e-5,
+                    what=str(dims))
 
 
 def test_tight_budget_evicts_and_agrees():
     reqs = make_requests(13, 30, sides2=(64, 128), sides3=(32,))
     outs_free, srv_free = serve(reqs, slots=4)
     reqs2 = make_requests(13, 30, sides2=(64, 128), sides3=(32,))
-    outs_tight, srv_tight = serve(reqs2, slots=4, budget=3 * 128 * 128 * 8 + 4 * 128 * 128 * 8)
+    # room for the largest request with its plan (as charged before
+    # planning) plus one more output: far less than the ~24 plans the mix
+    # uses, so plans are evicted and prepared again
+    from paper_2506_12718_amd.serve import GpuExecutor, Request
+    ex = GpuExecutor(dtype=torch.complex64, slots=1)
+    worst = max(ex.request_bytes(r) + ex.plan_bytes(r) for r in reqs2)
+    budget = worst + max(ex.request_bytes(r) for r in reqs2)
+    outs_tight, srv_tight = serve(reqs2, slots=4, budget=budget)
+    assert not srv_tight.failed
     assert srv_tight.cache.evictions > 0
     for rid in outs_free:
         assert np.array_equal(outs_free[rid], outs_tight[rid])

@@ -162,3 +162,56 @@ def test_latency_stats():
         r.arrival, r.done = float(i), float(i) + 0.001 * (i + 1)
     st = latency_stats(reqs)
     assert st["n"] == 4 and abs(st["p50_ms"] - 2.5) < 1e-9
+
+
+class SizedExecutor(FakeExecutor):
+    """Plans charged at an estimate before planning and at what they really
+    hold afterwards (held_bytes), as the GPU executor does."""
+
+    def plan_bytes(self, req):
+        return 2 * self._n(req) * self.elem
+
+    def held_bytes(self, obj):
+        n = 1
+        for d in obj["key"][0]:
+            n *= d
+        return n * self.elem + 100
+
+
+def test_budget_holds_after_every_step_with_hits():
+    """reserved + cached bytes never exceed the budget: a cache hit is pinned
+    while its admission is decided, so it is not counted as memory that
+    evicting it could free, and hits evict other unused entries when needed.
+    The sequence interleaves a small and a large grid so that hits on the
+    small plan arrive while the large one is in flight."""
+    import random
+    for executor in (FakeExecutor, SizedExecutor):
+        rnd = random.Random(3)
+        ex = executor(polls=4)
+        small, large = (32, 32), (64, 64)
+        n_s, n_l = 32 * 32 * 8, 64 * 64 * 8
+        budget = 2 * n_l + 2 * n_s + n_l // 2
+        s = Server(ex, budget_bytes=budget, slots=3, clock=FakeClock())
+        reqs = [Request(rid=i, dims=rnd.choice([small, large]), fid=rnd.randrange(3))
+                for i in range(200)]
+        for r in reqs:
+            s.submit(r)
+        steps = 0
+        while not s.idle():
+            s.step()
+            steps += 1
+            assert s.reserved + s.cache.bytes <= budget, (steps, s.reserved, s.cache.bytes)
+            assert steps < 100000
+        assert len(s.completed) + len(s.failed) == len(reqs)
+        assert not s.failed
+        assert s.cache.hits > 0 and s.cache.evictions > 0
+        assert s.cache.hits + s.cache.misses == len(reqs)
+
+
+def test_request_that_cannot_fit_alone_fails():
+    ex = FakeExecutor()
+    s = Server(ex, budget_bytes=64 * 64 * 8, slots=2, clock=FakeClock())
+    reqs = [Request(rid=0, dims=(64, 64), fid=0), Request(rid=1, dims=(16, 16), fid=0)]
+    done = run_closed_loop(s, reqs)
+    assert [r.rid for r in s.failed] == [0] and "does not fit" in s.failed[0].error
+    assert [r.rid for r in done] == [1]
