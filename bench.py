@@ -2,23 +2,36 @@
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 
-Default workload: 3-D periodic convolution, 256 x 256 x 256 complex128,
-radix 4 per axis, input iid N(0,1), filter = unit-sum periodic Gaussian of
-width 4 (seeded synthetic data).  A step is one full convolution
-y = x (*) h with the filter spectrum resident on the device and the input
-already in HBM.  Prints ONE JSON line: conv/s, the roofline of the dominant
-kernel (the axis-pass kernel, timed with HIP events on its own stream during
-the timed region), the explicit-permutation comparison variant on the same
-GPU, per-convolution latency percentiles, the error against the FP64 oracle,
-and the oracle itself timed on the host cores.
+Default (``--workload all``): the headline workload -- 3-D periodic
+convolution, 256 x 256 x 256 complex128, radix 4 per axis, input iid N(0,1),
+filter = unit-sum periodic Gaussian of width 4 (seeded synthetic data) -- and,
+in the same JSON line under ``configs``, every other workload of the
+benchmark set measured in the same run:
+
+* the single 4096-point 1-D convolution, radix-2 and radix-4 plans;
+* 256^3 in complex64;
+* 2187 x 2187 radix 3 with a spectral filter;
+* n = 5^9 radix 5, complex128 and complex64;
+* 4096 independent 1-D convolutions of mixed sizes, one hipGraph replay per
+  batch, complex128 and complex64, beside the same problems run one plan at
+  a time;
+* served 2-D/3-D requests with Poisson arrivals (p50/p99 latency), beside the
+  same requests served one at a time.
+
+A step is one full convolution y = x (*) h with the filter spectrum resident
+on the device and the input already in HBM.  For each workload: conv/s, the
+algorithmic HBM bytes of one convolution and their rate against 8 TB/s, the
+dominant launch timed with HIP events, the explicit-permutation variant of
+the same plan, the error against the FP64 oracle (rel-L2 and the largest
+entry error over the RMS of the reference), and the oracle itself timed on
+the host cores (all of them, and one thread).
 """
 from __future__ import annotations
 
 import argparse
-import glob
-import hashlib
 import json
 import os
+import subprocess
 import sys
 import time
 
@@ -27,7 +40,9 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
+HBM_PEAK_GBS = 8000.0     # MI355X HBM3E, 8 TB/s
+LDS_BYTES = 160 * 1024    # LDS of one compute unit
+METRIC = "convolutions/s + HBM GB/s (% roofline), perm-free vs explicit-perm; p99 latency"
 
 
 def load_traffic(workload):
@@ -51,6 +66,41 @@ def pct(a, q):
     return float(np.percentile(np.asarray(a), q))
 
 
+def minimal_passes(dims, elem):
+    """HBM passes of the minimal pass structure: a 1-D transform whose array
+    fits one compute unit's LDS runs in 1 pass; other 1-D lengths and 2-D
+    grids in 3 (forward outer, fused middle, inverse outer); 3-D grids in 5."""
+    n = int(np.prod(dims))
+    if len(dims) == 1:
+        return 1 if n * elem <= LDS_BYTES else 3
+    return 3 if len(dims) == 2 else 5
+
+
+def alg_bytes(dims, elem):
+    """Algorithmic HBM bytes of one convolution: one read and one write of
+    the array per pass of the minimal pass structure, plus one read of the
+    filter spectrum (3, 7 or 11 N elem)."""
+    n = int(np.prod(dims))
+    return (2 * minimal_passes(dims, elem) + 1) * n * elem
+
+
+def errors(got, ref):
+    """rel-L2 error and the largest entry error over the RMS of the reference."""
+    a = np.asarray(got, dtype=np.complex128).ravel()
+    b = np.asarray(ref, dtype=np.complex128).ravel()
+    nb = float(np.linalg.norm(b))
+    d = np.abs(a - b)
+    return float(np.linalg.norm(a - b)) / nb, float(d.max()) / (nb / np.sqrt(b.size))
+
+
+def roofline_obj(nbytes, ms, **extra):
+    ach = nbytes / (ms * 1e-3) / 1e9
+    d = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+         "frac": round(ach / HBM_PEAK_GBS, 4)}
+    d.update(extra)
+    return d
+
+
 # ----------------------------------------------------------------- workloads
 
 def wl_conv3d(dtype_name):
@@ -63,13 +113,18 @@ def wl_conv3d(dtype_name):
                         "dims": [256, 256, 256], "radix": 4, "filter": "gaussian_sigma4"})
 
 
-def wl_conv1d(dtype_name):
+def wl_conv1d(dtype_name, radix=4):
     from paper_2506_12718_amd import inputs
     x, h = inputs.conv1d_4096()
-    return dict(name="conv1d_4096_%s_r4" % dtype_name, x=x, h=h, radix=[4], domain="spatial",
-                rhos=[[4] * 6],
-                config={"workload": "1-D circular convolution n=4096, radix 4, single instance",
-                        "dims": [4096], "radix": 4})
+    t = 12 if radix == 2 else 6
+    return dict(name="conv1d_4096_%s_r%d" % (dtype_name, radix), x=x, h=h, radix=[radix],
+                domain="spatial", rhos=[[radix] * t], oracle="direct",
+                config={"workload": "1-D circular convolution n=4096, radix %d, single instance"
+                                    % radix, "dims": [4096], "radix": radix})
+
+
+def wl_conv1d_r2(dtype_name):
+    return wl_conv1d(dtype_name, radix=2)
 
 
 def wl_conv2d(dtype_name):
@@ -186,172 +241,147 @@ def wl_rader1d(dtype_name):
 
 
 WORKLOADS = {"conv3d": wl_conv3d, "poisson3d": wl_poisson3d, "pfa1d": wl_pfa1d,
-             "bluestein1d": wl_bluestein1d, "rader1d": wl_rader1d, "conv1d": wl_conv1d, "conv2d": wl_conv2d,
+             "bluestein1d": wl_bluestein1d, "rader1d": wl_rader1d, "conv1d": wl_conv1d,
+             "conv1d_r2": wl_conv1d_r2, "conv2d": wl_conv2d,
              "conv1d5": wl_conv1d5, "batched": wl_batched, "serving": wl_serving,
              "aniso2d": wl_aniso2d, "aniso3d": wl_aniso3d}
 
 
-def bench_serving(pafc, torch, wl, tdtype, args):
-    """Warm-up + calibration (closed loop, twice over the first 200 requests),
-    then 2000 requests with Poisson arrivals at 0.7 x the calibrated capacity."""
+# ------------------------------------------------------------- oracle timing
+
+def oracle_reference(wl, tdtype_is_c64):
+    """The FP64 oracle's result for a plain workload (inputs rounded to the
+    plan's precision first), and the function that recomputes it."""
+    import oracle
+    x, h = wl["x"], wl["h"]
+    if tdtype_is_c64:
+        x = x.astype(np.complex64).astype(np.complex128)
+        if h is not None:
+            h = h.astype(np.complex64).astype(np.complex128)
+    if wl.get("oracle") == "direct":
+        def run():
+            return oracle.conv_direct(x, h)
+    elif wl["domain"] == "spatial":
+        def run():
+            return oracle.conv_fft(x, h, wl["rhos"])
+    elif wl["domain"] == "symbol":
+        from oracle import symbols
+        kind, params = wl["symbol"]
+
+        def run():
+            return symbols.apply(x, getattr(symbols, kind)(x.shape, *params))
+    else:
+        def run():
+            return oracle.fft(h * oracle.fft(x, wl["rhos"]), wl["rhos"], inverse=True)
+    return run
+
+
+def time_oracle(run, min_s):
+    """Run the oracle until min_s seconds have passed (at least once)."""
+    runs, t0 = 0, time.perf_counter()
+    ref = None
+    while True:
+        ref = run()
+        runs += 1
+        t = time.perf_counter() - t0
+        if t >= min_s or runs >= 10000:
+            return ref, runs, t
+
+
+def oracle_samples(min_s):
+    """The oracle's bounded samples of every workload of the default run:
+    name -> (prepare, text); prepare() makes the inputs and returns run(),
+    which does the timed oracle work and returns (convolutions, seconds)."""
+    import oracle
     from paper_2506_12718_amd import inputs
-    from paper_2506_12718_amd.serve import (GpuExecutor, Request, Server, latency_stats,
-                                            run_closed_loop, run_open_loop)
-    raw = inputs.serving_requests(seed=5, count=2200)
-    pool = {}
+    out = {}
 
-    def make_input(req):
-        key = (tuple(req.dims), req.meta["x_seed"] % 2)
-        if key not in pool:
-            x = inputs.serving_input({"dims": req.dims, "x_seed": key[1] + 1000 * req.dims[0]},
-                                     dtype=np.complex64 if tdtype == torch.complex64 else np.complex128)
-            pool[key] = torch.from_numpy(x).cuda()
-            torch.cuda.synchronize()
-        return pool[key]
-
-    def reqs(lo, hi):
-        return [Request(rid=r["id"], dims=r["dims"], fid=r["filter"], meta={"x_seed": r["x_seed"]})
-                for r in raw[lo:hi]]
-
-    slots = 4
-    ex = GpuExecutor(dtype=tdtype, sigma_of=inputs.serving_sigma, slots=slots)
-    budget = 64 << 30
-    srv = Server(ex, budget_bytes=budget, slots=slots)
-    print("bench: serving warm-up", file=sys.stderr, flush=True)
-    for r in reqs(0, 200):
-        make_input(r)
-    run_closed_loop(srv, reqs(0, 200), make_input=make_input)
-    srv.completed = []
-    t0 = time.perf_counter()
-    run_closed_loop(srv, reqs(0, 200), make_input=make_input)
-    cap = 200 / (time.perf_counter() - t0)
-    rate = 0.7 * cap
-    srv.completed = []
-    meas = reqs(200, 2200)
-    for r in meas:
-        make_input(r)
-    print("bench: serving 2000 requests at %.1f/s (capacity %.1f/s)" % (rate, cap),
-          file=sys.stderr, flush=True)
-    keep = {r.rid for r in meas[::50]}
-    done = run_open_loop(srv, meas, rate, make_input=make_input)
-    torch.cuda.synchronize()
-    st = latency_stats(done)
-    kept = {r.rid: (r, r.out.cpu().numpy()) for r in done if r.rid in keep}
-    for r in done:
-        r.out = None
-    elems = sum(int(np.prod(r.dims)) for r in done)
-    elem = 8 if tdtype == torch.complex64 else 16
-    out = {
-        "metric": "convolutions/s + HBM GB/s (% roofline), perm-free vs explicit-perm; p99 latency",
-        "value": round(st["throughput_per_s"], 2), "unit": "conv/s", "n_gpus": 1,
-        "steps": len(done), "warmup": 200, "ms_per_step": round(1e3 / st["throughput_per_s"], 5),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32" if tdtype == torch.complex64 else "f64", "data": "synthetic",
-        "config": dict(wl["config"], slots=slots, hbm_budget_bytes=budget),
-        "latency_ms": {"p50": round(st["p50_ms"], 4), "p99": round(st["p99_ms"], 4),
-                       "mean": round(st["mean_ms"], 4)},
-        "offered_rate_per_s": round(rate, 2), "closed_loop_capacity_per_s": round(cap, 2),
-        "max_inflight": srv.max_inflight,
-        "cache": {"plans_prepared": ex.prepared, "hits": srv.cache.hits,
-                  "evictions": srv.cache.evictions, "bytes": srv.cache.bytes},
-        "elements_served": elems,
-        "roofline": None,
-    }
-    if not args.no_cpu:
-        import oracle
-        errs = []
+    def timed(run):
         t0 = time.perf_counter()
-        for rid, (r, y) in sorted(kept.items()):
-            x = make_input(r).cpu().numpy().astype(np.complex128)
-            h = inputs.wrapped_gaussian(r.dims, inputs.serving_sigma(r.dims, r.fid))
-            if tdtype == torch.complex64:
-                h = h.astype(np.complex64)
-            ref = oracle.conv_fft(x, h.astype(np.complex128))
-            errs.append(float(np.linalg.norm(y - ref) / np.linalg.norm(ref)))
-        t_cpu = time.perf_counter() - t0
-        out["rel_l2_vs_fp64_oracle_max_sampled"] = max(errs)
-        out["oracle_checked_requests"] = len(errs)
-        out["cpu_baseline"] = {"value": round(len(errs) / t_cpu, 3), "unit": "conv/s",
-                               "cores": oracle.num_threads(), "kind": "oracle",
-                               "sample": "1 in 50 of the measured requests (%d), FP64 explicit "
-                                         "route; %.2f s" % (len(errs), t_cpu)}
-    print(json.dumps(out), flush=True)
+        k = time_oracle(run, min_s)[1]
+        return k, time.perf_counter() - t0
+
+    for name, fn in (("conv1d_4096_r2", wl_conv1d_r2), ("conv1d_4096_r4", wl_conv1d),
+                     ("conv3d_256", wl_conv3d), ("conv2d_2187_r3", wl_conv2d),
+                     ("conv1d_5p9_r5", wl_conv1d5)):
+        def prep(fn=fn):
+            run = oracle_reference(dict(fn("c128"), oracle=None), False)  # the FFT route
+            return lambda: timed(run)
+        out[name] = (prep, "whole convolutions, standard FFT route with explicit index "
+                           "reversal, FP64")
+
+    def prep_direct():
+        wl = wl_conv1d("c128")
+        return lambda: timed(lambda: oracle.conv_direct(wl["x"], wl["h"]))
+    out["conv1d_4096_direct"] = (prep_direct, "whole convolutions by the direct O(n^2) sum "
+                                              "in long double")
+
+    def prep_batched():
+        psizes, xs, filters = inputs.batched_problems()
+
+        def run():
+            k, t = 0, 0.0
+            while t < min_s and k < len(psizes):
+                t0 = time.perf_counter()
+                oracle.conv_fft(xs[k], filters[psizes[k]])
+                t += time.perf_counter() - t0
+                k += 1
+            return k, t
+        return run
+    out["batched_4096"] = (prep_batched, "the first problems of the 4096 in order, standard "
+                                         "FFT route, FP64")
+
+    def prep_served():
+        raw = inputs.serving_requests(seed=5, count=2200)[200:]
+
+        def run():
+            k, t = 0, 0.0
+            while t < min_s and k < len(raw):
+                r = raw[k]
+                x = inputs.serving_input(r).astype(np.complex128)
+                h = inputs.wrapped_gaussian(r["dims"],
+                                            inputs.serving_sigma(r["dims"], r["filter"]))
+                t0 = time.perf_counter()
+                oracle.conv_fft(x, h)
+                t += time.perf_counter() - t0
+                k += 1
+            return k, t
+        return run
+    out["serving"] = (prep_served, "the first measured requests in order, standard FFT "
+                                   "route, FP64")
+    return out
 
 
-def bench_batched(pafc, torch, wl, tdtype, args):
-    B = pafc.Batch(wl["sizes"], wl["fids"], len(wl["filters"]), tdtype)
-    for f, h in wl["filters"].items():
-        B.set_filter(f, torch.from_numpy(h).to(tdtype).cuda())
-    x = torch.from_numpy(np.concatenate(wl["xs"])).to(tdtype).cuda()
-    y = torch.empty_like(x)
-    for _ in range(args.warmup):
-        B.convolve(x, out=y)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ms_lv, by_lv, ms_rep = B.profile_levels(x, y, reps=args.steps)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    nprob = len(wl["sizes"])
-    value = nprob * args.steps / wall
-    dom = max(range(len(ms_lv)), key=lambda i: ms_lv[i])
-    ach = by_lv[dom] / (ms_lv[dom] * 1e-3) / 1e9
-    alg = sum(by_lv)
-    out = {
-        "metric": "convolutions/s + HBM GB/s (% roofline), perm-free vs explicit-perm; p99 latency",
-        "value": round(value, 1), "unit": "conv/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(wall * 1e3 / args.steps, 5),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64" if tdtype == torch.complex128 else "f32", "data": "synthetic",
-        "config": dict(wl["config"], variant="perm_free", levels=len(ms_lv)),
-        "hbm_gbps_alg": round(alg / (sum(ms_lv) * 1e-3) / 1e9, 1),
-        "alg_bytes_per_batch": alg,
-        "latency_ms": {"p50": round(pct(ms_rep, 50), 5), "p99": round(pct(ms_rep, 99), 5)},
-        "ms_per_level": [round(v, 5) for v in ms_lv],
-        "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
-                     "traffic": load_traffic(wl["name"]),
-                     "kernel": "batch_kernel level %d" % dom, "alg_bytes_per_launch": by_lv[dom],
-                     "avg_launch_ms": round(ms_lv[dom], 5)},
-    }
-    yh = y.cpu().numpy().astype(np.complex128)
-    B.close()
-    if not args.no_cpu:
-        import oracle
-        offs = np.concatenate([[0], np.cumsum(wl["sizes"])])
-        # bounded sample: the first 512 problems in order (about 1/8 of the batch)
-        sample = list(range(512))
-        errs = []
-        t0 = time.perf_counter()
-        for i in sample:
-            xi = wl["xs"][i]
-            hi = wl["filters"][wl["fids"][i]]
-            if tdtype == torch.complex64:
-                xi = xi.astype(np.complex64).astype(np.complex128)
-                hi = hi.astype(np.complex64).astype(np.complex128)
-            ref = oracle.conv_fft(xi, hi)
-            got = yh[offs[i]:offs[i + 1]]
-            errs.append(float(np.linalg.norm(got - ref) / np.linalg.norm(ref)))
-        t_cpu = time.perf_counter() - t0
-        out["rel_l2_vs_fp64_oracle_max_sampled"] = max(errs)
-        out["cpu_baseline"] = {
-            "value": round(len(sample) / t_cpu, 3), "unit": "conv/s",
-            "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": "the first %d of the 4096 problems (%d elements), FP64 explicit route; "
-                      "%.2f s" % (len(sample), int(sum(wl["sizes"][:len(sample)])), t_cpu)}
-    print(json.dumps(out), flush=True)
+def oracle_worker(min_s):
+    """Time every sample with the threads this process was started with and
+    print one JSON line (the bench runs this at one thread, in a process of
+    its own, while the GPU is measured)."""
+    import oracle
+    res = {}
+    for name, (prep, text) in oracle_samples(min_s).items():
+        k, t = prep()()
+        res[name] = {"value": round(k / t, 6), "unit": "conv/s",
+                     "cores": oracle.num_threads(), "sample": "%d %s; %.2f s" % (k, text, t)}
+    print(json.dumps(res), flush=True)
 
 
-def conv_bytes(desc, filter_per_call):
-    """Algorithmic HBM bytes of one convolution; with the filter transformed
-    in the call, its forward passes (and, for the explicit variant, its
-    reversal) count too."""
-    b = desc["hbm_bytes_conv"]
-    if filter_per_call:
-        b += desc["hbm_bytes_forward"]
-        if desc.get("variant") == 1:  # explicit: the filter's reversal pass
-            b += 2 * desc["N"] * (16 if desc["dtype"] == "c128" else 8)
-    return b
+def start_one_thread_oracle(min_s):
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    return subprocess.Popen([sys.executable, os.path.abspath(__file__), "--oracle-worker",
+                             "--oracle-min-s", str(min_s)], env=env, stdout=subprocess.PIPE,
+                            stderr=subprocess.DEVNULL, text=True)
 
+
+def collect_one_thread_oracle(proc):
+    try:
+        out, _ = proc.communicate(timeout=300)
+        return json.loads(out.strip().splitlines()[-1])
+    except Exception as e:  # reported, never fatal for the GPU figures
+        proc.kill()
+        return {"error": str(e)}
+
+
+# ------------------------------------------------------------ plain workloads
 
 def measure(pafc, torch, wl, tdtype, variant, steps, warmup, filter_per_call=False):
     """Plan, set the filter, warm up (with a HIP event around every launch,
@@ -423,12 +453,514 @@ def measure(pafc, torch, wl, tdtype, variant, steps, warmup, filter_per_call=Fal
                 labels=desc["conv_passes"], dom=dom, dom_ms=dom_ms)
 
 
+def conv_bytes(desc, filter_per_call):
+    """HBM bytes the plan moves in one convolution; with the filter
+    transformed in the call, its forward passes (and, for the explicit
+    variant, its reversal) count too."""
+    b = desc["hbm_bytes_conv"]
+    if filter_per_call:
+        b += desc["hbm_bytes_forward"]
+        if desc.get("variant") == 1:  # explicit: the filter's reversal pass
+            b += 2 * desc["N"] * (16 if desc["dtype"] == "c128" else 8)
+    return b
+
+
+def bench_plain(pafc, torch, wl, tdtype, args, cpu_min_s=10.0, steps=None):
+    """One plain workload: the JSON object of its measurement."""
+    steps = steps or args.steps
+    dname = "c128" if tdtype == torch.complex128 else "c64"
+    elem = 16 if dname == "c128" else 8
+    N = wl["x"].size
+    print("bench: %s steps=%d warmup=%d" % (wl["name"], steps, args.warmup),
+          file=sys.stderr, flush=True)
+    fpc = args.filter_per_call
+    main_variant = wl.get("variant", "perm_free")
+    main_r = measure(pafc, torch, wl, tdtype, main_variant, steps, args.warmup, fpc)
+    total_s = sum(main_r["ms_rep"]) / 1e3
+    value = steps / main_r["wall"]
+    ms_step = main_r["wall"] * 1e3 / steps
+
+    # dominant kernel: the single most expensive launch of a convolution (for
+    # multi-pass plans the fused middle pass, which also reads the spectrum),
+    # its mean duration from the events of the timed region
+    dom = main_r["dom"]
+    dom_ms = main_r["dom_ms"]
+    dom_bytes = main_r["bytes_pass"][dom]
+    kern = [i for i, l in enumerate(main_r["labels"]) if not l.startswith(("mul", "permute"))]
+    all_ms = sum(main_r["ms_pass"][i] for i in kern)
+    all_bytes = sum(main_r["bytes_pass"][i] for i in kern)
+    roof = roofline_obj(dom_bytes, dom_ms, traffic=load_traffic(wl["name"]),
+                        kernel=main_r["labels"][dom], alg_bytes_per_launch=dom_bytes,
+                        avg_launch_ms=round(dom_ms, 5),
+                        all_passes={"source": "per-launch breakdown run after the timed region",
+                                    "launches": len(kern), "alg_bytes": all_bytes,
+                                    "ms": round(all_ms, 5),
+                                    "achieved": round(all_bytes / (all_ms * 1e-3) / 1e9, 1)})
+    plan_bytes = conv_bytes(main_r["desc"], fpc)
+    minimal = alg_bytes(wl["x"].shape, elem) if wl.get("variant") is None else plan_bytes
+    if fpc:
+        minimal = plan_bytes
+    out = {
+        "metric": METRIC, "value": round(value, 3), "unit": "conv/s", "n_gpus": 1,
+        "steps": steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if dname == "c128" else "f32", "data": "synthetic",
+        "config": dict(wl["config"], variant=main_variant, dtype=dname,
+                       passes=main_r["labels"], filter_per_call=fpc),
+        "alg_bytes_per_conv": minimal,
+        "hbm_gbps_alg": round(minimal * value / 1e9, 1),
+        "hbm_frac_alg": round(minimal * value / 1e9 / HBM_PEAK_GBS, 4),
+        "plan_bytes_per_conv": plan_bytes,
+        "latency_ms": {"p50": round(pct(main_r["ms_rep"], 50), 5),
+                       "p99": round(pct(main_r["ms_rep"], 99), 5),
+                       "mean": round(total_s * 1e3 / steps, 5)},
+        "ms_per_pass": [round(v, 5) for v in main_r["ms_pass"]],
+        "roofline": roof,
+    }
+    if not args.no_compare:
+        comp = {}
+        compare = wl.get("compare", ["explicit_perm", "perm_free_unfused"])
+        for variant in compare:
+            print("bench: comparison variant %s" % variant, file=sys.stderr, flush=True)
+            r = measure(pafc, torch, wl, tdtype, variant, max(5, steps // 2), 2, fpc)
+            v = len(r["ms_rep"]) / r["wall"]
+            comp[variant] = {
+                "conv_per_s": round(v, 3),
+                "ms_per_conv": round(1e3 / v, 5),
+                "p99_ms": round(pct(r["ms_rep"], 99), 5),
+                "plan_bytes_per_conv": conv_bytes(r["desc"], fpc),
+                "hbm_gbps_plan_bytes": round(conv_bytes(r["desc"], fpc) * v / 1e9, 1),
+                "ms_per_pass": [round(t, 5) for t in r["ms_pass"]],
+                "passes": r["labels"],
+                "max_abs_diff_vs_perm_free": float(np.abs(r["y"] - main_r["y"]).max()),
+            }
+        comp["speedup_perm_free_over_explicit"] = round(
+            value / comp[compare[0]]["conv_per_s"], 3)
+        out["compare"] = comp
+    if not args.no_cpu:
+        import oracle
+        print("bench: oracle on host cores", file=sys.stderr, flush=True)
+        x, h = wl["x"], wl["h"]
+        if dname == "c64":
+            x = x.astype(np.complex64).astype(np.complex128)
+            if h is not None:
+                h = h.astype(np.complex64).astype(np.complex128)
+        if wl.get("oracle") == "direct_sampled":
+            # the oracle's FFT has no route for a prime length: the direct
+            # sum at a bounded sample of outputs, scaled to whole convolutions
+            t0 = time.perf_counter()
+            idx = np.random.default_rng(46).integers(0, N, 81920)
+            ref = oracle.conv_direct_at(x, h, idx)
+            t_cpu = time.perf_counter() - t0
+            e2, emax = errors(main_r["y"].reshape(-1)[idx], ref)
+            out["rel_l2_vs_fp64_oracle_sampled"] = e2
+            out["max_entry_err_over_rms_sampled"] = emax
+            out["cpu_baseline"] = {
+                "value": round(idx.size / N / t_cpu, 8), "unit": "conv/s",
+                "cores": oracle.num_threads(), "kind": "oracle",
+                "sample": "%d of the %d outputs by the direct sum (long double, OpenMP over "
+                          "outputs), scaled to one convolution; %.2f s" % (idx.size, N, t_cpu)}
+            return out, main_r["y"]
+        # whole convolutions of the same workload, repeated until cpu_min_s
+        # of host time have passed
+        ref, runs, t_cpu = time_oracle(oracle_reference(wl, dname == "c64"), cpu_min_s)
+        e2, emax = errors(main_r["y"], ref)
+        out["rel_l2_vs_fp64_oracle"] = e2
+        out["max_entry_err_over_rms"] = emax
+        route = ("direct O(n^2) sum in long double" if wl.get("oracle") == "direct" else
+                 "standard FFT route with explicit index reversal, FP64, OpenMP over pencils")
+        out["cpu_baseline"] = {
+            "value": round(runs / t_cpu, 5), "unit": "conv/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": "%d full convolution(s) of the same workload (%s); %.2f s"
+                      % (runs, route, t_cpu)}
+    return out, main_r["y"]
+
+
+# -------------------------------------------------------------------- batched
+
+def graph_of(torch, fn):
+    """Capture fn(stream) in a CUDA/HIP graph on a side stream."""
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        fn(s)  # warm-up outside the graph
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g, stream=s):
+            fn(s)
+    torch.cuda.synchronize()
+    return g
+
+
+def batch_alg_bytes(sizes, filters, elem):
+    """Algorithmic bytes of one batch: per problem one read and one write per
+    pass of its minimal pass structure, plus one read of each size class's
+    spectrum."""
+    b = sum(2 * minimal_passes((n,), elem) * n * elem for n in sizes)
+    return b + sum(int(np.asarray(h).size) * elem for h in filters.values())
+
+
+def bench_batched(pafc, torch, wl, tdtype, args, cpu_min_s=10.0):
+    """The batch timed as one graph replay per batch (conv/s = problems /
+    median replay), the per-launch breakdown from an eager run, and the same
+    problems run one plan at a time (the plain form)."""
+    elem = 16 if tdtype == torch.complex128 else 8
+    B = pafc.Batch(wl["sizes"], wl["fids"], len(wl["filters"]), tdtype)
+    for f, h in wl["filters"].items():
+        B.set_filter(f, torch.from_numpy(h).to(tdtype).cuda())
+    x = torch.from_numpy(np.concatenate(wl["xs"])).to(tdtype).cuda()
+    y = torch.empty_like(x)
+    nprob = len(wl["sizes"])
+    g = graph_of(torch, lambda s: B.convolve(x, out=y, stream=s))
+    for _ in range(args.warmup):
+        g.replay()
+    torch.cuda.synchronize()
+    steps = args.steps
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    t0 = time.perf_counter()
+    ev[0].record()
+    for k in range(steps):
+        g.replay()
+        ev[k + 1].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_rep = [ev[k].elapsed_time(ev[k + 1]) for k in range(steps)]
+    med = pct(ms_rep, 50)
+    value = nprob / (med * 1e-3)
+    # per-launch breakdown (eager, an event around every launch)
+    ms_lv, by_lv, _ = B.profile_levels(x, y, reps=max(5, steps // 2))
+    dom = max(range(len(ms_lv)), key=lambda i: ms_lv[i])
+    alg = batch_alg_bytes(wl["sizes"], wl["filters"], elem)
+    desc = B.describe()
+    out = {
+        "metric": METRIC, "value": round(value, 1), "unit": "conv/s", "n_gpus": 1,
+        "steps": steps, "warmup": args.warmup, "ms_per_step": round(med, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if elem == 16 else "f32", "data": "synthetic",
+        "config": dict(wl["config"], variant="perm_free", launches=len(ms_lv),
+                       timing="one graph replay per batch (median)"),
+        "alg_bytes_per_batch": alg,
+        "hbm_gbps_alg": round(alg / (med * 1e-3) / 1e9, 1),
+        "hbm_frac_alg": round(alg / (med * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "wall_conv_per_s": round(nprob * steps / wall, 1),
+        "latency_ms": {"p50": round(med, 5), "p99": round(pct(ms_rep, 99), 5)},
+        "ms_per_launch": [round(v, 5) for v in ms_lv],
+        "roofline": roofline_obj(by_lv[dom], ms_lv[dom], traffic=load_traffic(wl["name"]),
+                                 kernel="batched launch %d of %d" % (dom, len(ms_lv)),
+                                 alg_bytes_per_launch=by_lv[dom],
+                                 avg_launch_ms=round(ms_lv[dom], 5)),
+        "launch_desc": desc.get("levels"),
+    }
+    yh = y.cpu().numpy().astype(np.complex128)
+    B.close()
+    del x, y, g
+    torch.cuda.empty_cache()
+    if not args.no_compare:
+        out["plain"] = bench_batched_plain(pafc, torch, wl, tdtype, yh)
+        out["plain"]["speedup_batched_over_plain"] = round(
+            value / out["plain"]["conv_per_s"], 3)
+    if not args.no_cpu:
+        batched_oracle(out, wl, yh, elem, cpu_min_s)
+    return out, yh
+
+
+def batched_oracle(out, wl, yh, elem, cpu_min_s):
+    """Check the first problems in order against the FP64 oracle (inputs
+    rounded to the plan's precision) until cpu_min_s of host time have
+    passed, and report that rate as the CPU baseline."""
+    import oracle
+    nprob = len(wl["sizes"])
+    offs = np.concatenate([[0], np.cumsum(wl["sizes"])])
+    errs, emaxs = [], []
+    k = 0
+    t0 = time.perf_counter()
+    while True:
+        xi = wl["xs"][k]
+        hi = wl["filters"][wl["fids"][k]]
+        if elem == 8:
+            xi = xi.astype(np.complex64).astype(np.complex128)
+            hi = hi.astype(np.complex64).astype(np.complex128)
+        ref = oracle.conv_fft(xi, hi)
+        e2, em = errors(yh[offs[k]:offs[k + 1]], ref)
+        errs.append(e2)
+        emaxs.append(em)
+        k += 1
+        if time.perf_counter() - t0 >= cpu_min_s or k == nprob:
+            break
+    t_cpu = time.perf_counter() - t0
+    out["rel_l2_vs_fp64_oracle_max_sampled"] = max(errs)
+    out["max_entry_err_over_rms_sampled"] = max(emaxs)
+    out["cpu_baseline"] = {
+        "value": round(k / t_cpu, 3), "unit": "conv/s",
+        "cores": oracle.num_threads(), "kind": "oracle",
+        "sample": "the first %d of the 4096 problems (%d elements), FP64 standard route; "
+                  "%.2f s" % (k, int(sum(wl["sizes"][:k])), t_cpu)}
+
+
+def bench_batched_plain(pafc, torch, wl, tdtype, y_batched):
+    """The same problems, one pafc_convolve per problem on one plan per size
+    class (views into the packed arrays), timed by wall clock over the
+    stream."""
+    sizes = wl["sizes"]
+    plans = {}
+    for f, h in wl["filters"].items():
+        n = int(np.asarray(h).size)
+        p = pafc.Plan((n,), tdtype)
+        p.set_filter(torch.from_numpy(h).to(tdtype).cuda())
+        plans[f] = p
+    x = torch.from_numpy(np.concatenate(wl["xs"])).to(tdtype).cuda()
+    y = torch.empty_like(x)
+    offs = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    views = [(plans[wl["fids"][i]], x[offs[i]:offs[i + 1]], y[offs[i]:offs[i + 1]])
+             for i in range(len(sizes))]
+
+    def run():
+        for p, xi, yi in views:
+            p.convolve(xi, out=yi)
+    run()
+    torch.cuda.synchronize()
+    reps = 3
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        run()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / reps
+    yh = y.cpu().numpy().astype(np.complex128)
+    for p in plans.values():
+        p.close()
+    del x, y, views
+    torch.cuda.empty_cache()
+    return {"conv_per_s": round(len(sizes) / wall, 1), "ms_per_batch": round(wall * 1e3, 4),
+            "form": "one pafc_convolve per problem, one plan per size class",
+            "max_abs_diff_vs_batched": float(np.abs(yh - y_batched).max())}
+
+
+# -------------------------------------------------------------------- serving
+
+def bench_serving(pafc, torch, wl, tdtype, args):
+    """Warm-up + calibration (closed loop, twice over the first 200 requests),
+    then 2000 requests with Poisson arrivals at 0.7 x the calibrated capacity;
+    the plain form serves the calibration requests one at a time."""
+    from paper_2506_12718_amd import inputs
+    from paper_2506_12718_amd.serve import (GpuExecutor, Request, Server, latency_stats,
+                                            run_closed_loop, run_open_loop)
+    raw = inputs.serving_requests(seed=5, count=2200)
+    pool = {}
+
+    def make_input(req):
+        key = (tuple(req.dims), req.meta["x_seed"] % 2)
+        if key not in pool:
+            x = inputs.serving_input({"dims": req.dims, "x_seed": key[1] + 1000 * req.dims[0]},
+                                     dtype=np.complex64 if tdtype == torch.complex64 else np.complex128)
+            pool[key] = torch.from_numpy(x).cuda()
+            torch.cuda.synchronize()
+        return pool[key]
+
+    def reqs(lo, hi):
+        return [Request(rid=r["id"], dims=r["dims"], fid=r["filter"], meta={"x_seed": r["x_seed"]})
+                for r in raw[lo:hi]]
+
+    slots = 4
+    ex = GpuExecutor(dtype=tdtype, sigma_of=inputs.serving_sigma, slots=slots)
+    budget = 64 << 30
+    srv = Server(ex, budget_bytes=budget, slots=slots)
+    print("bench: serving warm-up", file=sys.stderr, flush=True)
+    for r in reqs(0, 200):
+        make_input(r)
+    run_closed_loop(srv, reqs(0, 200), make_input=make_input)
+    srv.completed = []
+    t0 = time.perf_counter()
+    run_closed_loop(srv, reqs(0, 200), make_input=make_input)
+    cap = 200 / (time.perf_counter() - t0)
+    rate = 0.7 * cap
+    srv.completed = []
+    # the plain form: the same 200 requests served one at a time (one slot,
+    # plans already cached)
+    one = Server(ex, budget_bytes=budget, slots=1)
+    one.cache = srv.cache
+    t0 = time.perf_counter()
+    run_closed_loop(one, reqs(0, 200), make_input=make_input)
+    plain = 200 / (time.perf_counter() - t0)
+    meas = reqs(200, 2200)
+    for r in meas:
+        make_input(r)
+    print("bench: serving 2000 requests at %.1f/s (capacity %.1f/s)" % (rate, cap),
+          file=sys.stderr, flush=True)
+    keep = {r.rid for r in meas[::50]}
+    done = run_open_loop(srv, meas, rate, make_input=make_input)
+    torch.cuda.synchronize()
+    st = latency_stats(done)
+    kept = {r.rid: (r, r.out.cpu().numpy()) for r in done if r.rid in keep}
+    for r in done:
+        r.out = None
+    elems = sum(int(np.prod(r.dims)) for r in done)
+    elem = 8 if tdtype == torch.complex64 else 16
+    abytes = sum(alg_bytes(r.dims, elem) for r in done)
+    span = st["n"] / st["throughput_per_s"]
+    out = {
+        "metric": METRIC,
+        "value": round(st["throughput_per_s"], 2), "unit": "conv/s", "n_gpus": 1,
+        "steps": len(done), "warmup": 200, "ms_per_step": round(1e3 / st["throughput_per_s"], 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if tdtype == torch.complex64 else "f64", "data": "synthetic",
+        "config": dict(wl["config"], slots=slots, hbm_budget_bytes=budget),
+        "latency_ms": {"p50": round(st["p50_ms"], 4), "p99": round(st["p99_ms"], 4),
+                       "mean": round(st["mean_ms"], 4)},
+        "offered_rate_per_s": round(rate, 2), "closed_loop_capacity_per_s": round(cap, 2),
+        "plain_one_at_a_time_per_s": round(plain, 2),
+        "speedup_served_over_plain": round(cap / plain, 3),
+        "max_inflight": srv.max_inflight,
+        "cache": {"plans_prepared": ex.prepared, "hits": srv.cache.hits,
+                  "evictions": srv.cache.evictions, "bytes": srv.cache.bytes},
+        "elements_served": elems,
+        "alg_bytes_served": abytes,
+        "hbm_gbps_alg_at_offered_rate": round(abytes / span / 1e9, 1),
+        "roofline": None,
+    }
+    checked = [(r.dims, r.fid, make_input(r).cpu().numpy(), y)
+               for rid, (r, y) in sorted(kept.items())]
+    pool.clear()
+    torch.cuda.empty_cache()
+    if not args.no_cpu:
+        serving_oracle(out, checked)
+    return out, checked
+
+
+def serving_oracle(out, checked):
+    """Check the kept requests (1 in 50) against the FP64 oracle: the served
+    input with the unit-sum wrapped Gaussian formed in space."""
+    import oracle
+    from paper_2506_12718_amd import inputs
+    errs, emaxs = [], []
+    t0 = time.perf_counter()
+    for dims, fid, x, y in checked:
+        h = inputs.wrapped_gaussian(dims, inputs.serving_sigma(dims, fid))
+        ref = oracle.conv_fft(x.astype(np.complex128), h)
+        e2, em = errors(y, ref)
+        errs.append(e2)
+        emaxs.append(em)
+    t_cpu = time.perf_counter() - t0
+    out["rel_l2_vs_fp64_oracle_max_sampled"] = max(errs)
+    out["max_entry_err_over_rms_sampled"] = max(emaxs)
+    out["oracle_checked_requests"] = len(errs)
+    out["cpu_baseline"] = {"value": round(len(errs) / t_cpu, 3), "unit": "conv/s",
+                           "cores": oracle.num_threads(), "kind": "oracle",
+                           "sample": "1 in 50 of the measured requests (%d), FP64 standard "
+                                     "route; %.2f s" % (len(errs), t_cpu)}
+
+
+# ----------------------------------------------------------------------- main
+
+def brief(o):
+    """The compact form of one workload's measurement under `configs`."""
+    keys = ("value", "unit", "dtype", "ms_per_step", "latency_ms", "alg_bytes_per_conv",
+            "alg_bytes_per_batch", "plan_bytes_per_conv", "hbm_gbps_alg", "hbm_frac_alg",
+            "rel_l2_vs_fp64_oracle", "max_entry_err_over_rms",
+            "rel_l2_vs_fp64_oracle_max_sampled", "max_entry_err_over_rms_sampled",
+            "cpu_baseline", "offered_rate_per_s", "closed_loop_capacity_per_s",
+            "plain_one_at_a_time_per_s", "speedup_served_over_plain", "max_inflight",
+            "hbm_gbps_alg_at_offered_rate", "wall_conv_per_s", "plain")
+    d = {k: o[k] for k in keys if k in o}
+    d["workload"] = o["config"]["workload"]
+    if o.get("roofline"):
+        r = o["roofline"]
+        d["roofline_dominant_launch"] = {k: r[k] for k in ("achieved", "frac", "kernel",
+                                                           "avg_launch_ms", "traffic")
+                                         if k in r}
+    if "compare" in o:
+        c = o["compare"]
+        d["explicit_perm_conv_per_s"] = c.get("explicit_perm", {}).get("conv_per_s")
+        d["speedup_perm_free_over_explicit"] = c.get("speedup_perm_free_over_explicit")
+        if "perm_free_unfused" in c:
+            d["unfused_conv_per_s"] = c["perm_free_unfused"]["conv_per_s"]
+    return d
+
+
+def run_all(pafc, torch, args):
+    """The headline workload with every other workload of the set under
+    `configs`; the one-thread oracle runs in a process of its own meanwhile,
+    and the all-core oracle timings run after it has finished."""
+    worker = None if args.no_cpu else start_one_thread_oracle(0.5 * args.oracle_min_s)
+    gpu_args = argparse.Namespace(**dict(vars(args), no_cpu=True))
+    results = {}
+    head, y_head = bench_plain(pafc, torch, wl_conv3d("c128"), torch.complex128, gpu_args)
+    plain_runs = [("conv1d_4096_c128_r2", wl_conv1d_r2, torch.complex128, 200),
+                  ("conv1d_4096_c128_r4", wl_conv1d, torch.complex128, 200),
+                  ("conv3d_256_c64_r4", wl_conv3d, torch.complex64, None),
+                  ("conv2d_2187_c128_r3", wl_conv2d, torch.complex128, None),
+                  ("conv1d_5p9_c128_r5", wl_conv1d5, torch.complex128, None),
+                  ("conv1d_5p9_c64_r5", wl_conv1d5, torch.complex64, None)]
+    ys = {}
+    for name, fn, dt, steps in plain_runs:
+        wl = fn("c128" if dt == torch.complex128 else "c64")
+        results[name], ys[name] = bench_plain(pafc, torch, wl, dt, gpu_args, steps=steps)
+    kept = {}
+    for dname, dt in (("c128", torch.complex128), ("c64", torch.complex64)):
+        print("bench: batched %s" % dname, file=sys.stderr, flush=True)
+        wl = wl_batched(dname)
+        results["batched_4096_%s" % dname], yb = bench_batched(
+            pafc, torch, wl, dt, argparse.Namespace(**dict(vars(gpu_args), steps=10)))
+        kept["batched_4096_%s" % dname] = (wl, yb)
+    print("bench: serving c64", file=sys.stderr, flush=True)
+    results["serving_c64"], kept["serving_c64"] = bench_serving(
+        pafc, torch, wl_serving("c64"), torch.complex64, gpu_args)
+    if not args.no_cpu:
+        import oracle
+        print("bench: waiting for the one-thread oracle", file=sys.stderr, flush=True)
+        one = collect_one_thread_oracle(worker)
+        print("bench: oracle on all host cores", file=sys.stderr, flush=True)
+        cores = oracle.num_threads()
+        # headline: whole FP64 convolutions of the same workload
+        wl = wl_conv3d("c128")
+        ref, runs, t = time_oracle(oracle_reference(wl, False), args.oracle_min_s)
+        e2, em = errors(y_head, ref)
+        head["rel_l2_vs_fp64_oracle"] = e2
+        head["max_entry_err_over_rms"] = em
+        head["cpu_baseline"] = {
+            "value": round(runs / t, 5), "unit": "conv/s", "cores": cores, "kind": "oracle",
+            "sample": "%d full convolution(s) of the same workload (standard FFT route with "
+                      "explicit index reversal, FP64, OpenMP over pencils); %.2f s" % (runs, t),
+            "one_thread": one.get("conv3d_256")}
+        del ref
+        for name, fn, dt, steps in plain_runs:
+            wl = fn("c128" if dt == torch.complex128 else "c64")
+            ref, runs, t = time_oracle(oracle_reference(wl, dt == torch.complex64),
+                                       0.25 * args.oracle_min_s)
+            e2, em = errors(ys[name], ref)
+            results[name]["rel_l2_vs_fp64_oracle"] = e2
+            results[name]["max_entry_err_over_rms"] = em
+            key = {"conv1d_4096_c128_r2": "conv1d_4096_r2", "conv1d_4096_c128_r4": "conv1d_4096_r4",
+                   "conv3d_256_c64_r4": "conv3d_256", "conv2d_2187_c128_r3": "conv2d_2187_r3",
+                   "conv1d_5p9_c128_r5": "conv1d_5p9_r5",
+                   "conv1d_5p9_c64_r5": "conv1d_5p9_r5"}[name]
+            route = ("direct O(n^2) sum in long double" if wl.get("oracle") == "direct" else
+                     "standard FFT route with explicit index reversal, FP64")
+            results[name]["cpu_baseline"] = {
+                "value": round(runs / t, 5), "unit": "conv/s", "cores": cores, "kind": "oracle",
+                "sample": "%d full convolution(s) (%s); %.2f s" % (runs, route, t),
+                "one_thread": one.get(key)}
+            if name == "conv1d_4096_c128_r4":
+                results[name]["cpu_baseline"]["one_thread_direct"] = one.get("conv1d_4096_direct")
+            del ref
+        for name in ("batched_4096_c128", "batched_4096_c64"):
+            wl, yb = kept.pop(name)
+            batched_oracle(results[name], wl, yb, 16 if name.endswith("c128") else 8,
+                           0.25 * args.oracle_min_s)
+            results[name]["cpu_baseline"]["one_thread"] = one.get("batched_4096")
+            del wl, yb
+        serving_oracle(results["serving_c64"], kept.pop("serving_c64"))
+        results["serving_c64"]["cpu_baseline"]["one_thread"] = one.get("serving")
+    head["configs"] = {k: brief(v) for k, v in results.items()}
+    return head
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="conv3d", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="all", choices=["all"] + sorted(WORKLOADS))
     ap.add_argument("--dtype", default="c128", choices=["c128", "c64"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing and error check")
     ap.add_argument("--no-compare", action="store_true", help="skip the comparison variants")
@@ -437,8 +969,14 @@ def main():
                          "convolution, as the paper times it)")
     ap.add_argument("--calibrate", action="store_true",
                     help="run only the plain streaming copy of 256 MiB (counter calibration)")
+    ap.add_argument("--oracle-min-s", type=float, default=8.0,
+                    help="host seconds of oracle work per timed sample")
+    ap.add_argument("--oracle-worker", action="store_true", help=argparse.SUPPRESS)
     args = ap.parse_args()
 
+    if args.oracle_worker:
+        oracle_worker(args.oracle_min_s)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the library has no multi-GPU path "
               "(each convolution runs on a single MI355X); run with --gpus 1", file=sys.stderr)
@@ -462,145 +1000,24 @@ def main():
         print(json.dumps({"calibration_copy_bytes": nbytes, "ms": dt * 1e3,
                           "GBps_read_plus_write": 2 * nbytes / dt / 1e9}))
         return
+    if args.workload == "all":
+        if args.filter_per_call:
+            print("--filter-per-call needs a single --workload", file=sys.stderr)
+            sys.exit(2)
+        out = run_all(pafc, torch, args)
+        print(json.dumps(out), flush=True)
+        return
     tdtype = torch.complex128 if args.dtype == "c128" else torch.complex64
     wl = WORKLOADS[args.workload](args.dtype)
     if args.workload == "batched":
-        print("bench: %s steps=%d warmup=%d" % (wl["name"], args.steps, args.warmup),
-              file=sys.stderr, flush=True)
-        bench_batched(pafc, torch, wl, tdtype, args)
-        return
-    if args.workload == "serving":
-        bench_serving(pafc, torch, wl, tdtype, args)
-        return
-    N = wl["x"].size
-    elem = 16 if args.dtype == "c128" else 8
-
-    print("bench: %s steps=%d warmup=%d" % (wl["name"], args.steps, args.warmup),
-          file=sys.stderr, flush=True)
-    fpc = args.filter_per_call
-    if fpc and wl["domain"] != "spatial":
-        print("--filter-per-call needs a workload with a spatial filter", file=sys.stderr)
-        sys.exit(2)
-    main_variant = wl.get("variant", "perm_free")
-    main_r = measure(pafc, torch, wl, tdtype, main_variant, args.steps, args.warmup, fpc)
-    total_s = sum(main_r["ms_rep"]) / 1e3
-    value = args.steps / main_r["wall"]
-    ms_step = main_r["wall"] * 1e3 / args.steps
-
-    # dominant kernel: the single most expensive launch of a convolution (for
-    # multi-pass plans the fused middle pass, which also reads the spectrum),
-    # its mean duration from the events of the timed region
-    dom = main_r["dom"]
-    dom_ms = main_r["dom_ms"]
-    dom_bytes = main_r["bytes_pass"][dom]
-    achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
-    traffic = load_traffic(wl["name"])
-    kern = [i for i, l in enumerate(main_r["labels"]) if not l.startswith(("mul", "permute"))]
-    all_ms = sum(main_r["ms_pass"][i] for i in kern)
-    all_bytes = sum(main_r["bytes_pass"][i] for i in kern)
-    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "kernel": main_r["labels"][dom], "alg_bytes_per_launch": dom_bytes,
-            "avg_launch_ms": round(dom_ms, 5),
-            "all_passes": {"source": "per-launch breakdown run after the timed region",
-                           "launches": len(kern), "alg_bytes": all_bytes,
-                           "ms": round(all_ms, 5),
-                           "achieved": round(all_bytes / (all_ms * 1e-3) / 1e9, 1)}}
-    alg_bytes = conv_bytes(main_r["desc"], fpc)
-    out = {
-        "metric": "convolutions/s + HBM GB/s (% roofline), perm-free vs explicit-perm; p99 latency",
-        "value": round(value, 3),
-        "unit": "conv/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms_step, 5),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64" if args.dtype == "c128" else "f32",
-        "data": "synthetic",
-        "config": dict(wl["config"], variant=main_variant, dtype=args.dtype,
-                       passes=main_r["labels"], filter_per_call=fpc),
-        "hbm_gbps_alg": round(alg_bytes * value / 1e9, 1),
-        "hbm_frac_alg": round(alg_bytes * value / 1e9 / HBM_PEAK_GBS, 4),
-        "alg_bytes_per_conv": alg_bytes,
-        "latency_ms": {"p50": round(pct(main_r["ms_rep"], 50), 5),
-                       "p99": round(pct(main_r["ms_rep"], 99), 5),
-                       "mean": round(total_s * 1e3 / args.steps, 5)},
-        "ms_per_pass": [round(v, 5) for v in main_r["ms_pass"]],
-        "roofline": roof,
-    }
-    if not args.no_compare:
-        comp = {}
-        compare = wl.get("compare", ["explicit_perm", "perm_free_unfused"])
-        for variant in compare:
-            print("bench: comparison variant %s" % variant, file=sys.stderr, flush=True)
-            r = measure(pafc, torch, wl, tdtype, variant, max(5, args.steps // 2), 2, fpc)
-            v = len(r["ms_rep"]) / r["wall"]
-            comp[variant] = {
-                "conv_per_s": round(v, 3),
-                "ms_per_conv": round(1e3 / v, 5),
-                "p99_ms": round(pct(r["ms_rep"], 99), 5),
-                "alg_bytes_per_conv": conv_bytes(r["desc"], fpc),
-                "hbm_gbps_alg": round(conv_bytes(r["desc"], fpc) * v / 1e9, 1),
-                "ms_per_pass": [round(t, 5) for t in r["ms_pass"]],
-                "passes": r["labels"],
-                "max_abs_diff_vs_perm_free": float(np.abs(r["y"] - main_r["y"]).max()),
-            }
-        comp["speedup_perm_free_over_explicit"] = round(
-            value / comp[compare[0]]["conv_per_s"], 3)
-        out["compare"] = comp
-    if not args.no_cpu:
-        import oracle
-        print("bench: oracle on host cores", file=sys.stderr, flush=True)
-        x = wl["x"]
-        h = wl["h"]
-        if args.dtype == "c64":
-            x = x.astype(np.complex64).astype(np.complex128)
-            if h is not None:
-                h = h.astype(np.complex64).astype(np.complex128)
-        t0 = time.perf_counter()
-        if wl.get("oracle") == "direct_sampled":
-            # the oracle's FFT has no route for a prime length: the direct
-            # sum at a bounded sample of outputs, scaled to whole convolutions
-            idx = np.random.default_rng(46).integers(0, N, 81920)
-            ref = oracle.conv_direct_at(x, h, idx)
-            t_cpu = time.perf_counter() - t0
-            got = main_r["y"].reshape(-1)[idx]
-            out["rel_l2_vs_fp64_oracle_sampled"] = float(
-                np.linalg.norm(got - ref) / np.linalg.norm(ref))
-            out["cpu_baseline"] = {
-                "value": round(idx.size / N / t_cpu, 8), "unit": "conv/s",
-                "cores": oracle.num_threads(), "kind": "oracle",
-                "sample": "%d of the %d outputs by the direct sum (long double, OpenMP over "
-                          "outputs), scaled to one convolution; %.2f s" % (idx.size, N, t_cpu)}
-            print(json.dumps(out), flush=True)
-            return
-        # whole convolutions of the same workload, repeated until about 10 s
-        # of host time have passed
-        runs = 0
-        while True:
-            if wl["domain"] == "spatial":
-                ref = oracle.conv_fft(x, h, wl["rhos"])
-            elif wl["domain"] == "symbol":
-                from oracle import symbols
-                kind, params = wl["symbol"]
-                sym = getattr(symbols, kind)(x.shape, *params)
-                ref = symbols.apply(x, sym)
-            else:
-                ref = oracle.fft(h * oracle.fft(x, wl["rhos"]), wl["rhos"], inverse=True)
-            runs += 1
-            t_cpu = time.perf_counter() - t0
-            if t_cpu >= 10.0 or runs >= 10000:
-                break
-        err = float(np.linalg.norm(main_r["y"] - ref) / np.linalg.norm(ref))
-        out["rel_l2_vs_fp64_oracle"] = err
-        out["cpu_baseline"] = {
-            "value": round(runs / t_cpu, 5), "unit": "conv/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": "%d full convolution(s) of the same workload (standard FFT route with "
-                      "explicit index reversal, FP64, OpenMP over pencils); %.2f s" % (runs, t_cpu)}
+        out, _ = bench_batched(pafc, torch, wl, tdtype, args)
+    elif args.workload == "serving":
+        out, _ = bench_serving(pafc, torch, wl, tdtype, args)
+    else:
+        if args.filter_per_call and wl["domain"] != "spatial":
+            print("--filter-per-call needs a workload with a spatial filter", file=sys.stderr)
+            sys.exit(2)
+        out, _ = bench_plain(pafc, torch, wl, tdtype, args)
     print(json.dumps(out), flush=True)
 
 
