@@ -280,6 +280,35 @@ pafc_status pafc_convolve_with_filter(pafc_plan_t p, const void* x_dev,
                                       void* hip_stream);
 
 /*
+ * pafc_convolve_with_filter_noalloc -- for callers that cannot allocate
+ * device memory at call time (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): the same y = x * h as
+ * pafc_convolve_with_filter (same kernels, same results), but the per-call
+ * filter spectrum lives in a fixed array that the library holds on every
+ * device it runs on (PAFC_NOALLOC_MAX_BYTES, from module load to process
+ * exit), not in the plan's spectrum, which this call leaves unchanged (a
+ * filter set with pafc_set_filter stays in effect for pafc_convolve).
+ * The call allocates nothing and calls no allocating routine; everything
+ * else it needs was prepared when the plan was made.
+ * Every call on one device shares that one array, which keeps the last
+ * call's spectrum: calls that overlap on one device (other streams, other
+ * plans, other threads) race and give wrong results.  Serialise them.
+ * The plan's staging array is also written (tile-major plans), so the call
+ * must not overlap other work on the same plan either.
+ * p: a PAFC_PERM_FREE plan of a {2,3,5}-smooth shape; x_dev, h_dev, y_dev
+ * as for pafc_convolve_with_filter.
+ * Errors: INVALID_VALUE (NULL or misaligned pointers; a plan of another
+ * variant or of a prime-length or prime-factor route), UNSUPPORTED_SIZE (the
+ * plan's spectrum, N elements or, for tile-major plans, every slot of the
+ * middle pass's tiles, exceeds PAFC_NOALLOC_MAX_BYTES: 2^21 complex128 or
+ * 2^22 complex64 elements), DEVICE.
+ */
+#define PAFC_NOALLOC_MAX_BYTES ((size_t)32 << 20)
+pafc_status pafc_convolve_with_filter_noalloc(pafc_plan_t p, const void* x_dev,
+                                              const void* h_dev, void* y_dev,
+                                              void* hip_stream);
+
+/*
  * pafc_forward -- z = (A_1^T (x) ... (x) A_d^T) x: the forward transform
  * without permutation (Alg. alg:uFFT1D..alg:uFFT3D, uFFT2 branch): the DFT
  * of x in digit-reversed order along every axis, unscaled.  Entry

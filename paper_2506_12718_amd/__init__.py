@@ -33,6 +33,8 @@ _VARIANTS = {"perm_free": PERM_FREE, "explicit_perm": EXPLICIT_PERM,
              "perm_free_unfused": PERM_FREE_UNFUSED, "prime_factor": 3,
              "prime_factor_explicit": 4}
 _C64, _C128 = 1, 2
+# PAFC_NOALLOC_MAX_BYTES of include/pafc.h
+NOALLOC_MAX_BYTES = 32 << 20
 _DOMAINS = {"spatial": 0, "spectral_natural": 1}
 
 # every symbol include/pafc.h declares
@@ -43,7 +45,8 @@ EXPORTS = ("pafc_plan", "pafc_set_filter", "pafc_convolve", "pafc_forward",
            "pafc_batch_destroy", "pafc_batch_device_bytes",
            "pafc_batch_describe", "pafc_set_tuning", "pafc_profile_passes",
            "pafc_stream_copy", "pafc_batch_profile", "pafc_twiddle",
-           "pafc_convolve_with_filter", "pafc_set_symbol", "pafc_profile_launch")
+           "pafc_convolve_with_filter", "pafc_set_symbol", "pafc_profile_launch",
+           "pafc_convolve_with_filter_noalloc")
 
 
 class PafcError(RuntimeError):
@@ -72,6 +75,7 @@ def lib():
             "pafc_set_filter": [vp, vp, ctypes.c_int, vp],
             "pafc_convolve": [vp, vp, vp, vp],
             "pafc_convolve_with_filter": [vp, vp, vp, vp, vp],
+            "pafc_convolve_with_filter_noalloc": [vp, vp, vp, vp, vp],
             "pafc_set_symbol": [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.c_int,
                                 vp],
             "pafc_forward": [vp, vp, vp, vp],
@@ -300,6 +304,22 @@ class Plan:
                                                ctypes.c_void_p(h.data_ptr()),
                                                ctypes.c_void_p(out.data_ptr()), _stream(stream)),
                "pafc_convolve_with_filter")
+        return out
+
+    def convolve_with_filter_noalloc(self, x, h, out, stream=None):
+        """As convolve_with_filter, allocating nothing: the per-call spectrum
+        goes to the library's fixed per-device array (PAFC_NOALLOC_MAX_BYTES)
+        and the plan's own filter is left as it is.  `out` is required.
+        Calls that overlap on one device race on that array."""
+        self._check_tensor(x, "x")
+        self._check_tensor(h, "h")
+        self._check_tensor(out, "out")
+        if out.data_ptr() == h.data_ptr():
+            raise ValueError("out may not alias h")
+        _check(lib().pafc_convolve_with_filter_noalloc(
+            self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(h.data_ptr()),
+            ctypes.c_void_p(out.data_ptr()), _stream(stream)),
+            "pafc_convolve_with_filter_noalloc (device array of %d bytes)" % NOALLOC_MAX_BYTES)
         return out
 
     def profile_passes(self, x, out, reps=10, stream=None):

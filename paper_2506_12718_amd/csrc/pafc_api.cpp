@@ -24,6 +24,13 @@
 #include "pafc.h"
 #include "pafc_internal.h"
 
+// Device memory of pafc_convolve_with_filter_noalloc: the per-call filter
+// spectrum.  Every device the library runs on holds its own copy from module
+// load to process exit.  In host code the name is only a host-side stand-in:
+// host code uses the address hipGetSymbolAddress returns for the current
+// device (scratch_address below), never the name.
+static __device__ __align__(256) unsigned char scratch[PAFC_NOALLOC_MAX_BYTES];
+
 namespace pafc {
 hipError_t launch_pass(bool dbl, int cls, const PassArgs* d_desc, uint32_t ntiles, const void* in,
                        void* out, uint32_t threads, size_t lds_bytes, hipStream_t s);
@@ -1104,9 +1111,36 @@ struct pafc_plan_s {
   std::vector<Pass> fwd_tm;
   bool filter_set = false;
   size_t bytes = 0;
+  // pafc_convolve_with_filter_noalloc: this device's address of `scratch`
+  // (NULL when the plan cannot use it, noalloc_status says why) and the
+  // convolution sequence whose middle pass reads the spectrum from there
+  void* noalloc_H = nullptr;
+  pafc_status noalloc_status = PAFC_ERROR_INVALID_VALUE;
+  std::vector<Pass> conv_noalloc;
 };
 
 namespace {
+
+// Address of `scratch` on each device, looked up once per device with that
+// device current (the first plan made on it), then reused.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kMaxDevices] = {};
+
+hipError_t scratch_address(int dev, void** out) {
+  *out = nullptr;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!ptr) return hipErrorInvalidSymbol;
+    g_scratch_addr[dev] = ptr;
+  }
+  *out = g_scratch_addr[dev];
+  return hipSuccess;
+}
 
 pafc_status from_hip(hipError_t e) {
   if (e == hipSuccess) return PAFC_SUCCESS;
@@ -2115,6 +2149,28 @@ pafc_status pafc_plan(pafc_plan_t* out, int ndim, const int64_t* dims, const int
     last.desc = (uint32_t)descs.size();
     descs.push_back(a);
   }
+  // pafc_convolve_with_filter_noalloc: the middle pass once more, reading
+  // the spectrum from this device's `scratch` array (fused permutation-free
+  // plans whose spectrum fits the array)
+  if (P.variant != PAFC_PERM_FREE || p->mid_pass < 0) {
+    p->noalloc_status = PAFC_ERROR_INVALID_VALUE;
+  } else if ((uint64_t)h_elems * P.elem > (uint64_t)PAFC_NOALLOC_MAX_BYTES) {
+    p->noalloc_status = PAFC_ERROR_UNSUPPORTED_SIZE;
+  } else {
+    void* addr = nullptr;
+    if (scratch_address(p->device, &addr) != hipSuccess) {
+      p->noalloc_status = PAFC_ERROR_DEVICE;
+    } else {
+      p->conv_noalloc = p->P.conv;
+      Pass& m = p->conv_noalloc[(size_t)p->mid_pass];
+      PassArgs a = descs[m.desc];
+      a.H = addr;
+      m.desc = (uint32_t)descs.size();
+      descs.push_back(a);
+      p->noalloc_H = addr;
+      p->noalloc_status = PAFC_SUCCESS;
+    }
+  }
   if (e == hipSuccess)
     e = hipMalloc((void**)&p->d_descs, std::max<size_t>(1, descs.size()) * sizeof(PassArgs));
   if (e != hipSuccess) {
@@ -2227,6 +2283,33 @@ pafc_status pafc_convolve_with_filter(pafc_plan_t p, const void* x_dev, const vo
   PAFC_TRY(load_filter(p, h_dev, PAFC_FILTER_SPATIAL, s));
   p->filter_set = true;
   return run_sequence(p, p->P.conv, x_dev, y_dev, s);
+}
+
+pafc_status pafc_convolve_with_filter_noalloc(pafc_plan_t p, const void* x_dev,
+                                              const void* h_dev, void* y_dev,
+                                              void* hip_stream) {
+  if (!p || !x_dev || !h_dev || !y_dev) return PAFC_ERROR_INVALID_VALUE;
+  if (!aligned_for(x_dev, p->P.dtype) || !aligned_for(y_dev, p->P.dtype) ||
+      !aligned_for(h_dev, p->P.dtype))
+    return PAFC_ERROR_INVALID_VALUE;
+  if (p->inner) return PAFC_ERROR_INVALID_VALUE;  // prime-length and prime-factor routes
+  if (!p->noalloc_H) return p->noalloc_status;
+  hipStream_t s = (hipStream_t)hip_stream;
+  void* H = p->noalloc_H;
+  // the filter's forward transform into the array (the plan's own spectrum
+  // is left as it is); a tile-major spectrum is staged in the plan's
+  // staging array and written by the last pass in the middle pass's order
+  if (p->h_tm) {
+    const void* src = h_dev;
+    for (size_t i = 0; i + 1 < p->fwd_tm.size(); ++i) {
+      PAFC_TRY(run_pass(p, p->fwd_tm[i], src, p->d_scratch, s));
+      src = p->d_scratch;
+    }
+    PAFC_TRY(run_pass(p, p->fwd_tm.back(), src, H, s));
+  } else {
+    PAFC_TRY(run_sequence(p, p->P.fwd, h_dev, H, s));
+  }
+  return run_sequence(p, p->conv_noalloc, x_dev, y_dev, s);
 }
 
 pafc_status pafc_set_symbol(pafc_plan_t p, pafc_symbol kind, const double* params, int nparams,
