@@ -601,22 +601,19 @@ def batch_alg_bytes(sizes, filters, elem):
     return b + sum(int(np.asarray(h).size) * elem for h in filters.values())
 
 
-def bench_batched(pafc, torch, wl, tdtype, args, cpu_min_s=10.0):
-    """The batch timed as one graph replay per batch (conv/s = problems /
-    median replay), the per-launch breakdown from an eager run, and the same
-    problems run one plan at a time (the plain form)."""
-    elem = 16 if tdtype == torch.complex128 else 8
-    B = pafc.Batch(wl["sizes"], wl["fids"], len(wl["filters"]), tdtype)
+def time_batch_form(pafc, torch, wl, tdtype, form, steps, warmup):
+    """One batch form timed as one graph replay per batch: median and p99 ms
+    per replay, the per-launch breakdown of an eager run (mean ms and
+    algorithmic bytes per launch), the plan description and the output."""
+    B = pafc.Batch(wl["sizes"], wl["fids"], len(wl["filters"]), tdtype, form=form)
     for f, h in wl["filters"].items():
         B.set_filter(f, torch.from_numpy(h).to(tdtype).cuda())
     x = torch.from_numpy(np.concatenate(wl["xs"])).to(tdtype).cuda()
     y = torch.empty_like(x)
-    nprob = len(wl["sizes"])
     g = graph_of(torch, lambda s: B.convolve(x, out=y, stream=s))
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         g.replay()
     torch.cuda.synchronize()
-    steps = args.steps
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     t0 = time.perf_counter()
     ev[0].record()
@@ -626,37 +623,69 @@ def bench_batched(pafc, torch, wl, tdtype, args, cpu_min_s=10.0):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_rep = [ev[k].elapsed_time(ev[k + 1]) for k in range(steps)]
-    med = pct(ms_rep, 50)
-    value = nprob / (med * 1e-3)
-    # per-launch breakdown (eager, an event around every launch)
     ms_lv, by_lv, _ = B.profile_levels(x, y, reps=max(5, steps // 2))
+    desc = B.describe()
+    yh = y.cpu().numpy().astype(np.complex128)
+    B.close()
+    del x, y, g
+    torch.cuda.empty_cache()
+    return {"ms_rep": ms_rep, "wall": wall, "ms_lv": ms_lv, "by_lv": by_lv, "desc": desc,
+            "y": yh}
+
+
+BATCH_FORMS = {"persistent": "one persistent launch: resident blocks claim whole problems "
+                             "(largest first) and run all of a problem's passes",
+               "levels": "one launch per pass level, register class and LDS occupancy"}
+
+
+def bench_batched(pafc, torch, wl, tdtype, args, cpu_min_s=10.0):
+    """The batch timed as one graph replay per batch (conv/s = problems /
+    median replay) in the form args.batch_form, the other form timed the
+    same way beside it, and the same problems run one plan at a time (the
+    plain form)."""
+    elem = 16 if tdtype == torch.complex128 else 8
+    nprob = len(wl["sizes"])
+    steps = args.steps
+    form = args.batch_form
+    if form == "auto":  # the library's choice (PAFC_BATCH_AUTO)
+        form = "persistent" if elem == 16 else "levels"
+    r = time_batch_form(pafc, torch, wl, tdtype, form, steps, args.warmup)
+    med = pct(r["ms_rep"], 50)
+    value = nprob / (med * 1e-3)
+    ms_lv, by_lv = r["ms_lv"], r["by_lv"]
     dom = max(range(len(ms_lv)), key=lambda i: ms_lv[i])
     alg = batch_alg_bytes(wl["sizes"], wl["filters"], elem)
-    desc = B.describe()
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "conv/s", "n_gpus": 1,
         "steps": steps, "warmup": args.warmup, "ms_per_step": round(med, 5),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if elem == 16 else "f32", "data": "synthetic",
-        "config": dict(wl["config"], variant="perm_free", launches=len(ms_lv),
+        "config": dict(wl["config"], variant="perm_free", form=form, launches=len(ms_lv),
                        timing="one graph replay per batch (median)"),
+        "form": BATCH_FORMS[form],
         "alg_bytes_per_batch": alg,
         "hbm_gbps_alg": round(alg / (med * 1e-3) / 1e9, 1),
         "hbm_frac_alg": round(alg / (med * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-        "wall_conv_per_s": round(nprob * steps / wall, 1),
-        "latency_ms": {"p50": round(med, 5), "p99": round(pct(ms_rep, 99), 5)},
+        "wall_conv_per_s": round(nprob * steps / r["wall"], 1),
+        "latency_ms": {"p50": round(med, 5), "p99": round(pct(r["ms_rep"], 99), 5)},
         "ms_per_launch": [round(v, 5) for v in ms_lv],
         "roofline": roofline_obj(by_lv[dom], ms_lv[dom], traffic=load_traffic(wl["name"]),
                                  kernel="batched launch %d of %d" % (dom, len(ms_lv)),
                                  alg_bytes_per_launch=by_lv[dom],
                                  avg_launch_ms=round(ms_lv[dom], 5)),
-        "launch_desc": desc.get("levels"),
+        "launch_desc": r["desc"].get("levels"),
     }
-    yh = y.cpu().numpy().astype(np.complex128)
-    B.close()
-    del x, y, g
-    torch.cuda.empty_cache()
+    yh = r["y"]
     if not args.no_compare:
+        other = "levels" if form == "persistent" else "persistent"
+        o = time_batch_form(pafc, torch, wl, tdtype, other, steps, args.warmup)
+        omed = pct(o["ms_rep"], 50)
+        out["other_form"] = {
+            "form": other, "what": BATCH_FORMS[other], "conv_per_s": round(nprob / (omed * 1e-3), 1),
+            "ms_per_batch": round(omed, 5), "launches": len(o["ms_lv"]),
+            "hbm_gbps_alg": round(alg / (omed * 1e-3) / 1e9, 1),
+            "max_abs_diff": float(np.abs(o["y"] - yh).max()),
+            "speedup_of_%s" % form: round(omed / med, 3)}
         out["plain"] = bench_batched_plain(pafc, torch, wl, tdtype, yh)
         out["plain"]["speedup_batched_over_plain"] = round(
             value / out["plain"]["conv_per_s"], 3)
@@ -860,7 +889,7 @@ def brief(o):
             "rel_l2_vs_fp64_oracle_max_sampled", "max_entry_err_over_rms_sampled",
             "cpu_baseline", "offered_rate_per_s", "closed_loop_capacity_per_s",
             "plain_one_at_a_time_per_s", "speedup_served_over_plain", "max_inflight",
-            "hbm_gbps_alg_at_offered_rate", "wall_conv_per_s", "plain")
+            "hbm_gbps_alg_at_offered_rate", "wall_conv_per_s", "plain", "form", "other_form")
     d = {k: o[k] for k in keys if k in o}
     d["workload"] = o["config"]["workload"]
     if o.get("roofline"):
@@ -955,6 +984,48 @@ def run_all(pafc, torch, args):
     return head
 
 
+def counter_run(pafc, torch, args):
+    """K convolutions of one workload after its set-up, for rocprofv3 counter
+    runs: the last K x launches_per_conv dispatches of library kernels are
+    the convolutions."""
+    tdtype = torch.complex128 if args.dtype == "c128" else torch.complex64
+    elem = 16 if args.dtype == "c128" else 8
+    wl = WORKLOADS[args.workload](args.dtype)
+    K = args.counter_run
+    if args.workload == "batched":
+        B = pafc.Batch(wl["sizes"], wl["fids"], len(wl["filters"]), tdtype, form=args.batch_form)
+        for f, h in wl["filters"].items():
+            B.set_filter(f, torch.from_numpy(h).to(tdtype).cuda())
+        x = torch.from_numpy(np.concatenate(wl["xs"])).to(tdtype).cuda()
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        for _ in range(K):
+            B.convolve(x, out=y)
+        torch.cuda.synchronize()
+        out = {"workload": wl["name"], "form": args.batch_form, "convs": K,
+               "launches_per_conv": len(B.describe()["levels"]),
+               "alg_bytes_per_conv": batch_alg_bytes(wl["sizes"], wl["filters"], elem)}
+        B.close()
+        return out
+    plan = pafc.Plan(wl["x"].shape, tdtype, radix=wl["radix"])
+    x = torch.from_numpy(wl["x"]).to(tdtype).cuda()
+    y = torch.empty_like(x)
+    if wl["domain"] == "symbol":
+        plan.set_symbol(wl["symbol"][0], *wl["symbol"][1])
+    else:
+        plan.set_filter(torch.from_numpy(wl["h"]).to(tdtype).cuda(), domain=wl["domain"])
+    torch.cuda.synchronize()
+    for _ in range(K):
+        plan.convolve(x, out=y)
+    torch.cuda.synchronize()
+    d = plan.describe()
+    out = {"workload": wl["name"], "convs": K, "launches_per_conv": len(d["conv_passes"]),
+           "conv_passes": d["conv_passes"], "alg_bytes_per_conv": alg_bytes(wl["x"].shape, elem),
+           "plan_bytes_per_conv": d["hbm_bytes_conv"]}
+    plan.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -964,6 +1035,13 @@ def main():
     ap.add_argument("--dtype", default="c128", choices=["c128", "c64"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing and error check")
     ap.add_argument("--no-compare", action="store_true", help="skip the comparison variants")
+    ap.add_argument("--counter-run", type=int, default=0, metavar="K",
+                    help="plan, set the filter, then run exactly K convolutions of --workload "
+                         "and nothing else (for hardware counter runs); prints the launches "
+                         "of one convolution and its algorithmic bytes")
+    ap.add_argument("--batch-form", default="auto", choices=sorted(BATCH_FORMS) + ["auto"],
+                    help="form of the batched workload that `value` reports (auto: the "
+                         "library's choice for the dtype)")
     ap.add_argument("--filter-per-call", action="store_true",
                     help="transform the filter inside every timed call (three transforms per "
                          "convolution, as the paper times it)")
@@ -990,15 +1068,21 @@ def main():
         nbytes = 256 << 20
         a = torch.zeros(nbytes // 16, dtype=torch.complex128, device="cuda")
         b = torch.empty_like(a)
-        pafc.stream_copy(a, b)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(10):
-            pafc.stream_copy(a, b)
-        torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / 10
-        print(json.dumps({"calibration_copy_bytes": nbytes, "ms": dt * 1e3,
-                          "GBps_read_plus_write": 2 * nbytes / dt / 1e9}))
+        out = {"calibration_bytes": nbytes}
+        for kind in ("copy16", "copy8", "read"):
+            pafc.stream_copy(a, b, kind=kind)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(10):
+                pafc.stream_copy(a, b, kind=kind)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / 10
+            moved = nbytes if kind == "read" else 2 * nbytes
+            out[kind] = {"ms": round(dt * 1e3, 5), "GBps": round(moved / dt / 1e9, 1)}
+        print(json.dumps(out))
+        return
+    if args.counter_run:
+        print(json.dumps(counter_run(pafc, torch, args)), flush=True)
         return
     if args.workload == "all":
         if args.filter_per_call:

@@ -410,13 +410,18 @@ pafc_status pafc_profile_launch(pafc_plan_t p, const void* x_dev, void* y_dev,
 pafc_status pafc_twiddle(int64_t n, int64_t e, double* re, double* im);
 
 /*
- * pafc_stream_copy -- a plain streaming copy of `bytes` bytes (multiple of
- * 16) from src_dev to dst_dev on hip_stream.  Not part of the convolution:
- * it is the reference kernel of known traffic used to calibrate hardware
- * byte counters (one read and one write of every byte).
- * Errors: INVALID_VALUE (NULL, misaligned, bytes not a multiple of 16), DEVICE.
+ * pafc_stream_copy -- a reference kernel of known traffic over `bytes`
+ * bytes (multiple of 16) on hip_stream, used to calibrate hardware byte
+ * counters; not part of the convolution.  kind 0: streaming copy src_dev ->
+ * dst_dev with 16 bytes per lane (one read and one write of every byte);
+ * kind 1: the same copy with 8 bytes per lane; kind 2: read-only sweep of
+ * src_dev (every byte read once), writing one 16-byte partial sum per block
+ * of 256 lanes at the start of dst_dev (at most bytes / 256 + 16 bytes).
+ * Both arrays hold `bytes` bytes and are 16-byte aligned.
+ * Errors: INVALID_VALUE (NULL, misaligned, bytes not a multiple of 16, kind
+ * not 0..2), DEVICE.
  */
-pafc_status pafc_stream_copy(const void* src_dev, void* dst_dev, size_t bytes,
+pafc_status pafc_stream_copy(const void* src_dev, void* dst_dev, size_t bytes, int kind,
                              void* hip_stream);
 
 /* ------------------------------------------------------------------------
@@ -429,20 +434,45 @@ pafc_status pafc_stream_copy(const void* src_dev, void* dst_dev, size_t bytes,
  * elements of problem i start at offset sum_{j<i} sizes[j] of one device
  * array.  The batch owns per-size-class plans (radix splits and tiles chosen
  * by the planner, or from the table set by pafc_set_tuning) and a device
- * work list; pafc_batch_convolve enqueues, for each pass level in turn (at
- * most three), one launch per register class and LDS-bound occupancy
- * present, which a caller may capture in a hipGraph.  All arguments are
- * checked before any device call.
+ * work list, in one of two forms:
+ *   PAFC_BATCH_PERSISTENT: pafc_batch_convolve enqueues ONE launch.  Its
+ *     blocks (as many as fit the device at once) claim whole problems from
+ *     a device counter, largest first, and each runs every pass of its
+ *     problem in order; blocks never wait for one another.  The size-class
+ *     plans are made for that one kernel: 256 threads, register groups of
+ *     at most 16 points, tiles within one LDS size (80 KB in FP64, 32 KB in
+ *     FP32 by default).  The
+ *     launch leaves its two control words zero, so it can be replayed from a
+ *     captured hipGraph; two launches of one batch must not overlap.
+ *   PAFC_BATCH_LEVELS: pafc_batch_convolve enqueues, for each pass level in
+ *     turn (at most five), one launch per register class and LDS-bound
+ *     occupancy present (up to 18 launches for the mixed workload of
+ *     powers of 2, 3 and 5), with the size-class plans of pafc_plan.
+ *   PAFC_BATCH_AUTO: one of the two, by element type (below).
+ * Either may be captured in a hipGraph.  All arguments are checked before
+ * any device call.
  * Errors: INVALID_VALUE (out, sizes or filter_ids NULL, count < 1,
  * nfilters < 1, a length < 2, a filter id out of range, two lengths on one
- * filter, bad dtype), UNSUPPORTED_SIZE (a length with a prime factor above
- * 5), OUT_OF_MEMORY, DEVICE.
+ * filter, bad dtype or form), UNSUPPORTED_SIZE (a length with a prime factor
+ * above 5, or one that no plan within the persistent form's limits holds),
+ * OUT_OF_MEMORY, DEVICE.
  */
 typedef struct pafc_batch_s* pafc_batch_t;
 
+typedef enum pafc_batch_form {
+  PAFC_BATCH_PERSISTENT = 0,
+  PAFC_BATCH_LEVELS = 1,
+  /* the form measured faster on MI355X for the element type (the mixed
+     workload of 4096 problems): persistent for complex128, levels for
+     complex64 */
+  PAFC_BATCH_AUTO = 2,
+  PAFC_BATCH_FORM_MAX_ENUM = 0x7FFFFFFF
+} pafc_batch_form;
+
 pafc_status pafc_batch_plan(pafc_batch_t* out, int count, const int64_t* sizes,
                             const int* filter_ids, int nfilters,
-                            pafc_dtype dtype, void* hip_stream);
+                            pafc_dtype dtype, pafc_batch_form form,
+                            void* hip_stream);
 
 /* Set filter f (length = the size class of f) from a device array. */
 pafc_status pafc_batch_set_filter(pafc_batch_t b, int filter_id,

@@ -86,14 +86,14 @@ def lib():
             "pafc_describe": [ctypes.c_int, i64p, ip, ctypes.c_int, ctypes.c_int,
                               ctypes.c_char_p, sz, ctypes.POINTER(sz)],
             "pafc_batch_plan": [ctypes.POINTER(vp), ctypes.c_int, i64p, ip, ctypes.c_int,
-                                ctypes.c_int, vp],
+                                ctypes.c_int, ctypes.c_int, vp],
             "pafc_batch_set_filter": [vp, ctypes.c_int, vp, ctypes.c_int, vp],
             "pafc_batch_convolve": [vp, vp, vp, vp],
             "pafc_batch_destroy": [vp],
             "pafc_batch_device_bytes": [vp, ctypes.POINTER(sz)],
             "pafc_batch_describe": [vp, ctypes.c_char_p, sz, ctypes.POINTER(sz)],
             "pafc_set_tuning": [ctypes.c_char_p],
-            "pafc_stream_copy": [vp, vp, sz, vp],
+            "pafc_stream_copy": [vp, vp, sz, ctypes.c_int, vp],
             "pafc_twiddle": [ctypes.c_int64, ctypes.c_int64, ctypes.POINTER(ctypes.c_double),
                              ctypes.POINTER(ctypes.c_double)],
             "pafc_batch_profile": [vp, vp, vp, vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
@@ -203,12 +203,17 @@ def twiddle(n, e):
     return complex(re.value, im.value)
 
 
-def stream_copy(src, dst, stream=None):
-    """Plain streaming copy (the counter-calibration kernel)."""
+STREAM_KINDS = {"copy16": 0, "copy8": 1, "read": 2}
+
+
+def stream_copy(src, dst, stream=None, kind="copy16"):
+    """Reference kernels of known traffic for counter calibration: a
+    streaming copy with 16 or 8 bytes per lane, or a read-only sweep of
+    src (pafc_stream_copy)."""
     nbytes = src.numel() * src.element_size()
     assert dst.numel() * dst.element_size() == nbytes
     _check(lib().pafc_stream_copy(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()),
-                                  nbytes, _stream(stream)), "pafc_stream_copy")
+                                  nbytes, STREAM_KINDS[kind], _stream(stream)), "pafc_stream_copy")
 
 
 def set_tuning(text):
@@ -386,8 +391,11 @@ class Batch:
     uses; inputs and outputs are packed 1-D tensors of ``sum(sizes)`` elements.
     """
 
-    def __init__(self, sizes, filter_ids, nfilters, dtype=None, stream=None):
+    FORMS = {"persistent": 0, "levels": 1, "auto": 2}
+
+    def __init__(self, sizes, filter_ids, nfilters, dtype=None, stream=None, form="auto"):
         import torch
+        self.form = form
         self.sizes = [int(n) for n in sizes]
         self.filter_ids = [int(f) for f in filter_ids]
         self.dtype = dtype if dtype is not None else torch.complex128
@@ -397,7 +405,7 @@ class Batch:
         n = len(self.sizes)
         st = lib().pafc_batch_plan(ctypes.byref(self._h), n, (ctypes.c_int64 * n)(*self.sizes),
                                    (ctypes.c_int * n)(*self.filter_ids), int(nfilters),
-                                   self._code, _stream(stream))
+                                   self._code, self.FORMS[form], _stream(stream))
         _check(st, "pafc_batch_plan")
 
     def set_filter(self, fid, h, domain="spatial", stream=None):

@@ -34,25 +34,30 @@ static __device__ __align__(256) unsigned char scratch[PAFC_NOALLOC_MAX_BYTES];
 namespace pafc {
 hipError_t launch_pass(bool dbl, int cls, const PassArgs* d_desc, uint32_t ntiles, const void* in,
                        void* out, uint32_t threads, size_t lds_bytes, hipStream_t s);
+int batch_persist_blocks_per_cu(bool dbl, size_t lds_bytes);
+hipError_t launch_batch_persist(bool dbl, const PassArgs* descs, const BatchJob* jobs,
+                                uint32_t njobs, BatchCtl* ctl, uint32_t grid, size_t lds_bytes,
+                                const void* in, void* out, hipStream_t s);
 hipError_t launch_batch(bool dbl, int cls, const PassArgs* descs, const BatchTile* tiles,
                         uint32_t first, uint32_t count, const void* in, void* out,
                         uint32_t threads, size_t lds_bytes, hipStream_t s);
 hipError_t launch_scale(bool dbl, void* p, int64_t n, double s, hipStream_t st);
 bool pipe_supported(int r, int g, int ng);
 bool pipe_outer_supported(int r, int g, int ng);
-int pipe_thread_limit(int r, int g);
+bool pipe_mid_supported(int r, int g, int ng, int gm, int xc, int mode);
+int pipe_thread_limit(int r, int g, bool dbl = true, int xc = 0);
 
 int pipe_blocks_per_cu(bool dbl, int r, int g, int ng, int kind, int mode, uint32_t threads,
-                       size_t lds);
+                       size_t lds, int gm, int xc);
 hipError_t launch_pipe_htm(bool dbl, int r, int g, int ng, int mode, const PassArgs* d,
                            uint32_t ntiles, uint32_t threads, const void* src, void* dst,
                            hipStream_t s);
 hipError_t launch_pipe(bool dbl, int r, int g, int ng, int kind, int mode, const PassArgs* d,
                        uint32_t grid, uint32_t threads, size_t lds, const void* in, void* out,
-                       hipStream_t s);
+                       hipStream_t s, int gm, int xc);
 hipError_t launch_mul(bool dbl, const void* x, const void* h, void* y, int64_t n, double s,
                       hipStream_t st);
-hipError_t launch_stream_copy(const void* src, void* dst, int64_t n16, hipStream_t st);
+hipError_t launch_stream_copy(int kind, const void* src, void* dst, int64_t n16, hipStream_t st);
 hipError_t launch_pfa_gather(bool dbl, const void* in, void* out, const uint32_t* t0,
                              const uint32_t* t1, const uint32_t* t2, uint32_t N1, uint32_t N2,
                              uint32_t n, hipStream_t st);
@@ -282,6 +287,7 @@ struct Seg {  // one pass-sized piece of an axis transform
   bool tw_global = false;  // twiddles from the global table, no LDS copy
   std::vector<int> rho;  // this piece's stages, innermost first
   GroupCaps caps;
+  size_t lds = kLdsBudget;  // LDS one tile of the piece may use
 };
 
 struct Pass {
@@ -299,6 +305,8 @@ struct Pass {
   bool pipe = false;
   int pipe_r = 0, pipe_g = 0, pipe_ng = 0, pipe_kind = 0;
   int pipe_mode = 0;  // MODE_CONTIG, MODE_STRIDED, or MODE_OUTER (an outer piece)
+  int pipe_gm = 0;    // stages of the innermost group (a middle pass's may be fewer)
+  int pipe_xc = 0;    // folded length-2 column axes of a strided middle pass
   uint32_t pipe_grid = 0;
   uint32_t pipe_threads = 0;  // one per item (the general engine's count is `threads`)
   size_t pipe_lds = 0;
@@ -385,21 +393,23 @@ void choose_width(Seg& s, size_t elem, int tuneW) {
   if (envW > 0) W = std::min<uint32_t>(pow2_floor((uint64_t)envW),
                                        pow2_floor(std::max<uint64_t>(1, s.ncols)));
   const size_t tw = s.tw_global ? 0 : twl_bytes(s.n_tw, elem);
-  while (W > 1 && tile_lds_bytes((uint64_t)s.L * W, elem) + tw > kLdsBudget) W /= 2;
+  while (W > 1 && tile_lds_bytes((uint64_t)s.L * W, elem) + tw > s.lds) W /= 2;
   s.W = W;
 }
 
-bool fits_lds(int64_t L, size_t elem) { return tile_lds_bytes((uint64_t)L, elem) <= kLdsBudget; }
+bool fits_lds(int64_t L, size_t elem, size_t budget) {
+  return tile_lds_bytes((uint64_t)L, elem) <= budget;
+}
 
 // A piece reads its twiddles from the global (L2-resident) table instead of
 // an LDS copy when the copy would not fit beside a one-column tile, or when
 // it is larger than 64 KB (PAFC_TUNE_TWG bytes): staging it would cost more
 // than the tile's own data (measured: 2^24-long axes twice as fast with
 // global reads, the 48 KB tables of 5^9 faster in LDS).
-bool twiddles_global(int64_t L, int64_t n_tw, size_t elem) {
+bool twiddles_global(int64_t L, int64_t n_tw, size_t elem, size_t budget) {
   const size_t tw = twl_bytes(n_tw, elem);
   const int lim = env_int("PAFC_TUNE_TWG", 64 * 1024);
-  return tile_lds_bytes((uint64_t)L, elem) + tw > kLdsBudget || (lim > 0 && tw > (size_t)lim);
+  return tile_lds_bytes((uint64_t)L, elem) + tw > budget || (lim > 0 && tw > (size_t)lim);
 }
 
 // Build the op list of one pass over segment s.  kind: 0 = DIF only,
@@ -546,21 +556,43 @@ bool validate_pass(const PassArgs& a, int64_t extent, int64_t n_tw) {
 // (r, g), one item per thread: with flat twiddles of the piece's own length,
 // or (*outer) a strided outer piece of a cut axis with the whole axis's
 // twiddles from a two-level LDS copy (PAFC_PIPE_OUTER=0: general engine).
+// A middle pass (kind 2, when gm and xc are asked for) may also have an
+// innermost group of fewer stages (*gm < *g; its fused op runs R / r^gm
+// groups per thread) and, in a strided tile whose row is exactly the folded
+// faster axes, up to two folded axes of length 2 (*xc; their DFTs are
+// exchanged across lanes) -- PAFC_PIPE_MIDX=0 turns both off.
 bool pipe_shape(const Seg& s, const std::vector<CrossAxis>* cross, int* r, int* g, int* ng,
-                bool* outer = nullptr) {
-  if (env_int("PAFC_PIPE", 1) == 0 || (cross && !cross->empty()) || s.tw_global) return false;
+                bool* outer = nullptr, int kind = -1, int* gm = nullptr, int* xc = nullptr) {
+  if (gm) *gm = -1;
+  if (xc) *xc = 0;
+  if (env_int("PAFC_PIPE", 1) == 0 || s.tw_global) return false;
   const bool out = s.col_in_j != 0 && s.mode == MODE_STRIDED;
   if (out ? env_int("PAFC_PIPE_OUTER", 1) == 0 : (s.jmul != 1 || s.n_tw != (int64_t)s.L))
     return false;
+  const bool ext = kind == 2 && !out && gm && xc && env_int("PAFC_PIPE_MIDX", 1) != 0;
+  int ncross = 0;
+  if (cross && !cross->empty()) {
+    if (!ext || s.mode != MODE_STRIDED || cross->size() > 2) return false;
+    for (const CrossAxis& c : *cross)
+      if (c.r != 2 || c.g != 1 || c.cs != (1u << ncross++)) return false;
+    if (s.W != (1u << ncross) || s.ncols != s.W) return false;
+  }
   const auto groups = group_runs(s.rho, s.caps);
   if (groups.empty()) return false;
-  for (auto& gr : groups)
-    if (gr != groups[0]) return false;
+  for (size_t i = 0; i + 1 < groups.size(); ++i)
+    if (groups[i] != groups[0]) return false;
+  const auto& last = groups.back();  // the innermost group (DIF order)
+  if (last.first != groups[0].first || last.second > groups[0].second) return false;
+  const bool uniform = last == groups[0] && ncross == 0;
+  if (!uniform && !ext) return false;
   *r = groups[0].first;
   *g = groups[0].second;
   *ng = (int)groups.size();
   if (outer) *outer = out;
-  return out ? pipe_outer_supported(*r, *g, *ng) : pipe_supported(*r, *g, *ng);
+  if (uniform) return out ? pipe_outer_supported(*r, *g, *ng) : pipe_supported(*r, *g, *ng);
+  *gm = last.second;
+  *xc = ncross;
+  return pipe_mid_supported(*r, *g, *ng, *gm, *xc, (int)s.mode);
 }
 
 bool make_pass(const Seg& s_in, int kind, size_t elem, Pass* p,
@@ -612,21 +644,24 @@ bool make_pass(const Seg& s_in, int kind, size_t elem, Pass* p,
     a.twl_off = (uint32_t)((LW + (LW >> 4) + 2) & ~1ull);
   }
   p->lds = (size_t)(a.twl_off + (s.tw_global ? 0u : (1u << a.twl_bits) + a.twl_nhi)) * elem;
-  if (p->lds > kLdsBudget) return false;
+  if (p->lds > s.lds) return false;
   p->tw_n = s.n_tw;
   p->mid = (kind == 2);
   p->kind = 0;
   // pipelined kernel: every group of the piece has the same (r, g), each op
   // has one item per thread, flat twiddles of the piece's own length
   {
-    int r = 0, g = 0, ng = 0;
+    int r = 0, g = 0, ng = 0, gm = -1, xc = 0;
     bool outer = false;
     // it also addresses with 32-bit byte offsets: the span of elements the
     // pass touches must stay below 4 GiB
     const uint64_t span = (uint64_t)(s.nouter - 1) * (uint64_t)s.S_o +
                           (uint64_t)(s.L - 1) * (uint64_t)s.S_i +
                           (uint64_t)(s.ncols - 1) * (uint64_t)s.S_c + 1;
-    bool ok = pipe_shape(s, cross, &r, &g, &ng, &outer) && span * elem <= 0xFFFFFFFFull;
+    bool ok = pipe_shape(s, cross, &r, &g, &ng, &outer, kind, &gm, &xc) &&
+              span * elem <= 0xFFFFFFFFull;
+    // a middle pass with a short innermost group or folded columns
+    const bool ext = ok && gm >= 0;
     // an outer piece is never the middle pass (the product sits in the
     // innermost piece)
     if (outer && kind == 2) ok = false;
@@ -642,10 +677,23 @@ bool make_pass(const Seg& s_in, int kind, size_t elem, Pass* p,
     // one item per thread: the radix-16 shapes in whole waves (as the
     // general engine would size the block), the short ones in blocks of
     // exactly one thread per item
-    const uint32_t items = a.nops ? a.ops[0].nitems : 0;
-    for (uint32_t i = 0; ok && i < a.nops; ++i) ok = a.ops[i].nitems == items;
-    const bool small = ok && pipe_thread_limit(r, g) > 256;
-    if (ok) ok = small ? items <= (uint32_t)pipe_thread_limit(r, g) : items == p->threads;
+    uint32_t items = a.nops ? a.ops[0].nitems : 0;
+    if (ext) {
+      // one R-point item per thread in the axis ops, R / RM innermost groups
+      // in the middle op; the column ops run inside the first and last op
+      const uint32_t R = (uint32_t)ipow64(r, g), RM = (uint32_t)ipow64(r, gm);
+      items = a.LW / R;
+      for (uint32_t i = 0; ok && i < a.nops; ++i) {
+        const OpDesc& o = a.ops[i];
+        if (o.cross) continue;
+        ok = o.type == OP_MID ? (uint32_t)o.R == RM : ((uint32_t)o.R == R && o.nitems == items);
+      }
+      ok = ok && items % 64 == 0 && items <= (uint32_t)pipe_thread_limit(r, g, elem == 16, xc);
+    } else {
+      for (uint32_t i = 0; ok && i < a.nops; ++i) ok = a.ops[i].nitems == items;
+    }
+    const bool small = ok && !ext && pipe_thread_limit(r, g) > 256;
+    if (ok && !ext) ok = small ? items <= (uint32_t)pipe_thread_limit(r, g) : items == p->threads;
     if (ok) {
       p->pipe = true;
       p->pipe_r = r;
@@ -653,6 +701,8 @@ bool make_pass(const Seg& s_in, int kind, size_t elem, Pass* p,
       p->pipe_ng = ng;
       p->pipe_kind = kind;
       p->pipe_mode = outer ? (int)MODE_OUTER : (int)s.mode;
+      p->pipe_gm = ext ? gm : g;
+      p->pipe_xc = ext ? xc : 0;
       p->pipe_threads = items;
       const uint64_t LW = a.LW;
       // tile, then the flat table of the piece (or, outer, the two-level
@@ -693,8 +743,13 @@ bool make_pass(const Seg& s_in, int kind, size_t elem, Pass* p,
 
   if (p->pipe) {
     char nm[96];
-    snprintf(nm, sizeof(nm), " pipe_kernel<%s,%d,%d,%d,%d,%d>", elem == 16 ? "double" : "float",
-             p->pipe_r, p->pipe_g, p->pipe_ng, kind, p->pipe_mode);
+    if (p->pipe_gm != p->pipe_g || p->pipe_xc != 0)
+      snprintf(nm, sizeof(nm), " pipe_kernel<%s,%d,%d,%d,%d,%d,%d,%d>",
+               elem == 16 ? "double" : "float", p->pipe_r, p->pipe_g, p->pipe_ng, kind,
+               p->pipe_mode, p->pipe_gm, p->pipe_xc);
+    else
+      snprintf(nm, sizeof(nm), " pipe_kernel<%s,%d,%d,%d,%d,%d>", elem == 16 ? "double" : "float",
+               p->pipe_r, p->pipe_g, p->pipe_ng, kind, p->pipe_mode);
     p->label += nm;
   }
   return true;
@@ -705,8 +760,11 @@ bool make_pass(const Seg& s_in, int kind, size_t elem, Pass* p,
 // the pieces outermost first; false if some piece cannot fit LDS.
 bool split_axis(int64_t n, const std::vector<int>& rho, int64_t st, int64_t outer, size_t elem,
                 const GroupCaps& caps, const TuneVal* tv, const TuneVal* tsplit,
-                std::vector<Seg>& segs) {
+                std::vector<Seg>& segs, size_t budget) {
   const int t = (int)rho.size();
+  // LDS of a strided piece's tile (16 columns, or the stride) above which
+  // the axis is cut: one resident block per CU otherwise
+  const size_t strided_cap = (size_t)std::max(8, env_int("PAFC_TUNE_STRIDED_KB", 72)) * 1024;
   auto tile16 = [&](int64_t L) { return tile_lds_bytes((uint64_t)L * 16, elem); };
   // a strided piece's tile is at most 16 columns wide, and no wider than
   // the stride (its column count)
@@ -717,11 +775,11 @@ bool split_axis(int64_t n, const std::vector<int>& rho, int64_t st, int64_t oute
   if (tsplit) {
     while (ti < t && ni < tsplit->split) ni *= rho[ti++];
     if (ni != tsplit->split) return false;
-  } else if (!fits_lds(n, elem) && st == 1) {
+  } else if (!fits_lds(n, elem, budget) && st == 1) {
     const size_t cap = elem == 16 ? 4096 : 8192;
     while (ti < t - 1 && ni * rho[ti] <= (int64_t)cap) ni *= rho[ti++];
-  } else if (st > 1 && tilew(n) > 72 * 1024) {
-    while (ti < t - 1 && tilew(ni * rho[ti]) <= 72 * 1024) ni *= rho[ti++];
+  } else if (st > 1 && tilew(n) > strided_cap) {
+    while (ti < t - 1 && tilew(ni * rho[ti]) <= strided_cap) ni *= rho[ti++];
     if (n / ni < 2) ti = 0, ni = 1;
   }
   // an outer piece that does not fit LDS, or whose tile would be too narrow
@@ -733,26 +791,27 @@ bool split_axis(int64_t n, const std::vector<int>& rho, int64_t st, int64_t oute
     o.L = (uint32_t)L;
     o.ncols = (uint32_t)std::min<int64_t>(n / L * st, UINT32_MAX);
     o.n_tw = n;
-    o.tw_global = twiddles_global(L, n, elem);
+    o.lds = budget;
+    o.tw_global = twiddles_global(L, n, elem, budget);
     choose_width(o, elem, 0);
     return o.W;
   };
   if (ti > 0 && !tsplit) {
-    if (!fits_lds(n / ni, elem)) {
+    if (!fits_lds(n / ni, elem, budget)) {
       // far too long for one outer piece: 16-column outer tiles within
       // 72 KB, like every other strided pass
-      while (ti < t - 1 && tile16(n / ni) > 72 * 1024) ni *= rho[ti++];
+      while (ti < t - 1 && tile16(n / ni) > strided_cap) ni *= rho[ti++];
     } else {
       // 8 columns at least; an axis of a grid (stride > 1) is held to the
       // 16-column tiles within 72 KB of every other strided pass (the 1-D
       // pieces keep 8 columns: the tuned 1-D plans were measured so)
       while (ti < t - 1 &&
-             (outer_width(n / ni) < 8 || (st > 1 && tile16(n / ni) > 72 * 1024)))
+             (outer_width(n / ni) < 8 || (st > 1 && tile16(n / ni) > strided_cap)))
         ni *= rho[ti++];
     }
   }
   if (ti == 0) {
-    if (!fits_lds(n, elem)) return false;
+    if (!fits_lds(n, elem, budget)) return false;
     Seg s;
     s.L = (uint32_t)n;
     s.rho = rho;
@@ -774,14 +833,15 @@ bool split_axis(int64_t n, const std::vector<int>& rho, int64_t st, int64_t oute
       s.nouter = (uint32_t)outer;
     }
     if ((uint64_t)outer >= (1ull << 32) || (uint64_t)st >= (1ull << 32)) return false;
-    s.tw_global = twiddles_global(s.L, s.n_tw, elem);
+    s.lds = budget;
+    s.tw_global = twiddles_global(s.L, s.n_tw, elem, budget);
     choose_width(s, elem, tv ? tv->W : 0);
-    if (tile_lds_bytes(s.L * (uint64_t)s.W, elem) > kLdsBudget) return false;
+    if (tile_lds_bytes(s.L * (uint64_t)s.W, elem) > budget) return false;
     segs.push_back(s);
     return true;
   }
   const int64_t no = n / ni;
-  if (!fits_lds(no, elem) || ti == t) return false;
+  if (!fits_lds(no, elem, budget) || ti == t) return false;
   if ((uint64_t)ni * st >= (1ull << 32) || (uint64_t)outer * no >= (1ull << 32)) return false;
   // element (o, i_o, i_i, f) of the sub-axis sits at
   // o*n*st + i_o*ni*st + i_i*st + f
@@ -799,16 +859,27 @@ bool split_axis(int64_t n, const std::vector<int>& rho, int64_t st, int64_t oute
   so.n_tw = n;
   so.rho.assign(rho.begin() + ti, rho.end());
   so.caps = caps;
-  so.tw_global = twiddles_global(so.L, so.n_tw, elem);
+  so.lds = budget;
+  so.tw_global = twiddles_global(so.L, so.n_tw, elem, budget);
   choose_width(so, elem, tv ? tv->Wo : 0);
   segs.push_back(so);
   // inner: an axis of length ni at stride st, one block per (o, i_o)
   const std::vector<int> rin(rho.begin(), rho.begin() + ti);
-  return split_axis(ni, rin, st, outer * no, elem, caps, tv, nullptr, segs);
+  return split_axis(ni, rin, st, outer * no, elem, caps, tv, nullptr, segs, budget);
 }
 
+// Limits a caller may put on a plan beyond the device's: the LDS one tile
+// may use, and the largest radix-3 / radix-5 register groups (0: no limit
+// beyond the planner's own).  The persistent batched launch runs every pass
+// of every size class in one kernel whose LDS size and register class are
+// fixed for the whole launch.
+struct PlanLimits {
+  size_t lds = kLdsBudget;
+  int g3 = 0, g5 = 0;
+};
+
 pafc_status plan_once(PlanCore& P, int ndim, const int64_t* dims, const int* radix, int dtype,
-                      int variant, bool use_table) {
+                      int variant, bool use_table, const PlanLimits& lim) {
   if (ndim < 1 || ndim > 3 || !dims) return PAFC_ERROR_INVALID_VALUE;
   if (dtype != PAFC_C64 && dtype != PAFC_C128) return PAFC_ERROR_INVALID_VALUE;
   if (variant < PAFC_PERM_FREE || variant > PAFC_PERM_FREE_UNFUSED) return PAFC_ERROR_INVALID_VALUE;
@@ -854,6 +925,8 @@ pafc_status plan_once(PlanCore& P, int ndim, const int64_t* dims, const int* rad
     GroupCaps caps;
     caps.g3 = tuned && tv.gmax3 > 0 ? tv.gmax3 : env_int("PAFC_TUNE_GMAX3", 3);
     caps.g5 = tuned && tv.gmax5 > 0 ? tv.gmax5 : env_int("PAFC_TUNE_GMAX5", 2);
+    if (lim.g3 > 0) caps.g3 = std::min(caps.g3, lim.g3);
+    if (lim.g5 > 0) caps.g5 = std::min(caps.g5, lim.g5);
     // Cut the axis into pieces (G2): an outer piece takes its outermost
     // stages, strided over the inner length; the inner length is again an
     // axis of its own and is cut the same way while it is too long.  A piece
@@ -862,7 +935,8 @@ pafc_status plan_once(PlanCore& P, int ndim, const int64_t* dims, const int* rad
     // block, or at the top level of a 1-D transform when the tuning table
     // says so (the table is measured on 1-D transforms).
     const TuneVal* tvp = tuned && tv.split > 0 && tv.split < ax.n && ndim == 1 ? &tv : nullptr;
-    if (!split_axis(ax.n, ax.rho, st, outer, P.elem, caps, tuned ? &tv : nullptr, tvp, ax.segs))
+    if (!split_axis(ax.n, ax.rho, st, outer, P.elem, caps, tuned ? &tv : nullptr, tvp, ax.segs,
+                    lim.lds))
       return PAFC_ERROR_UNSUPPORTED_SIZE;
   }
   // twiddle tables, one per distinct n_tw
@@ -921,7 +995,7 @@ pafc_status plan_once(PlanCore& P, int ndim, const int64_t* dims, const int* rad
     if (ok) {
       mseg.W = (uint32_t)cs;
       const size_t tw = mseg.tw_global ? 0 : twl_bytes(mseg.n_tw, P.elem);
-      ok = tile_lds_bytes((uint64_t)mseg.L * mseg.W, P.elem) + tw <= kLdsBudget;
+      ok = tile_lds_bytes((uint64_t)mseg.L * mseg.W, P.elem) + tw <= lim.lds;
     }
     if (!ok) fold.clear();
   }
@@ -1023,11 +1097,11 @@ pafc_status plan_once(PlanCore& P, int ndim, const int64_t* dims, const int* rad
 // transform is one middle pass, which single radix-3 groups would give more
 // ops than a pass holds): the plan is then made with the planner defaults.
 pafc_status plan_core(PlanCore& P, int ndim, const int64_t* dims, const int* radix, int dtype,
-                      int variant) {
-  pafc_status st = plan_once(P, ndim, dims, radix, dtype, variant, true);
+                      int variant, const PlanLimits& lim = PlanLimits()) {
+  pafc_status st = plan_once(P, ndim, dims, radix, dtype, variant, true, lim);
   if (st != PAFC_ERROR_UNSUPPORTED_SIZE) return st;
   P = PlanCore();
-  return plan_once(P, ndim, dims, radix, dtype, variant, false);
+  return plan_once(P, ndim, dims, radix, dtype, variant, false, lim);
 }
 
 std::string describe_core(const PlanCore& P) {
@@ -1214,7 +1288,7 @@ pafc_status run_pass(pafc_plan_t p, const Pass& ps, const void* in, void* out, h
   if (ps.pipe && ps.pipe_grid > 0)
     return from_hip(launch_pipe(dbl, ps.pipe_r, ps.pipe_g, ps.pipe_ng, ps.pipe_kind, ps.pipe_mode,
                                 p->d_descs + ps.desc, ps.pipe_grid, ps.pipe_threads, ps.pipe_lds,
-                                in, out, s));
+                                in, out, s, ps.pipe_gm, ps.pipe_xc));
 
   return from_hip(launch_pass(dbl, ps.cls, p->d_descs + ps.desc, ps.a.ntiles, in, out, ps.threads,
                               ps.lds, s));
@@ -2000,19 +2074,19 @@ pafc_status pafc_describe(int ndim, const int64_t* dims, const int* radix, pafc_
   return PAFC_SUCCESS;
 }
 
-pafc_status pafc_plan(pafc_plan_t* out, int ndim, const int64_t* dims, const int* radix,
-                      pafc_dtype dtype, pafc_variant variant, void* hip_stream) {
-  if (!out) return PAFC_ERROR_INVALID_VALUE;
+}  // extern "C"
+
+namespace {
+
+// A plan of a {2,3,5}-smooth shape under the given limits (pafc_plan's
+// direct route).
+pafc_status make_plan(pafc_plan_t* out, int ndim, const int64_t* dims, const int* radix,
+                      pafc_dtype dtype, pafc_variant variant, void* hip_stream,
+                      const PlanLimits& lim) {
   *out = nullptr;
-  if (variant == PAFC_PRIME_FACTOR || variant == PAFC_PRIME_FACTOR_EXPLICIT)
-    return plan_prime_factor(out, ndim, dims, radix, dtype, variant, hip_stream);
-  if (is_rader_case(ndim, dims, radix, variant))
-    return plan_rader(out, dims[0], dtype, variant, hip_stream);
-  if (is_bluestein_case(ndim, dims, radix, variant))
-    return plan_bluestein(out, dims[0], dtype, variant, hip_stream);
   pafc_plan_t p = new (std::nothrow) pafc_plan_s;
   if (!p) return PAFC_ERROR_OUT_OF_MEMORY;
-  pafc_status st = plan_core(p->P, ndim, dims, radix, dtype, variant);
+  pafc_status st = plan_core(p->P, ndim, dims, radix, dtype, variant, lim);
   if (st != PAFC_SUCCESS) {
     delete p;
     return st;
@@ -2089,7 +2163,8 @@ pafc_status pafc_plan(pafc_plan_t* out, int ndim, const int64_t* dims, const int
         if (!ps.pipe) continue;
         int nb = ncu > 0 ? pipe_blocks_per_cu(P.dtype == PAFC_C128, ps.pipe_r, ps.pipe_g,
                                               ps.pipe_ng, ps.pipe_kind, ps.pipe_mode,
-                                              ps.pipe_threads, ps.pipe_lds)
+                                              ps.pipe_threads, ps.pipe_lds, ps.pipe_gm,
+                                              ps.pipe_xc)
                          : 0;
         const int64_t want = (int64_t)nb * ncu;
         ps.pipe_grid = (uint32_t)std::min<int64_t>(want, ps.a.ntiles);
@@ -2109,6 +2184,8 @@ pafc_status pafc_plan(pafc_plan_t* out, int ndim, const int64_t* dims, const int
     const Pass& f = P.fwd.back();
     const PassArgs &x = m.a, &y = f.a;
     p->h_tm = m.pipe && f.pipe && m.pipe_r == f.pipe_r && m.pipe_g == f.pipe_g &&
+              m.pipe_gm == m.pipe_g && f.pipe_gm == f.pipe_g && m.pipe_xc == 0 &&
+              f.pipe_xc == 0 &&
               m.pipe_ng == f.pipe_ng && m.pipe_threads == f.pipe_threads &&
               m.pipe_mode == MODE_STRIDED && f.pipe_mode == MODE_STRIDED &&
               x.mode == MODE_STRIDED &&
@@ -2196,6 +2273,23 @@ pafc_status pafc_plan(pafc_plan_t* out, int ndim, const int64_t* dims, const int
              (size_t)h_elems * P.elem;
   *out = p;
   return PAFC_SUCCESS;
+}
+
+}  // namespace
+
+extern "C" {
+
+pafc_status pafc_plan(pafc_plan_t* out, int ndim, const int64_t* dims, const int* radix,
+                      pafc_dtype dtype, pafc_variant variant, void* hip_stream) {
+  if (!out) return PAFC_ERROR_INVALID_VALUE;
+  *out = nullptr;
+  if (variant == PAFC_PRIME_FACTOR || variant == PAFC_PRIME_FACTOR_EXPLICIT)
+    return plan_prime_factor(out, ndim, dims, radix, dtype, variant, hip_stream);
+  if (is_rader_case(ndim, dims, radix, variant))
+    return plan_rader(out, dims[0], dtype, variant, hip_stream);
+  if (is_bluestein_case(ndim, dims, radix, variant))
+    return plan_bluestein(out, dims[0], dtype, variant, hip_stream);
+  return make_plan(out, ndim, dims, radix, dtype, variant, hip_stream, PlanLimits());
 }
 
 pafc_status pafc_destroy(pafc_plan_t p) {
@@ -2490,10 +2584,13 @@ pafc_status pafc_twiddle(int64_t n, int64_t e, double* re, double* im) {
   return PAFC_SUCCESS;
 }
 
-pafc_status pafc_stream_copy(const void* src_dev, void* dst_dev, size_t bytes, void* hip_stream) {
-  if (!src_dev || !dst_dev || (bytes % 16) != 0) return PAFC_ERROR_INVALID_VALUE;
+pafc_status pafc_stream_copy(const void* src_dev, void* dst_dev, size_t bytes, int kind,
+                             void* hip_stream) {
+  if (!src_dev || !dst_dev || (bytes % 16) != 0 || kind < 0 || kind > 2)
+    return PAFC_ERROR_INVALID_VALUE;
   if (((uintptr_t)src_dev & 15) || ((uintptr_t)dst_dev & 15)) return PAFC_ERROR_INVALID_VALUE;
-  return from_hip(launch_stream_copy(src_dev, dst_dev, (int64_t)(bytes / 16), (hipStream_t)hip_stream));
+  return from_hip(launch_stream_copy(kind, src_dev, dst_dev, (int64_t)(bytes / 16),
+                                     (hipStream_t)hip_stream));
 }
 
 pafc_status pafc_set_tuning(const char* text) {
@@ -2535,6 +2632,7 @@ pafc_status pafc_set_tuning(const char* text) {
 // =================================================================== batch
 
 struct pafc_batch_s {
+  int form = PAFC_BATCH_PERSISTENT;
   int dtype = PAFC_C128;
   size_t elem = 16;
   int count = 0;
@@ -2548,13 +2646,20 @@ struct pafc_batch_s {
   std::vector<bool> fset;
   PassArgs* d_descs = nullptr;
   BatchTile* d_tiles = nullptr;
+  // persistent form: one job per problem, claimed through the control words
+  BatchJob* d_jobs = nullptr;
+  BatchCtl* d_ctl = nullptr;
+  uint32_t njobs = 0;
   struct Level {  // one launch: the tiles of one pass level in one register class
                   // whose LDS needs allow the same number of resident blocks
+                  // (levels form), or the whole batch (persistent form)
     int level = 0;
     uint32_t first = 0, count = 0, threads = 64;
     size_t lds = 0;
     int cls = 0;
     int64_t bytes = 0;  // algorithmic HBM bytes of the launch
+    bool persist = false;
+    uint32_t grid = 0;  // persistent form: resident blocks
   };
   std::vector<Level> levels;
   std::string desc;
@@ -2569,7 +2674,34 @@ void free_batch(pafc_batch_t b) {
     if (p) (void)hipFree(p);
   if (b->d_descs) (void)hipFree(b->d_descs);
   if (b->d_tiles) (void)hipFree(b->d_tiles);
+  if (b->d_jobs) (void)hipFree(b->d_jobs);
+  if (b->d_ctl) (void)hipFree(b->d_ctl);
   delete b;
+}
+
+hipError_t launch_level(pafc_batch_t b, const pafc_batch_s::Level& L, const void* x, void* y,
+                        hipStream_t s) {
+  const bool dbl = b->dtype == PAFC_C128;
+  if (L.persist)
+    return launch_batch_persist(dbl, b->d_descs, b->d_jobs, b->njobs, b->d_ctl, L.grid, L.lds, x,
+                                y, s);
+  return launch_batch(dbl, L.cls, b->d_descs, b->d_tiles, L.first, L.count, L.level == 0 ? x : y,
+                      y, L.threads, L.lds, s);
+}
+
+// Limits of the size-class plans of the persistent form: every pass runs in
+// one kernel of 256 threads, the register class of groups up to R = 16 (so
+// radix-3 groups of at most 2 stages, radix-5 of 1), and one dynamic LDS
+// size for the whole launch, which sets the resident blocks per CU: tiles
+// are held to PAFC_BATCH_LDS_KB (measured best on the mixed workload: 80 KB
+// in FP64, two blocks per CU; 32 KB in FP32, five).
+PlanLimits persist_limits(int dtype) {
+  PlanLimits lim;
+  const int kb = env_int("PAFC_BATCH_LDS_KB", dtype == PAFC_C128 ? 80 : 32);
+  lim.lds = (size_t)std::max(16, std::min(156, kb)) * 1024;  // below the 159 KB limit
+  lim.g3 = 2;
+  lim.g5 = 1;
+  return lim;
 }
 }  // namespace
 
@@ -2577,13 +2709,18 @@ extern "C" {
 
 pafc_status pafc_batch_plan(pafc_batch_t* out, int count, const int64_t* sizes,
                             const int* filter_ids, int nfilters, pafc_dtype dtype,
-                            void* hip_stream) {
+                            pafc_batch_form form, void* hip_stream) {
   if (!out) return PAFC_ERROR_INVALID_VALUE;
   *out = nullptr;
   if (count < 1 || !sizes || !filter_ids || nfilters < 1) return PAFC_ERROR_INVALID_VALUE;
   if (dtype != PAFC_C64 && dtype != PAFC_C128) return PAFC_ERROR_INVALID_VALUE;
+  if (form != PAFC_BATCH_PERSISTENT && form != PAFC_BATCH_LEVELS && form != PAFC_BATCH_AUTO)
+    return PAFC_ERROR_INVALID_VALUE;
+  // the form measured faster for the element type on the mixed workload
+  if (form == PAFC_BATCH_AUTO) form = dtype == PAFC_C128 ? PAFC_BATCH_PERSISTENT : PAFC_BATCH_LEVELS;
   pafc_batch_t b = new (std::nothrow) pafc_batch_s;
   if (!b) return PAFC_ERROR_OUT_OF_MEMORY;
+  b->form = form;
   b->dtype = dtype;
   b->elem = dtype == PAFC_C128 ? 16 : 8;
   b->count = count;
@@ -2617,7 +2754,8 @@ pafc_status pafc_batch_plan(pafc_batch_t* out, int count, const int64_t* sizes,
     b->total += n;
     if (!b->plans.count(n)) {
       pafc_plan_t p = nullptr;
-      pafc_status st = pafc_plan(&p, 1, &n, nullptr, dtype, PAFC_PERM_FREE, hip_stream);
+      const PlanLimits lim = form == PAFC_BATCH_PERSISTENT ? persist_limits(dtype) : PlanLimits();
+      pafc_status st = make_plan(&p, 1, &n, nullptr, dtype, PAFC_PERM_FREE, hip_stream, lim);
       if (st != PAFC_SUCCESS) return fail(st);
       b->plans[n] = p;
     }
@@ -2659,10 +2797,51 @@ pafc_status pafc_batch_plan(pafc_batch_t* out, int count, const int64_t* sizes,
                    [&](int x, int y) { return b->sizes[(size_t)x] > b->sizes[(size_t)y]; });
   auto blocks_per_cu = [](size_t lds) { return (int)std::min<size_t>(8, kLdsBudget / std::max<size_t>(lds, 1)); };
   std::vector<BatchTile> tiles;
+  std::vector<BatchJob> jobs;
   // every pass level of the longest plan (a 1-D plan has 1, 3 or, for
   // lengths cut twice, 5 passes)
   int nlevels = 0;
   for (auto& kv : b->plans) nlevels = std::max(nlevels, (int)kv.second->P.conv.size());
+  if (form == PAFC_BATCH_PERSISTENT) {
+    // one job per problem, largest first: every pass of its size class, whose
+    // descriptors are consecutive from the first one
+    pafc_batch_s::Level L;
+    L.persist = true;
+    L.threads = 256;
+    for (size_t d = 0; d < descs.size(); ++d) {
+      // the kernel holds the register groups up to R = 16 (class 0; class 2
+      // is a subset of it)
+      if (dcls[d] == 1) return fail(PAFC_ERROR_UNSUPPORTED_SIZE);
+      L.lds = std::max(L.lds, dlds[d]);
+    }
+    std::vector<bool> fseen((size_t)nfilters, false);
+    for (int i : order) {
+      const int f = b->fid[(size_t)i];
+      const pafc_plan_t pp = b->plans[b->sizes[(size_t)i]];
+      const uint32_t d0 = didx.at({f, 0});
+      const uint32_t np = (uint32_t)pp->P.conv.size();
+      for (uint32_t q = 1; q < np; ++q)
+        if (didx.at({f, (int)q}) != d0 + q) return fail(PAFC_ERROR_DEVICE);
+      jobs.push_back(BatchJob{d0, np, b->offsets[(size_t)i]});
+      L.bytes += 2 * (int64_t)np * b->sizes[(size_t)i] * (int64_t)b->elem;
+      if (!fseen[(size_t)f]) {
+        fseen[(size_t)f] = true;
+        L.bytes += b->sizes[(size_t)i] * (int64_t)b->elem;
+      }
+    }
+    int ncu = 0;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      return fail(PAFC_ERROR_DEVICE);
+    const int bpc = batch_persist_blocks_per_cu(b->dtype == PAFC_C128, L.lds);
+    if (bpc <= 0 || ncu <= 0) return fail(PAFC_ERROR_DEVICE);
+    L.grid = (uint32_t)std::min<int64_t>((int64_t)bpc * ncu, (int64_t)jobs.size());
+    L.count = (uint32_t)jobs.size();
+    b->njobs = (uint32_t)jobs.size();
+    b->levels.push_back(L);
+    nlevels = 0;  // no level launches
+  }
   for (int l = 0; l < nlevels; ++l) {
     for (int cls = 0; cls < 3; ++cls)
     for (int bpc = 1; bpc <= 8; ++bpc) {
@@ -2703,9 +2882,27 @@ pafc_status pafc_batch_plan(pafc_batch_t* out, int count, const int64_t* sizes,
       if (t.offset < 0 || t.offset + n > b->total || t.tile >= descs[t.desc].ntiles)
         return fail(PAFC_ERROR_INVALID_VALUE);
     }
+    for (const BatchJob& j : jobs) {
+      if (j.npass == 0 || (size_t)j.desc + j.npass > descs.size())
+        return fail(PAFC_ERROR_INVALID_VALUE);
+      for (uint32_t q = 0; q < j.npass; ++q) {
+        const int64_t n = desc_n[j.desc + q];
+        if (j.offset < 0 || j.offset + n > b->total || n != desc_n[j.desc])
+          return fail(PAFC_ERROR_INVALID_VALUE);
+      }
+    }
   }
   hipError_t e = hipMalloc((void**)&b->d_descs, descs.size() * sizeof(PassArgs));
   if (e == hipSuccess) e = hipMalloc((void**)&b->d_tiles, std::max<size_t>(1, tiles.size()) * sizeof(BatchTile));
+  if (e == hipSuccess && !jobs.empty()) {
+    e = hipMalloc((void**)&b->d_jobs, jobs.size() * sizeof(BatchJob));
+    if (e == hipSuccess) e = hipMalloc((void**)&b->d_ctl, sizeof(BatchCtl));
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(b->d_jobs, jobs.data(), jobs.size() * sizeof(BatchJob),
+                         hipMemcpyHostToDevice, s);
+    // zero once here; each launch leaves the control words zero again
+    if (e == hipSuccess) e = hipMemsetAsync(b->d_ctl, 0, sizeof(BatchCtl), s);
+  }
   if (e == hipSuccess)
     e = hipMemcpyAsync(b->d_descs, descs.data(), descs.size() * sizeof(PassArgs),
                        hipMemcpyHostToDevice, s);
@@ -2717,14 +2914,22 @@ pafc_status pafc_batch_plan(pafc_batch_t* out, int count, const int64_t* sizes,
   // description and bytes
   char buf[256];
   snprintf(buf, sizeof(buf),
-           "{\"count\": %d, \"total_elems\": %lld, \"size_classes\": %zu, \"levels\": [", count,
-           (long long)b->total, b->plans.size());
+           "{\"count\": %d, \"total_elems\": %lld, \"size_classes\": %zu, \"form\": \"%s\", "
+           "\"levels\": [",
+           count, (long long)b->total, b->plans.size(),
+           form == PAFC_BATCH_PERSISTENT ? "persistent" : "levels");
   b->desc = buf;
   for (size_t l = 0; l < b->levels.size(); ++l) {
     auto& L = b->levels[l];
-    snprintf(buf, sizeof(buf),
-             "%s{\"level\": %d, \"tiles\": %u, \"threads\": %u, \"lds\": %zu, \"cls\": %d}",
-             l ? ", " : "", L.level, L.count, L.threads, L.lds, L.cls);
+    if (L.persist)
+      snprintf(buf, sizeof(buf),
+               "%s{\"persistent\": 1, \"jobs\": %u, \"grid\": %u, \"threads\": %u, "
+               "\"lds\": %zu}",
+               l ? ", " : "", L.count, L.grid, L.threads, L.lds);
+    else
+      snprintf(buf, sizeof(buf),
+               "%s{\"level\": %d, \"tiles\": %u, \"threads\": %u, \"lds\": %zu, \"cls\": %d}",
+               l ? ", " : "", L.level, L.count, L.threads, L.lds, L.cls);
     b->desc += buf;
   }
   b->desc += "], \"plans\": [";
@@ -2735,7 +2940,8 @@ pafc_status pafc_batch_plan(pafc_batch_t* out, int count, const int64_t* sizes,
     b->desc += describe_core(kv.second->P);
   }
   b->desc += "]}";
-  b->bytes = descs.size() * sizeof(PassArgs) + tiles.size() * sizeof(BatchTile);
+  b->bytes = descs.size() * sizeof(PassArgs) + tiles.size() * sizeof(BatchTile) +
+             jobs.size() * sizeof(BatchJob) + (jobs.empty() ? 0 : sizeof(BatchCtl));
   for (auto& kv : b->plans) b->bytes += kv.second->bytes - (size_t)kv.second->P.N * b->elem;
   for (int f = 0; f < nfilters; ++f) b->bytes += (size_t)b->fsize[(size_t)f] * b->elem;
   *out = b;
@@ -2769,12 +2975,7 @@ pafc_status pafc_batch_convolve(pafc_batch_t b, const void* x_dev, void* y_dev, 
   for (int i = 0; i < b->count; ++i)
     if (!b->fset[(size_t)b->fid[(size_t)i]]) return PAFC_ERROR_FILTER_NOT_SET;
   hipStream_t s = (hipStream_t)hip_stream;
-  const bool dbl = b->dtype == PAFC_C128;
-  for (auto& L : b->levels) {
-    const void* src = L.level == 0 ? x_dev : y_dev;
-    PAFC_TRY(from_hip(launch_batch(dbl, L.cls, b->d_descs, b->d_tiles, L.first, L.count, src,
-                                   y_dev, L.threads, L.lds, s)));
-  }
+  for (auto& L : b->levels) PAFC_TRY(from_hip(launch_level(b, L, x_dev, y_dev, s)));
   return PAFC_SUCCESS;
 }
 
@@ -2791,7 +2992,6 @@ pafc_status pafc_batch_profile(pafc_batch_t b, const void* x_dev, void* y_dev, v
   for (int i = 0; i < b->count; ++i)
     if (!b->fset[(size_t)b->fid[(size_t)i]]) return PAFC_ERROR_FILTER_NOT_SET;
   hipStream_t s = (hipStream_t)hip_stream;
-  const bool dbl = b->dtype == PAFC_C128;
   std::vector<hipEvent_t> ev((size_t)(n + 1) * reps, nullptr);
   pafc_status st = PAFC_SUCCESS;
   for (auto& e : ev)
@@ -2801,8 +3001,7 @@ pafc_status pafc_batch_profile(pafc_batch_t b, const void* x_dev, void* y_dev, v
     st = from_hip(hipEventRecord(E[0], s));
     for (int k = 0; k < n && st == PAFC_SUCCESS; ++k) {
       auto& L = b->levels[used[(size_t)k]];
-      st = from_hip(launch_batch(dbl, L.cls, b->d_descs, b->d_tiles, L.first, L.count,
-                                 L.level == 0 ? x_dev : y_dev, y_dev, L.threads, L.lds, s));
+      st = from_hip(launch_level(b, L, x_dev, y_dev, s));
       if (st == PAFC_SUCCESS) st = from_hip(hipEventRecord(E[k + 1], s));
     }
   }

@@ -150,4 +150,18 @@ struct BatchTile {
   int64_t offset;   // element offset of the problem in the packed arrays
 };
 
+// Jobs of the persistent batched launch: one whole problem, all of its
+// passes, run by the block that claims it.
+struct BatchJob {
+  uint32_t desc;    // index of the PassArgs of its first pass; the others follow
+  uint32_t npass;   // passes of its size class
+  int64_t offset;   // element offset of the problem in the packed arrays
+};
+
+// Control words of the persistent batched launch (zero between launches).
+struct BatchCtl {
+  uint32_t next;    // next job to claim
+  uint32_t exited;  // blocks that have left the claim loop
+};
+
 }  // namespace pafc

@@ -44,6 +44,52 @@ __global__ void __launch_bounds__(class_max_threads<CLS>()) batch_kernel(const P
   do_tile<T, CLS>(descs[bt.desc], in, out, bt.tile, bt.offset, lds);
 }
 
+// Persistent batched form: one launch for the whole batch.  A resident
+// block claims whole problems from a device counter, in the host's order
+// (largest first), and runs every pass of a problem itself, tile by tile;
+// so a pass's dependence on the previous pass of the same problem is
+// ordered by the block's own barriers, and blocks never wait for each
+// other.  The last block to leave resets the control words, so the launch
+// can be replayed (a captured graph) without a memset between launches.
+template <typename T>
+__global__ void __launch_bounds__(256) batch_persist_kernel(const PassArgs* __restrict__ descs,
+                                                            const BatchJob* __restrict__ jobs,
+                                                            uint32_t njobs, BatchCtl* ctl,
+                                                            const void* in, void* out) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
+  __shared__ uint32_t s_job;
+  for (;;) {
+    if (threadIdx.x == 0)
+      s_job = __hip_atomic_fetch_add(&ctl->next, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    const uint32_t k = __builtin_amdgcn_readfirstlane(s_job);
+    __syncthreads();  // every thread has read s_job before thread 0 writes it again
+    if (k >= njobs) break;
+    const BatchJob j = jobs[k];
+    for (uint32_t q = 0; q < j.npass; ++q) {
+      const PassArgs& a = descs[j.desc + q];
+      // the first pass reads the input, the later ones work in place on the
+      // output (which the previous pass of this block wrote)
+      const void* src = q == 0 ? in : out;
+      for (uint32_t t = 0; t < a.ntiles; ++t) {
+        do_tile<T, 0>(a, src, out, t, j.offset, lds);
+        // LDS is reused by the next tile, and the next pass reads what this
+        // one wrote to global memory: a workgroup-scope fence and barrier
+        __syncthreads();
+      }
+    }
+  }
+  if (threadIdx.x == 0) {
+    const uint32_t before =
+        __hip_atomic_fetch_add(&ctl->exited, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    if (before == gridDim.x - 1) {  // every other block has left the loop
+      __hip_atomic_store(&ctl->next, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&ctl->exited, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
 // ------------------------------------------------------------ elementwise
 
 template <typename T>
@@ -61,6 +107,38 @@ __global__ void stream_copy_kernel(const double2* __restrict__ a, double2* __res
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
     b[i] = a[i];
+}
+
+// The same copy with 8 bytes per lane.
+__global__ void stream_copy8_kernel(const uint64_t* __restrict__ a, uint64_t* __restrict__ b,
+                                    int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    b[i] = a[i];
+}
+
+// Read-only sweep: every 16-byte element read once; one 16-byte sum per
+// block is written (so the reads cannot be dropped), a negligible write.
+__global__ void __launch_bounds__(256) stream_read_kernel(const double2* __restrict__ a,
+                                                          double2* __restrict__ out, int64_t n) {
+  __shared__ double2 part[256];
+  double2 acc = {0.0, 0.0};
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const double2 v = a[i];
+    acc.x += v.x;
+    acc.y += v.y;
+  }
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  for (uint32_t h = blockDim.x / 2; h > 0; h /= 2) {
+    if (threadIdx.x < h) {
+      part[threadIdx.x].x += part[threadIdx.x + h].x;
+      part[threadIdx.x].y += part[threadIdx.x + h].y;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] = part[0];
 }
 
 template <typename T>
@@ -512,6 +590,35 @@ hipError_t launch_batch(bool dbl, int cls, const PassArgs* descs, const BatchTil
 #undef PAFC_LB
 }
 
+template <typename T>
+static const void* persist_fn() {
+  return (const void*)batch_persist_kernel<T>;
+}
+
+int batch_persist_blocks_per_cu(bool dbl, size_t lds_bytes) {
+  const void* fn = dbl ? persist_fn<double>() : persist_fn<float>();
+  // the kernel's static LDS (the claimed job) counts against the same 160 KB
+  if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 159 * 1024) != hipSuccess)
+    return 0;
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, 256, lds_bytes) != hipSuccess) return 0;
+  return nb;
+}
+
+// The dynamic LDS limit was raised at planning (batch_persist_blocks_per_cu).
+hipError_t launch_batch_persist(bool dbl, const PassArgs* descs, const BatchJob* jobs,
+                                uint32_t njobs, BatchCtl* ctl, uint32_t grid, size_t lds_bytes,
+                                const void* in, void* out, hipStream_t s) {
+  if (grid == 0) return hipErrorInvalidValue;
+  if (dbl)
+    hipLaunchKernelGGL(batch_persist_kernel<double>, dim3(grid), dim3(256), lds_bytes, s, descs,
+                       jobs, njobs, ctl, in, out);
+  else
+    hipLaunchKernelGGL(batch_persist_kernel<float>, dim3(grid), dim3(256), lds_bytes, s, descs,
+                       jobs, njobs, ctl, in, out);
+  return hipGetLastError();
+}
+
 static uint32_t grid_for(int64_t n) {
   int64_t b = (n + 255) / 256;
   if (b > 65536) b = 65536;
@@ -654,9 +761,18 @@ hipError_t launch_rader(bool dbl, int stage, int mode, const void* src, const vo
   return hipGetLastError();
 }
 
-hipError_t launch_stream_copy(const void* src, void* dst, int64_t n16, hipStream_t st) {
-  hipLaunchKernelGGL(stream_copy_kernel, dim3(grid_for(n16)), dim3(256), 0, st,
-                     (const double2*)src, (double2*)dst, n16);
+hipError_t launch_stream_copy(int kind, const void* src, void* dst, int64_t n16, hipStream_t st) {
+  if (kind == 0)
+    hipLaunchKernelGGL(stream_copy_kernel, dim3(grid_for(n16)), dim3(256), 0, st,
+                       (const double2*)src, (double2*)dst, n16);
+  else if (kind == 1)
+    hipLaunchKernelGGL(stream_copy8_kernel, dim3(grid_for(2 * n16)), dim3(256), 0, st,
+                       (const uint64_t*)src, (uint64_t*)dst, 2 * n16);
+  else if (kind == 2)  // at most 65536 blocks, so at most 1 MiB of dst is written
+    hipLaunchKernelGGL(stream_read_kernel, dim3(grid_for(n16)), dim3(256), 0, st,
+                       (const double2*)src, (double2*)dst, n16);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

@@ -19,9 +19,13 @@ namespace pafc {
 
 enum { PIPE_FWD = 0, PIPE_INV = 1, PIPE_MID = 2 };
 
-template <int R, int NG, int KIND>
+// An axis of NG groups: NG - 1 of radix R and, innermost, one of radix RM
+// (RM divides R; RM = R for a uniform axis).  Only the middle pass takes a
+// shorter innermost group: its fused op then runs R / RM items of RM points
+// per thread.
+template <int R, int NG, int KIND, int RM = R>
 struct PipeShape {
-  static constexpr int L = ipow(R, NG);
+  static constexpr int L = ipow(R, NG - 1) * RM;
   static constexpr int NOPS = KIND == PIPE_MID ? 2 * NG - 1 : NG;
   // op i of the pass: its type and its level k (block size K = L / R^k)
   static constexpr int type(int i) {
@@ -74,6 +78,13 @@ constexpr int pipe_waves_per_eu() { return KIND == PIPE_FWD && NG == 2 ? 2 : 1; 
 // thread); the count need not be a multiple of the wave size.
 template <int r, int g>
 constexpr int pipe_max_threads() { return (r == 3 || r == 5) && g == 1 ? 1024 : 256; }
+// FP32 middle passes with folded columns also take 512 threads (a 4096-long
+// axis with two columns): their items fit 2 waves per SIMD unspilled.
+template <typename T, int r, int g, int XC>
+constexpr int pipe_block_limit() {
+  return XC > 0 && sizeof(T) == 4 && !((r == 3 || r == 5) && g == 1) ? 512
+                                                                      : pipe_max_threads<r, g>();
+}
 
 // Outer pieces of a cut axis (MODE_OUTER) are compiled for the shapes the
 // tuned 1-D plans cut off (243 = 3^5 and 625 = 5^4 positions) and the
@@ -84,8 +95,44 @@ constexpr bool pipe_outer_shape() {
          ((r == 3 && (NG == 2 || NG == 4 || NG == 5)) || (r == 5 && (NG == 3 || NG == 4)));
 }
 
-template <typename T, int r, int g, int NG, int KIND, int MODE_ARG>
-__global__ void __launch_bounds__((pipe_max_threads<r, g>()))
+// Butterflies of a 2-point DFT across lane bit b (the two values of a pair
+// of lanes differing in bit b): the lower lane keeps x0 + x1, the upper
+// x0 - x1.  F_2 is its own conjugate, so the same exchange serves the
+// forward and the inverse transform.  The partner's value comes through a
+// DPP quad permutation (lanes stay within their group of four).
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float x) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), CTRL,
+                                                            0xF, 0xF, true));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double x) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, x);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)u, CTRL, 0xF, 0xF, true);
+  const uint32_t hi =
+      (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(u >> 32), CTRL, 0xF, 0xF, true);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// The DFTs of XC folded axes of length 2 along the columns of a strided tile
+// whose row holds exactly those columns (W = 2^XC, column c = lane bits
+// 0..XC-1; axis b has column stride 2^b): a butterfly across each of those
+// lane bits, for all N values a thread holds.
+template <typename T, int XC, int N>
+__device__ __forceinline__ void column_dfts(cx<T>* v, uint32_t lane) {
+  static_for<XC>([&](auto bc) {
+    constexpr int b = decltype(bc)::value;
+    constexpr int CTRL = b == 0 ? 0xB1 : 0x4E;  // quad_perm [1,0,3,2] / [2,3,0,1]
+    const bool upper = ((lane >> b) & 1u) != 0;
+    static_for<N>([&](auto s) {
+      const cx<T> p = {dpp_move<CTRL>(v[s.value].re), dpp_move<CTRL>(v[s.value].im)};
+      v[s.value] = upper ? csub(p, v[s.value]) : cadd(v[s.value], p);
+    });
+  });
+}
+
+template <typename T, int r, int g, int NG, int KIND, int MODE_ARG, int GM = g, int XC = 0>
+__global__ void __launch_bounds__((pipe_block_limit<T, r, g, XC>()))
 __attribute__((amdgpu_waves_per_eu(pipe_waves_per_eu<KIND, NG>())))
 pipe_kernel(const PassArgs* __restrict__ desc, const void* in, void* out) {
   // in and out may be the same array (every pass after the first runs in
@@ -96,7 +143,15 @@ pipe_kernel(const PassArgs* __restrict__ desc, const void* in, void* out) {
   constexpr bool OUTER = MODE_ARG == MODE_OUTER;
   constexpr int MODE = OUTER ? MODE_STRIDED : MODE_ARG;
   constexpr int R = ipow(r, g);
-  using Sh = PipeShape<R, NG, KIND>;
+  // the middle pass's innermost group (RM points; NU of them per thread)
+  // and the folded length-2 column axes (strided tiles only)
+  constexpr int RM = ipow(r, GM);
+  constexpr int NU = R / RM;
+  static_assert(GM <= g && R % RM == 0, "innermost group no larger than the others");
+  static_assert((GM == g && XC == 0) || (KIND == PIPE_MID && MODE == MODE_STRIDED && !OUTER) ||
+                    (GM < g && XC == 0 && KIND == PIPE_MID),
+                "short innermost groups and folded columns in the middle pass only");
+  using Sh = PipeShape<R, NG, KIND, RM>;
   constexpr int L = Sh::L;
   constexpr int NOPS = Sh::NOPS;
   constexpr int MID_OP = NG - 1;
@@ -187,10 +242,12 @@ pipe_kernel(const PassArgs* __restrict__ desc, const void* in, void* out) {
                                    : cx<T>{(T)0, (T)0};
         });
       } else {
+        // slot m = u RM + m2 multiplies frequency m2 of the thread's u-th
+        // innermost group, which sits at its digit-reversed position
         const uint32_t gb = base + it.i0 * S_i + it.c * S_c;
         static_for<R>([&](auto m) {
-          preh[m.value] = it.valid ? ld_g32<T>(a.H, gb + (uint32_t)digrev<r, g>(m.value) * S_i)
-                                   : cx<T>{(T)0, (T)0};
+          constexpr int pos = (m.value / RM) * RM + digrev<r, GM>(m.value % RM);
+          preh[m.value] = it.valid ? ld_g32<T>(a.H, gb + (uint32_t)pos * S_i) : cx<T>{(T)0, (T)0};
         });
       }
     }
@@ -222,7 +279,9 @@ pipe_kernel(const PassArgs* __restrict__ desc, const void* in, void* out) {
       constexpr int i = decltype(opi)::value;
       constexpr int type = Sh::type(i);
       constexpr int k = Sh::level(i);
-      constexpr int K = L / ipow(R, k);
+      // the middle op's items are the thread's R consecutive positions
+      // (NU innermost groups of RM points)
+      constexpr int K = type == OP_MID ? R : L / ipow(R, k);
       constexpr int S = K / R;
       constexpr bool first = (i == 0) && !LINEAR_LOAD;
       constexpr bool last = (i == NOPS - 1) && !LINEAR_STORE;
@@ -266,6 +325,10 @@ pipe_kernel(const PassArgs* __restrict__ desc, const void* in, void* out) {
             v[mm.value + 1] = cmul(v[mm.value + 1], w);
         });
       };
+      // folded column axes: their forward DFTs before the first op's own,
+      // their inverse DFTs after the last op's (they commute with the
+      // stages along the axis)
+      if constexpr (XC > 0 && i == 0) column_dfts<T, XC, R>(v, tid);
       if constexpr (type == OP_DIF) {
         Dft<R, r, false, T>::run(v);
         if constexpr (OUTER) {
@@ -291,13 +354,14 @@ pipe_kernel(const PassArgs* __restrict__ desc, const void* in, void* out) {
         }
         Dft<R, r, true, T>::run(v);
       } else {  // MID
-        Dft<R, r, false, T>::run(v);
+        static_for<NU>([&](auto u) { Dft<RM, r, false, T>::run(v + u.value * RM); });
         const T hs = (T)a.hscale;
         static_for<R>([&](auto m) { v[m.value] = cscale(cmul(v[m.value], preh[m.value]), hs); });
         if constexpr (!PF_LATE)
           if (next < a.ntiles) fetch_h(next);
-        Dft<R, r, true, T>::run(v);
+        static_for<NU>([&](auto u) { Dft<RM, r, true, T>::run(v + u.value * RM); });
       }
+      if constexpr (XC > 0 && i == NOPS - 1) column_dfts<T, XC, R>(v, tid);
       // outputs
       bool tm = false;
       if constexpr (last && KIND == PIPE_FWD) tm = a.tm_store != 0;
@@ -400,13 +464,50 @@ static const void* pipe_fn(int kind, int mode) {
   return nullptr;
 }
 
-static const void* pipe_lookup(bool dbl, int r, int g, int ng, int kind, int mode) {
+// Middle passes whose innermost group is shorter (GM < g stages) and/or
+// whose strided tile row holds XC folded length-2 axes: (r, g, NG, GM, XC).
+#define PAFC_PIPE_MID_SHAPES(X)                      \
+  X(4, 2, 3, 1, 0) /* L = 1024 = 16 x 16 x 4 */      \
+  X(4, 2, 3, 1, 1) /* L = 1024, two columns */       \
+  X(4, 2, 3, 1, 2) /* L = 1024, four columns */      \
+  X(4, 2, 3, 2, 1) /* L = 4096, two columns */       \
+  X(4, 2, 2, 2, 1) /* L = 256, two columns */        \
+  X(4, 2, 2, 2, 2) /* L = 256, four columns */
+
+template <typename T, int r, int g, int NG, int GM, int XC>
+static const void* pipe_mid_fn(int mode) {
+  if (mode == MODE_STRIDED)
+    return (const void*)pipe_kernel<T, r, g, NG, PIPE_MID, MODE_STRIDED, GM, XC>;
+  if constexpr (XC == 0)
+    if (mode == MODE_CONTIG) return (const void*)pipe_kernel<T, r, g, NG, PIPE_MID, MODE_CONTIG, GM, 0>;
+  return nullptr;
+}
+
+static const void* pipe_lookup(bool dbl, int r, int g, int ng, int kind, int mode, int gm = -1,
+                               int xc = 0) {
+  if (gm < 0) gm = g;
+  if (gm != g || xc != 0) {
+    if (kind != PIPE_MID) return nullptr;
+#define PAFC_PIPE_MID_GO(rr, gg, nn, mm, xx)                                              \
+  if (r == rr && g == gg && ng == nn && gm == mm && xc == xx)                             \
+    return dbl ? pipe_mid_fn<double, rr, gg, nn, mm, xx>(mode)                            \
+               : pipe_mid_fn<float, rr, gg, nn, mm, xx>(mode);
+    PAFC_PIPE_MID_SHAPES(PAFC_PIPE_MID_GO)
+#undef PAFC_PIPE_MID_GO
+    return nullptr;
+  }
 #define PAFC_PIPE_GO(rr, gg, nn)                                                          \
   if (r == rr && g == gg && ng == nn)                                                     \
     return dbl ? pipe_fn<double, rr, gg, nn>(kind, mode) : pipe_fn<float, rr, gg, nn>(kind, mode);
   PAFC_PIPE_SHAPES(PAFC_PIPE_GO)
 #undef PAFC_PIPE_GO
   return nullptr;
+}
+
+// A middle pass with a shorter innermost group (gm < g) or folded
+// length-2 column axes (xc > 0) in the given tile mode.
+bool pipe_mid_supported(int r, int g, int ng, int gm, int xc, int mode) {
+  return pipe_lookup(true, r, g, ng, PIPE_MID, mode, gm, xc) != nullptr;
 }
 
 bool pipe_supported(int r, int g, int ng) {
@@ -417,13 +518,17 @@ bool pipe_outer_supported(int r, int g, int ng) {
   return pipe_lookup(true, r, g, ng, PIPE_FWD, MODE_OUTER) != nullptr;
 }
 
-// Most threads a block of the pipelined kernel for groups r^g may have.
-int pipe_thread_limit(int r, int g) { return (r == 3 || r == 5) && g == 1 ? 1024 : 256; }
+// Most threads a block of the pipelined kernel for groups r^g may have (xc:
+// folded column axes of a middle pass).
+int pipe_thread_limit(int r, int g, bool dbl, int xc) {
+  if ((r == 3 || r == 5) && g == 1) return 1024;
+  return xc > 0 && !dbl ? 512 : 256;
+}
 
 // Resident blocks per CU of a pipelined kernel instance (0 on error).
 int pipe_blocks_per_cu(bool dbl, int r, int g, int ng, int kind, int mode, uint32_t threads,
-                       size_t lds) {
-  const void* fn = pipe_lookup(dbl, r, g, ng, kind, mode);
+                       size_t lds, int gm, int xc) {
+  const void* fn = pipe_lookup(dbl, r, g, ng, kind, mode, gm, xc);
   if (!fn) return 0;
   if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) != hipSuccess)
     return 0;
@@ -462,8 +567,8 @@ hipError_t launch_pipe_htm(bool dbl, int r, int g, int ng, int mode, const PassA
 
 hipError_t launch_pipe(bool dbl, int r, int g, int ng, int kind, int mode, const PassArgs* d,
                        uint32_t grid, uint32_t threads, size_t lds, const void* in, void* out,
-                       hipStream_t s) {
-  const void* fn = pipe_lookup(dbl, r, g, ng, kind, mode);
+                       hipStream_t s, int gm, int xc) {
+  const void* fn = pipe_lookup(dbl, r, g, ng, kind, mode, gm, xc);
   if (!fn) return hipErrorInvalidValue;
   // the LDS limit of every instance is raised when its occupancy is queried
   // at plan time (pipe_blocks_per_cu), before any launch

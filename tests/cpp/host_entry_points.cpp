@@ -118,14 +118,18 @@ int main() {
     pafc_batch_t b = nullptr;
     const int64_t sizes[3] = {64, 97, 64};
     const int fids[3] = {0, 1, 0};
-    expect(pafc_batch_plan(&b, 3, sizes, fids, 2, PAFC_C128, nullptr) ==
-               PAFC_ERROR_UNSUPPORTED_SIZE && b == nullptr, "batch non-smooth", 0, 0);
-    const int bad_fids[3] = {0, 0, 0};
-    const int64_t sizes2[3] = {64, 128, 64};
-    expect(pafc_batch_plan(&b, 3, sizes2, bad_fids, 1, PAFC_C128, nullptr) ==
-               PAFC_ERROR_INVALID_VALUE && b == nullptr, "batch filter sizes", 0, 0);
-    expect(pafc_batch_plan(&b, 0, sizes, fids, 1, PAFC_C128, nullptr) ==
-               PAFC_ERROR_INVALID_VALUE, "batch count", 0, 0);
+    for (pafc_batch_form form : {PAFC_BATCH_PERSISTENT, PAFC_BATCH_LEVELS}) {
+      expect(pafc_batch_plan(&b, 3, sizes, fids, 2, PAFC_C128, form, nullptr) ==
+                 PAFC_ERROR_UNSUPPORTED_SIZE && b == nullptr, "batch non-smooth", form, 0);
+      const int bad_fids[3] = {0, 0, 0};
+      const int64_t sizes2[3] = {64, 128, 64};
+      expect(pafc_batch_plan(&b, 3, sizes2, bad_fids, 1, PAFC_C128, form, nullptr) ==
+                 PAFC_ERROR_INVALID_VALUE && b == nullptr, "batch filter sizes", form, 0);
+      expect(pafc_batch_plan(&b, 0, sizes, fids, 1, PAFC_C128, form, nullptr) ==
+                 PAFC_ERROR_INVALID_VALUE, "batch count", form, 0);
+    }
+    expect(pafc_batch_plan(&b, 3, sizes, fids, 2, PAFC_C128, (pafc_batch_form)7, nullptr) ==
+               PAFC_ERROR_INVALID_VALUE && b == nullptr, "batch form", 0, 0);
   }
   for (int s = 0; s <= 6; ++s) expect(pafc_status_string((pafc_status)s) != nullptr, "status", s, 0);
   int smooth_count = 0;

@@ -13,7 +13,7 @@ import pytest
 
 import oracle
 from paper_2506_12718_amd import inputs
-from gpu_util import TOL, check_close, rel_l2, rounded, to_dev, to_host, torch
+from gpu_util import AGREE_C, TOL, check_close, rel_l2, rounded, to_dev, to_host, torch
 
 pytestmark = pytest.mark.gpu
 
@@ -221,3 +221,45 @@ def test_folded_forward_layout(dims, radix, monkeypatch):
     z0 = to_host(P.forward(to_dev(x, C128)))
     P.close()
     check_close(z, z0, 1e-14)
+
+
+# middle passes on the pipelined kernel with folded length-2 columns
+# (exchanged across lanes) and/or a shorter innermost group (16 x 16 x 4)
+MIDX = [
+    ((1024, 2, 2), None, C128),
+    ((1024, 2, 2), None, C64),
+    ((1024, 2), None, C128),
+    ((4096, 2), None, C128),
+    ((256, 2, 2), None, C64),
+    ((2 ** 14, 2, 2), [4, 2, 2], C64),
+    ((2 ** 16, 2), [4, 2], C128),
+    ((2 ** 16, 2, 2), [4, 2, 2], C128),
+    ((4096, 2), None, C64),
+    ((2 ** 16, 2), [4, 2], C64),
+]
+
+
+@pytest.mark.parametrize("dims,radix,dtype", MIDX)
+def test_folded_middle_pass_pipelined(dims, radix, dtype, monkeypatch):
+    """The fused middle pass of an anisotropic grid runs on the pipelined
+    kernel: against the oracle, against the general engine (PAFC_PIPE_MIDX=0)
+    to a few ulps, and unchanged with its LDS poisoned."""
+    dt = "c128" if dtype == C128 else "c64"
+    _, labels = pieces(dims, dt, radix)
+    mid = [l for l in labels if "MID" in l]
+    say("midx", dims, dt, mid)
+    assert len(mid) == 1 and "pipe_kernel" in mid[0] and "XDIF2" in mid[0]
+    rng = np.random.default_rng([dims[0], len(dims), 17])
+    x = inputs.complex_uniform(rng, dims)
+    h = inputs.complex_uniform(rng, dims)
+    y = conv_gpu(x, h, dtype, radix)
+    check_close(y, ref_conv(x, h, dtype), TOL[dtype], "midx %s" % (dims,))
+    monkeypatch.setenv("PAFC_LDS_POISON", "1")
+    yp = conv_gpu(x, h, dtype, radix)
+    assert np.array_equal(y, yp)
+    monkeypatch.delenv("PAFC_LDS_POISON")
+    monkeypatch.setenv("PAFC_PIPE_MIDX", "0")
+    _, labels0 = pieces(dims, dt, radix)
+    assert not any("pipe_kernel" in l and "MID" in l for l in labels0)
+    y0 = conv_gpu(x, h, dtype, radix)
+    check_close(y, y0, 2e-15 if dtype == C128 else 2e-6, "midx vs engine", elem_c=AGREE_C)

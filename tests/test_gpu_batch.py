@@ -1,6 +1,7 @@
 """GPU parity of the batched form (many independent 1-D convolutions of
 uneven, mixed-radix sizes) against the CPU oracle, and of its hipGraph replay
-against eager execution."""
+against eager execution, in both forms: one persistent launch, and one
+launch per pass level and kernel class."""
 import sys
 
 import numpy as np
@@ -8,9 +9,10 @@ import pytest
 
 import oracle
 from paper_2506_12718_amd import inputs
-from gpu_util import TOL, check_close, rel_l2, rounded, to_dev, to_host, torch
+from gpu_util import AGREE_C, TOL, check_close, rel_l2, rounded, to_dev, to_host, torch
 
 pytestmark = pytest.mark.gpu
+FORMS = ["persistent", "levels"]
 
 
 def say(*a):
@@ -41,9 +43,10 @@ def unpack(y, sizes):
     return out
 
 
-def check_batch(sizes, fids, filters, xs, dtype, spectral=False, sample=None):
+def check_batch(sizes, fids, filters, xs, dtype, spectral=False, sample=None, form="persistent"):
     m = pafc()
-    B = m.Batch(sizes, fids, len(filters), dtype)
+    B = m.Batch(sizes, fids, len(filters), dtype, form=form)
+    say("batch form", form, B.describe()["levels"])
     for f, h in filters.items():
         B.set_filter(f, to_dev(h, dtype), domain="spectral_natural" if spectral else "spatial")
     y = to_host(B.convolve(to_dev(pack(xs), dtype)))
@@ -61,30 +64,33 @@ def check_batch(sizes, fids, filters, xs, dtype, spectral=False, sample=None):
     return ys
 
 
+@pytest.mark.parametrize("form", FORMS)
 @pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
-def test_small_mixed_batch(dtype):
+def test_small_mixed_batch(dtype, form):
     rng = np.random.default_rng(5)
     classes = [16, 27, 64, 81, 125, 243, 256, 625, 1024, 4096, 3 ** 8, 2 ** 14, 5 ** 6, 3 ** 9]
     sizes = [classes[i] for i in rng.integers(0, len(classes), 60)] + classes
     filters = {k: inputs.complex_uniform(rng, (n,)) for k, n in enumerate(classes)}
     fids = [classes.index(n) for n in sizes]
     xs = [inputs.complex_uniform(rng, (n,)) for n in sizes]
-    say("small batch", dtype, len(sizes))
-    check_batch(sizes, fids, filters, xs, dtype)
+    say("small batch", dtype, len(sizes), form)
+    check_batch(sizes, fids, filters, xs, dtype, form=form)
 
 
-def test_two_filters_per_size_class_and_spectral():
+@pytest.mark.parametrize("form", FORMS)
+def test_two_filters_per_size_class_and_spectral(form):
     rng = np.random.default_rng(6)
     sizes = [256, 256, 243, 243, 256]
     fids = [0, 1, 2, 3, 1]
     filters = {0: inputs.complex_normal(rng, (256,)), 1: inputs.complex_normal(rng, (256,)),
                2: inputs.complex_normal(rng, (243,)), 3: inputs.complex_normal(rng, (243,))}
     xs = [inputs.complex_uniform(rng, (n,)) for n in sizes]
-    check_batch(sizes, fids, filters, xs, torch.complex128, spectral=True)
+    check_batch(sizes, fids, filters, xs, torch.complex128, spectral=True, form=form)
 
 
+@pytest.mark.parametrize("form", FORMS)
 @pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
-def test_full_batched_workload_sampled(dtype):
+def test_full_batched_workload_sampled(dtype, form):
     """The 4096-problem batched workload in the launch configuration the
     benchmark times; 48 problems (the largest of every size class first)
     checked against the oracle."""
@@ -96,11 +102,38 @@ def test_full_batched_workload_sampled(dtype):
     for i, n in enumerate(psizes):
         first_of.setdefault(n, i)
     sample = sorted(set(list(first_of.values()) + list(np.random.default_rng(0).integers(0, 4096, 30))))
-    say("full batch", dtype, sum(psizes))
-    check_batch(psizes, fids, filt, xs, dtype, sample=sample)
+    say("full batch", dtype, sum(psizes), form)
+    check_batch(psizes, fids, filt, xs, dtype, sample=sample, form=form)
 
 
-def test_batch_graph_replays_match_eager():
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+def test_forms_agree(dtype):
+    """The two forms plan the size classes under different limits (other
+    register groups and tiles), so they agree to rounding, entry by entry,
+    on every problem of a mixed batch."""
+    rng = np.random.default_rng(12)
+    classes = [256, 729, 4096, 6561, 3125, 2 ** 15, 3 ** 10, 5 ** 7]
+    sizes = [classes[i] for i in rng.integers(0, len(classes), 50)] + classes
+    filters = {k: inputs.complex_uniform(rng, (n,)) for k, n in enumerate(classes)}
+    fids = [classes.index(n) for n in sizes]
+    x = to_dev(pack([inputs.complex_uniform(rng, (n,)) for n in sizes]), dtype)
+    out = {}
+    for form in FORMS:
+        B = pafc().Batch(sizes, fids, len(classes), dtype, form=form)
+        for f, h in filters.items():
+            B.set_filter(f, to_dev(h, dtype))
+        say("forms agree", dtype, form, B.describe()["levels"])
+        out[form] = to_host(B.convolve(x))
+        B.close()
+    ya, yb = unpack(out["persistent"], sizes), unpack(out["levels"], sizes)
+    for i in range(len(sizes)):
+        # two roundings of the same sums: a few ulps in rel-L2
+        check_close(ya[i], yb[i], 2e-6 if dtype == torch.complex64 else 2e-15,
+                    what="forms %d" % sizes[i], elem_c=AGREE_C)
+
+
+@pytest.mark.parametrize("form", FORMS)
+def test_batch_graph_replays_match_eager(form):
     rng = np.random.default_rng(8)
     classes = [64, 243, 3125, 2 ** 14]
     sizes = [classes[i] for i in rng.integers(0, 4, 40)]
@@ -108,11 +141,15 @@ def test_batch_graph_replays_match_eager():
     fids = [classes.index(n) for n in sizes]
     xs = [inputs.complex_uniform(rng, (n,)) for n in sizes]
     m = pafc()
-    B = m.Batch(sizes, fids, len(classes), torch.complex128)
+    B = m.Batch(sizes, fids, len(classes), torch.complex128, form=form)
     for f, h in filters.items():
         B.set_filter(f, to_dev(h, torch.complex128))
     x = to_dev(pack(xs), torch.complex128)
+    say("graph replays", form, B.describe()["levels"])
     eager = to_host(B.convolve(x))
+    for i, n in enumerate(sizes[:6]):
+        check_close(unpack(eager, sizes)[i], oracle.conv_fft(xs[i], filters[fids[i]]), 1e-12,
+                    what="eager %d" % n)
     y = torch.empty_like(x)
     s = torch.cuda.Stream()
     s.wait_stream(torch.cuda.current_stream())
@@ -135,18 +172,20 @@ def test_batch_graph_replays_match_eager():
     B.close()
 
 
-def test_batch_errors():
+@pytest.mark.parametrize("form", FORMS)
+def test_batch_errors(form):
     m = pafc()
     with pytest.raises(m.PafcError):
-        m.Batch([256, 128], [0, 0], 1, torch.complex128)  # one filter, two sizes
-    B = m.Batch([64, 64], [0, 0], 1, torch.complex128)
+        m.Batch([256, 128], [0, 0], 1, torch.complex128, form=form)  # one filter, two sizes
+    B = m.Batch([64, 64], [0, 0], 1, torch.complex128, form=form)
     with pytest.raises(m.PafcError) as e:
         B.convolve(to_dev(np.zeros(128, complex), torch.complex128))
     assert e.value.status == 5
     B.close()
 
 
-def test_batch_with_five_pass_size():
+@pytest.mark.parametrize("form", FORMS)
+def test_batch_with_five_pass_size(form):
     """A length whose 1-D plan runs five passes (2^23 complex128: the axis is
     cut twice) in a batch with one- and three-pass lengths: every pass level
     runs.  The long problem is checked at sampled outputs (first, last,
@@ -158,7 +197,7 @@ def test_batch_with_five_pass_size():
     sizes = [256, n, 4096, 3 ** 9]
     filters = {k: inputs.complex_uniform(rng, (s,)) for k, s in enumerate(sizes)}
     xs = [inputs.complex_uniform(rng, (s,)) for s in sizes]
-    B = m.Batch(sizes, [0, 1, 2, 3], 4, torch.complex128)
+    B = m.Batch(sizes, [0, 1, 2, 3], 4, torch.complex128, form=form)
     for f, h in filters.items():
         B.set_filter(f, to_dev(h, torch.complex128))
     say("batch with a five-pass length", B.describe()["levels"])
@@ -170,3 +209,13 @@ def test_batch_with_five_pass_size():
     idx[0], idx[1] = 0, n - 1
     check_close(ys[1][idx], oracle.conv_direct_at(xs[1], filters[1], idx), 1e-12,
                 what="2^23 sampled")
+
+
+def test_auto_form_by_dtype():
+    """PAFC_BATCH_AUTO picks the form measured faster for the element type:
+    one persistent launch in complex128, one launch per level in complex64."""
+    m = pafc()
+    for dtype, want in ((torch.complex128, "persistent"), (torch.complex64, "levels")):
+        B = m.Batch([256, 729, 4096], [0, 1, 2], 3, dtype)
+        assert B.describe()["form"] == want, (dtype, B.describe()["form"])
+        B.close()

@@ -374,7 +374,8 @@ def test_lds_poison_leaves_results_unchanged(shape, radix, dtype, monkeypatch):
             assert np.array_equal(out["0"][1], out["1"][1]), (shape, variant)
 
 
-def test_lds_poison_batched(monkeypatch):
+@pytest.mark.parametrize("form", ["persistent", "levels"])
+def test_lds_poison_batched(monkeypatch, form):
     sizes = [256, 729, 625, 4096, 8192, 6561, 3125, 256, 15625, 2048]
     classes = sorted(set(sizes))
     fids = [classes.index(n) for n in sizes]
@@ -384,7 +385,7 @@ def test_lds_poison_batched(monkeypatch):
     out = {}
     for flag in ("0", "1"):
         monkeypatch.setenv("PAFC_LDS_POISON", flag)
-        B = pafc().Batch(sizes, fids, len(classes), C128)
+        B = pafc().Batch(sizes, fids, len(classes), C128, form=form)
         for n in classes:
             B.set_filter(classes.index(n), to_dev(hs[n], C128))
         out[flag] = to_host(B.convolve(to_dev(xs, C128)))
