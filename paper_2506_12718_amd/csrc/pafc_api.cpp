@@ -44,7 +44,7 @@ hipError_t launch_batch(bool dbl, int cls, const PassArgs* descs, const BatchTil
 hipError_t launch_scale(bool dbl, void* p, int64_t n, double s, hipStream_t st);
 bool pipe_supported(int r, int g, int ng);
 bool pipe_outer_supported(int r, int g, int ng);
-bool pipe_mid_supported(int r, int g, int ng, int gm, int xc, int mode);
+bool pipe_ext_supported(int r, int g, int ng, int gm, int xc, int kind, int mode);
 int pipe_thread_limit(int r, int g, bool dbl = true, int xc = 0);
 
 int pipe_blocks_per_cu(bool dbl, int r, int g, int ng, int kind, int mode, uint32_t threads,
@@ -556,11 +556,11 @@ bool validate_pass(const PassArgs& a, int64_t extent, int64_t n_tw) {
 // (r, g), one item per thread: with flat twiddles of the piece's own length,
 // or (*outer) a strided outer piece of a cut axis with the whole axis's
 // twiddles from a two-level LDS copy (PAFC_PIPE_OUTER=0: general engine).
-// A middle pass (kind 2, when gm and xc are asked for) may also have an
-// innermost group of fewer stages (*gm < *g; its fused op runs R / r^gm
-// groups per thread) and, in a strided tile whose row is exactly the folded
-// faster axes, up to two folded axes of length 2 (*xc; their DFTs are
-// exchanged across lanes) -- PAFC_PIPE_MIDX=0 turns both off.
+// Any pass (when gm and xc are asked for) may also have an innermost group
+// of fewer stages (*gm < *g; its op runs R / r^gm groups per thread) and, in
+// a strided tile whose row is exactly the folded faster axes, up to two
+// folded axes of length 2 (*xc; their DFTs are exchanged across lanes) --
+// PAFC_PIPE_MIDX=0 turns both off.
 bool pipe_shape(const Seg& s, const std::vector<CrossAxis>* cross, int* r, int* g, int* ng,
                 bool* outer = nullptr, int kind = -1, int* gm = nullptr, int* xc = nullptr) {
   if (gm) *gm = -1;
@@ -569,7 +569,7 @@ bool pipe_shape(const Seg& s, const std::vector<CrossAxis>* cross, int* r, int* 
   const bool out = s.col_in_j != 0 && s.mode == MODE_STRIDED;
   if (out ? env_int("PAFC_PIPE_OUTER", 1) == 0 : (s.jmul != 1 || s.n_tw != (int64_t)s.L))
     return false;
-  const bool ext = kind == 2 && !out && gm && xc && env_int("PAFC_PIPE_MIDX", 1) != 0;
+  const bool ext = kind >= 0 && !out && gm && xc && env_int("PAFC_PIPE_MIDX", 1) != 0;
   int ncross = 0;
   if (cross && !cross->empty()) {
     if (!ext || s.mode != MODE_STRIDED || cross->size() > 2) return false;
@@ -592,7 +592,7 @@ bool pipe_shape(const Seg& s, const std::vector<CrossAxis>* cross, int* r, int* 
   if (uniform) return out ? pipe_outer_supported(*r, *g, *ng) : pipe_supported(*r, *g, *ng);
   *gm = last.second;
   *xc = ncross;
-  return pipe_mid_supported(*r, *g, *ng, *gm, *xc, (int)s.mode);
+  return pipe_ext_supported(*r, *g, *ng, *gm, *xc, kind, (int)s.mode);
 }
 
 bool make_pass(const Seg& s_in, int kind, size_t elem, Pass* p,
@@ -679,15 +679,25 @@ bool make_pass(const Seg& s_in, int kind, size_t elem, Pass* p,
     // exactly one thread per item
     uint32_t items = a.nops ? a.ops[0].nitems : 0;
     if (ext) {
-      // one R-point item per thread in the axis ops, R / RM innermost groups
-      // in the middle op; the column ops run inside the first and last op
+      // one R-point item per thread in every op: the innermost group's op
+      // (last forward, first inverse, the middle op) runs R / RM groups of
+      // RM points; the column ops run inside the first and last op
       const uint32_t R = (uint32_t)ipow64(r, g), RM = (uint32_t)ipow64(r, gm);
       items = a.LW / R;
+      std::vector<uint32_t> want;  // group sizes of the axis ops, in op order
+      for (int q = 0; q < ng - 1 && kind != 1; ++q) want.push_back(R);
+      want.push_back(RM);
+      for (int q = 0; q < ng - 1 && kind != 0; ++q) want.push_back(R);
+      size_t n = 0;
       for (uint32_t i = 0; ok && i < a.nops; ++i) {
         const OpDesc& o = a.ops[i];
         if (o.cross) continue;
-        ok = o.type == OP_MID ? (uint32_t)o.R == RM : ((uint32_t)o.R == R && o.nitems == items);
+        ok = n < want.size() && (uint32_t)o.R == want[n] &&
+             (o.R != (int32_t)RM || o.R == (int32_t)R || o.nitems == a.LW / RM) &&
+             (o.R != (int32_t)R || o.nitems == items);
+        ++n;
       }
+      ok = ok && n == want.size();
       ok = ok && items % 64 == 0 && items <= (uint32_t)pipe_thread_limit(r, g, elem == 16, xc);
     } else {
       for (uint32_t i = 0; ok && i < a.nops; ++i) ok = a.ops[i].nitems == items;

@@ -20,9 +20,10 @@ namespace pafc {
 enum { PIPE_FWD = 0, PIPE_INV = 1, PIPE_MID = 2 };
 
 // An axis of NG groups: NG - 1 of radix R and, innermost, one of radix RM
-// (RM divides R; RM = R for a uniform axis).  Only the middle pass takes a
-// shorter innermost group: its fused op then runs R / RM items of RM points
-// per thread.
+// (RM divides R; RM = R for a uniform axis).  An op of the innermost group
+// then runs R / RM groups of RM points per thread, over the thread's R
+// consecutive positions, so that every thread still owns one R-point item
+// of every op.
 template <int R, int NG, int KIND, int RM = R>
 struct PipeShape {
   static constexpr int L = ipow(R, NG - 1) * RM;
@@ -131,6 +132,15 @@ __device__ __forceinline__ void column_dfts(cx<T>* v, uint32_t lane) {
   });
 }
 
+// Digit-reversed slot of value s of a thread's R values in an op at level k
+// of an axis of NG groups: the reversal of the op's group, or, for the
+// innermost level with groups of RM = r^GM points, of each RM-group.
+template <int r, int g, int GM, int NG>
+constexpr int slot_rev(int k, int s) {
+  return k == NG - 1 ? (s / ipow(r, GM)) * ipow(r, GM) + digrev<r, GM>(s % ipow(r, GM))
+                     : digrev<r, g>(s);
+}
+
 template <typename T, int r, int g, int NG, int KIND, int MODE_ARG, int GM = g, int XC = 0>
 __global__ void __launch_bounds__((pipe_block_limit<T, r, g, XC>()))
 __attribute__((amdgpu_waves_per_eu(pipe_waves_per_eu<KIND, NG>())))
@@ -148,9 +158,8 @@ pipe_kernel(const PassArgs* __restrict__ desc, const void* in, void* out) {
   constexpr int RM = ipow(r, GM);
   constexpr int NU = R / RM;
   static_assert(GM <= g && R % RM == 0, "innermost group no larger than the others");
-  static_assert((GM == g && XC == 0) || (KIND == PIPE_MID && MODE == MODE_STRIDED && !OUTER) ||
-                    (GM < g && XC == 0 && KIND == PIPE_MID),
-                "short innermost groups and folded columns in the middle pass only");
+  static_assert((GM == g && XC == 0) || (!OUTER && (XC == 0 || MODE == MODE_STRIDED)),
+                "short innermost groups: not in outer pieces; folded columns: strided tiles");
   using Sh = PipeShape<R, NG, KIND, RM>;
   constexpr int L = Sh::L;
   constexpr int NOPS = Sh::NOPS;
@@ -219,13 +228,13 @@ pipe_kernel(const PassArgs* __restrict__ desc, const void* in, void* out) {
       });
     } else {
       constexpr int k0 = Sh::level(0);
-      constexpr int K0 = L / ipow(R, k0);
+      constexpr int K0 = k0 == NG - 1 ? R : L / ipow(R, k0);
       constexpr int S0 = K0 / R;
       const Item it = item_of<R, L, K0, MODE>(tid, W, logW, col0, a.ncols);
       const uint32_t gb = base + it.i0 * S_i + it.c * S_c;
       static_for<R>([&](auto s) {
         // DIF reads natural positions, DIT reads digit-reversed ones
-        constexpr int p = Sh::type(0) == OP_DIT ? digrev<r, g>(s.value) : s.value;
+        constexpr int p = Sh::type(0) == OP_DIT ? slot_rev<r, g, GM, NG>(k0, s.value) : s.value;
         pre[s.value] = it.valid ? ld_g32<T>(in, gb + (uint32_t)(p * S0) * S_i) : cx<T>{(T)0, (T)0};
       });
     }
@@ -279,9 +288,9 @@ pipe_kernel(const PassArgs* __restrict__ desc, const void* in, void* out) {
       constexpr int i = decltype(opi)::value;
       constexpr int type = Sh::type(i);
       constexpr int k = Sh::level(i);
-      // the middle op's items are the thread's R consecutive positions
-      // (NU innermost groups of RM points)
-      constexpr int K = type == OP_MID ? R : L / ipow(R, k);
+      // an innermost-level op's items are the thread's R consecutive
+      // positions (NU groups of RM points)
+      constexpr int K = k == NG - 1 ? R : L / ipow(R, k);
       constexpr int S = K / R;
       constexpr bool first = (i == 0) && !LINEAR_LOAD;
       constexpr bool last = (i == NOPS - 1) && !LINEAR_STORE;
@@ -291,7 +300,7 @@ pipe_kernel(const PassArgs* __restrict__ desc, const void* in, void* out) {
       cx<T> v[R];
       // inputs
       static_for<R>([&](auto s) {
-        constexpr int p = type == OP_DIT ? digrev<r, g>(s.value) : s.value;
+        constexpr int p = type == OP_DIT ? slot_rev<r, g, GM, NG>(k, s.value) : s.value;
         if constexpr (first)
           v[s.value] = pre[s.value];
         else
@@ -328,9 +337,12 @@ pipe_kernel(const PassArgs* __restrict__ desc, const void* in, void* out) {
       // folded column axes: their forward DFTs before the first op's own,
       // their inverse DFTs after the last op's (they commute with the
       // stages along the axis)
-      if constexpr (XC > 0 && i == 0) column_dfts<T, XC, R>(v, tid);
+      if constexpr (XC > 0 && i == 0 && KIND != PIPE_INV) column_dfts<T, XC, R>(v, tid);
       if constexpr (type == OP_DIF) {
-        Dft<R, r, false, T>::run(v);
+        if constexpr (k == NG - 1)
+          static_for<NU>([&](auto u) { Dft<RM, r, false, T>::run(v + u.value * RM); });
+        else
+          Dft<R, r, false, T>::run(v);
         if constexpr (OUTER) {
           outer_tw(std::false_type{});
         } else if constexpr (S > 1) {
@@ -352,7 +364,10 @@ pipe_kernel(const PassArgs* __restrict__ desc, const void* in, void* out) {
             v[mm.value + 1] = cmulc(v[mm.value + 1], tw[E * (uint32_t)(L / K)]);
           });
         }
-        Dft<R, r, true, T>::run(v);
+        if constexpr (k == NG - 1)
+          static_for<NU>([&](auto u) { Dft<RM, r, true, T>::run(v + u.value * RM); });
+        else
+          Dft<R, r, true, T>::run(v);
       } else {  // MID
         static_for<NU>([&](auto u) { Dft<RM, r, false, T>::run(v + u.value * RM); });
         const T hs = (T)a.hscale;
@@ -361,10 +376,10 @@ pipe_kernel(const PassArgs* __restrict__ desc, const void* in, void* out) {
           if (next < a.ntiles) fetch_h(next);
         static_for<NU>([&](auto u) { Dft<RM, r, true, T>::run(v + u.value * RM); });
       }
-      if constexpr (XC > 0 && i == NOPS - 1) column_dfts<T, XC, R>(v, tid);
+      if constexpr (XC > 0 && i == NOPS - 1 && KIND != PIPE_FWD) column_dfts<T, XC, R>(v, tid);
       // outputs
       bool tm = false;
-      if constexpr (last && KIND == PIPE_FWD) tm = a.tm_store != 0;
+      if constexpr (last && KIND == PIPE_FWD && RM == R) tm = a.tm_store != 0;
       if (tm) {
         // the tile-major spectrum order the middle pass reads (PassArgs::h_tm):
         // this last op has the middle op's items (level NG - 1, S = 1), and
@@ -376,7 +391,7 @@ pipe_kernel(const PassArgs* __restrict__ desc, const void* in, void* out) {
       } else {
         static_for<R>([&](auto s) {
           // DIF writes frequency m at its digit-reversed position
-          constexpr int p = type == OP_DIF ? digrev<r, g>(s.value) : s.value;
+          constexpr int p = type == OP_DIF ? slot_rev<r, g, GM, NG>(k, s.value) : s.value;
           if constexpr (last) {
             if (it.valid) st_g32<T>(out, gb + (uint32_t)(p * S) * S_i, v[s.value]);
           } else {
@@ -464,9 +479,10 @@ static const void* pipe_fn(int kind, int mode) {
   return nullptr;
 }
 
-// Middle passes whose innermost group is shorter (GM < g stages) and/or
-// whose strided tile row holds XC folded length-2 axes: (r, g, NG, GM, XC).
-#define PAFC_PIPE_MID_SHAPES(X)                      \
+// Passes whose innermost group is shorter (GM < g stages) and/or whose
+// strided tile row holds XC folded length-2 axes: (r, g, NG, GM, XC), every
+// kind (forward, inverse, middle).
+#define PAFC_PIPE_EXT_SHAPES(X)                      \
   X(4, 2, 3, 1, 0) /* L = 1024 = 16 x 16 x 4 */      \
   X(4, 2, 3, 1, 1) /* L = 1024, two columns */       \
   X(4, 2, 3, 1, 2) /* L = 1024, four columns */      \
@@ -475,11 +491,17 @@ static const void* pipe_fn(int kind, int mode) {
   X(4, 2, 2, 2, 2) /* L = 256, four columns */
 
 template <typename T, int r, int g, int NG, int GM, int XC>
-static const void* pipe_mid_fn(int mode) {
-  if (mode == MODE_STRIDED)
-    return (const void*)pipe_kernel<T, r, g, NG, PIPE_MID, MODE_STRIDED, GM, XC>;
-  if constexpr (XC == 0)
-    if (mode == MODE_CONTIG) return (const void*)pipe_kernel<T, r, g, NG, PIPE_MID, MODE_CONTIG, GM, 0>;
+static const void* pipe_ext_fn(int kind, int mode) {
+#define PAFC_PIPE_EXT_SEL(K)                                                                 \
+  if (kind == K) {                                                                           \
+    if (mode == MODE_STRIDED) return (const void*)pipe_kernel<T, r, g, NG, K, MODE_STRIDED, GM, XC>; \
+    if constexpr (XC == 0)                                                                   \
+      if (mode == MODE_CONTIG) return (const void*)pipe_kernel<T, r, g, NG, K, MODE_CONTIG, GM, 0>;  \
+  }
+  PAFC_PIPE_EXT_SEL(PIPE_FWD)
+  PAFC_PIPE_EXT_SEL(PIPE_INV)
+  PAFC_PIPE_EXT_SEL(PIPE_MID)
+#undef PAFC_PIPE_EXT_SEL
   return nullptr;
 }
 
@@ -487,13 +509,12 @@ static const void* pipe_lookup(bool dbl, int r, int g, int ng, int kind, int mod
                                int xc = 0) {
   if (gm < 0) gm = g;
   if (gm != g || xc != 0) {
-    if (kind != PIPE_MID) return nullptr;
-#define PAFC_PIPE_MID_GO(rr, gg, nn, mm, xx)                                              \
+#define PAFC_PIPE_EXT_GO(rr, gg, nn, mm, xx)                                              \
   if (r == rr && g == gg && ng == nn && gm == mm && xc == xx)                             \
-    return dbl ? pipe_mid_fn<double, rr, gg, nn, mm, xx>(mode)                            \
-               : pipe_mid_fn<float, rr, gg, nn, mm, xx>(mode);
-    PAFC_PIPE_MID_SHAPES(PAFC_PIPE_MID_GO)
-#undef PAFC_PIPE_MID_GO
+    return dbl ? pipe_ext_fn<double, rr, gg, nn, mm, xx>(kind, mode)                      \
+               : pipe_ext_fn<float, rr, gg, nn, mm, xx>(kind, mode);
+    PAFC_PIPE_EXT_SHAPES(PAFC_PIPE_EXT_GO)
+#undef PAFC_PIPE_EXT_GO
     return nullptr;
   }
 #define PAFC_PIPE_GO(rr, gg, nn)                                                          \
@@ -504,10 +525,10 @@ static const void* pipe_lookup(bool dbl, int r, int g, int ng, int kind, int mod
   return nullptr;
 }
 
-// A middle pass with a shorter innermost group (gm < g) or folded
-// length-2 column axes (xc > 0) in the given tile mode.
-bool pipe_mid_supported(int r, int g, int ng, int gm, int xc, int mode) {
-  return pipe_lookup(true, r, g, ng, PIPE_MID, mode, gm, xc) != nullptr;
+// A pass of the given kind with a shorter innermost group (gm < g) or
+// folded length-2 column axes (xc > 0) in the given tile mode.
+bool pipe_ext_supported(int r, int g, int ng, int gm, int xc, int kind, int mode) {
+  return pipe_lookup(true, r, g, ng, kind, mode, gm, xc) != nullptr;
 }
 
 bool pipe_supported(int r, int g, int ng) {

@@ -263,3 +263,45 @@ def test_folded_middle_pass_pipelined(dims, radix, dtype, monkeypatch):
     assert not any("pipe_kernel" in l and "MID" in l for l in labels0)
     y0 = conv_gpu(x, h, dtype, radix)
     check_close(y, y0, 2e-15 if dtype == C128 else 2e-6, "midx vs engine", elem_c=AGREE_C)
+
+
+# forward and inverse passes with a short innermost group and/or folded
+# columns (the comparison variants' and the transforms' passes of the
+# anisotropic grids, and 1024-long contiguous axes)
+EXT_ALL = [
+    ((1024, 2, 2), None, C128),
+    ((4096, 2), None, C64),
+    ((2 ** 14, 2, 2), [4, 2, 2], C64),
+    ((2 ** 16, 2), [4, 2], C128),
+    ((64, 1024), None, C128),
+    ((96, 1024), None, C64),
+]
+
+
+@pytest.mark.parametrize("dims,radix,dtype", EXT_ALL)
+@pytest.mark.parametrize("variant", ["explicit_perm", "perm_free_unfused", "perm_free"])
+def test_pipelined_short_and_folded_passes_every_kind(dims, radix, dtype, variant, monkeypatch):
+    """Forward and inverse passes on the pipelined kernel with a shorter
+    innermost group or folded length-2 columns: the convolution of every
+    variant against the oracle, and the unordered forward transform against
+    the general engine's (PAFC_PIPE_MIDX=0) to a few ulps."""
+    dt = "c128" if dtype == C128 else "c64"
+    labels = pafc().describe(dims, dt, radix=radix, variant=variant)["conv_passes"]
+    ext = [l for l in labels if "pipe_kernel" in l and l.count(",") >= 7]
+    say("ext", dims, dt, variant, ext)
+    assert ext
+    rng = np.random.default_rng([dims[0], len(dims), 23])
+    x = inputs.complex_uniform(rng, dims)
+    h = inputs.complex_uniform(rng, dims)
+    P = pafc().Plan(dims, dtype, radix=radix, variant=variant)
+    P.set_filter(to_dev(h, dtype))
+    y = to_host(P.convolve(to_dev(x, dtype)))
+    z = to_host(P.forward(to_dev(x, dtype))) if variant == "perm_free" else None
+    P.close()
+    check_close(y, ref_conv(x, h, dtype), TOL[dtype], "ext %s %s" % (dims, variant))
+    if z is not None:
+        monkeypatch.setenv("PAFC_PIPE_MIDX", "0")
+        P = pafc().Plan(dims, dtype, radix=radix)
+        z0 = to_host(P.forward(to_dev(x, dtype)))
+        P.close()
+        check_close(z, z0, 2e-15 if dtype == C128 else 2e-6, "forward vs engine", elem_c=AGREE_C)
