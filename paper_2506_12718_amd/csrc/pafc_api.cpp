@@ -555,7 +555,8 @@ bool validate_pass(const PassArgs& a, int64_t extent, int64_t n_tw) {
 // The pipelined kernel runs a piece whose register groups are all the same
 // (r, g), one item per thread: with flat twiddles of the piece's own length,
 // or (*outer) a strided outer piece of a cut axis with the whole axis's
-// twiddles from a two-level LDS copy (PAFC_PIPE_OUTER=0: general engine).
+// twiddles from a two-level LDS copy, or from the global table when the copy
+// would not fit (PAFC_PIPE_OUTER=0: general engine).
 // Any pass (when gm and xc are asked for) may also have an innermost group
 // of fewer stages (*gm < *g; its op runs R / r^gm groups per thread) and, in
 // a strided tile whose row is exactly the folded faster axes, up to two
@@ -565,8 +566,11 @@ bool pipe_shape(const Seg& s, const std::vector<CrossAxis>* cross, int* r, int* 
                 bool* outer = nullptr, int kind = -1, int* gm = nullptr, int* xc = nullptr) {
   if (gm) *gm = -1;
   if (xc) *xc = 0;
-  if (env_int("PAFC_PIPE", 1) == 0 || s.tw_global) return false;
+  if (env_int("PAFC_PIPE", 1) == 0) return false;
   const bool out = s.col_in_j != 0 && s.mode == MODE_STRIDED;
+  // a piece without an LDS twiddle copy runs pipelined only as an outer
+  // piece (which reads the global table and forms the powers itself)
+  if (s.tw_global && !out) return false;
   if (out ? env_int("PAFC_PIPE_OUTER", 1) == 0 : (s.jmul != 1 || s.n_tw != (int64_t)s.L))
     return false;
   const bool ext = kind >= 0 && !out && gm && xc && env_int("PAFC_PIPE_MIDX", 1) != 0;

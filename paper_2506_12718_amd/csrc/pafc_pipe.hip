@@ -92,8 +92,9 @@ constexpr int pipe_block_limit() {
 // shorter ones of cut grid axes (9 = 3^2, 81 = 3^4, 125 = 5^3).
 template <int r, int g, int NG>
 constexpr bool pipe_outer_shape() {
-  return g == 1 &&
-         ((r == 3 && (NG == 2 || NG == 4 || NG == 5)) || (r == 5 && (NG == 3 || NG == 4)));
+  return (g == 1 &&
+          ((r == 3 && (NG == 2 || NG == 4 || NG == 5)) || (r == 5 && (NG == 3 || NG == 4)))) ||
+         (r == 4 && g == 2 && (NG == 1 || NG == 2));  // the 16- and 256-long pieces of long axes
 }
 
 // Butterflies of a 2-point DFT across lane bit b (the two values of a pair
@@ -323,6 +324,21 @@ pipe_kernel(const PassArgs* __restrict__ desc, const void* in, void* out) {
         const uint32_t Kf = (uint32_t)K * jmul;
         const uint32_t esc = a.ops[i].escale;
         const uint32_t jf = it.j * jmul + (col_in_j && it.valid ? fdiv(col0 + it.c, a.divJc) : 0u);
+        if (a.twl_global) {
+          // the axis's table is too large for LDS: one read of the global
+          // (two-level) table, the other twiddles as its powers,
+          // w^(m jf) = (w^jf)^m (jf < Kf / R)
+          const cx<T> w1 = twiddle<T>(a, jf * esc);
+          cx<T> w = w1;
+          static_for<R - 1>([&](auto mm) {
+            if constexpr (decltype(conj_tag)::value)
+              v[mm.value + 1] = cmulc(v[mm.value + 1], w);
+            else
+              v[mm.value + 1] = cmul(v[mm.value + 1], w);
+            w = cmul(w, w1);
+          });
+          return;
+        }
         uint32_t E = 0;
         static_for<R - 1>([&](auto mm) {
           E += jf;

@@ -22,6 +22,10 @@ sweep), so that one factor is checked against the others.
 `conv-traffic` sums the counters over every kernel of one convolution: the
 last K x launches dispatches of library kernels of a ``bench.py
 --counter-run K`` run (whose JSON line gives K and the launches).
+`sq` tabulates shader counters (SQ_*) per library kernel of such a run,
+mean per dispatch, with LDS bank-conflict cycles per LDS instruction.
+
+    python -m paper_2506_12718_amd.profiling sq <counter_collection.csv> --cmd "<command>"
 """
 from __future__ import annotations
 
@@ -167,6 +171,29 @@ def conv_traffic(a):
             "kernel_source_hash": kernel_source_hash(), "commands": a.cmd}
 
 
+def sq(path, cmd):
+    per = {}
+    for r in csv.DictReader(open(path)):
+        if "pafc::" not in r["Kernel_Name"]:
+            continue
+        k = per.setdefault(r["Kernel_Name"], {})
+        k.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    names = sorted({c for k in per.values() for c in k})
+    out = ["# rocprofv3 --pmc %s (mean per dispatch)" % " ".join(names), "# command: %s" % cmd, "",
+           "| kernel | dispatches | " + " | ".join(names) + " | bank-conflict cycles / LDS instr |",
+           "|---|---|" + "---|" * len(names) + "---|"]
+    for kname, k in sorted(per.items(), key=lambda kv: -max(len(v) for v in kv[1].values())):
+        mean = {c: sum(v) / len(v) for c, v in k.items()}
+        n = max(len(v) for v in k.values())
+        bc = mean.get("SQ_LDS_BANK_CONFLICT")
+        li = mean.get("SQ_INSTS_LDS")
+        ratio = "%.3f" % (bc / li) if bc is not None and li else "-"
+        short = kname.split("(")[0].replace("void pafc::", "")
+        out.append("| %s | %d | %s | %s |" % (short, n, " | ".join("%.4g" % mean.get(c, float("nan"))
+                                                              for c in names), ratio))
+    return "\n".join(out) + "\n"
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="what", required=True)
@@ -185,9 +212,15 @@ def main(argv=None):
     for k in ("fetch", "write", "calib_fetch", "calib_write", "run", "cmd", "out"):
         v.add_argument("--" + k.replace("_", "-"), required=True)
     v.add_argument("--calib-bytes", type=float, required=True)
+    q = sub.add_parser("sq")
+    q.add_argument("csv")
+    q.add_argument("--cmd", required=True)
     a = ap.parse_args(argv)
     if a.what == "stats":
         sys.stdout.write(stats(a.csv, a.cmd))
+        return
+    if a.what == "sq":
+        sys.stdout.write(sq(a.csv, a.cmd))
         return
     d = {"traffic": traffic, "calib": calib, "conv-traffic": conv_traffic}[a.what](a)
     with open(a.out, "w") as f:

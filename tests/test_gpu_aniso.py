@@ -98,7 +98,7 @@ def test_global_table_twiddles(dims, radix, dtype, monkeypatch):
     monkeypatch.setenv("PAFC_TUNE_TWG", "1")
     dt = "c128" if dtype == C128 else "c64"
     _, labels = pieces(dims, dt, radix)
-    assert all(l.endswith(" twg") for l in labels), labels
+    assert all(" twg" in l for l in labels), labels
     say("twg", dims, dt, len(labels), "passes")
     rng = np.random.default_rng(7)
     x = inputs.complex_uniform(rng, dims)
@@ -305,3 +305,37 @@ def test_pipelined_short_and_folded_passes_every_kind(dims, radix, dtype, varian
         z0 = to_host(P.forward(to_dev(x, dtype)))
         P.close()
         check_close(z, z0, 2e-15 if dtype == C128 else 2e-6, "forward vs engine", elem_c=AGREE_C)
+
+
+# radix-16 outer pieces of cut axes on the pipelined kernel, with the axis's
+# twiddles from the LDS copy or (forced: PAFC_TUNE_TWG) the global table
+OUTER16 = [
+    ((2 ** 20, 2), [4, 2], C128),
+    ((2 ** 18, 2, 2), None, C64),
+    ((2 ** 20, 4), [4, 4], C64),
+]
+
+
+@pytest.mark.parametrize("twg", [False, True])
+@pytest.mark.parametrize("dims,radix,dtype", OUTER16)
+def test_radix16_outer_pieces_pipelined(dims, radix, dtype, twg, monkeypatch):
+    """Outer pieces of 256 positions (two radix-16 groups) with the whole
+    axis's twiddles: against the oracle, and against the general engine
+    (PAFC_PIPE_OUTER=0) to a few ulps."""
+    if twg:
+        monkeypatch.setenv("PAFC_TUNE_TWG", "1")
+    dt = "c128" if dtype == C128 else "c64"
+    labels = pafc().describe(dims, dt, radix=radix)["conv_passes"]
+    outer = [l for l in labels if "L=256 W=16" in l and "pipe_kernel" in l]
+    say("outer16", dims, dt, twg, outer)
+    assert outer and all((" twg" in l) == twg for l in outer)
+    rng = np.random.default_rng([dims[0], len(dims), 29])
+    x = inputs.complex_uniform(rng, dims)
+    h = inputs.complex_uniform(rng, dims)
+    y = conv_gpu(x, h, dtype, radix)
+    check_close(y, ref_conv(x, h, dtype), TOL[dtype], "outer16 %s" % (dims,))
+    monkeypatch.setenv("PAFC_PIPE_OUTER", "0")
+    assert not any("L=256 W=16" in l and "pipe_kernel" in l
+                   for l in pafc().describe(dims, dt, radix=radix)["conv_passes"])
+    y0 = conv_gpu(x, h, dtype, radix)
+    check_close(y, y0, 4e-15 if dtype == C128 else 4e-6, "outer16 vs engine", elem_c=AGREE_C)
