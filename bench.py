@@ -45,19 +45,30 @@ LDS_BYTES = 160 * 1024    # LDS of one compute unit
 METRIC = "convolutions/s + HBM GB/s (% roofline), perm-free vs explicit-perm; p99 latency"
 
 
-def load_traffic(workload):
+def load_traffic(workload, launch=None):
     """HBM bytes per launch of the dominant kernel from committed rocprofv3
-    counter runs, if they were taken on the current kernel sources."""
+    counter runs, if they were taken on the current kernel sources: the
+    kernel's own summary (<workload>_traffic.json), else its launch in the
+    per-convolution breakdown (<workload>_conv_traffic.json, launch index
+    `launch` of one convolution)."""
     from paper_2506_12718_amd.profiling import kernel_source_hash
-    path = os.path.join(ROOT, "profiles", "%s_traffic.json" % workload)
-    if not os.path.exists(path):
-        return None
     try:
+        h = kernel_source_hash()
+        path = os.path.join(ROOT, "profiles", "%s_traffic.json" % workload)
+        if os.path.exists(path):
+            with open(path) as f:
+                d = json.load(f)
+            if d.get("kernel_source_hash") == h:
+                return d.get("hbm_bytes_per_launch")
+        path = os.path.join(ROOT, "profiles", "%s_conv_traffic.json" % workload)
+        if launch is None or not os.path.exists(path):
+            return None
         with open(path) as f:
             d = json.load(f)
-        if d.get("kernel_source_hash") != kernel_source_hash():
+        if d.get("kernel_source_hash") != h or launch >= len(d["launches"]):
             return None
-        return d.get("hbm_bytes_per_launch")
+        e = d["launches"][launch]
+        return e["fetch_bytes"] + e["write_bytes"]
     except Exception:
         return None
 
@@ -489,7 +500,7 @@ def bench_plain(pafc, torch, wl, tdtype, args, cpu_min_s=10.0, steps=None):
     kern = [i for i, l in enumerate(main_r["labels"]) if not l.startswith(("mul", "permute"))]
     all_ms = sum(main_r["ms_pass"][i] for i in kern)
     all_bytes = sum(main_r["bytes_pass"][i] for i in kern)
-    roof = roofline_obj(dom_bytes, dom_ms, traffic=load_traffic(wl["name"]),
+    roof = roofline_obj(dom_bytes, dom_ms, traffic=load_traffic(wl["name"], dom),
                         kernel=main_r["labels"][dom], alg_bytes_per_launch=dom_bytes,
                         avg_launch_ms=round(dom_ms, 5),
                         all_passes={"source": "per-launch breakdown run after the timed region",
@@ -669,7 +680,7 @@ def bench_batched(pafc, torch, wl, tdtype, args, cpu_min_s=10.0):
         "wall_conv_per_s": round(nprob * steps / r["wall"], 1),
         "latency_ms": {"p50": round(med, 5), "p99": round(pct(r["ms_rep"], 99), 5)},
         "ms_per_launch": [round(v, 5) for v in ms_lv],
-        "roofline": roofline_obj(by_lv[dom], ms_lv[dom], traffic=load_traffic(wl["name"]),
+        "roofline": roofline_obj(by_lv[dom], ms_lv[dom], traffic=load_traffic(wl["name"], dom),
                                  kernel="batched launch %d of %d" % (dom, len(ms_lv)),
                                  alg_bytes_per_launch=by_lv[dom],
                                  avg_launch_ms=round(ms_lv[dom], 5)),
