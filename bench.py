@@ -646,21 +646,21 @@ def time_batch_form(pafc, torch, wl, tdtype, form, steps, warmup):
 
 BATCH_FORMS = {"persistent": "one persistent launch: resident blocks claim whole problems "
                              "(largest first) and run all of a problem's passes",
-               "levels": "one launch per pass level, register class and LDS occupancy"}
+               "levels": "one launch per pass level, register class and LDS occupancy",
+               "classes": "per pass level, one pipelined launch per size class whose plan "
+                          "runs that pass on the pipelined kernel, the rest as in levels"}
 
 
 def bench_batched(pafc, torch, wl, tdtype, args, cpu_min_s=10.0):
     """The batch timed as one graph replay per batch (conv/s = problems /
-    median replay) in the form args.batch_form, the other form timed the
+    median replay) in the form args.batch_form, the other forms timed the
     same way beside it, and the same problems run one plan at a time (the
     plain form)."""
     elem = 16 if tdtype == torch.complex128 else 8
     nprob = len(wl["sizes"])
     steps = args.steps
-    form = args.batch_form
-    if form == "auto":  # the library's choice (PAFC_BATCH_AUTO)
-        form = "persistent" if elem == 16 else "levels"
-    r = time_batch_form(pafc, torch, wl, tdtype, form, steps, args.warmup)
+    r = time_batch_form(pafc, torch, wl, tdtype, args.batch_form, steps, args.warmup)
+    form = r["desc"]["form"]  # "auto" resolved by the library
     med = pct(r["ms_rep"], 50)
     value = nprob / (med * 1e-3)
     ms_lv, by_lv = r["ms_lv"], r["by_lv"]
@@ -688,15 +688,19 @@ def bench_batched(pafc, torch, wl, tdtype, args, cpu_min_s=10.0):
     }
     yh = r["y"]
     if not args.no_compare:
-        other = "levels" if form == "persistent" else "persistent"
-        o = time_batch_form(pafc, torch, wl, tdtype, other, steps, args.warmup)
-        omed = pct(o["ms_rep"], 50)
-        out["other_form"] = {
-            "form": other, "what": BATCH_FORMS[other], "conv_per_s": round(nprob / (omed * 1e-3), 1),
-            "ms_per_batch": round(omed, 5), "launches": len(o["ms_lv"]),
-            "hbm_gbps_alg": round(alg / (omed * 1e-3) / 1e9, 1),
-            "max_abs_diff": float(np.abs(o["y"] - yh).max()),
-            "speedup_of_%s" % form: round(omed / med, 3)}
+        out["other_forms"] = []
+        for other in sorted(BATCH_FORMS):
+            if other == form:
+                continue
+            o = time_batch_form(pafc, torch, wl, tdtype, other, steps, args.warmup)
+            omed = pct(o["ms_rep"], 50)
+            out["other_forms"].append({
+                "form": other, "what": BATCH_FORMS[other],
+                "conv_per_s": round(nprob / (omed * 1e-3), 1),
+                "ms_per_batch": round(omed, 5), "launches": len(o["ms_lv"]),
+                "hbm_gbps_alg": round(alg / (omed * 1e-3) / 1e9, 1),
+                "max_abs_diff": float(np.abs(o["y"] - yh).max()),
+                "speedup_of_%s" % form: round(omed / med, 3)})
         out["plain"] = bench_batched_plain(pafc, torch, wl, tdtype, yh)
         out["plain"]["speedup_batched_over_plain"] = round(
             value / out["plain"]["conv_per_s"], 3)
@@ -900,7 +904,7 @@ def brief(o):
             "rel_l2_vs_fp64_oracle_max_sampled", "max_entry_err_over_rms_sampled",
             "cpu_baseline", "offered_rate_per_s", "closed_loop_capacity_per_s",
             "plain_one_at_a_time_per_s", "speedup_served_over_plain", "max_inflight",
-            "hbm_gbps_alg_at_offered_rate", "wall_conv_per_s", "plain", "form", "other_form")
+            "hbm_gbps_alg_at_offered_rate", "wall_conv_per_s", "plain", "form", "other_forms")
     d = {k: o[k] for k in keys if k in o}
     d["workload"] = o["config"]["workload"]
     if o.get("roofline"):
@@ -1013,7 +1017,7 @@ def counter_run(pafc, torch, args):
         for _ in range(K):
             B.convolve(x, out=y)
         torch.cuda.synchronize()
-        out = {"workload": wl["name"], "form": args.batch_form, "convs": K,
+        out = {"workload": wl["name"], "form": B.describe()["form"], "convs": K,
                "launches_per_conv": len(B.describe()["levels"]),
                "alg_bytes_per_conv": batch_alg_bytes(wl["sizes"], wl["filters"], elem)}
         B.close()

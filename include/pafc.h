@@ -434,7 +434,7 @@ pafc_status pafc_stream_copy(const void* src_dev, void* dst_dev, size_t bytes, i
  * elements of problem i start at offset sum_{j<i} sizes[j] of one device
  * array.  The batch owns per-size-class plans (radix splits and tiles chosen
  * by the planner, or from the table set by pafc_set_tuning) and a device
- * work list, in one of two forms:
+ * work list, in one of three forms:
  *   PAFC_BATCH_PERSISTENT: pafc_batch_convolve enqueues ONE launch.  Its
  *     blocks (as many as fit the device at once) claim whole problems from
  *     a device counter, largest first, and each runs every pass of its
@@ -448,14 +448,19 @@ pafc_status pafc_stream_copy(const void* src_dev, void* dst_dev, size_t bytes, i
  *     turn (at most five), one launch per register class and LDS-bound
  *     occupancy present (up to 18 launches for the mixed workload of
  *     powers of 2, 3 and 5), with the size-class plans of pafc_plan.
- *   PAFC_BATCH_AUTO: one of the two, by element type (below).
- * Either may be captured in a hipGraph.  All arguments are checked before
+ *   PAFC_BATCH_CLASSES: as LEVELS, except that each pass of a size class
+ *     that its plan runs on the pipelined kernel is one launch of that
+ *     kernel over every problem of the class (a device table gives each
+ *     problem's offset); the other passes go to the level launches.  The
+ *     packed arrays and the spectra must each stay within 4 GiB.
+ *   PAFC_BATCH_AUTO: one of the three, by element type (below).
+ * Any form may be captured in a hipGraph.  All arguments are checked before
  * any device call.
  * Errors: INVALID_VALUE (out, sizes or filter_ids NULL, count < 1,
  * nfilters < 1, a length < 2, a filter id out of range, two lengths on one
  * filter, bad dtype or form), UNSUPPORTED_SIZE (a length with a prime factor
- * above 5, or one that no plan within the persistent form's limits holds),
- * OUT_OF_MEMORY, DEVICE.
+ * above 5, one that no plan within the persistent form's limits holds, or
+ * the classes form's 4 GiB bound exceeded), OUT_OF_MEMORY, DEVICE.
  */
 typedef struct pafc_batch_s* pafc_batch_t;
 
@@ -463,9 +468,11 @@ typedef enum pafc_batch_form {
   PAFC_BATCH_PERSISTENT = 0,
   PAFC_BATCH_LEVELS = 1,
   /* the form measured faster on MI355X for the element type (the mixed
-     workload of 4096 problems): persistent for complex128, levels for
-     complex64 */
+     workload of 4096 problems): persistent for complex128, classes for
+     complex64 (which falls back to levels where the classes form's 4 GiB
+     bound is exceeded) */
   PAFC_BATCH_AUTO = 2,
+  PAFC_BATCH_CLASSES = 3,
   PAFC_BATCH_FORM_MAX_ENUM = 0x7FFFFFFF
 } pafc_batch_form;
 

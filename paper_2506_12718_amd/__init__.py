@@ -122,14 +122,16 @@ TUNING_TABLE = os.path.join(_HERE, "tuning", "mi355x.txt")
 
 def _load_tuning_table(L):
     """Install the autotuner's table (schedule choices only; results do not
-    depend on it) unless PAFC_NO_TUNING_TABLE is set."""
-    if os.environ.get("PAFC_NO_TUNING_TABLE") or not os.path.exists(TUNING_TABLE):
+    depend on it) unless PAFC_NO_TUNING_TABLE is set; PAFC_TUNING_TABLE names
+    another table file."""
+    path = os.environ.get("PAFC_TUNING_TABLE") or TUNING_TABLE
+    if os.environ.get("PAFC_NO_TUNING_TABLE") or not os.path.exists(path):
         return
-    with open(TUNING_TABLE) as f:
+    with open(path) as f:
         text = f.read()
     st = L.pafc_set_tuning(text.encode())
     if st != 0:
-        raise PafcError(st, "loading %s" % TUNING_TABLE)
+        raise PafcError(st, "loading %s" % path)
 
 
 def _status_string(st):
@@ -391,7 +393,7 @@ class Batch:
     uses; inputs and outputs are packed 1-D tensors of ``sum(sizes)`` elements.
     """
 
-    FORMS = {"persistent": 0, "levels": 1, "auto": 2}
+    FORMS = {"persistent": 0, "levels": 1, "auto": 2, "classes": 3}
 
     def __init__(self, sizes, filter_ids, nfilters, dtype=None, stream=None, form="auto"):
         import torch

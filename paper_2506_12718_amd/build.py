@@ -31,6 +31,7 @@ DEVICE = ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang",
 UNITS = [
     ("pafc_kernels.hip", ["-x", "hip"] + DEVICE),
     ("pafc_pipe.hip", ["-x", "hip"] + DEVICE),
+    ("pafc_pipe_batch.hip", ["-x", "hip"] + DEVICE),
     ("pafc_api.cpp", ["-x", "hip"] + DEVICE),
 ]
 

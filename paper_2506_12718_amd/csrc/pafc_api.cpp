@@ -55,6 +55,11 @@ hipError_t launch_pipe_htm(bool dbl, int r, int g, int ng, int mode, const PassA
 hipError_t launch_pipe(bool dbl, int r, int g, int ng, int kind, int mode, const PassArgs* d,
                        uint32_t grid, uint32_t threads, size_t lds, const void* in, void* out,
                        hipStream_t s, int gm, int xc);
+int pipe_batch_blocks_per_cu(bool dbl, int r, int g, int ng, int kind, int mode,
+                             uint32_t threads, size_t lds, int gm);
+hipError_t launch_pipe_batch(bool dbl, int r, int g, int ng, int kind, int mode, int gm,
+                             const PassArgs* d, uint32_t grid, uint32_t threads, size_t lds,
+                             const void* in, void* out, hipStream_t s);
 hipError_t launch_mul(bool dbl, const void* x, const void* h, void* y, int64_t n, double s,
                       hipStream_t st);
 hipError_t launch_stream_copy(int kind, const void* src, void* dst, int64_t n16, hipStream_t st);
@@ -2656,10 +2661,15 @@ struct pafc_batch_s {
   int64_t total = 0;
   std::map<int64_t, pafc_plan_t> plans;  // one plan per size class
   std::vector<int64_t> fsize;            // size class of each filter
-  std::vector<void*> d_spec;             // per-filter spectra
+  std::vector<void*> d_spec;             // per-filter spectra, inside d_spec_all
+  std::vector<int64_t> spec_off;         // element offset of each in d_spec_all
+  void* d_spec_all = nullptr;
   std::vector<bool> fset;
   PassArgs* d_descs = nullptr;
   BatchTile* d_tiles = nullptr;
+  // classes form: per size class, (data offset, spectrum offset) of each of
+  // its problems
+  uint32_t* d_prob = nullptr;
   // persistent form: one job per problem, claimed through the control words
   BatchJob* d_jobs = nullptr;
   BatchCtl* d_ctl = nullptr;
@@ -2673,7 +2683,12 @@ struct pafc_batch_s {
     int cls = 0;
     int64_t bytes = 0;  // algorithmic HBM bytes of the launch
     bool persist = false;
-    uint32_t grid = 0;  // persistent form: resident blocks
+    uint32_t grid = 0;  // persistent form and pipelined launches: resident blocks
+    // classes form: one pipelined launch over every problem of a size class
+    bool pipe = false;
+    int r = 0, g = 0, ng = 0, kind = 0, mode = 0, gm = 0;
+    uint32_t desc = 0;
+    int64_t n = 0;  // the class's length
   };
   std::vector<Level> levels;
   std::string desc;
@@ -2684,8 +2699,8 @@ namespace {
 void free_batch(pafc_batch_t b) {
   if (!b) return;
   for (auto& kv : b->plans) free_plan(kv.second);
-  for (void* p : b->d_spec)
-    if (p) (void)hipFree(p);
+  if (b->d_spec_all) (void)hipFree(b->d_spec_all);
+  if (b->d_prob) (void)hipFree(b->d_prob);
   if (b->d_descs) (void)hipFree(b->d_descs);
   if (b->d_tiles) (void)hipFree(b->d_tiles);
   if (b->d_jobs) (void)hipFree(b->d_jobs);
@@ -2699,6 +2714,9 @@ hipError_t launch_level(pafc_batch_t b, const pafc_batch_s::Level& L, const void
   if (L.persist)
     return launch_batch_persist(dbl, b->d_descs, b->d_jobs, b->njobs, b->d_ctl, L.grid, L.lds, x,
                                 y, s);
+  if (L.pipe)
+    return launch_pipe_batch(dbl, L.r, L.g, L.ng, L.kind, L.mode, L.gm, b->d_descs + L.desc,
+                             L.grid, L.threads, L.lds, L.level == 0 ? x : y, y, s);
   return launch_batch(dbl, L.cls, b->d_descs, b->d_tiles, L.first, L.count, L.level == 0 ? x : y,
                       y, L.threads, L.lds, s);
 }
@@ -2728,10 +2746,12 @@ pafc_status pafc_batch_plan(pafc_batch_t* out, int count, const int64_t* sizes,
   *out = nullptr;
   if (count < 1 || !sizes || !filter_ids || nfilters < 1) return PAFC_ERROR_INVALID_VALUE;
   if (dtype != PAFC_C64 && dtype != PAFC_C128) return PAFC_ERROR_INVALID_VALUE;
-  if (form != PAFC_BATCH_PERSISTENT && form != PAFC_BATCH_LEVELS && form != PAFC_BATCH_AUTO)
+  if (form != PAFC_BATCH_PERSISTENT && form != PAFC_BATCH_LEVELS && form != PAFC_BATCH_AUTO &&
+      form != PAFC_BATCH_CLASSES)
     return PAFC_ERROR_INVALID_VALUE;
   // the form measured faster for the element type on the mixed workload
-  if (form == PAFC_BATCH_AUTO) form = dtype == PAFC_C128 ? PAFC_BATCH_PERSISTENT : PAFC_BATCH_LEVELS;
+  const bool auto_form = form == PAFC_BATCH_AUTO;
+  if (auto_form) form = dtype == PAFC_C128 ? PAFC_BATCH_PERSISTENT : PAFC_BATCH_CLASSES;
   pafc_batch_t b = new (std::nothrow) pafc_batch_s;
   if (!b) return PAFC_ERROR_OUT_OF_MEMORY;
   b->form = form;
@@ -2774,9 +2794,47 @@ pafc_status pafc_batch_plan(pafc_batch_t* out, int count, const int64_t* sizes,
       b->plans[n] = p;
     }
   }
+  // the filter spectra, in one allocation, each 256-byte aligned
+  int64_t spec_total = 0;
+  b->spec_off.assign((size_t)nfilters, -1);
   for (int f = 0; f < nfilters; ++f) {
     if (b->fsize[(size_t)f] == 0) continue;  // unused filter id
-    if (hipMalloc(&b->d_spec[(size_t)f], (size_t)b->fsize[(size_t)f] * b->elem) != hipSuccess)
+    b->spec_off[(size_t)f] = spec_total;
+    const int64_t al = 256 / (int64_t)b->elem;
+    spec_total += (b->fsize[(size_t)f] + al - 1) / al * al;
+  }
+  // the pipelined kernel indexes with 32-bit byte offsets
+  const bool fits32 = (uint64_t)b->total * b->elem <= (1ull << 32) &&
+                      (uint64_t)spec_total * b->elem <= (1ull << 32);
+  if (form == PAFC_BATCH_CLASSES && !fits32) {
+    // the levels form has the same size-class plans and no such bound
+    if (!auto_form) return fail(PAFC_ERROR_UNSUPPORTED_SIZE);
+    form = PAFC_BATCH_LEVELS;
+    b->form = form;
+  }
+  if (hipMalloc(&b->d_spec_all, (size_t)spec_total * b->elem) != hipSuccess)
+    return fail(PAFC_ERROR_OUT_OF_MEMORY);
+  for (int f = 0; f < nfilters; ++f)
+    if (b->spec_off[(size_t)f] >= 0)
+      b->d_spec[(size_t)f] = (char*)b->d_spec_all + b->spec_off[(size_t)f] * (int64_t)b->elem;
+  // classes form: the problems of each size class in memory order, as
+  // (data offset, spectrum offset) pairs
+  std::map<int64_t, uint32_t> ptab_first, ptab_count;
+  std::vector<uint32_t> ptab;
+  if (form == PAFC_BATCH_CLASSES) {
+    for (auto& kv : b->plans) {
+      const int64_t n = kv.first;
+      ptab_first[n] = (uint32_t)ptab.size();
+      uint32_t c = 0;
+      for (int i = 0; i < count; ++i)
+        if (b->sizes[(size_t)i] == n) {
+          ptab.push_back((uint32_t)b->offsets[(size_t)i]);
+          ptab.push_back((uint32_t)b->spec_off[(size_t)b->fid[(size_t)i]]);
+          ++c;
+        }
+      ptab_count[n] = c;
+    }
+    if (hipMalloc((void**)&b->d_prob, ptab.size() * sizeof(uint32_t)) != hipSuccess)
       return fail(PAFC_ERROR_OUT_OF_MEMORY);
   }
   // descriptors: one per (filter, pass level)
@@ -2798,6 +2856,69 @@ pafc_status pafc_batch_plan(pafc_batch_t* out, int count, const int64_t* sizes,
       dthreads.push_back(conv[l].threads);
       dlds.push_back(conv[l].lds);
       dcls.push_back(conv[l].cls);
+    }
+  }
+  // classes form: each pass of a size class that its plan runs on the
+  // pipelined kernel becomes one launch over every problem of the class
+  std::map<std::pair<int64_t, int>, pafc_batch_s::Level> pipe_levels;
+  if (form == PAFC_BATCH_CLASSES) {
+    int ncu = 0, dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        ncu <= 0)
+      return fail(PAFC_ERROR_DEVICE);
+    const bool dbl = dtype == PAFC_C128;
+    for (auto& kv : b->plans) {
+      const int64_t n = kv.first;
+      const pafc_plan_t pp = kv.second;
+      const uint32_t np = ptab_count[n];
+      // filters of the class (each read once by the middle pass)
+      std::vector<bool> fcls((size_t)nfilters, false);
+      int64_t nf = 0;
+      for (int i = 0; i < count; ++i)
+        if (b->sizes[(size_t)i] == n && !fcls[(size_t)b->fid[(size_t)i]]) {
+          fcls[(size_t)b->fid[(size_t)i]] = true;
+          ++nf;
+        }
+      for (size_t l = 0; l < pp->P.conv.size(); ++l) {
+        const Pass& ps = pp->P.conv[l];
+        if (ps.kind != 0 || !ps.pipe || ps.pipe_grid == 0 || ps.pipe_xc != 0) continue;
+        const uint64_t nt = (uint64_t)ps.a.ntiles * np;
+        if (np == 0 || nt >= (1ull << 32)) continue;
+        const int bpc = pipe_batch_blocks_per_cu(dbl, ps.pipe_r, ps.pipe_g, ps.pipe_ng, ps.pipe_kind,
+                                                 ps.pipe_mode, ps.pipe_threads, ps.pipe_lds,
+                                                 ps.pipe_gm);
+        if (bpc <= 0) continue;  // no batched instance: the general engine runs it
+        PassArgs a;
+        finalize_args(pp->P, pp->d_tw, b->d_spec_all, ps, &a);
+        a.poison = env_int("PAFC_LDS_POISON", 0) != 0 ? 1u : 0u;
+        a.tm_store = 0;
+        a.prob_off = b->d_prob + ptab_first[n];
+        a.tiles_per_prob = a.ntiles;
+        a.divProb = make_fastdiv(a.ntiles);
+        a.ntiles = (uint32_t)nt;
+        pafc_batch_s::Level L;
+        L.pipe = true;
+        L.level = (int)l;
+        L.n = n;
+        L.r = ps.pipe_r;
+        L.g = ps.pipe_g;
+        L.ng = ps.pipe_ng;
+        L.kind = ps.pipe_kind;
+        L.mode = ps.pipe_mode;
+        L.gm = ps.pipe_gm;
+        L.desc = (uint32_t)descs.size();
+        L.count = (uint32_t)nt;
+        L.threads = ps.pipe_threads;
+        L.lds = ps.pipe_lds;
+        L.grid = (uint32_t)std::min<uint64_t>((uint64_t)bpc * (uint64_t)ncu, nt);
+        L.bytes = 2 * n * (int64_t)b->elem * np + (ps.mid ? nf * n * (int64_t)b->elem : 0);
+        descs.push_back(a);
+        dthreads.push_back(ps.pipe_threads);
+        dlds.push_back(ps.pipe_lds);
+        dcls.push_back(ps.cls);
+        pipe_levels[{n, (int)l}] = L;
+      }
     }
   }
   // tiles per (level, register class, LDS occupancy) launch, longest
@@ -2857,6 +2978,10 @@ pafc_status pafc_batch_plan(pafc_batch_t* out, int count, const int64_t* sizes,
     nlevels = 0;  // no level launches
   }
   for (int l = 0; l < nlevels; ++l) {
+    // the level's pipelined launches (classes form), longest classes first,
+    // then the general engine's for the rest of the level
+    for (auto it = pipe_levels.rbegin(); it != pipe_levels.rend(); ++it)
+      if (it->first.second == l) b->levels.push_back(it->second);
     for (int cls = 0; cls < 3; ++cls)
     for (int bpc = 1; bpc <= 8; ++bpc) {
       pafc_batch_s::Level L;
@@ -2866,6 +2991,7 @@ pafc_status pafc_batch_plan(pafc_batch_t* out, int count, const int64_t* sizes,
       std::vector<bool> fseen((size_t)nfilters, false);
       for (int i : order) {
         const int f = b->fid[(size_t)i];
+        if (pipe_levels.count({b->sizes[(size_t)i], l})) continue;
         auto it = didx.find({f, l});
         if (it == didx.end() || dcls[it->second] != cls) continue;
         if (blocks_per_cu(dlds[it->second]) != bpc) continue;
@@ -2896,6 +3022,15 @@ pafc_status pafc_batch_plan(pafc_batch_t* out, int count, const int64_t* sizes,
       if (t.offset < 0 || t.offset + n > b->total || t.tile >= descs[t.desc].ntiles)
         return fail(PAFC_ERROR_INVALID_VALUE);
     }
+    for (size_t q = 0; q + 1 < ptab.size(); q += 2)
+      if (ptab[q] >= (uint64_t)b->total || ptab[q + 1] >= (uint64_t)spec_total)
+        return fail(PAFC_ERROR_INVALID_VALUE);
+    for (auto& kv : pipe_levels) {
+      const int64_t n = kv.first.first;
+      const uint32_t q0 = ptab_first[n], nq = ptab_count[n];
+      for (uint32_t q = 0; q < nq; ++q)
+        if ((int64_t)ptab[q0 + 2 * q] + n > b->total) return fail(PAFC_ERROR_INVALID_VALUE);
+    }
     for (const BatchJob& j : jobs) {
       if (j.npass == 0 || (size_t)j.desc + j.npass > descs.size())
         return fail(PAFC_ERROR_INVALID_VALUE);
@@ -2917,6 +3052,9 @@ pafc_status pafc_batch_plan(pafc_batch_t* out, int count, const int64_t* sizes,
     // zero once here; each launch leaves the control words zero again
     if (e == hipSuccess) e = hipMemsetAsync(b->d_ctl, 0, sizeof(BatchCtl), s);
   }
+  if (e == hipSuccess && !ptab.empty())
+    e = hipMemcpyAsync(b->d_prob, ptab.data(), ptab.size() * sizeof(uint32_t),
+                       hipMemcpyHostToDevice, s);
   if (e == hipSuccess)
     e = hipMemcpyAsync(b->d_descs, descs.data(), descs.size() * sizeof(PassArgs),
                        hipMemcpyHostToDevice, s);
@@ -2931,7 +3069,9 @@ pafc_status pafc_batch_plan(pafc_batch_t* out, int count, const int64_t* sizes,
            "{\"count\": %d, \"total_elems\": %lld, \"size_classes\": %zu, \"form\": \"%s\", "
            "\"levels\": [",
            count, (long long)b->total, b->plans.size(),
-           form == PAFC_BATCH_PERSISTENT ? "persistent" : "levels");
+           form == PAFC_BATCH_PERSISTENT ? "persistent"
+           : form == PAFC_BATCH_CLASSES  ? "classes"
+                                         : "levels");
   b->desc = buf;
   for (size_t l = 0; l < b->levels.size(); ++l) {
     auto& L = b->levels[l];
@@ -2940,6 +3080,11 @@ pafc_status pafc_batch_plan(pafc_batch_t* out, int count, const int64_t* sizes,
                "%s{\"persistent\": 1, \"jobs\": %u, \"grid\": %u, \"threads\": %u, "
                "\"lds\": %zu}",
                l ? ", " : "", L.count, L.grid, L.threads, L.lds);
+    else if (L.pipe)
+      snprintf(buf, sizeof(buf),
+               "%s{\"level\": %d, \"class\": %lld, \"pipe\": 1, \"tiles\": %u, \"grid\": %u, "
+               "\"threads\": %u, \"lds\": %zu}",
+               l ? ", " : "", L.level, (long long)L.n, L.count, L.grid, L.threads, L.lds);
     else
       snprintf(buf, sizeof(buf),
                "%s{\"level\": %d, \"tiles\": %u, \"threads\": %u, \"lds\": %zu, \"cls\": %d}",
@@ -2955,7 +3100,8 @@ pafc_status pafc_batch_plan(pafc_batch_t* out, int count, const int64_t* sizes,
   }
   b->desc += "]}";
   b->bytes = descs.size() * sizeof(PassArgs) + tiles.size() * sizeof(BatchTile) +
-             jobs.size() * sizeof(BatchJob) + (jobs.empty() ? 0 : sizeof(BatchCtl));
+             jobs.size() * sizeof(BatchJob) + (jobs.empty() ? 0 : sizeof(BatchCtl)) +
+             ptab.size() * sizeof(uint32_t);
   for (auto& kv : b->plans) b->bytes += kv.second->bytes - (size_t)kv.second->P.N * b->elem;
   for (int f = 0; f < nfilters; ++f) b->bytes += (size_t)b->fsize[(size_t)f] * b->elem;
   *out = b;

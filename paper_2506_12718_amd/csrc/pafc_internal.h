@@ -140,6 +140,14 @@ struct PassArgs {
                        // strides are odd and conflict-free unpadded
   uint32_t poison;     // debug: fill the LDS tile with NaN before each tile,
                        // so a read of LDS that no op wrote shows in the result
+  // one launch over many problems of one length (the batched form's size
+  // classes, pipelined kernel only): launch tile t is tile t mod
+  // tiles_per_prob of problem t / tiles_per_prob, whose data start at element
+  // prob_off[2 q] of the packed arrays and whose filter spectrum at element
+  // prob_off[2 q + 1] of H.  NULL for a single problem.
+  const uint32_t* prob_off;
+  uint32_t tiles_per_prob;
+  FastDiv divProb;
   OpDesc ops[kMaxOps];
 };
 

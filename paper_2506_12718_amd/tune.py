@@ -61,14 +61,15 @@ def line(dt, n, cfg):
 
 
 class Timer:
-    def __init__(self, pafc, torch, dt, reps=5):
+    def __init__(self, pafc, torch, dt, reps=5, batch_form="auto"):
         self.pafc, self.torch, self.dt, self.reps = pafc, torch, dt, reps
+        self.batch_form = batch_form
         self.tdt = torch.complex128 if dt == "c128" else torch.complex64
 
     def batch(self, n):
         torch = self.torch
         count = max(2, (1 << 24) // n)
-        B = self.pafc.Batch([n] * count, [0] * count, 1, self.tdt)
+        B = self.pafc.Batch([n] * count, [0] * count, 1, self.tdt, form=self.batch_form)
         h = torch.ones(n, dtype=self.tdt, device="cuda")
         B.set_filter(0, h)
         x = torch.ones(n * count, dtype=self.tdt, device="cuda")
@@ -175,6 +176,8 @@ def main(argv=None):
     ap.add_argument("--reps", type=int, default=7)
     ap.add_argument("--prev", default=DEFAULT_TABLE,
                     help="existing table whose entries are tried as starting points ('' for none)")
+    ap.add_argument("--batch-form", default="auto",
+                    help="batched form the size classes are timed in (Batch form names)")
     ap.add_argument("--sizes", nargs="*", type=int, default=None,
                     help="tune only these axis lengths; the other entries of --prev are kept")
     a = ap.parse_args(argv)
@@ -189,7 +192,7 @@ def main(argv=None):
              "# format: dtype n split W Wo g3 g5   (0 = planner default)"]
     report = []
     for dt in a.dtypes:
-        timer = Timer(pafc, torch, dt, reps=a.reps)
+        timer = Timer(pafc, torch, dt, reps=a.reps, batch_form=a.batch_form)
         # whole grids first; a batched size class with the same axis length
         # keeps the grid's entry (the table is keyed by axis length).  The
         # split field acts on 1-D plans only and the width candidates come

@@ -118,7 +118,7 @@ int main() {
     pafc_batch_t b = nullptr;
     const int64_t sizes[3] = {64, 97, 64};
     const int fids[3] = {0, 1, 0};
-    for (pafc_batch_form form : {PAFC_BATCH_PERSISTENT, PAFC_BATCH_LEVELS}) {
+    for (pafc_batch_form form : {PAFC_BATCH_PERSISTENT, PAFC_BATCH_LEVELS, PAFC_BATCH_CLASSES}) {
       expect(pafc_batch_plan(&b, 3, sizes, fids, 2, PAFC_C128, form, nullptr) ==
                  PAFC_ERROR_UNSUPPORTED_SIZE && b == nullptr, "batch non-smooth", form, 0);
       const int bad_fids[3] = {0, 0, 0};

@@ -307,16 +307,16 @@ def test_size_limits_and_batch_argument_errors():
         (1, [64], [0], 0),                 # no filters
     ]
     for count, sizes, fids, nf in cases:
-        for form in (0, 1, 2):
+        for form in (0, 1, 2, 3):
             st = L.pafc_batch_plan(ctypes.byref(h), count, (I64 * max(1, count))(*sizes),
                                    (I32 * max(1, count))(*fids), nf, 2, form, None)
             assert st == 1, (count, sizes, fids, nf, form)
             assert not h.value
     # a form that does not exist
-    st = L.pafc_batch_plan(ctypes.byref(h), 1, (I64 * 1)(64), (I32 * 1)(0), 1, 2, 3, None)
+    st = L.pafc_batch_plan(ctypes.byref(h), 1, (I64 * 1)(64), (I32 * 1)(0), 1, 2, 4, None)
     assert st == 1 and not h.value
     # a length with a prime factor above 5 (no pass plan), after a valid one
-    for form in (0, 1):
+    for form in (0, 1, 3):
         st = L.pafc_batch_plan(ctypes.byref(h), 2, (I64 * 2)(64, 97), (I32 * 2)(0, 1), 2, 2, form,
                                None)
         assert st == 2 and not h.value

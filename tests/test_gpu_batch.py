@@ -1,7 +1,8 @@
 """GPU parity of the batched form (many independent 1-D convolutions of
 uneven, mixed-radix sizes) against the CPU oracle, and of its hipGraph replay
-against eager execution, in both forms: one persistent launch, and one
-launch per pass level and kernel class."""
+against eager execution, in every form: one persistent launch; one launch
+per pass level and kernel class; and the same with one pipelined launch per
+size class for the passes whose plan runs on the pipelined kernel."""
 import sys
 
 import numpy as np
@@ -12,7 +13,7 @@ from paper_2506_12718_amd import inputs
 from gpu_util import AGREE_C, TOL, check_close, rel_l2, rounded, to_dev, to_host, torch
 
 pytestmark = pytest.mark.gpu
-FORMS = ["persistent", "levels"]
+FORMS = ["persistent", "levels", "classes"]
 
 
 def say(*a):
@@ -46,7 +47,11 @@ def unpack(y, sizes):
 def check_batch(sizes, fids, filters, xs, dtype, spectral=False, sample=None, form="persistent"):
     m = pafc()
     B = m.Batch(sizes, fids, len(filters), dtype, form=form)
-    say("batch form", form, B.describe()["levels"])
+    levels = B.describe()["levels"]
+    say("batch form", form, levels)
+    if form == "classes" and any(n >= 4096 and n % 4 == 0 for n in sizes):
+        # a 4096-long class runs its middle pass on the pipelined kernel
+        assert any(L.get("pipe") for L in levels), levels
     for f, h in filters.items():
         B.set_filter(f, to_dev(h, dtype), domain="spectral_natural" if spectral else "spatial")
     y = to_host(B.convolve(to_dev(pack(xs), dtype)))
@@ -125,11 +130,13 @@ def test_forms_agree(dtype):
         say("forms agree", dtype, form, B.describe()["levels"])
         out[form] = to_host(B.convolve(x))
         B.close()
-    ya, yb = unpack(out["persistent"], sizes), unpack(out["levels"], sizes)
-    for i in range(len(sizes)):
-        # two roundings of the same sums: a few ulps in rel-L2
-        check_close(ya[i], yb[i], 2e-6 if dtype == torch.complex64 else 2e-15,
-                    what="forms %d" % sizes[i], elem_c=AGREE_C)
+    yb = unpack(out["levels"], sizes)
+    for form in ("persistent", "classes"):
+        ya = unpack(out[form], sizes)
+        for i in range(len(sizes)):
+            # two roundings of the same sums: a few ulps in rel-L2
+            check_close(ya[i], yb[i], 2e-6 if dtype == torch.complex64 else 2e-15,
+                        what="%s vs levels %d" % (form, sizes[i]), elem_c=AGREE_C)
 
 
 @pytest.mark.parametrize("form", FORMS)
@@ -213,9 +220,9 @@ def test_batch_with_five_pass_size(form):
 
 def test_auto_form_by_dtype():
     """PAFC_BATCH_AUTO picks the form measured faster for the element type:
-    one persistent launch in complex128, one launch per level in complex64."""
+    one persistent launch in complex128, the classes form in complex64."""
     m = pafc()
-    for dtype, want in ((torch.complex128, "persistent"), (torch.complex64, "levels")):
+    for dtype, want in ((torch.complex128, "persistent"), (torch.complex64, "classes")):
         B = m.Batch([256, 729, 4096], [0, 1, 2], 3, dtype)
         assert B.describe()["form"] == want, (dtype, B.describe()["form"])
         B.close()

@@ -374,7 +374,7 @@ def test_lds_poison_leaves_results_unchanged(shape, radix, dtype, monkeypatch):
             assert np.array_equal(out["0"][1], out["1"][1]), (shape, variant)
 
 
-@pytest.mark.parametrize("form", ["persistent", "levels"])
+@pytest.mark.parametrize("form", ["persistent", "levels", "classes"])
 def test_lds_poison_batched(monkeypatch, form):
     sizes = [256, 729, 625, 4096, 8192, 6561, 3125, 256, 15625, 2048]
     classes = sorted(set(sizes))

@@ -36,7 +36,8 @@ def test_oracle_under_sanitizers(tmp_path):
 def test_planner_under_sanitizers(tmp_path):
     hipcc = "/opt/rocm/bin/hipcc"
     build = os.path.join(ROOT, "paper_2506_12718_amd", "_build")
-    objs = [os.path.join(build, f) for f in ("pafc_kernels.hip.o", "pafc_pipe.hip.o")]
+    objs = [os.path.join(build, f)
+            for f in ("pafc_kernels.hip.o", "pafc_pipe.hip.o", "pafc_pipe_batch.hip.o")]
     if not os.path.exists(hipcc) or not all(os.path.exists(o) for o in objs):
         pytest.skip("needs hipcc and the library's kernel objects (build first)")
     inc = ["-I" + os.path.join(ROOT, "include"),
