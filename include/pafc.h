@@ -517,15 +517,17 @@ pafc_status pafc_batch_describe(pafc_batch_t b, char* buf, size_t cap,
 
 /*
  * pafc_set_tuning -- install planner overrides for plans created afterwards.
- * text: lines "<c64|c128> <n> <split> <W>" or
- * "<c64|c128> <n> <split> <W> <Wo> <g3> <g5>" ('#' starts a comment), keyed
- * by element type and axis length n:
+ * text: lines "<c64|c128> <n> <split> <W>",
+ * "<c64|c128> <n> <split> <W> <Wo> <g3> <g5>" or the same with <g3i> after
+ * <g5> ('#' starts a comment), keyed by element type and axis length n:
  *   split  inner length of a 1-D transform cut into an outer (strided) and an
  *          inner (contiguous) pass; 0 = planner default
  *   W, Wo  tile width of the axis pass (of the inner piece when split) and
  *          of the outer piece; 0 = default
  *   g3, g5 largest number of radix-3 (<= 3) and radix-5 (<= 2) stages fused
  *          into one register group; 0 = default (3 and 2)
+ *   g3i    the same as g3 for the inner pieces of an axis cut into pieces
+ *          (the piece that carries the fused product); 0 = g3
  * None of these changes the result, only the pass and register schedule.
  * An entry applies to every axis of length n; a plan that its choices make
  * infeasible (more ops in one pass than a pass holds) is made with the

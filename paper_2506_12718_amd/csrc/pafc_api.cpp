@@ -135,6 +135,7 @@ struct TuneVal {
   int Wo = 0;         // tile width of the outer piece of a split 1-D transform
   int gmax3 = 0;      // largest group of radix-3 stages (0 = default)
   int gmax5 = 0;      // largest group of radix-5 stages (0 = default)
+  int gmax3i = 0;     // the same for the inner pieces of a cut axis (0 = gmax3)
 };
 std::mutex g_tune_mu;
 std::map<TuneKey, TuneVal> g_tune;
@@ -174,6 +175,7 @@ int env_int(const char* name, int dflt);
 struct GroupCaps {
   int g3 = 3;  // R = 27 (9 with 2)
   int g5 = 2;  // R = 25 (5 with 1)
+  int lim3 = 0;  // a caller's bound on g3 (0: none)
 };
 
 int gmax_of(int r, const GroupCaps& gc) {
@@ -610,10 +612,14 @@ bool make_pass(const Seg& s_in, int kind, size_t elem, Pass* p,
   // of up to 1024 threads: narrow its tile until it holds that many items
   Seg s = s_in;
   {
-    int r = 0, g = 0, ng = 0;
-    if (pipe_shape(s, cross, &r, &g, &ng) && pipe_thread_limit(r, g) > 256) {
+    // odd-radix pieces run one thread per R-point item: narrow the tile
+    // until its block holds them
+    int r = 0, g = 0, ng = 0, gm = -1, xc = 0;
+    if (pipe_shape(s, cross, &r, &g, &ng, nullptr, kind, &gm, &xc) && xc == 0 &&
+        (r == 3 || r == 5)) {
       const uint32_t R = (uint32_t)ipow64(r, g);
-      while (s.W > 1 && (s.L / R) * s.W > (uint32_t)pipe_thread_limit(r, g)) s.W /= 2;
+      const uint32_t lim = (uint32_t)pipe_thread_limit(r, g, elem == 16, 0);
+      while (s.W > 1 && (s.L / R) * s.W > lim) s.W /= 2;
     }
   }
   PassArgs& a = p->a;
@@ -707,11 +713,14 @@ bool make_pass(const Seg& s_in, int kind, size_t elem, Pass* p,
         ++n;
       }
       ok = ok && n == want.size();
-      ok = ok && items % 64 == 0 && items <= (uint32_t)pipe_thread_limit(r, g, elem == 16, xc);
+      // (folded columns exchange values across lanes: whole waves)
+      ok = ok && (xc == 0 || items % 64 == 0) &&
+           items <= (uint32_t)pipe_thread_limit(r, g, elem == 16, xc);
     } else {
       for (uint32_t i = 0; ok && i < a.nops; ++i) ok = a.ops[i].nitems == items;
     }
-    const bool small = ok && !ext && pipe_thread_limit(r, g) > 256;
+    // odd radices: one thread per item, any count within the block limit
+    const bool small = ok && !ext && (r == 3 || r == 5);
     if (ok && !ext) ok = small ? items <= (uint32_t)pipe_thread_limit(r, g) : items == p->threads;
     if (ok) {
       p->pipe = true;
@@ -882,9 +891,12 @@ bool split_axis(int64_t n, const std::vector<int>& rho, int64_t st, int64_t oute
   so.tw_global = twiddles_global(so.L, so.n_tw, elem, budget);
   choose_width(so, elem, tv ? tv->Wo : 0);
   segs.push_back(so);
-  // inner: an axis of length ni at stride st, one block per (o, i_o)
+  // inner: an axis of length ni at stride st, one block per (o, i_o); its
+  // radix-3 grouping may be tuned apart from the outer piece's
   const std::vector<int> rin(rho.begin(), rho.begin() + ti);
-  return split_axis(ni, rin, st, outer * no, elem, caps, tv, nullptr, segs, budget);
+  GroupCaps caps_in = caps;
+  if (tv && tv->gmax3i > 0) caps_in.g3 = std::min(tv->gmax3i, caps.lim3 > 0 ? caps.lim3 : 3);
+  return split_axis(ni, rin, st, outer * no, elem, caps_in, tv, nullptr, segs, budget);
 }
 
 // Limits a caller may put on a plan beyond the device's: the LDS one tile
@@ -945,6 +957,7 @@ pafc_status plan_once(PlanCore& P, int ndim, const int64_t* dims, const int* rad
     caps.g3 = tuned && tv.gmax3 > 0 ? tv.gmax3 : env_int("PAFC_TUNE_GMAX3", 3);
     caps.g5 = tuned && tv.gmax5 > 0 ? tv.gmax5 : env_int("PAFC_TUNE_GMAX5", 2);
     if (lim.g3 > 0) caps.g3 = std::min(caps.g3, lim.g3);
+    caps.lim3 = lim.g3;
     if (lim.g5 > 0) caps.g5 = std::min(caps.g5, lim.g5);
     // Cut the axis into pieces (G2): an outer piece takes its outermost
     // stages, strided over the inner length; the inner length is again an
@@ -2625,12 +2638,13 @@ pafc_status pafc_set_tuning(const char* text) {
       if (line.find_first_not_of(" \t\r") == std::string::npos) continue;
       char dt[16];
       long long n = 0, split = 0;
-      int W = 0, Wo = 0, g3 = 0, g5 = 0;
-      const int got = sscanf(line.c_str(), "%15s %lld %lld %d %d %d %d", dt, &n, &split, &W, &Wo,
-                             &g3, &g5);
-      if (got != 4 && got != 7) return PAFC_ERROR_INVALID_VALUE;
+      int W = 0, Wo = 0, g3 = 0, g5 = 0, g3i = 0;
+      const int got = sscanf(line.c_str(), "%15s %lld %lld %d %d %d %d %d", dt, &n, &split, &W,
+                             &Wo, &g3, &g5, &g3i);
+      if (got != 4 && got != 7 && got != 8) return PAFC_ERROR_INVALID_VALUE;
       const int d = !strcmp(dt, "c128") ? PAFC_C128 : !strcmp(dt, "c64") ? PAFC_C64 : -1;
-      if (d < 0 || n < 2 || split < 0 || W < 0 || Wo < 0 || g3 < 0 || g3 > 3 || g5 < 0 || g5 > 2)
+      if (d < 0 || n < 2 || split < 0 || W < 0 || Wo < 0 || g3 < 0 || g3 > 3 || g5 < 0 ||
+          g5 > 2 || g3i < 0 || g3i > 3)
         return PAFC_ERROR_INVALID_VALUE;
       TuneVal v;
       v.split = split;
@@ -2638,6 +2652,7 @@ pafc_status pafc_set_tuning(const char* text) {
       v.Wo = Wo;
       v.gmax3 = g3;
       v.gmax5 = g5;
+      v.gmax3i = g3i;
       t[{d, (int64_t)n}] = v;
     }
   }

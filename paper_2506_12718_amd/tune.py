@@ -4,7 +4,8 @@ For every (element type, axis length) it searches, on the GPU, the choices
 that change only the schedule -- never the result:
 
 * g3 / g5: how many radix-3 / radix-5 stages are fused into one register
-  group (larger groups: fewer LDS round trips, more registers);
+  group (larger groups: fewer LDS round trips, more registers); g3i the same
+  for the inner pieces of a cut axis (the middle pass's piece);
 * split: the inner length of a 1-D transform cut into an outer (strided) and
   an inner (contiguous) pass;
 * W / Wo: the tile widths of the inner and outer pieces.
@@ -56,8 +57,12 @@ def _factors(n):
     return f
 
 
+FIELDS = ("split", "W", "Wo", "g3", "g5", "g3i")
+
+
 def line(dt, n, cfg):
-    return "%s %d %d %d %d %d %d" % (dt, n, cfg["split"], cfg["W"], cfg["Wo"], cfg["g3"], cfg["g5"])
+    s = "%s %d %d %d %d %d %d" % (dt, n, cfg["split"], cfg["W"], cfg["Wo"], cfg["g3"], cfg["g5"])
+    return s + (" %d" % cfg["g3i"] if cfg.get("g3i") else "")
 
 
 class Timer:
@@ -95,7 +100,7 @@ class Timer:
 
 def candidates(pafc, dt, n, key, cfg):
     f = _factors(n)
-    if key == "g3":
+    if key in ("g3", "g3i"):
         return [1, 2, 3] if 3 in f else []
     if key == "g5":
         return [1, 2] if 5 in f else []
@@ -129,14 +134,16 @@ def read_table(path, raw=False):
         return out
     for text in open(path):
         f = text.split("#")[0].split()
-        if len(f) == 7:
-            out[(f[0], int(f[1]))] = text.rstrip("\n") if raw else \
-                dict(zip(("split", "W", "Wo", "g3", "g5"), map(int, f[2:])))
+        if len(f) in (7, 8):
+            cfg = dict(zip(FIELDS, map(int, f[2:])))
+            cfg.setdefault("g3i", 0)
+            out[(f[0], int(f[1]))] = text.rstrip("\n") if raw else cfg
     return out
 
 
-def tune_one(pafc, timer, dt, n, measure, prev=None, keys=("g3", "g5", "split", "W", "Wo")):
-    cfg = {"split": 0, "W": 0, "Wo": 0, "g3": 0, "g5": 0}
+def tune_one(pafc, timer, dt, n, measure, prev=None,
+             keys=("g3", "g5", "split", "W", "Wo", "g3i")):
+    cfg = {"split": 0, "W": 0, "Wo": 0, "g3": 0, "g5": 0, "g3i": 0}
     pafc.set_tuning(None)
     best = measure()
     log = [("default", best)]
@@ -198,9 +205,9 @@ def main(argv=None):
         # split field acts on 1-D plans only and the width candidates come
         # from the 1-D plan's pieces, so a grid of more than one axis
         # searches the register grouping alone.
-        one_d = ("g3", "g5", "split", "W", "Wo")
+        one_d = ("g3", "g5", "split", "W", "Wo", "g3i")
         jobs = [(dims[0], (lambda d=dims, r=radix: timer.grid(d, r)),
-                 one_d if len(dims) == 1 else ("g3", "g5")) for dims, radix in GRIDS]
+                 one_d if len(dims) == 1 else ("g3", "g5", "g3i")) for dims, radix in GRIDS]
         jobs += [(n, (lambda n=n: timer.batch(n)), one_d) for n in BATCH_SIZES
                  if n not in [d[0] for d, _ in GRIDS]]
         jobs += [(n, (lambda n=n: timer.grid((n,), None)), one_d) for n in INNER_1D]

@@ -121,6 +121,28 @@ def test_infeasible_tuning_entry_falls_back_to_defaults():
     assert pafc.describe((2187,), "c128")["conv_passes"] == one["conv_passes"]
 
 
+def test_inner_piece_grouping_and_radix9_pieces():
+    # g3 = 2 with g3i = 1: the 2187 x 2187 grid's contiguous axis runs
+    # radix-9 groups ending in a radix-3 one (9 x 9 x 9 x 3), its strided
+    # axis's 9-long outer piece one radix-9 group, and the inner 243-long
+    # piece (the middle pass) single radix-3 stages -- all pipelined
+    try:
+        pafc.set_tuning("c128 2187 0 0 0 2 0 1\n")
+        grid = pafc.describe((2187, 2187), "c128")["conv_passes"]
+        assert "[DIF9,DIF9,DIF9,DIF3] pipe_kernel<double,3,2,4,0,0,1,0>" in grid[0], grid
+        assert "[DIF9] pipe_kernel<double,3,2,1,0,2>" in grid[1], grid
+        assert "[DIF3,DIF3,DIF3,DIF3,MID3,DIT3,DIT3,DIT3,DIT3] pipe_kernel<double,3,1,5,2,1>" in grid[2], grid
+        assert "[DIT3,DIT9,DIT9,DIT9] pipe_kernel<double,3,2,4,1,0,1,0>" in grid[4], grid
+        # g3i = 2 puts radix-9 groups in the inner piece too
+        pafc.set_tuning("c128 2187 0 0 0 2 0 2\n")
+        grid = pafc.describe((2187, 2187), "c128")["conv_passes"]
+        assert "[DIF9,DIF9,MID3,DIT9,DIT9] pipe_kernel<double,3,2,3,2,1,1,0>" in grid[2], grid
+    finally:
+        pafc.set_tuning(None)
+    with pytest.raises(pafc.PafcError):
+        pafc.set_tuning("c128 2187 0 0 0 2 0 4\n")
+
+
 def test_outer_pieces_take_the_pipelined_kernel(monkeypatch):
     # one-stage radix-5 groups: 5^9 is cut into 625 x 3125, and the 625-long
     # outer pieces run the pipelined kernel in its outer-piece mode, one

@@ -482,6 +482,42 @@ def test_small_radix_pipelined_passes(shape, radix, dtype, monkeypatch):
         m._load_tuning_table(m.lib())  # the table the other tests plan with
 
 
+# radix-9 groups of radix-3 axes on the pipelined kernel: uniform (729 =
+# 9^3), ending in a radix-3 group (2187 = 9 x 9 x 9 x 3, 243 = 9 x 9 x 3),
+# one group (9-long outer pieces), with the inner pieces' grouping (g3i)
+# single-stage or radix-9
+RADIX9 = [((2187, 2187), "2 0 1"), ((2187, 2187), "2 0 2"), ((243, 2187), "2 0 2"),
+          ((2187,), "2 0 2"), ((729,), "2 0 2"), ((81, 729), "2 0 2"), ((59049,), "2 0 2")]
+
+
+@pytest.mark.parametrize("shape,g", RADIX9)
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_radix9_pipelined_passes(shape, g, dtype):
+    """Planner entries with radix-9 groups (g3 = 2) put radix-3 axes on the
+    pipelined kernel's radix-9 instances; against the oracle and against the
+    general engine's result of the same plan (PAFC_PIPE=0 is not needed: the
+    single-stage plan is the reference)."""
+    import paper_2506_12718_amd as m
+    dt = "c128" if dtype == C128 else "c64"
+    table = "".join("%s %d 0 0 0 %s\n" % (dt, n, g) for n in sorted(set(shape)))
+    try:
+        m.set_tuning(table)
+        labels = m.describe(shape, dt)["conv_passes"]
+        say("radix-9", shape, dt, g, labels)
+        assert any(",3,2," in l for l in labels), labels
+        rng = np.random.default_rng([len(shape), shape[0], 23])
+        x = inputs.complex_uniform(rng, shape)
+        h = inputs.complex_uniform(rng, shape)
+        P = m.Plan(shape, dtype)
+        P.set_filter(to_dev(h, dtype))
+        y = to_host(P.convolve(to_dev(x, dtype)))
+        P.close()
+        check_close(y, oracle.conv_fft(rounded(x, dtype), rounded(h, dtype)), TOL[dtype])
+    finally:
+        m.set_tuning(None)
+        m._load_tuning_table(m.lib())  # the table the other tests plan with
+
+
 # (shape, dtype, table): outer pieces of cut axes on the pipelined kernel
 # (MODE_OUTER): the tuned 1-D plans' 625- and 243-long outer pieces (tuning
 # table), and the 9- and 125-long outer pieces of cut grid axes, whose

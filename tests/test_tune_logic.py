@@ -36,8 +36,15 @@ def test_line_and_table_roundtrip(tmp_path):
     p = tmp_path / "t.txt"
     p.write_text("# header\n" + text + "   # comment\nc64 729 0 0 0 2 0\n")
     t = tune.read_table(str(p))
-    assert t[("c128", 78125)] == cfg
+    assert t[("c128", 78125)] == dict(cfg, g3i=0)
     assert t[("c64", 729)]["g3"] == 2
+    # the inner pieces' radix-3 grouping is an optional eighth field
+    cfg3 = {"split": 0, "W": 0, "Wo": 0, "g3": 2, "g5": 0, "g3i": 1}
+    assert tune.line("c128", 2187, cfg3) == "c128 2187 0 0 0 2 0 1"
+    p.write_text(tune.line("c128", 2187, cfg3) + "\n")
+    assert tune.read_table(str(p))[("c128", 2187)] == cfg3
+    pafc.set_tuning(tune.line("c128", 2187, cfg3))
+    pafc.set_tuning(None)
     assert tune.read_table(str(tmp_path / "missing.txt")) == {}
     # the planner accepts every line the tuner writes
     pafc.set_tuning(text)
@@ -48,6 +55,8 @@ def test_candidates_follow_the_factorisation():
     lib = FakeLib()
     base = {"split": 0, "W": 0, "Wo": 0, "g3": 0, "g5": 0}
     assert tune.candidates(lib, "c128", 2187, "g3", base) == [1, 2, 3]
+    assert tune.candidates(lib, "c128", 2187, "g3i", base) == [1, 2, 3]
+    assert tune.candidates(lib, "c128", 3125, "g3i", base) == []
     assert tune.candidates(lib, "c128", 2187, "g5", base) == []
     assert tune.candidates(lib, "c128", 3125, "g5", base) == [1, 2]
     splits = tune.candidates(lib, "c128", 78125, "split", base)
