@@ -453,7 +453,7 @@ pafc_status pafc_stream_copy(const void* src_dev, void* dst_dev, size_t bytes, i
  *     kernel over every problem of the class (a device table gives each
  *     problem's offset); the other passes go to the level launches.  The
  *     packed arrays and the spectra must each stay within 4 GiB.
- *   PAFC_BATCH_AUTO: one of the three, by element type (below).
+ *   PAFC_BATCH_AUTO: the fastest of the three (below).
  * Any form may be captured in a hipGraph.  All arguments are checked before
  * any device call.
  * Errors: INVALID_VALUE (out, sizes or filter_ids NULL, count < 1,
@@ -467,10 +467,9 @@ typedef struct pafc_batch_s* pafc_batch_t;
 typedef enum pafc_batch_form {
   PAFC_BATCH_PERSISTENT = 0,
   PAFC_BATCH_LEVELS = 1,
-  /* the form measured faster on MI355X for the element type (the mixed
-     workload of 4096 problems): persistent for complex128, classes for
-     complex64 (which falls back to levels where the classes form's 4 GiB
-     bound is exceeded) */
+  /* the form measured fastest on MI355X (the mixed workload of 4096
+     problems, both element types): classes, which falls back to levels
+     where the classes form's 4 GiB bound is exceeded */
   PAFC_BATCH_AUTO = 2,
   PAFC_BATCH_CLASSES = 3,
   PAFC_BATCH_FORM_MAX_ENUM = 0x7FFFFFFF

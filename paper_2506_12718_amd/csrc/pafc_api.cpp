@@ -2766,7 +2766,7 @@ pafc_status pafc_batch_plan(pafc_batch_t* out, int count, const int64_t* sizes,
     return PAFC_ERROR_INVALID_VALUE;
   // the form measured faster for the element type on the mixed workload
   const bool auto_form = form == PAFC_BATCH_AUTO;
-  if (auto_form) form = dtype == PAFC_C128 ? PAFC_BATCH_PERSISTENT : PAFC_BATCH_CLASSES;
+  if (auto_form) form = PAFC_BATCH_CLASSES;
   pafc_batch_t b = new (std::nothrow) pafc_batch_s;
   if (!b) return PAFC_ERROR_OUT_OF_MEMORY;
   b->form = form;
@@ -2822,7 +2822,8 @@ pafc_status pafc_batch_plan(pafc_batch_t* out, int count, const int64_t* sizes,
   const bool fits32 = (uint64_t)b->total * b->elem <= (1ull << 32) &&
                       (uint64_t)spec_total * b->elem <= (1ull << 32);
   if (form == PAFC_BATCH_CLASSES && !fits32) {
-    // the levels form has the same size-class plans and no such bound
+    // the levels form has the same size-class plans and no such bound (the
+    // persistent form's limits would need other plans)
     if (!auto_form) return fail(PAFC_ERROR_UNSUPPORTED_SIZE);
     form = PAFC_BATCH_LEVELS;
     b->form = form;

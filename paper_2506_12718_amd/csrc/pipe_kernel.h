@@ -90,14 +90,17 @@ constexpr int pipe_block_limit() {
 }
 
 // Outer pieces of a cut axis (MODE_OUTER) are compiled for the shapes the
-// tuned 1-D plans cut off (243 = 3^5 and 625 = 5^4 positions) and the
-// shorter ones of cut grid axes (9 = 3^2, 81 = 3^4, 125 = 5^3).
+// tuned 1-D plans cut off (243 = 3^5 and 625 = 5^4 positions, and the 8-,
+// 25- and 27-long pieces of the batched lengths) and the shorter ones of
+// cut grid axes (9 = 3^2, 81 = 3^4, 125 = 5^3).
 template <int r, int g, int NG>
 constexpr bool pipe_outer_shape() {
   return (g == 1 &&
           ((r == 3 && (NG == 2 || NG == 4 || NG == 5)) || (r == 5 && (NG == 3 || NG == 4)))) ||
          (r == 4 && g == 2 && (NG == 1 || NG == 2)) ||  // the 16- and 256-long pieces of long axes
-         (r == 3 && g == 2 && NG == 1);                 // 9-long pieces in one radix-9 group
+         (r == 3 && g == 2 && NG == 1) ||               // 9-long pieces in one radix-9 group
+         (r == 3 && g == 1 && NG == 3) || (r == 5 && g == 1 && NG == 2) ||
+         (r == 8 && g == 1 && NG == 1);  // the short outer pieces of the batched 1-D lengths
 }
 
 // Butterflies of a 2-point DFT across lane bit b (the two values of a pair
@@ -513,7 +516,10 @@ __global__ void __launch_bounds__((pipe_max_threads<r, g>())) pipe_htm_kernel(co
   X(5, 1, 4) /* L = 625 */    \
   X(5, 1, 5) /* L = 3125 */   \
   X(3, 2, 1) /* L = 9 */      \
-  X(3, 2, 3) /* L = 729 */
+  X(3, 2, 3) /* L = 729 */    \
+  X(8, 1, 1) /* L = 8 */      \
+  X(3, 1, 3) /* L = 27 */     \
+  X(5, 1, 2) /* L = 25 */
 
 template <typename T, int r, int g, int NG, bool PB>
 const void* pipe_fn(int kind, int mode) {

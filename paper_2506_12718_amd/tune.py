@@ -196,7 +196,7 @@ def main(argv=None):
     dev = torch.cuda.get_device_properties(0)
     lines = ["# pafc planner tuning table (python -m paper_2506_12718_amd.tune)",
              "# device: %s (%s)" % (dev.name, getattr(dev, "gcnArchName", "?")),
-             "# format: dtype n split W Wo g3 g5   (0 = planner default)"]
+             "# format: dtype n split W Wo g3 g5 [g3i]   (0 = planner default)"]
     report = []
     for dt in a.dtypes:
         timer = Timer(pafc, torch, dt, reps=a.reps, batch_form=a.batch_form)
