@@ -735,7 +735,12 @@ bool make_pass(const Seg& s_in, int kind, size_t elem, Pass* p,
       const uint64_t LW = a.LW;
       // tile, then the flat table of the piece (or, outer, the two-level
       // table of the general engine's layout)
-      p->pipe_lds = outer ? p->lds : (size_t)(((LW + (LW >> 4) + 2) & ~1ull) + s.L) * elem;
+      // (long contiguous tiles of even length pad the table one in 16, as
+      // the kernel's pipe_tw_pad)
+      const bool twpad = s.mode == MODE_CONTIG && s.L % 2 == 0 && s.L >= 1024;
+      p->pipe_lds = outer ? p->lds
+                          : (size_t)(((LW + (LW >> 4) + 2) & ~1ull) + s.L + (twpad ? s.L / 16 : 0)) *
+                                elem;
     }
   }
   // wide register class: every group R <= 9 and every op at least two full

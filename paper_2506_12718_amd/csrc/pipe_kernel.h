@@ -103,6 +103,11 @@ constexpr bool pipe_outer_shape() {
          (r == 8 && g == 1 && NG == 1);  // the short outer pieces of the batched 1-D lengths
 }
 
+// Long contiguous tiles of even length pad their LDS twiddle table (see
+// pipe_kernel); the host sizes the table by the same rule.
+template <int MODE, int L>
+constexpr bool pipe_tw_pad() { return MODE == MODE_CONTIG && L % 2 == 0 && L >= 1024; }
+
 // Butterflies of a 2-point DFT across lane bit b (the two values of a pair
 // of lanes differing in bit b): the lower lane keeps x0 + x1, the upper
 // x0 - x1.  F_2 is its own conjugate, so the same exchange serves the
@@ -198,6 +203,16 @@ pipe_kernel(const PassArgs* __restrict__ desc, const void* in, void* out) {
     else
       return lds_phys(x);
   };
+  // LDS slot of twiddle w_L^e.  In a long contiguous tile each op's items
+  // run over consecutive j, so an op reads w^(m j (L/K)): strides of m and
+  // of 16 m elements, which land on few banks.  One pad element every 16
+  // spreads them (the padded table takes L + L / 16 slots).
+  auto twp = [](uint32_t e) -> uint32_t {
+    if constexpr (pipe_tw_pad<MODE, Sh::L>())
+      return e + (e >> 4);
+    else
+      return e;
+  };
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
   const uint32_t LW = a.LW;
@@ -212,7 +227,7 @@ pipe_kernel(const PassArgs* __restrict__ desc, const void* in, void* out) {
     stage_twiddles<T>(a, lds);  // at a.twl_off == the offset of tw
   } else {
     const cx<T>* lo = reinterpret_cast<const cx<T>*>(a.tw_lo);
-    for (uint32_t e = tid; e < (uint32_t)L; e += nthr) tw[e] = lo[e];
+    for (uint32_t e = tid; e < (uint32_t)L; e += nthr) tw[twp(e)] = lo[e];
   }
   const uint32_t jmul = a.jmul;
   const bool col_in_j = a.col_in_j != 0;
@@ -405,7 +420,7 @@ pipe_kernel(const PassArgs* __restrict__ desc, const void* in, void* out) {
           static_for<R - 1>([&](auto mm) {
             E += it.j;
             if (E >= (uint32_t)K) E -= (uint32_t)K;
-            v[mm.value + 1] = cmul(v[mm.value + 1], tw[E * (uint32_t)(L / K)]);
+            v[mm.value + 1] = cmul(v[mm.value + 1], tw[twp(E * (uint32_t)(L / K))]);
           });
         }
       } else if constexpr (type == OP_DIT) {
@@ -416,7 +431,7 @@ pipe_kernel(const PassArgs* __restrict__ desc, const void* in, void* out) {
           static_for<R - 1>([&](auto mm) {
             E += it.j;
             if (E >= (uint32_t)K) E -= (uint32_t)K;
-            v[mm.value + 1] = cmulc(v[mm.value + 1], tw[E * (uint32_t)(L / K)]);
+            v[mm.value + 1] = cmulc(v[mm.value + 1], tw[twp(E * (uint32_t)(L / K))]);
           });
         }
         if constexpr (k == NG - 1)
