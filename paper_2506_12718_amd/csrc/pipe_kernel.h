@@ -194,11 +194,14 @@ pipe_kernel(const PassArgs* __restrict__ desc, const void* in, void* out) {
   constexpr bool PF_LATE = sizeof(T) == 4;
   const PassArgs& a = *desc;
   // LDS slot of tile element x: one pad element every 16 breaks the
-  // power-of-two strides; contiguous tiles of odd length have odd strides
-  // and measured fewer bank conflicts unpadded (2187- and 3125-long tiles:
-  // 4.6 and 5.5 conflict cycles per LDS instruction padded, 2.9 unpadded)
+  // power-of-two strides.  Tiles of odd length have odd strides and measured
+  // fewer bank conflicts unpadded when contiguous (2187- and 3125-long
+  // tiles: 4.6 and 5.5 conflict cycles per LDS instruction padded, 2.9
+  // unpadded) or strided in FP64 (the 2187^2 middle pass 60.5 -> 58.8 us);
+  // strided FP32 tiles (8-byte elements) measured slower unpadded (the 5^9
+  // inverse outer pass 20.4 -> 27.3 us) and keep the padding
   auto lphys = [](uint32_t x) -> uint32_t {
-    if constexpr (MODE == MODE_CONTIG && Sh::L % 2 == 1)
+    if constexpr (Sh::L % 2 == 1 && (MODE == MODE_CONTIG || sizeof(T) == 16))
       return x;
     else
       return lds_phys(x);
