@@ -451,8 +451,11 @@ pafc_status pafc_stream_copy(const void* src_dev, void* dst_dev, size_t bytes, i
  *   PAFC_BATCH_CLASSES: as LEVELS, except that each pass of a size class
  *     that its plan runs on the pipelined kernel is one launch of that
  *     kernel over every problem of the class (a device table gives each
- *     problem's offset); the other passes go to the level launches.  The
- *     packed arrays and the spectra must each stay within 4 GiB.
+ *     problem's offset), and each size class's launches form a chain: the
+ *     chains run on 4 streams (PAFC_BATCH_STREAMS), three of them the
+ *     batch's own, forked from the caller's stream and joined back into it
+ *     by events (capturable).  The packed arrays and the spectra must each
+ *     stay within 4 GiB.
  *   PAFC_BATCH_AUTO: the fastest of the three (below).
  * Any form may be captured in a hipGraph.  All arguments are checked before
  * any device call.

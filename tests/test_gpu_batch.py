@@ -179,6 +179,59 @@ def test_batch_graph_replays_match_eager(form):
     B.close()
 
 
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+def test_classes_form_on_several_streams(dtype, monkeypatch):
+    """The classes form's size-class chains forked onto four streams and
+    joined back into the caller's: the same result, bit for bit, as on one
+    stream (the same kernels on the same tiles), eager and replayed from a
+    captured hipGraph with eager work between the replays."""
+    m = pafc()
+    rng = np.random.default_rng(17)
+    classes = [256, 729, 3125, 4096, 2 ** 14, 3 ** 9, 5 ** 6, 2 ** 16]
+    sizes = [classes[i] for i in rng.integers(0, len(classes), 60)] + classes
+    filters = {k: inputs.complex_uniform(rng, (n,)) for k, n in enumerate(classes)}
+    fids = [classes.index(n) for n in sizes]
+    x = to_dev(pack([inputs.complex_uniform(rng, (n,)) for n in sizes]), dtype)
+    out = {}
+    for k in ("1", "4"):
+        monkeypatch.setenv("PAFC_BATCH_STREAMS", k)
+        B = m.Batch(sizes, fids, len(classes), dtype, form="classes")
+        d = B.describe()
+        assert d["streams"] == int(k), d["streams"]
+        if k == "4":
+            assert len({L["stream"] for L in d["levels"]}) == 4, d["levels"]
+        for f, h in filters.items():
+            B.set_filter(f, to_dev(h, dtype))
+        say("streams", k, dtype, d["levels"])
+        out[k] = to_host(B.convolve(x))
+        if k == "4":
+            y = torch.empty_like(x)
+            s = torch.cuda.Stream()
+            s.wait_stream(torch.cuda.current_stream())
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.stream(s):
+                B.convolve(x, out=y, stream=s)
+                torch.cuda.synchronize()
+                with torch.cuda.graph(g, stream=s):
+                    B.convolve(x, out=y, stream=s)
+            torch.cuda.synchronize()
+            for rep in range(3):
+                y.zero_()
+                torch.cuda.synchronize()
+                g.replay()
+                torch.cuda.synchronize()
+                assert np.array_equal(to_host(y), out["1"]), rep
+                _ = B.convolve(x)
+                torch.cuda.synchronize()
+        B.close()
+    assert np.array_equal(out["4"], out["1"])
+    ys = unpack(out["4"], sizes)
+    for i in range(len(sizes) - len(classes), len(sizes)):
+        check_close(ys[i], oracle.conv_fft(rounded(unpack(to_host(x), sizes)[i], dtype),
+                                           rounded(filters[fids[i]], dtype)),
+                    TOL[dtype], what="streams %d" % sizes[i])
+
+
 @pytest.mark.parametrize("form", FORMS)
 def test_batch_errors(form):
     m = pafc()
