@@ -45,15 +45,21 @@ LDS_BYTES = 160 * 1024    # LDS of one compute unit
 METRIC = "convolutions/s + HBM GB/s (% roofline), perm-free vs explicit-perm; p99 latency"
 
 
-def load_traffic(workload, launch=None):
+def load_traffic(workload, launch=None, whole=False):
     """HBM bytes per launch of the dominant kernel from committed rocprofv3
     counter runs, if they were taken on the current kernel sources: the
     kernel's own summary (<workload>_traffic.json), else its launch in the
     per-convolution breakdown (<workload>_conv_traffic.json, launch index
-    `launch` of one convolution)."""
+    `launch` of one convolution), or with `whole` that breakdown's total over
+    one convolution (one batch)."""
     from paper_2506_12718_amd.profiling import kernel_source_hash
     try:
         h = kernel_source_hash()
+        if whole:
+            path = os.path.join(ROOT, "profiles", "%s_conv_traffic.json" % workload)
+            with open(path) as f:
+                d = json.load(f)
+            return d["hbm_bytes_per_conv"] if d.get("kernel_source_hash") == h else None
         path = os.path.join(ROOT, "profiles", "%s_traffic.json" % workload)
         if os.path.exists(path):
             with open(path) as f:
@@ -680,10 +686,18 @@ def bench_batched(pafc, torch, wl, tdtype, args, cpu_min_s=10.0):
         "wall_conv_per_s": round(nprob * steps / r["wall"], 1),
         "latency_ms": {"p50": round(med, 5), "p99": round(pct(r["ms_rep"], 99), 5)},
         "ms_per_launch": [round(v, 5) for v in ms_lv],
-        "roofline": roofline_obj(by_lv[dom], ms_lv[dom], traffic=load_traffic(wl["name"], dom),
-                                 kernel="batched launch %d of %d" % (dom, len(ms_lv)),
-                                 alg_bytes_per_launch=by_lv[dom],
-                                 avg_launch_ms=round(ms_lv[dom], 5)),
+        # the batch's unit of work is one graph launch: its launches overlap
+        # on several streams (classes form), and one kernel instance serves
+        # several size classes, so no single kernel's duration stands for it
+        "roofline": roofline_obj(alg, med, traffic=load_traffic(wl["name"], whole=True),
+                                 kernel="one hipGraph launch of the batch (%d launches, %d "
+                                        "stream(s), form %s)" % (len(ms_lv),
+                                                                 r["desc"].get("streams", 1), form),
+                                 alg_bytes_per_launch=alg, avg_launch_ms=round(med, 5)),
+        "longest_launch": {"index": dom, "ms_alone": round(ms_lv[dom], 5),
+                           "alg_bytes": by_lv[dom],
+                           "achieved_gbs": round(by_lv[dom] / (ms_lv[dom] * 1e-3) / 1e9, 1),
+                           "desc": (r["desc"].get("levels") or [None] * (dom + 1))[dom]},
         "launch_desc": r["desc"].get("levels"),
     }
     yh = r["y"]
@@ -999,6 +1013,31 @@ def run_all(pafc, torch, args):
     return head
 
 
+def stream_probe(pafc, torch, args):
+    """The strided middle pass's access pattern with no arithmetic, beside a
+    plain copy: 256 MiB arrays, 256-byte row segments (pafc_stream_copy kinds
+    tile_copy / tile_mul); GB/s of the bytes each kernel moves."""
+    nbytes = 256 << 20
+    n16 = nbytes // 16
+    src = torch.zeros(2 * n16, dtype=torch.complex128, device="cuda")
+    dst = torch.zeros(n16, dtype=torch.complex128, device="cuda")
+    out = {"bytes_per_array": nbytes}
+    for kind, moved, s_view in (("copy16", 2, src[:n16]), ("tile_copy", 2, src[:n16]),
+                                ("tile_mul", 3, src)):
+        for _ in range(3):
+            pafc.stream_copy(s_view, dst, kind=kind)
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(21)]
+        ev[0].record()
+        for k in range(20):
+            pafc.stream_copy(s_view, dst, kind=kind)
+            ev[k + 1].record()
+        torch.cuda.synchronize()
+        ms = sorted(ev[k].elapsed_time(ev[k + 1]) for k in range(20))[10]
+        out[kind] = {"ms": round(ms, 5), "gbs": round(moved * nbytes / (ms * 1e-3) / 1e9, 1)}
+    return out
+
+
 def counter_run(pafc, torch, args):
     """K convolutions of one workload after its set-up, for rocprofv3 counter
     runs: the last K x launches_per_conv dispatches of library kernels are
@@ -1057,6 +1096,8 @@ def main():
     ap.add_argument("--batch-form", default="auto", choices=sorted(BATCH_FORMS) + ["auto"],
                     help="form of the batched workload that `value` reports (auto: the "
                          "library's choice for the dtype)")
+    ap.add_argument("--probe", action="store_true",
+                    help="streaming probes of the strided middle pass's access pattern")
     ap.add_argument("--filter-per-call", action="store_true",
                     help="transform the filter inside every timed call (three transforms per "
                          "convolution, as the paper times it)")
@@ -1079,6 +1120,9 @@ def main():
     import paper_2506_12718_amd as pafc
     pafc.lib()
     torch.cuda.set_device(0)
+    if args.probe:
+        print(json.dumps(stream_probe(pafc, torch, args)))
+        return
     if args.calibrate:
         nbytes = 256 << 20
         a = torch.zeros(nbytes // 16, dtype=torch.complex128, device="cuda")

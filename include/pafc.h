@@ -417,9 +417,14 @@ pafc_status pafc_twiddle(int64_t n, int64_t e, double* re, double* im);
  * kind 1: the same copy with 8 bytes per lane; kind 2: read-only sweep of
  * src_dev (every byte read once), writing one 16-byte partial sum per block
  * of 256 lanes at the start of dst_dev (at most bytes / 256 + 16 bytes).
- * Both arrays hold `bytes` bytes and are 16-byte aligned.
- * Errors: INVALID_VALUE (NULL, misaligned, bytes not a multiple of 16, kind
- * not 0..2), DEVICE.
+ * Both arrays hold `bytes` bytes and are 16-byte aligned.  kinds 3 and 4
+ * probe the access pattern of a strided middle pass: the arrays are 256 rows
+ * of bytes / 4096 16-byte elements, walked in tiles of all rows x 16 columns
+ * (256-byte row segments); kind 3 copies src_dev to dst_dev that way, kind 4
+ * writes x * h, where src_dev holds x (`bytes`) followed by h (`bytes`, read
+ * contiguously in tile order).  bytes must then be a multiple of 65536.
+ * Errors: INVALID_VALUE (NULL, misaligned, bytes not a multiple of 16 (of
+ * 65536 for kinds 3 and 4), kind not 0..4), DEVICE.
  */
 pafc_status pafc_stream_copy(const void* src_dev, void* dst_dev, size_t bytes, int kind,
                              void* hip_stream);

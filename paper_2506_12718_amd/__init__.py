@@ -205,15 +205,17 @@ def twiddle(n, e):
     return complex(re.value, im.value)
 
 
-STREAM_KINDS = {"copy16": 0, "copy8": 1, "read": 2}
+STREAM_KINDS = {"copy16": 0, "copy8": 1, "read": 2, "tile_copy": 3, "tile_mul": 4}
 
 
 def stream_copy(src, dst, stream=None, kind="copy16"):
-    """Reference kernels of known traffic for counter calibration: a
-    streaming copy with 16 or 8 bytes per lane, or a read-only sweep of
-    src (pafc_stream_copy)."""
-    nbytes = src.numel() * src.element_size()
-    assert dst.numel() * dst.element_size() == nbytes
+    """Reference kernels of known traffic (pafc_stream_copy): a streaming
+    copy with 16 or 8 bytes per lane or a read-only sweep of src (counter
+    calibration), and the strided middle pass's access pattern without its
+    arithmetic ("tile_copy"; "tile_mul": src holds x then h, dst gets x*h)."""
+    nbytes = dst.numel() * dst.element_size()
+    want = 2 * nbytes if kind == "tile_mul" else nbytes
+    assert src.numel() * src.element_size() == want
     _check(lib().pafc_stream_copy(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()),
                                   nbytes, STREAM_KINDS[kind], _stream(stream)), "pafc_stream_copy")
 

@@ -2625,7 +2625,10 @@ pafc_status pafc_twiddle(int64_t n, int64_t e, double* re, double* im) {
 
 pafc_status pafc_stream_copy(const void* src_dev, void* dst_dev, size_t bytes, int kind,
                              void* hip_stream) {
-  if (!src_dev || !dst_dev || (bytes % 16) != 0 || kind < 0 || kind > 2)
+  if (!src_dev || !dst_dev || (bytes % 16) != 0 || kind < 0 || kind > 4)
+    return PAFC_ERROR_INVALID_VALUE;
+  // the tile probes: 256 rows of a multiple of 16 columns, below 2^32 elements
+  if (kind >= 3 && (bytes % (256u * 16u * 16u) != 0 || bytes / 16 >= (1ull << 32)))
     return PAFC_ERROR_INVALID_VALUE;
   if (((uintptr_t)src_dev & 15) || ((uintptr_t)dst_dev & 15)) return PAFC_ERROR_INVALID_VALUE;
   return from_hip(launch_stream_copy(kind, src_dev, dst_dev, (int64_t)(bytes / 16),

@@ -117,6 +117,37 @@ __global__ void stream_copy8_kernel(const uint64_t* __restrict__ a, uint64_t* __
     b[i] = a[i];
 }
 
+// Streaming probes with the access pattern of a strided middle pass: the
+// array is 256 rows of `cols` 16-byte elements, a tile is all 256 rows x 16
+// columns (256-byte row segments), and each block walks the tiles
+// blockIdx.x, + gridDim.x, ...  Per tile every thread moves 16 elements, all
+// loads issued before the stores.  MUL: the output is x * h, h read
+// contiguously in tile order (as a tile-major spectrum).
+template <bool MUL>
+__global__ void __launch_bounds__(256) tile_stream_kernel(const double2* __restrict__ x,
+                                                          const double2* __restrict__ h,
+                                                          double2* __restrict__ y,
+                                                          uint32_t cols) {
+  const uint32_t ntiles = cols / 16u;
+  const uint32_t tid = threadIdx.x;
+  for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    double2 v[16], w[16];
+#pragma unroll
+    for (uint32_t k = 0; k < 16; ++k) {
+      const uint32_t idx = k * 256u + tid;  // row idx / 16, column idx % 16
+      v[k] = x[(size_t)(idx >> 4) * cols + t * 16u + (idx & 15u)];
+      if (MUL) w[k] = h[(size_t)t * 4096u + idx];
+    }
+#pragma unroll
+    for (uint32_t k = 0; k < 16; ++k) {
+      const uint32_t idx = k * 256u + tid;
+      double2 o = v[k];
+      if (MUL) o = double2{v[k].x * w[k].x - v[k].y * w[k].y, v[k].x * w[k].y + v[k].y * w[k].x};
+      y[(size_t)(idx >> 4) * cols + t * 16u + (idx & 15u)] = o;
+    }
+  }
+}
+
 // Read-only sweep: every 16-byte element read once; one 16-byte sum per
 // block is written (so the reads cannot be dropped), a negligible write.
 __global__ void __launch_bounds__(256) stream_read_kernel(const double2* __restrict__ a,
@@ -771,7 +802,17 @@ hipError_t launch_stream_copy(int kind, const void* src, void* dst, int64_t n16,
   else if (kind == 2)  // at most 65536 blocks, so at most 1 MiB of dst is written
     hipLaunchKernelGGL(stream_read_kernel, dim3(grid_for(n16)), dim3(256), 0, st,
                        (const double2*)src, (double2*)dst, n16);
-  else
+  else if (kind == 3 || kind == 4) {  // n16 = 256 rows x cols, cols a multiple of 16
+    const uint32_t cols = (uint32_t)(n16 / 256);
+    const uint32_t grid = std::min<uint32_t>(cols / 16u, 512u);
+    const double2* x = (const double2*)src;
+    if (kind == 3)
+      hipLaunchKernelGGL(tile_stream_kernel<false>, dim3(grid), dim3(256), 0, st, x, x,
+                         (double2*)dst, cols);
+    else
+      hipLaunchKernelGGL(tile_stream_kernel<true>, dim3(grid), dim3(256), 0, st, x, x + n16,
+                         (double2*)dst, cols);
+  } else
     return hipErrorInvalidValue;
   return hipGetLastError();
 }

@@ -342,3 +342,15 @@ def test_size_limits_and_batch_argument_errors():
         st = L.pafc_batch_plan(ctypes.byref(h), 2, (I64 * 2)(64, 97), (I32 * 2)(0, 1), 2, 2, form,
                                None)
         assert st == 2 and not h.value
+
+
+def test_stream_probe_argument_checks():
+    """pafc_stream_copy rejects unknown kinds and, for the tile probes, sizes
+    that are not whole 256-row x 16-column tiles -- before any device call."""
+    L = pafc.lib()
+    a, b = ctypes.c_void_p(1 << 20), ctypes.c_void_p(2 << 20)  # aligned, never dereferenced
+    assert L.pafc_stream_copy(a, b, 1 << 16, 5, None) == 1
+    assert L.pafc_stream_copy(a, b, 1 << 16, -1, None) == 1
+    for kind in (3, 4):
+        assert L.pafc_stream_copy(a, b, (1 << 16) + 16, kind, None) == 1
+        assert L.pafc_stream_copy(a, b, 4096, kind, None) == 1
