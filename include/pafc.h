@@ -457,7 +457,7 @@ pafc_status pafc_stream_copy(const void* src_dev, void* dst_dev, size_t bytes, i
  *     that its plan runs on the pipelined kernel is one launch of that
  *     kernel over every problem of the class (a device table gives each
  *     problem's offset), and each size class's launches form a chain: the
- *     chains run on 4 streams (PAFC_BATCH_STREAMS), three of them the
+ *     chains run on 6 streams (PAFC_BATCH_STREAMS), five of them the
  *     batch's own, forked from the caller's stream and joined back into it
  *     by events (capturable).  The packed arrays and the spectra must each
  *     stay within 4 GiB.

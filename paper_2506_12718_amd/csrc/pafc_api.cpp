@@ -110,7 +110,7 @@ constexpr size_t kLdsBudget = 160 * 1024;  // LDS per CU on gfx950
 //                  group (stages) where the tuning table has no entry
 //   PAFC_NO_TUNING_TABLE 1 (binding) loads no tuning table
 //   PAFC_LDS_POISON 1 (debug) every pass fills its LDS tile with NaN first
-//   PAFC_BATCH_STREAMS streams of the batched classes form (default 4)
+//   PAFC_BATCH_STREAMS streams of the batched classes form (default 6)
 //   PAFC_BATCH_LDS_KB  tile LDS bound of the batched persistent form
 //   PAFC_LDS_PAD   1 pads the LDS tiles of odd-length contiguous passes too
 //   PAFC_FAULT_INJECT=oom  pafc_plan fails with OUT_OF_MEMORY after its first
@@ -737,9 +737,9 @@ bool make_pass(const Seg& s_in, int kind, size_t elem, Pass* p,
       const uint64_t LW = a.LW;
       // tile, then the flat table of the piece (or, outer, the two-level
       // table of the general engine's layout)
-      // (long contiguous tiles of even length pad the table one in 16, as
-      // the kernel's pipe_tw_pad)
-      const bool twpad = s.mode == MODE_CONTIG && s.L % 2 == 0 && s.L >= 1024;
+      // (long contiguous or column-folded tiles of even length pad the table
+      // one in 16, as the kernel's pipe_tw_pad)
+      const bool twpad = (s.mode == MODE_CONTIG || (ext && xc > 0)) && s.L % 2 == 0 && s.L >= 1024;
       p->pipe_lds = outer ? p->lds
                           : (size_t)(((LW + (LW >> 4) + 2) & ~1ull) + s.L + (twpad ? s.L / 16 : 0)) *
                                 elem;
@@ -3016,13 +3016,14 @@ pafc_status pafc_batch_plan(pafc_batch_t* out, int count, const int64_t* sizes,
     b->levels.push_back(L);
     nlevels = 0;  // no level launches
   }
-  // classes form on several streams (PAFC_BATCH_STREAMS, default 4: one
-  // batch of 4096 problems measured 2.145 / 1.883 / 1.876 / 1.858 ms FP64 and
-  // 1.244 / 1.096 / 1.016 / 1.018 ms FP32 on 1 / 2 / 3 / 4 streams): the
-  // general engine's launches are made per size class too, so that every
-  // launch belongs to one chain
+  // classes form on several streams (PAFC_BATCH_STREAMS, default 6: one
+  // batch of 4096 problems measured 2.145 / 1.883 / 1.876 / 1.852 / 1.827 /
+  // 1.765 / 1.870 ms FP64 and 1.244 / 1.096 / 1.016 / 1.017 / 0.982 / 0.950 /
+  // 1.012 ms FP32 on 1 / 2 / 3 / 4 / 5 / 6 / 8 streams): the general engine's
+  // launches are made per size class too, so that every launch belongs to
+  // one chain
   if (form == PAFC_BATCH_CLASSES)
-    b->nstreams = std::max(1, std::min(8, env_int("PAFC_BATCH_STREAMS", 4)));
+    b->nstreams = std::max(1, std::min(8, env_int("PAFC_BATCH_STREAMS", 6)));
   std::vector<int64_t> split_classes{0};  // 0: one group over all classes
   if (b->nstreams > 1) {
     split_classes.clear();

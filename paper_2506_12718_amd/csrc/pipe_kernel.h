@@ -103,10 +103,14 @@ constexpr bool pipe_outer_shape() {
          (r == 8 && g == 1 && NG == 1);  // the short outer pieces of the batched 1-D lengths
 }
 
-// Long contiguous tiles of even length pad their LDS twiddle table (see
-// pipe_kernel); the host sizes the table by the same rule.
-template <int MODE, int L>
-constexpr bool pipe_tw_pad() { return MODE == MODE_CONTIG && L % 2 == 0 && L >= 1024; }
+// Long tiles of even length whose items run over consecutive j -- the
+// contiguous ones, and the strided ones with folded columns (W = 2^XC <= 4
+// columns per row) -- pad their LDS twiddle table (see pipe_kernel); the host
+// sizes the table by the same rule.
+template <int MODE, int L, int XC>
+constexpr bool pipe_tw_pad() {
+  return (MODE == MODE_CONTIG || XC > 0) && L % 2 == 0 && L >= 1024;
+}
 
 // Butterflies of a 2-point DFT across lane bit b (the two values of a pair
 // of lanes differing in bit b): the lower lane keeps x0 + x1, the upper
@@ -211,7 +215,7 @@ pipe_kernel(const PassArgs* __restrict__ desc, const void* in, void* out) {
   // of 16 m elements, which land on few banks.  One pad element every 16
   // spreads them (the padded table takes L + L / 16 slots).
   auto twp = [](uint32_t e) -> uint32_t {
-    if constexpr (pipe_tw_pad<MODE, Sh::L>())
+    if constexpr (pipe_tw_pad<MODE, Sh::L, XC>())
       return e + (e >> 4);
     else
       return e;
