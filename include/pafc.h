@@ -446,7 +446,7 @@ pafc_status pafc_stream_copy(const void* src_dev, void* dst_dev, size_t bytes, i
  *     problem in order; blocks never wait for one another.  The size-class
  *     plans are made for that one kernel: 256 threads, register groups of
  *     at most 16 points, tiles within one LDS size (80 KB in FP64, 32 KB in
- *     FP32 by default).  The
+ *     FP32 by default), and without the pafc_set_tuning table.  The
  *     launch leaves its two control words zero, so it can be replayed from a
  *     captured hipGraph; two launches of one batch must not overlap.
  *   PAFC_BATCH_LEVELS: pafc_batch_convolve enqueues, for each pass level in
