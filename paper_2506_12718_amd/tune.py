@@ -176,6 +176,107 @@ def tune_one(pafc, timer, dt, n, measure, prev=None,
     return cfg, best, log
 
 
+class TableLib:
+    """tune_one's view of the library when one entry of a whole table is
+    searched: set_tuning(line) installs the table with that entry replaced
+    (None: without it)."""
+
+    def __init__(self, pafc, lines, dt, n):
+        self.pafc, self.lines, self.key = pafc, dict(lines), (dt, n)
+
+    def text(self, entry):
+        lines = dict(self.lines)
+        lines.pop(self.key, None)
+        if entry:
+            lines[self.key] = entry
+        return "\n".join(lines.values()) + "\n"
+
+    def set_tuning(self, entry):
+        self.pafc.set_tuning(self.text(entry))
+
+    def describe(self, dims, dt):
+        return self.pafc.describe(dims, dt)
+
+
+class MixedBatch:
+    """The benchmark's mixed batch (4096 problems over the 18 size classes)
+    timed in one batched form as the benchmark times it: median of graph
+    replays, HIP events."""
+
+    def __init__(self, pafc, torch, dt, form, reps):
+        from paper_2506_12718_amd import inputs
+        self.pafc, self.torch, self.form, self.reps = pafc, torch, form, reps
+        self.tdt = torch.complex128 if dt == "c128" else torch.complex64
+        psizes, xs, filters = inputs.batched_problems()
+        classes = sorted(filters)
+        self.sizes = psizes
+        self.fids = [classes.index(n) for n in psizes]
+        self.nf = len(classes)
+        self.x = torch.from_numpy(np.concatenate(xs)).to(self.tdt).cuda()
+        self.y = torch.empty_like(self.x)
+        self.h = {classes.index(n): torch.from_numpy(h).to(self.tdt).cuda()
+                  for n, h in filters.items()}
+
+    def measure(self):
+        torch = self.torch
+        B = self.pafc.Batch(self.sizes, self.fids, self.nf, self.tdt, form=self.form)
+        for f, h in self.h.items():
+            B.set_filter(f, h)
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.stream(s):
+            B.convolve(self.x, out=self.y, stream=s)
+            torch.cuda.synchronize()
+            with torch.cuda.graph(g, stream=s):
+                B.convolve(self.x, out=self.y, stream=s)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(self.reps + 1)]
+        ev[0].record()
+        for k in range(self.reps):
+            g.replay()
+            ev[k + 1].record()
+        torch.cuda.synchronize()
+        del g
+        B.close()
+        return float(np.median([ev[k].elapsed_time(ev[k + 1]) for k in range(self.reps)]))
+
+
+def tune_mixed(pafc, torch, dt, form, lines, reps, sizes):
+    """Re-tune the batched size classes' entries against the whole mixed
+    batch in `form`, largest classes first, each search starting from the
+    table's entry; `lines` ((dtype, n) -> table line) is updated in place."""
+    mixed = MixedBatch(pafc, torch, dt, form, reps)
+    report = []
+    one_d = ("g3", "g5", "split", "W", "Wo", "g3i")
+    for n in sorted(sizes, reverse=True):
+        lib = TableLib(pafc, lines, dt, n)
+        prev = read_table_text(lines.get((dt, n), "")).get((dt, n))
+        cfg, t, log = tune_one(lib, None, dt, n, mixed.measure, prev, one_d)
+        if any(cfg.values()):
+            lines[(dt, n)] = line(dt, n, cfg) + "   # %.4f ms per mixed batch (%s form)" % (t, form)
+        else:
+            lines.pop((dt, n), None)
+        report.append({"dtype": dt, "n": n, "cfg": cfg, "batch_ms": round(t, 5),
+                       "start_ms": round(log[0][1], 5) if isinstance(log[0][1], float) else None})
+        print(json.dumps(report[-1]), flush=True)
+    pafc.set_tuning("\n".join(lines.values()) + "\n")
+    return report
+
+
+def read_table_text(text):
+    out = {}
+    for t in text.splitlines():
+        f = t.split("#")[0].split()
+        if len(f) in (7, 8):
+            cfg = dict(zip(FIELDS, map(int, f[2:])))
+            cfg.setdefault("g3i", 0)
+            out[(f[0], int(f[1]))] = cfg
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--dtypes", nargs="+", default=["c128", "c64"])
@@ -185,6 +286,9 @@ def main(argv=None):
                     help="existing table whose entries are tried as starting points ('' for none)")
     ap.add_argument("--batch-form", default="auto",
                     help="batched form the size classes are timed in (Batch form names)")
+    ap.add_argument("--mixed", action="store_true",
+                    help="re-tune the batched size classes against the whole mixed batch in "
+                         "--batch-form, starting from --prev; other entries are kept")
     ap.add_argument("--sizes", nargs="*", type=int, default=None,
                     help="tune only these axis lengths; the other entries of --prev are kept")
     a = ap.parse_args(argv)
@@ -197,6 +301,18 @@ def main(argv=None):
     lines = ["# pafc planner tuning table (python -m paper_2506_12718_amd.tune)",
              "# device: %s (%s)" % (dev.name, getattr(dev, "gcnArchName", "?")),
              "# format: dtype n split W Wo g3 g5 [g3i]   (0 = planner default)"]
+    if a.mixed:
+        table = {k: v.split("#")[0].rstrip() + ("   #" + v.split("#", 1)[1] if "#" in v else "")
+                 for k, v in prev_lines.items()}
+        sizes = a.sizes if a.sizes is not None else BATCH_SIZES
+        for dt in a.dtypes:
+            tune_mixed(pafc, torch, dt, a.batch_form, table, a.reps, sizes)
+        body = sorted(table.items(), key=lambda kv: (kv[0][0] != "c128", kv[0][1]))
+        os.makedirs(os.path.dirname(a.out), exist_ok=True)
+        with open(a.out, "w") as f:
+            f.write("\n".join(lines + [v for _, v in body]) + "\n")
+        print("wrote", a.out, flush=True)
+        return
     report = []
     for dt in a.dtypes:
         timer = Timer(pafc, torch, dt, reps=a.reps, batch_form=a.batch_form)
