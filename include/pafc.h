@@ -494,7 +494,9 @@ pafc_status pafc_batch_set_filter(pafc_batch_t b, int filter_id,
                                   void* hip_stream);
 
 /* y = x * h for every problem; x_dev and y_dev are packed arrays of
-   sum(sizes) elements; y_dev == x_dev allowed.
+   sum(sizes) elements; y_dev == x_dev allowed.  A batch is used on one
+   stream at a time (its control words, and in the classes form its own
+   streams and events, are shared by its calls).
    Errors: INVALID_VALUE, FILTER_NOT_SET (some filter used but not set), DEVICE. */
 pafc_status pafc_batch_convolve(pafc_batch_t b, const void* x_dev, void* y_dev,
                                 void* hip_stream);
@@ -505,13 +507,14 @@ pafc_status pafc_batch_device_bytes(pafc_batch_t b, size_t* bytes);
 
 /*
  * pafc_batch_profile -- run pafc_batch_convolve `reps` times with a hipEvent
- * around every launch (one launch per pass level, register class and
- * LDS-bound occupancy: at most 72), synchronise, and report the mean ms of
+ * around every launch, all on hip_stream (so the classes form's launches do
+ * not overlap here), synchronise, and report the mean ms of
  * each launch, its algorithmic HBM bytes (one read and one write of every
  * element of every problem in the launch, plus each filter spectrum once in
  * the launch that multiplies by it), and the ms of every repetition
  * (ms_per_rep may be NULL).  *nlevel: capacity in, count out.
- * Errors: as pafc_batch_convolve; INVALID_VALUE if the capacity is too small.
+ * Errors: as pafc_batch_convolve; INVALID_VALUE if the capacity is too small
+ * (with *nlevel set to the count and nothing launched).
  */
 pafc_status pafc_batch_profile(pafc_batch_t b, const void* x_dev, void* y_dev,
                                void* hip_stream, int reps, double* ms_per_level,

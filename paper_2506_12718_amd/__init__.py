@@ -435,9 +435,17 @@ class Batch:
         """Run `reps` batched convolutions with a HIP event around every
         launch.  Returns (mean ms per level, algorithmic bytes per level, ms of
         every repetition)."""
-        n = ctypes.c_int(72)
-        ms = (ctypes.c_double * 72)()
-        by = (ctypes.c_int64 * 72)()
+        n = ctypes.c_int(0)  # first ask for the number of launches
+        st = lib().pafc_batch_profile(self._h, ctypes.c_void_p(x.data_ptr()),
+                                      ctypes.c_void_p(out.data_ptr()), _stream(stream),
+                                      int(reps), (ctypes.c_double * 1)(), None, None,
+                                      ctypes.byref(n))
+        if st not in (0, 1):
+            _check(st, "pafc_batch_profile")
+        cap = max(1, n.value)
+        n = ctypes.c_int(cap)
+        ms = (ctypes.c_double * cap)()
+        by = (ctypes.c_int64 * cap)()
         per = (ctypes.c_double * int(reps))()
         _check(lib().pafc_batch_profile(self._h, ctypes.c_void_p(x.data_ptr()),
                                         ctypes.c_void_p(out.data_ptr()), _stream(stream),

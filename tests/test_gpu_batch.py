@@ -232,6 +232,34 @@ def test_classes_form_on_several_streams(dtype, monkeypatch):
                     TOL[dtype], what="streams %d" % sizes[i])
 
 
+def test_profile_reports_every_launch():
+    """32 size classes of three passes each: the classes form makes one
+    launch per class and pass on its streams (more than the 72 the binding
+    once assumed); the profile reports every one of them, timed in order
+    on one stream, and leaves the same result as a convolution."""
+    m = pafc()
+    sizes = [8192, 9216, 10000, 10800, 11664, 12500, 13500, 15000, 16000, 17280, 18432, 19683,
+             20736, 23040, 24576, 26244, 28800, 30720, 32400, 34560, 36864, 39366, 41472, 46080,
+             48600, 51200, 54675, 58320, 61440, 64800, 69120, 73728]
+    rng = np.random.default_rng(21)
+    xs = [inputs.complex_uniform(rng, (n,)) for n in sizes]
+    hs = [inputs.complex_uniform(rng, (n,)) for n in sizes]
+    B = m.Batch(sizes, list(range(len(sizes))), len(sizes), torch.complex128, form="classes")
+    for f, h in enumerate(hs):
+        B.set_filter(f, to_dev(h, torch.complex128))
+    levels = B.describe()["levels"]
+    assert len(levels) > 72, len(levels)
+    x = to_dev(pack(xs), torch.complex128)
+    y = torch.empty_like(x)
+    ms, by, per = B.profile_levels(x, y, reps=2)
+    assert len(ms) == len(by) == len(levels) and len(per) == 2
+    assert all(t > 0 for t in ms) and all(b > 0 for b in by)
+    ys = unpack(to_host(y), sizes)
+    for i in (0, 11, 31):
+        check_close(ys[i], oracle.conv_fft(xs[i], hs[i]), 1e-12, what=str(sizes[i]))
+    B.close()
+
+
 @pytest.mark.parametrize("form", FORMS)
 def test_batch_errors(form):
     m = pafc()
