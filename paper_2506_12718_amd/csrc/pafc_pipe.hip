@@ -27,6 +27,7 @@ bool pipe_outer_supported(int r, int g, int ng) {
 // folded column axes of a middle pass).
 int pipe_thread_limit(int r, int g, bool dbl, int xc) {
   if ((r == 3 || r == 5) && g == 1) return 1024;
+  if (r == 3 && g == 2) return 512;  // radix-9 items: 2 waves per SIMD unspilled
   return xc > 0 && !dbl ? 512 : 256;
 }
 

@@ -80,7 +80,9 @@ constexpr int pipe_waves_per_eu() { return KIND == PIPE_FWD && NG == 2 ? 2 : 1; 
 // (whose items need few registers: a 1024-thread block leaves 128 VGPRs per
 // thread); the count need not be a multiple of the wave size.
 template <int r, int g>
-constexpr int pipe_max_threads() { return (r == 3 || r == 5) && g == 1 ? 1024 : 256; }
+constexpr int pipe_max_threads() {
+  return (r == 3 || r == 5) && g == 1 ? 1024 : r == 3 && g == 2 ? 512 : 256;
+}
 // FP32 middle passes with folded columns also take 512 threads (a 4096-long
 // axis with two columns): their items fit 2 waves per SIMD unspilled.
 template <typename T, int r, int g, int XC>
