@@ -104,6 +104,8 @@ constexpr size_t kLdsBudget = 160 * 1024;  // LDS per CU on gfx950
 //   PAFC_SNAKE     0 walks every pass's tiles in the same direction
 //   PAFC_AXIS_ORDER 1 runs the other axes' forward passes slowest first
 //   PAFC_HTM       0 keeps the spectrum in plan layout (no tile-major order)
+//   PAFC_LLC_MB    array size in MiB from which the spectrum and a sequence's
+//                  input are read non-temporally (default 256; 1 << 20 never)
 //   PAFC_PIPE      0 runs every pass on the general engine (no pipelined kernel)
 //   PAFC_PIPE_OUTER 0 keeps outer pieces of cut axes on the general engine
 //   PAFC_TUNE_GMAX3 / PAFC_TUNE_GMAX5  largest radix-3 / radix-5 register
@@ -2242,6 +2244,21 @@ pafc_status make_plan(pafc_plan_t* out, int ndim, const int64_t* dims, const int
   // than it.
   const bool snake = env_int("PAFC_SNAKE", 1) != 0;
   const bool poison = env_int("PAFC_LDS_POISON", 0) != 0;
+  // Streamed reads.  Where the arrays outgrow the device's last-level cache
+  // (256 MB Infinity Cache on MI355X), the spectrum is read once per
+  // convolution and the sequence's first pass reads the caller's input cold;
+  // ordinary loads of either would only evict lines of the array the
+  // previous pass wrote, which the current and next passes still read.
+  // Non-temporal loads keep those lines (the 256^3 FP64 middle pass 161 ->
+  // 130 us, its first pass 101 -> 88 us).  The spectrum is streamed only
+  // where each load instruction covers whole 128-byte lines or halves of
+  // them (tile-major spectrum, or row segments of 64 bytes or more): with
+  // shorter segments the rest of a line is evicted before the tile that
+  // needs it reads it (the 2^24 x 2 middle passes, 2-column segments, ran
+  // 1.2-1.4x slower streamed).  Smaller arrays keep their spectrum cached
+  // across calls and use ordinary loads.
+  const int64_t llc = (int64_t)env_int("PAFC_LLC_MB", 256) << 20;
+  const int64_t ne = P.N * (int64_t)P.elem;
   std::vector<PassArgs> descs;
   for (auto* seq : {&p->P.conv, &p->P.fwd, &p->P.inv}) {
     int i = 0;
@@ -2253,6 +2270,9 @@ pafc_status make_plan(pafc_plan_t* out, int ndim, const int64_t* dims, const int
       a.rev = snake && (i++ % 2 == 1) ? 1u : 0u;
       a.poison = poison ? 1u : 0u;
       if (p->h_tm && seq == &p->P.conv && &ps == &p->P.conv[(size_t)p->mid_pass]) a.h_tm = 1;
+      const int64_t seg = (ps.a.mode == MODE_STRIDED ? (int64_t)ps.a.W : (int64_t)ps.a.L) * P.elem;
+      if (ps.mid && 2 * ne >= llc && (a.h_tm || seg >= 64)) a.nt |= 1u;
+      if (&ps == &seq->front() && ne >= llc) a.nt |= 2u;
       descs.push_back(a);
     }
   }

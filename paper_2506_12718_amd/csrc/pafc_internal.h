@@ -140,6 +140,11 @@ struct PassArgs {
                        // strides are odd and conflict-free unpadded
   uint32_t poison;     // debug: fill the LDS tile with NaN before each tile,
                        // so a read of LDS that no op wrote shows in the result
+  uint32_t nt;         // pipelined kernel: bit 0 reads the spectrum, bit 1
+                       // the pass's input, with non-temporal loads (set for
+                       // arrays too large to stay in the last-level cache,
+                       // where such a read would only evict lines that the
+                       // next pass could still use)
   // one launch over many problems of one length (the batched form's size
   // classes, pipelined kernel only): launch tile t is tile t mod
   // tiles_per_prob of problem t / tiles_per_prob, whose data start at element

@@ -280,49 +280,61 @@ pipe_kernel(const PassArgs* __restrict__ desc, const void* in, void* out) {
   cx<T> pre[R];
   cx<T> preh[KIND == PIPE_MID ? R : 1];
 
+  // a.nt selects non-temporal loads for the input (bit 1) and the spectrum
+  // (bit 0); the branch is uniform, taken once per tile
   auto fetch_x = [&](uint32_t tile) {
     uint32_t col0;
     const uint32_t base = tile_base(tile, col0);
-    if constexpr (LINEAR_LOAD) {
-      static_for<R>([&](auto q) {
-        const uint32_t x = tid + nthr * q.value;
-        const uint32_t c = x / (uint32_t)L, i = x - c * (uint32_t)L;
-        pre[q.value] = (col0 + c < a.ncols) ? ld_g32<T>(in, base + i + c * S_c)
-                                            : cx<T>{(T)0, (T)0};
-      });
-    } else {
-      constexpr int k0 = Sh::level(0);
-      constexpr int K0 = k0 == NG - 1 ? R : L / ipow(R, k0);
-      constexpr int S0 = K0 / R;
-      const Item it = item_of<R, L, K0, MODE>(tid, W, logW, col0, a.ncols);
-      const uint32_t gb = base + it.i0 * S_i + it.c * S_c;
-      static_for<R>([&](auto s) {
-        // DIF reads natural positions, DIT reads digit-reversed ones
-        constexpr int p = Sh::type(0) == OP_DIT ? slot_rev<r, g, GM, NG>(k0, s.value) : s.value;
-        pre[s.value] = it.valid ? ld_g32<T>(in, gb + (uint32_t)(p * S0) * S_i) : cx<T>{(T)0, (T)0};
-      });
-    }
+    auto load = [&](auto nt) {
+      constexpr bool NT = decltype(nt)::value;
+      if constexpr (LINEAR_LOAD) {
+        static_for<R>([&](auto q) {
+          const uint32_t x = tid + nthr * q.value;
+          const uint32_t c = x / (uint32_t)L, i = x - c * (uint32_t)L;
+          pre[q.value] = (col0 + c < a.ncols) ? ld_g32s<T, NT>(in, base + i + c * S_c)
+                                              : cx<T>{(T)0, (T)0};
+        });
+      } else {
+        constexpr int k0 = Sh::level(0);
+        constexpr int K0 = k0 == NG - 1 ? R : L / ipow(R, k0);
+        constexpr int S0 = K0 / R;
+        const Item it = item_of<R, L, K0, MODE>(tid, W, logW, col0, a.ncols);
+        const uint32_t gb = base + it.i0 * S_i + it.c * S_c;
+        static_for<R>([&](auto s) {
+          // DIF reads natural positions, DIT reads digit-reversed ones
+          constexpr int p = Sh::type(0) == OP_DIT ? slot_rev<r, g, GM, NG>(k0, s.value) : s.value;
+          pre[s.value] = it.valid ? ld_g32s<T, NT>(in, gb + (uint32_t)(p * S0) * S_i)
+                                  : cx<T>{(T)0, (T)0};
+        });
+      }
+    };
+    if (a.nt & 2u) load(std::true_type{}); else load(std::false_type{});
   };
   auto fetch_h = [&](uint32_t tile) {
     if constexpr (KIND == PIPE_MID) {
       // the spectrum has one problem's layout
       const Loc q = locate(tile);
       const Item it = item_of<R, L, R, MODE>(tid, W, logW, q.col0, a.ncols);
-      if (a.h_tm) {  // one contiguous block per tile, slot-major
-        const uint32_t tb = q.hb + q.lt * LW + tid;
-        static_for<R>([&](auto m) {
-          preh[m.value] = it.valid ? ld_g32<T>(a.H, tb + (uint32_t)m.value * nthr)
-                                   : cx<T>{(T)0, (T)0};
-        });
-      } else {
-        // slot m = u RM + m2 multiplies frequency m2 of the thread's u-th
-        // innermost group, which sits at its digit-reversed position
-        const uint32_t gb = q.hb + q.base + it.i0 * S_i + it.c * S_c;
-        static_for<R>([&](auto m) {
-          constexpr int pos = (m.value / RM) * RM + digrev<r, GM>(m.value % RM);
-          preh[m.value] = it.valid ? ld_g32<T>(a.H, gb + (uint32_t)pos * S_i) : cx<T>{(T)0, (T)0};
-        });
-      }
+      auto load = [&](auto nt) {
+        constexpr bool NT = decltype(nt)::value;
+        if (a.h_tm) {  // one contiguous block per tile, slot-major
+          const uint32_t tb = q.hb + q.lt * LW + tid;
+          static_for<R>([&](auto m) {
+            preh[m.value] = it.valid ? ld_g32s<T, NT>(a.H, tb + (uint32_t)m.value * nthr)
+                                     : cx<T>{(T)0, (T)0};
+          });
+        } else {
+          // slot m = u RM + m2 multiplies frequency m2 of the thread's u-th
+          // innermost group, which sits at its digit-reversed position
+          const uint32_t gb = q.hb + q.base + it.i0 * S_i + it.c * S_c;
+          static_for<R>([&](auto m) {
+            constexpr int pos = (m.value / RM) * RM + digrev<r, GM>(m.value % RM);
+            preh[m.value] = it.valid ? ld_g32s<T, NT>(a.H, gb + (uint32_t)pos * S_i)
+                                     : cx<T>{(T)0, (T)0};
+          });
+        }
+      };
+      if (a.nt & 1u) load(std::true_type{}); else load(std::false_type{});
     }
   };
 

@@ -335,6 +335,39 @@ def test_tile_major_spectrum(shape, radix, dtype, monkeypatch):
     check_close(out["1"][1], ref_b, TOL[dtype])
 
 
+STREAM_CASES = [((256, 256), [4, 4]), ((64, 64, 64), [4, 4, 4]), ((4096, 48), [4, 0]),
+                ((2048, 2, 2), None), ((1 << 14, 2), None), ((243, 243), None), ((4096,), [4])]
+
+
+@pytest.mark.parametrize("shape,radix", STREAM_CASES)
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_streamed_loads_leave_results_unchanged(shape, radix, dtype, monkeypatch):
+    """Plans read the spectrum and the first pass's input with non-temporal
+    loads when the arrays exceed the last-level cache (PAFC_LLC_MB, default
+    256).  With the bound at 0 every plan takes them wherever its layout
+    allows (tile-major spectra, contiguous and 64-byte-or-longer strided
+    segments, folded columns): bit-identical to ordinary loads (bound out of
+    reach), for the convolution, the filter's forward transform and the
+    per-call filter, and matching the oracle."""
+    rng = np.random.default_rng([len(shape), shape[0], 17])
+    x = inputs.complex_uniform(rng, shape)
+    h = inputs.complex_uniform(rng, shape)
+    out = {}
+    for mb in ("0", "1048576"):
+        monkeypatch.setenv("PAFC_LLC_MB", mb)
+        P = pafc().Plan(shape, dtype, radix=radix)
+        xd = to_dev(x, dtype)
+        P.set_filter(to_dev(h, dtype))
+        a = to_host(P.convolve(xd))
+        b = to_host(P.forward(xd))
+        c = to_host(P.convolve_with_filter(xd, to_dev(h, dtype)))
+        P.close()
+        out[mb] = (a, b, c)
+    for u, v in zip(out["0"], out["1048576"]):
+        assert np.array_equal(u, v), shape
+    check_close(out["0"][0], oracle.conv_fft(rounded(x, dtype), rounded(h, dtype)), TOL[dtype])
+
+
 POISON_CASES = [((256, 256), [4, 4]), ((4096,), [4]), ((4096, 48), [4, 0]), ((512, 40), [8, 0]),
                 ((2187, 12), None), ((5 ** 6,), None), ((81, 8, 8), None), ((729, 100), None),
                 ((1000, 2), None), ((2 ** 15 * 3,), None), ((97,), None), ((1001,), None),
