@@ -35,19 +35,23 @@ __device__ __forceinline__ cx<T> ld_g32(const void* p, uint32_t idx) {
   return *reinterpret_cast<const cx<T>*>(reinterpret_cast<const char*>(p) +
                                          idx * (uint32_t)sizeof(cx<T>));
 }
-// The same load, marked non-temporal when NT: a streamed read of data the
-// launch uses once, which should not displace other lines from the caches
-// (the global_load carries the nt bit).
+// A load marked non-temporal: a streamed read of data the launch uses once,
+// which should not displace other lines from the caches (the global_load
+// carries the nt bit).
+template <typename T>
+__device__ __forceinline__ cx<T> ld_nt(const cx<T>* p) {
+  typedef T v2 __attribute__((ext_vector_type(2)));
+  const v2 v = __builtin_nontemporal_load(reinterpret_cast<const v2*>(p));
+  return cx<T>{v.x, v.y};
+}
+// ld_g32, non-temporal when NT
 template <typename T, bool NT>
 __device__ __forceinline__ cx<T> ld_g32s(const void* p, uint32_t idx) {
-  if constexpr (NT) {
-    typedef T v2 __attribute__((ext_vector_type(2)));
-    const v2 v = __builtin_nontemporal_load(
-        reinterpret_cast<const v2*>(reinterpret_cast<const char*>(p) + idx * (uint32_t)sizeof(cx<T>)));
-    return cx<T>{v.x, v.y};
-  } else {
+  if constexpr (NT)
+    return ld_nt<T>(reinterpret_cast<const cx<T>*>(reinterpret_cast<const char*>(p) +
+                                                    idx * (uint32_t)sizeof(cx<T>)));
+  else
     return ld_g32<T>(p, idx);
-  }
 }
 template <typename T>
 __device__ __forceinline__ void st_g32(void* p, uint32_t idx, cx<T> v) {

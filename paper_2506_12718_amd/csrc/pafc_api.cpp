@@ -61,7 +61,7 @@ hipError_t launch_pipe_batch(bool dbl, int r, int g, int ng, int kind, int mode,
                              const PassArgs* d, uint32_t grid, uint32_t threads, size_t lds,
                              const void* in, void* out, hipStream_t s);
 hipError_t launch_mul(bool dbl, const void* x, const void* h, void* y, int64_t n, double s,
-                      hipStream_t st);
+                      bool nt_h, hipStream_t st);
 hipError_t launch_stream_copy(int kind, const void* src, void* dst, int64_t n16, hipStream_t st);
 hipError_t launch_pfa_gather(bool dbl, const void* in, void* out, const uint32_t* t0,
                              const uint32_t* t1, const uint32_t* t2, uint32_t N1, uint32_t N2,
@@ -79,13 +79,15 @@ hipError_t launch_symbol(bool dbl, void* H, const void* g, const int32_t* m0, co
 hipError_t launch_permute_rows(bool dbl, const void* in, void* out, const void* h,
                                const int32_t* m0, const int32_t* m1, const int32_t* mlast,
                                uint32_t n0, uint32_t n1, uint32_t nlast, uint32_t rows_per_block,
-                               double s, hipStream_t st);
+                               double s, bool nt_h, hipStream_t st);
 hipError_t launch_permute_gather(bool dbl, const void* in, void* out, const void* h,
                                  const int32_t* m0, const int32_t* m1, const int32_t* m2,
-                                 uint32_t n0, uint32_t n1, uint32_t n2, double s, hipStream_t st);
+                                 uint32_t n0, uint32_t n1, uint32_t n2, double s, bool nt_h,
+                                 hipStream_t st);
 hipError_t launch_permute_tile(bool dbl, const void* in, void* out, const void* h,
                                const int32_t* m0, const int32_t* m1, const int32_t* mlast,
-                               uint32_t n0, uint32_t n1, uint32_t log_nl, double s, hipStream_t st);
+                               uint32_t n0, uint32_t n1, uint32_t log_nl, double s, bool nt_h,
+                               hipStream_t st);
 }  // namespace pafc
 
 using namespace pafc;
@@ -1223,6 +1225,9 @@ struct pafc_plan_s {
   // tile-major spectrum (PassArgs::h_tm): the middle pass of the convolution
   // and, in fwd_tm, the forward sequence whose last pass writes that order
   bool h_tm = false;
+  // the comparison variants' product kernels read the spectrum streamed
+  // (the arrays reach the last-level cache size)
+  bool nt_h = false;
   int mid_pass = -1;  // index of the middle pass in P.conv
   std::vector<Pass> fwd_tm;
   bool filter_set = false;
@@ -1344,6 +1349,7 @@ pafc_status run_permute(pafc_plan_t p, int dir, const void* in, void* out, const
   const double hs = 1.0 / (double)P.N;
   const bool dbl = P.dtype == PAFC_C128;
   const bool inv = dir == 2;
+  const bool nt = h != nullptr && p->nt_h;
   uint32_t n0 = 1, n1 = 1, nl = (uint32_t)P.dims[P.ndim - 1];
   const int32_t* m0 = nullptr;
   const int32_t* m1 = nullptr;
@@ -1360,14 +1366,14 @@ pafc_status run_permute(pafc_plan_t p, int dir, const void* in, void* out, const
   const bool pow2 = (nl & (nl - 1)) == 0;
   if (pow2 && nl <= 4096 && ((uint64_t)n0 * n1 * nl) % 4096 == 0) {
     const uint32_t log_nl = ilog2u(nl);
-    return from_hip(launch_permute_tile(dbl, in, out, h, m0, m1, ml, n0, n1, log_nl, hs, s));
+    return from_hip(launch_permute_tile(dbl, in, out, h, m0, m1, ml, n0, n1, log_nl, hs, nt, s));
   }
   if (tile_lds_bytes(nl, P.elem) <= kLdsBudget) {
     uint32_t rows = std::max<uint32_t>(1, 2048 / nl);
     while (rows > 1 && tile_lds_bytes((uint64_t)rows * nl, P.elem) > 64 * 1024) rows /= 2;
-    return from_hip(launch_permute_rows(dbl, in, out, h, m0, m1, ml, n0, n1, nl, rows, hs, s));
+    return from_hip(launch_permute_rows(dbl, in, out, h, m0, m1, ml, n0, n1, nl, rows, hs, nt, s));
   }
-  return from_hip(launch_permute_gather(dbl, in, out, h, m0, m1, ml, n0, n1, nl, hs, s));
+  return from_hip(launch_permute_gather(dbl, in, out, h, m0, m1, ml, n0, n1, nl, hs, nt, s));
 }
 
 pafc_status run_sequence(pafc_plan_t p, const std::vector<Pass>& seq, const void* x, void* y,
@@ -1382,7 +1388,7 @@ pafc_status run_sequence(pafc_plan_t p, const std::vector<Pass>& seq, const void
       PAFC_TRY(run_pass(p, ps, cur, y, s));
       cur = y;
     } else if (ps.kind == 1) {
-      PAFC_TRY(from_hip(launch_mul(dbl, cur, p->d_H, y, P.N, 1.0 / (double)P.N, s)));
+      PAFC_TRY(from_hip(launch_mul(dbl, cur, p->d_H, y, P.N, 1.0 / (double)P.N, p->nt_h, s)));
       cur = y;
     } else if (ps.kind == 2) {
       if (ps.perm_dir == 1) {
@@ -2259,6 +2265,7 @@ pafc_status make_plan(pafc_plan_t* out, int ndim, const int64_t* dims, const int
   // across calls and use ordinary loads.
   const int64_t llc = (int64_t)env_int("PAFC_LLC_MB", 256) << 20;
   const int64_t ne = P.N * (int64_t)P.elem;
+  p->nt_h = 2 * ne >= llc;
   std::vector<PassArgs> descs;
   for (auto* seq : {&p->P.conv, &p->P.fwd, &p->P.inv}) {
     int i = 0;

@@ -174,10 +174,10 @@ __global__ void __launch_bounds__(256) stream_read_kernel(const double2* __restr
 
 template <typename T>
 __global__ void mul_kernel(const cx<T>* __restrict__ x, const cx<T>* __restrict__ h,
-                           cx<T>* __restrict__ y, int64_t n, T s) {
+                           cx<T>* __restrict__ y, int64_t n, T s, uint32_t nt_h) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
-    y[i] = cscale(cmul(x[i], h[i]), s);
+    y[i] = cscale(cmul(x[i], nt_h ? ld_nt(h + i) : h[i]), s);
 }
 
 // Per-axis index-reversal permutation as one HBM pass (the explicit variant's
@@ -191,7 +191,7 @@ __global__ void __launch_bounds__(256) permute_rows_kernel(
     const cx<T>* __restrict__ in, cx<T>* __restrict__ out, const cx<T>* __restrict__ h,
     const int32_t* __restrict__ map0, const int32_t* __restrict__ map1,
     const int32_t* __restrict__ map_last, uint32_t n0, uint32_t n1, uint32_t nlast,
-    uint32_t rows_per_block, uint32_t nrows, T s) {
+    uint32_t rows_per_block, uint32_t nrows, T s, uint32_t nt_h) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
   const uint32_t row0 = blockIdx.x * rows_per_block;
@@ -209,7 +209,7 @@ __global__ void __launch_bounds__(256) permute_rows_kernel(
     const uint32_t rr = x / nlast, k = x - rr * nlast;
     const int64_t o = (int64_t)(row0 + rr) * nlast + k;
     cx<T> v = lds[lds_phys(rr * nlast + (uint32_t)map_last[k])];
-    if (h) v = cscale(cmul(v, h[o]), s);
+    if (h) v = cscale(cmul(v, nt_h ? ld_nt(h + o) : h[o]), s);
     out[o] = v;
   }
 }
@@ -222,7 +222,7 @@ __global__ void __launch_bounds__(256) permute_tile_kernel(
     const cx<T>* __restrict__ in, cx<T>* __restrict__ out, const cx<T>* __restrict__ h,
     const int32_t* __restrict__ map0, const int32_t* __restrict__ map1,
     const int32_t* __restrict__ map_last, uint32_t n0, uint32_t n1, uint32_t log_nl,
-    FastDiv div_n1, T s) {
+    FastDiv div_n1, T s, uint32_t nt_h) {
   constexpr int EPT = 16;
   constexpr uint32_t TILE = 256 * EPT;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -255,7 +255,7 @@ __global__ void __launch_bounds__(256) permute_tile_kernel(
     const uint32_t x = tid + 256u * q;
     const uint32_t rr = x >> log_nl, k = x & (nl - 1u);
     cx<T> w = lds[lds_phys((rr << log_nl) + (uint32_t)lmap[k])];
-    if (h) w = cscale(cmul(w, h[base + x]), s);
+    if (h) w = cscale(cmul(w, nt_h ? ld_nt(h + base + x) : h[base + x]), s);
     out[base + x] = w;
   }
 }
@@ -267,7 +267,7 @@ __global__ void permute_gather_kernel(const cx<T>* __restrict__ in, cx<T>* __res
                                       const cx<T>* __restrict__ h,
                                       const int32_t* __restrict__ m0, const int32_t* __restrict__ m1,
                                       const int32_t* __restrict__ m2, uint32_t n0, uint32_t n1,
-                                      uint32_t n2, int64_t n, T sc) {
+                                      uint32_t n2, int64_t n, T sc, uint32_t nt_h) {
   for (int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; o < n;
        o += (int64_t)gridDim.x * blockDim.x) {
     const uint32_t k2 = (uint32_t)(o % n2);
@@ -276,7 +276,7 @@ __global__ void permute_gather_kernel(const cx<T>* __restrict__ in, cx<T>* __res
     const uint32_t k0 = (uint32_t)(q / n1);
     const int64_t s = ((int64_t)(n0 > 1 ? m0[k0] : 0) * n1 + (n1 > 1 ? m1[k1] : 0)) * n2 + m2[k2];
     cx<T> v = in[s];
-    if (h) v = cscale(cmul(v, h[o]), sc);
+    if (h) v = cscale(cmul(v, nt_h ? ld_nt(h + o) : h[o]), sc);
     out[o] = v;
   }
 }
@@ -818,20 +818,22 @@ hipError_t launch_stream_copy(int kind, const void* src, void* dst, int64_t n16,
 }
 
 hipError_t launch_mul(bool dbl, const void* x, const void* h, void* y, int64_t n, double s,
-                      hipStream_t st) {
+                      bool nt_h, hipStream_t st) {
   if (dbl)
     hipLaunchKernelGGL(mul_kernel<double>, dim3(grid_for(n)), dim3(256), 0, st,
-                       (const cx<double>*)x, (const cx<double>*)h, (cx<double>*)y, n, s);
+                       (const cx<double>*)x, (const cx<double>*)h, (cx<double>*)y, n, s,
+                       (uint32_t)nt_h);
   else
     hipLaunchKernelGGL(mul_kernel<float>, dim3(grid_for(n)), dim3(256), 0, st,
-                       (const cx<float>*)x, (const cx<float>*)h, (cx<float>*)y, n, (float)s);
+                       (const cx<float>*)x, (const cx<float>*)h, (cx<float>*)y, n, (float)s,
+                       (uint32_t)nt_h);
   return hipGetLastError();
 }
 
 hipError_t launch_permute_rows(bool dbl, const void* in, void* out, const void* h,
                                const int32_t* m0, const int32_t* m1, const int32_t* mlast,
                                uint32_t n0, uint32_t n1, uint32_t nlast, uint32_t rows_per_block,
-                               double s, hipStream_t st) {
+                               double s, bool nt_h, hipStream_t st) {
   static bool init_d = false, init_f = false;
   const uint32_t nrows = n0 * n1;
   const uint32_t blocks = (nrows + rows_per_block - 1) / rows_per_block;
@@ -846,7 +848,7 @@ hipError_t launch_permute_rows(bool dbl, const void* in, void* out, const void* 
     }
     hipLaunchKernelGGL(permute_rows_kernel<double>, dim3(blocks), dim3(256), lds, st,
                        (const cx<double>*)in, (cx<double>*)out, (const cx<double>*)h, m0, m1,
-                       mlast, n0, n1, nlast, rows_per_block, nrows, s);
+                       mlast, n0, n1, nlast, rows_per_block, nrows, s, (uint32_t)nt_h);
   } else {
     if (!init_f) {
       hipError_t e = set_lds_limit<float>((const void*)permute_rows_kernel<float>);
@@ -855,14 +857,15 @@ hipError_t launch_permute_rows(bool dbl, const void* in, void* out, const void* 
     }
     hipLaunchKernelGGL(permute_rows_kernel<float>, dim3(blocks), dim3(256), lds, st,
                        (const cx<float>*)in, (cx<float>*)out, (const cx<float>*)h, m0, m1, mlast,
-                       n0, n1, nlast, rows_per_block, nrows, (float)s);
+                       n0, n1, nlast, rows_per_block, nrows, (float)s, (uint32_t)nt_h);
   }
   return hipGetLastError();
 }
 
 hipError_t launch_permute_tile(bool dbl, const void* in, void* out, const void* h,
                                const int32_t* m0, const int32_t* m1, const int32_t* mlast,
-                               uint32_t n0, uint32_t n1, uint32_t log_nl, double s, hipStream_t st) {
+                               uint32_t n0, uint32_t n1, uint32_t log_nl, double s, bool nt_h,
+                               hipStream_t st) {
   const uint32_t tile = 4096;
   const uint64_t total = (uint64_t)n0 * n1 << log_nl;
   if ((1u << log_nl) > tile || total % tile != 0) return hipErrorInvalidValue;
@@ -880,26 +883,27 @@ hipError_t launch_permute_tile(bool dbl, const void* in, void* out, const void* 
   if (dbl)
     hipLaunchKernelGGL(permute_tile_kernel<double>, dim3(ntiles), dim3(256), lds, st,
                        (const cx<double>*)in, (cx<double>*)out, (const cx<double>*)h, m0, m1,
-                       mlast, n0, n1, log_nl, dn1, s);
+                       mlast, n0, n1, log_nl, dn1, s, (uint32_t)nt_h);
   else
     hipLaunchKernelGGL(permute_tile_kernel<float>, dim3(ntiles), dim3(256), lds, st,
                        (const cx<float>*)in, (cx<float>*)out, (const cx<float>*)h, m0, m1, mlast,
-                       n0, n1, log_nl, dn1, (float)s);
+                       n0, n1, log_nl, dn1, (float)s, (uint32_t)nt_h);
   return hipGetLastError();
 }
 
 hipError_t launch_permute_gather(bool dbl, const void* in, void* out, const void* h,
                                  const int32_t* m0, const int32_t* m1, const int32_t* m2,
-                                 uint32_t n0, uint32_t n1, uint32_t n2, double s, hipStream_t st) {
+                                 uint32_t n0, uint32_t n1, uint32_t n2, double s, bool nt_h,
+                                 hipStream_t st) {
   const int64_t n = (int64_t)n0 * n1 * n2;
   if (dbl)
     hipLaunchKernelGGL(permute_gather_kernel<double>, dim3(grid_for(n)), dim3(256), 0, st,
                        (const cx<double>*)in, (cx<double>*)out, (const cx<double>*)h, m0, m1, m2,
-                       n0, n1, n2, n, s);
+                       n0, n1, n2, n, s, (uint32_t)nt_h);
   else
     hipLaunchKernelGGL(permute_gather_kernel<float>, dim3(grid_for(n)), dim3(256), 0, st,
                        (const cx<float>*)in, (cx<float>*)out, (const cx<float>*)h, m0, m1, m2,
-                       n0, n1, n2, n, (float)s);
+                       n0, n1, n2, n, (float)s, (uint32_t)nt_h);
   return hipGetLastError();
 }
 

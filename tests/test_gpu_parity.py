@@ -348,7 +348,8 @@ def test_streamed_loads_leave_results_unchanged(shape, radix, dtype, monkeypatch
     allows (tile-major spectra, contiguous and 64-byte-or-longer strided
     segments, folded columns): bit-identical to ordinary loads (bound out of
     reach), for the convolution, the filter's forward transform and the
-    per-call filter, and matching the oracle."""
+    per-call filter, and in the comparison variants (their product kernels
+    stream the spectrum too), matching the oracle."""
     rng = np.random.default_rng([len(shape), shape[0], 17])
     x = inputs.complex_uniform(rng, shape)
     h = inputs.complex_uniform(rng, shape)
@@ -362,10 +363,18 @@ def test_streamed_loads_leave_results_unchanged(shape, radix, dtype, monkeypatch
         b = to_host(P.forward(xd))
         c = to_host(P.convolve_with_filter(xd, to_dev(h, dtype)))
         P.close()
-        out[mb] = (a, b, c)
+        ys = []
+        for variant in ("explicit_perm", "perm_free_unfused"):
+            Q = pafc().Plan(shape, dtype, radix=radix, variant=variant)
+            Q.set_filter(to_dev(h, dtype))
+            ys.append(to_host(Q.convolve(xd)))
+            Q.close()
+        out[mb] = (a, b, c, *ys)
     for u, v in zip(out["0"], out["1048576"]):
         assert np.array_equal(u, v), shape
-    check_close(out["0"][0], oracle.conv_fft(rounded(x, dtype), rounded(h, dtype)), TOL[dtype])
+    ref = oracle.conv_fft(rounded(x, dtype), rounded(h, dtype))
+    for y in (out["0"][0], out["0"][3], out["0"][4]):
+        check_close(y, ref, TOL[dtype])
 
 
 POISON_CASES = [((256, 256), [4, 4]), ((4096,), [4]), ((4096, 48), [4, 0]), ((512, 40), [8, 0]),
