@@ -385,14 +385,18 @@ pafc_status pafc_profile_passes(pafc_plan_t p, const void* x_dev, void* y_dev,
 
 /*
  * pafc_profile_launch -- the same measurement with fewer events: run
- * pafc_convolve `reps` times on hip_stream, recording timing-only events at
- * the start of every repetition and around launch `launch` only (its
- * position in pafc_profile_passes' order, 0 <= launch < *npass there), so
- * that a throughput measurement carries two or three event packets per
- * convolution instead of one per launch.  *ms_launch receives the mean
- * duration of that launch; ms_per_rep[0..reps-1] (may be NULL) the time from
- * the start of each repetition to the start of the next (the end, for the
- * last).  Same buffer rules as pafc_convolve.  Blocks the host.
+ * pafc_convolve `reps` times on hip_stream, with timing-only events around
+ * launch `launch` only (its position in pafc_profile_passes' order,
+ * 0 <= launch < *npass there) and, when ms_per_rep is not NULL, at the start
+ * of every repetition and the end of the last.  Where that launch is a
+ * pipelined pass kernel of a plain (not prime-length or prime-factor) plan,
+ * its two events are bound to the launch itself (hipExtLaunchKernel) and
+ * take the dispatch's own start and end timestamps, so that no event packet
+ * enters the stream around it; elsewhere they are marker packets.
+ * *ms_launch receives the mean duration of that launch;
+ * ms_per_rep[0..reps-1] (may be NULL) the time from the start of each
+ * repetition to the start of the next (the end, for the last).  Same buffer
+ * rules as pafc_convolve.  Blocks the host.
  * Errors: INVALID_VALUE (NULL pointers, reps < 1, launch out of range),
  * FILTER_NOT_SET, DEVICE.
  */

@@ -348,19 +348,20 @@ class Plan:
         return ([ms[i] for i in range(n.value)], [by[i] for i in range(n.value)],
                 [per[i] for i in range(int(reps))])
 
-    def profile_launch(self, x, out, launch, reps=10, stream=None):
-        """Run `reps` convolutions with HIP events at the start of every
-        repetition and around launch `launch` only.  Returns (mean ms of that
-        launch, ms of every repetition)."""
+    def profile_launch(self, x, out, launch, reps=10, stream=None, per_rep=True):
+        """Run `reps` convolutions with HIP events around launch `launch`
+        and, with `per_rep`, at the start of every repetition.  Returns (mean
+        ms of that launch, ms of every repetition, or None without
+        `per_rep`)."""
         self._check_tensor(x, "x")
         self._check_tensor(out, "out")
         ms = ctypes.c_double(0.0)
-        per = (ctypes.c_double * int(reps))()
+        per = (ctypes.c_double * int(reps))() if per_rep else None
         _check(lib().pafc_profile_launch(self._h, ctypes.c_void_p(x.data_ptr()),
                                          ctypes.c_void_p(out.data_ptr()), _stream(stream),
                                          int(reps), int(launch), ctypes.byref(ms), per),
                "pafc_profile_launch")
-        return ms.value, [per[i] for i in range(int(reps))]
+        return ms.value, ([per[i] for i in range(int(reps))] if per_rep else None)
 
     def describe(self):
         """The planner's JSON for this plan's problem (host only)."""

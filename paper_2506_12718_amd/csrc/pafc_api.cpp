@@ -54,7 +54,8 @@ hipError_t launch_pipe_htm(bool dbl, int r, int g, int ng, int mode, const PassA
                            hipStream_t s);
 hipError_t launch_pipe(bool dbl, int r, int g, int ng, int kind, int mode, const PassArgs* d,
                        uint32_t grid, uint32_t threads, size_t lds, const void* in, void* out,
-                       hipStream_t s, int gm, int xc);
+                       hipStream_t s, int gm, int xc, hipEvent_t t0 = nullptr,
+                       hipEvent_t t1 = nullptr);
 int pipe_batch_blocks_per_cu(bool dbl, int r, int g, int ng, int kind, int mode,
                              uint32_t threads, size_t lds, int gm);
 hipError_t launch_pipe_batch(bool dbl, int r, int g, int ng, int kind, int mode, int gm,
@@ -1328,14 +1329,21 @@ void finalize_args(const PlanCore& P, const void* d_tw, const void* H, const Pas
   a->tw_bits = t.bits;
 }
 
-// Launch one kernel pass reading `in` and writing `out`.
-pafc_status run_pass(pafc_plan_t p, const Pass& ps, const void* in, void* out, hipStream_t s) {
+// Does this pass launch the pipelined kernel (whose launch can carry its own
+// timing events)?
+bool pass_binds_events(const Pass& ps) { return ps.kind == 0 && ps.pipe && ps.pipe_grid > 0; }
+
+// Launch one kernel pass reading `in` and writing `out`.  t0 / t1 (only for
+// a pass where pass_binds_events holds) take the launch's start and end.
+pafc_status run_pass(pafc_plan_t p, const Pass& ps, const void* in, void* out, hipStream_t s,
+                     hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr) {
   const bool dbl = p->P.dtype == PAFC_C128;
   if (ps.kind != 0) return PAFC_ERROR_INVALID_VALUE;
   if (ps.pipe && ps.pipe_grid > 0)
     return from_hip(launch_pipe(dbl, ps.pipe_r, ps.pipe_g, ps.pipe_ng, ps.pipe_kind, ps.pipe_mode,
                                 p->d_descs + ps.desc, ps.pipe_grid, ps.pipe_threads, ps.pipe_lds,
-                                in, out, s, ps.pipe_gm, ps.pipe_xc));
+                                in, out, s, ps.pipe_gm, ps.pipe_xc, t0, t1));
+  if (t0 || t1) return PAFC_ERROR_INVALID_VALUE;
 
   return from_hip(launch_pass(dbl, ps.cls, p->d_descs + ps.desc, ps.a.ntiles, in, out, ps.threads,
                               ps.lds, s));
@@ -1376,14 +1384,25 @@ pafc_status run_permute(pafc_plan_t p, int dir, const void* in, void* out, const
   return from_hip(launch_permute_gather(dbl, in, out, h, m0, m1, ml, n0, n1, nl, hs, nt, s));
 }
 
+// Run a pass sequence; ev (if given) holds an event slot before every pass
+// and after the last, recorded as marker packets where the slot exists.  For
+// the pass at position `bind`, if it launches the pipelined kernel, slots
+// bind and bind + 1 are instead bound to that launch's own start and end.
 pafc_status run_sequence(pafc_plan_t p, const std::vector<Pass>& seq, const void* x, void* y,
-                         hipStream_t s, hipEvent_t* ev = nullptr) {
+                         hipStream_t s, hipEvent_t* ev = nullptr, int bind = -1) {
   const PlanCore& P = p->P;
   const bool dbl = P.dtype == PAFC_C128;
   const void* cur = x;
   size_t k = 0;
-  PAFC_TRY(rec(ev, 0, s));
+  const bool bound = ev && bind >= 0 && bind < (int)seq.size() && pass_binds_events(seq[bind]);
+  if (!(bound && bind == 0)) PAFC_TRY(rec(ev, 0, s));
   for (const Pass& ps : seq) {
+    if (bound && (int)k == bind) {
+      PAFC_TRY(run_pass(p, ps, cur, y, s, ev[k], ev[k + 1]));
+      cur = y;
+      ++k;
+      continue;
+    }
     if (ps.kind == 0) {
       PAFC_TRY(run_pass(p, ps, cur, y, s));
       cur = y;
@@ -1928,11 +1947,11 @@ int route_launches(pafc_plan_t p) {
 }
 
 pafc_status route_convolve(pafc_plan_t p, const void* x, void* y, hipStream_t s,
-                           hipEvent_t* ev) {
+                           hipEvent_t* ev, int bind) {
   if (is_bluestein(p)) return blue_convolve(p, x, y, s, ev);
   if (is_rader(p)) return rader_convolve(p, x, y, s, ev);
   if (p->inner) return pfa_convolve(p, x, y, s, ev);
-  return run_sequence(p, p->P.conv, x, y, s, ev);
+  return run_sequence(p, p->P.conv, x, y, s, ev, bind);
 }
 
 // algorithmic HBM bytes of launch i of one convolution
@@ -1977,15 +1996,19 @@ pafc_status profile_impl(pafc_plan_t p, const void* x, void* y, hipStream_t s, i
   const int n = route_launches(p);
   const size_t stride = (size_t)n + 1;
   std::vector<hipEvent_t> ev(stride * (size_t)reps, nullptr);
+  // one launch timed: events around it, and at the start of every
+  // repetition (and the end of the last) only when per-repetition times are
+  // asked for; a pipelined launch carries its pair itself
   auto want = [&](int r, int k) {
-    return sel < 0 || k == 0 || k == sel || k == sel + 1 || (k == n && r == reps - 1);
+    return sel < 0 || k == sel || k == sel + 1 ||
+           (ms_per_rep && (k == 0 || (k == n && r == reps - 1)));
   };
   pafc_status st = PAFC_SUCCESS;
   for (int r = 0; r < reps; ++r)
     for (int k = 0; k <= n && st == PAFC_SUCCESS; ++k)
       if (want(r, k)) st = from_hip(timing_event(&ev[(size_t)r * stride + (size_t)k]));
   for (int r = 0; r < reps && st == PAFC_SUCCESS; ++r)
-    st = route_convolve(p, x, y, s, ev.data() + (size_t)r * stride);
+    st = route_convolve(p, x, y, s, ev.data() + (size_t)r * stride, sel);
   if (st == PAFC_SUCCESS) st = from_hip(hipStreamSynchronize(s));
   auto elapsed = [&](hipEvent_t a, hipEvent_t b, double* out) {
     float ms = 0;

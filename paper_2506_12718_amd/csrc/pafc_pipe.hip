@@ -1,5 +1,7 @@
 // Launches of the pipelined pass kernel (pipe_kernel.h) for single
 // problems: one transform or convolution per launch.
+#include <hip/hip_ext.h>
+
 #include "pipe_kernel.h"
 
 namespace pafc {
@@ -73,12 +75,15 @@ hipError_t launch_pipe_htm(bool dbl, int r, int g, int ng, int mode, const PassA
 
 hipError_t launch_pipe(bool dbl, int r, int g, int ng, int kind, int mode, const PassArgs* d,
                        uint32_t grid, uint32_t threads, size_t lds, const void* in, void* out,
-                       hipStream_t s, int gm, int xc) {
+                       hipStream_t s, int gm, int xc, hipEvent_t t0, hipEvent_t t1) {
   const void* fn = pipe_lookup(dbl, r, g, ng, kind, mode, gm, xc);
   if (!fn) return hipErrorInvalidValue;
   // the LDS limit of every instance is raised when its occupancy is queried
   // at plan time (pipe_blocks_per_cu), before any launch
   void* args[] = {(void*)&d, (void*)&in, (void*)&out};
+  // Timing events, when given, take the dispatch's own start and end
+  // timestamps: no marker packet enters the stream around the launch.
+  if (t0 || t1) return hipExtLaunchKernel(fn, dim3(grid), dim3(threads), args, lds, s, t0, t1, 0);
   return hipLaunchKernel(fn, dim3(grid), dim3(threads), args, lds, s);
 }
 

@@ -271,7 +271,12 @@ def test_profile_launch(shape):
         t, per = P.profile_launch(xd, yd, k, reps=6)
         assert len(per) == 6 and min(per) > 0 and t > 0
         assert t <= max(per)
-        say("launch", k, "of", len(ms), t, ms[k])
+        # without per-repetition events: only the pair around the launch (a
+        # pipelined launch carries them itself), the same order of duration
+        t1, none = P.profile_launch(xd, yd, k, reps=6, per_rep=False)
+        assert none is None and t1 > 0
+        assert t1 <= 2.0 * max(per) + 0.05
+        say("launch", k, "of", len(ms), t, t1, ms[k])
     ref = oracle.conv_fft(x, h) if len(shape) > 1 or shape[0] in (4096, 1728) else \
         oracle.conv_direct(x, h)
     check_close(to_host(yd), ref, TOL[C128])
