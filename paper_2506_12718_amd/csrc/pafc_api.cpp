@@ -46,6 +46,7 @@ bool pipe_supported(int r, int g, int ng);
 bool pipe_outer_supported(int r, int g, int ng);
 bool pipe_ext_supported(int r, int g, int ng, int gm, int xc, int kind, int mode);
 int pipe_thread_limit(int r, int g, bool dbl = true, int xc = 0);
+int pipe_uniform_threads(int r, int g, int ng);
 
 int pipe_blocks_per_cu(bool dbl, int r, int g, int ng, int kind, int mode, uint32_t threads,
                        size_t lds, int gm, int xc);
@@ -180,6 +181,7 @@ int env_int(const char* name, int dflt);
 // Largest group of consecutive radix-r stages fused into one register op.
 // Groups with R > 16 need the large register class of the kernels.
 struct GroupCaps {
+  int g2 = 4;  // R = 16 (8 with 3)
   int g3 = 3;  // R = 27 (9 with 2)
   int g5 = 2;  // R = 25 (5 with 1)
   int lim3 = 0;  // a caller's bound on g3 (0: none)
@@ -187,7 +189,7 @@ struct GroupCaps {
 
 int gmax_of(int r, const GroupCaps& gc) {
   switch (r) {
-    case 2: return 4;  // R = 16
+    case 2: return gc.g2;
     case 4: return 2;  // R = 16
     case 8: return 1;  // R = 8
     case 3: return gc.g3;
@@ -728,7 +730,13 @@ bool make_pass(const Seg& s_in, int kind, size_t elem, Pass* p,
     }
     // odd radices: one thread per item, any count within the block limit
     const bool small = ok && !ext && (r == 3 || r == 5);
-    if (ok && !ext) ok = small ? items <= (uint32_t)pipe_thread_limit(r, g) : items == p->threads;
+    // (4096-long axes in four radix-8 groups: one 512-thread block, where
+    // the general engine's count is decided below)
+    if (ok && !ext)
+      ok = small ? items <= (uint32_t)pipe_thread_limit(r, g)
+                 : items == p->threads ||
+                       (ipow64(r, g) == 8 && ng == 4 && items > p->threads &&
+                        items <= (uint32_t)pipe_uniform_threads(r, g, ng));
     if (ok) {
       p->pipe = true;
       p->pipe_r = r;
@@ -972,6 +980,12 @@ pafc_status plan_once(PlanCore& P, int ndim, const int64_t* dims, const int* rad
     if (lim.g3 > 0) caps.g3 = std::min(caps.g3, lim.g3);
     caps.lim3 = lim.g3;
     if (lim.g5 > 0) caps.g5 = std::min(caps.g5, lim.g5);
+    // A 1-D transform of 4096 radix-2 stages is one tile: four groups of
+    // 2^3 in a 512-thread block run it faster than three of 2^4 in 256
+    // threads (more waves to cover the LDS round trips, fewer registers)
+    caps.g2 = ndim == 1 && ax.n == 4096 && ax.rho.size() == 12 && ax.rho[0] == 2
+                  ? env_int("PAFC_TUNE_GMAX2_4096", 3)
+                  : 4;
     // Cut the axis into pieces (G2): an outer piece takes its outermost
     // stages, strided over the inner length; the inner length is again an
     // axis of its own and is cut the same way while it is too long.  A piece

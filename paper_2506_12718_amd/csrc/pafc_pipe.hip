@@ -33,6 +33,13 @@ int pipe_thread_limit(int r, int g, bool dbl, int xc) {
   return xc > 0 && !dbl ? 512 : 256;
 }
 
+// Most threads a block of a uniform pipelined instance (no short group, no
+// folded columns) may have: 512 for 4096-long axes in four radix-8 groups,
+// as pipe_block_limit compiles them, else the radix's own limit.
+int pipe_uniform_threads(int r, int g, int ng) {
+  return ipow(r, g) == 8 && ng == 4 ? 512 : pipe_thread_limit(r, g, true, 0);
+}
+
 // Resident blocks per CU of a pipelined kernel instance (0 on error).
 int pipe_blocks_per_cu(bool dbl, int r, int g, int ng, int kind, int mode, uint32_t threads,
                        size_t lds, int gm, int xc) {

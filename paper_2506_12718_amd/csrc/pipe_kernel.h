@@ -84,11 +84,14 @@ constexpr int pipe_max_threads() {
   return (r == 3 || r == 5) && g == 1 ? 1024 : r == 3 && g == 2 ? 512 : 256;
 }
 // FP32 middle passes with folded columns also take 512 threads (a 4096-long
-// axis with two columns): their items fit 2 waves per SIMD unspilled.
-template <typename T, int r, int g, int XC>
+// axis with two columns): their items fit 2 waves per SIMD unspilled; so do
+// 4096-long axes in four radix-8 groups (8-point items).
+template <typename T, int r, int g, int XC, int NG>
 constexpr int pipe_block_limit() {
-  return XC > 0 && sizeof(T) == 4 && !((r == 3 || r == 5) && g == 1) ? 512
-                                                                      : pipe_max_threads<r, g>();
+  return (XC > 0 && sizeof(T) == 4 && !((r == 3 || r == 5) && g == 1)) ||
+                 (ipow(r, g) == 8 && NG == 4)
+             ? 512
+             : pipe_max_threads<r, g>();
 }
 
 // Outer pieces of a cut axis (MODE_OUTER) are compiled for the shapes the
@@ -163,7 +166,7 @@ constexpr int slot_rev(int k, int s) {
 // table of PassArgs (the batched form's size classes).
 template <typename T, int r, int g, int NG, int KIND, int MODE_ARG, int GM = g, int XC = 0,
           bool PB = false>
-__global__ void __launch_bounds__((pipe_block_limit<T, r, g, XC>()))
+__global__ void __launch_bounds__((pipe_block_limit<T, r, g, XC, NG>()))
 __attribute__((amdgpu_waves_per_eu(pipe_waves_per_eu<KIND, NG>())))
 pipe_kernel(const PassArgs* __restrict__ desc, const void* in, void* out) {
   // in and out may be the same array (every pass after the first runs in
@@ -540,8 +543,10 @@ __global__ void __launch_bounds__((pipe_max_threads<r, g>())) pipe_htm_kernel(co
   X(4, 2, 3) /* L = 4096 */   \
   X(2, 4, 2) /* L = 256 */    \
   X(2, 4, 3) /* L = 4096 */   \
+  X(2, 3, 4) /* L = 4096 in groups of 8 */ \
   X(8, 1, 2) /* L = 64 */     \
   X(8, 1, 3) /* L = 512 */    \
+  X(8, 1, 4) /* L = 4096 */   \
   X(4, 2, 1) /* L = 16 */     \
   X(3, 1, 2) /* L = 9 */      \
   X(3, 1, 4) /* L = 81 */     \

@@ -90,7 +90,7 @@ def test_small_multid_against_direct(shape, dtype):
 
 
 @pytest.mark.parametrize("n,radix", [(64, 2), (64, 4), (64, 8), (81, 3), (125, 5), (256, 2),
-                                     (256, 4), (512, 8), (729, 3), (625, 5)])
+                                     (256, 4), (512, 8), (729, 3), (625, 5), (4096, 8)])
 def test_uniform_radix_plans(n, radix):
     rng = np.random.default_rng(n + radix)
     x, h = crand(rng, (n,)), crand(rng, (n,))
@@ -101,6 +101,27 @@ def test_uniform_radix_plans(n, radix):
 
 
 # --------------------------------------------------- config 1: 1-D n = 4096
+
+@pytest.mark.parametrize("shape,radix", [((4096,), [8]), ((4096,), [2]), ((3, 4096), [3, 8]),
+                                         ((2, 5, 4096), [2, 5, 8]), ((8, 4096), [8, 8])])
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_radix8_4096_axis_pipelined(shape, radix, dtype):
+    """A 4096-long contiguous axis in four 8-point groups (radix-8 stages,
+    or a 1-D transform of radix-2 stages grouped by three) runs the
+    pipelined kernel in 512-thread blocks (one tile as the middle pass, and
+    persistent blocks over several tiles as forward and inverse passes); the
+    result is the convolution."""
+    m = pafc()
+    d = m.describe(shape, "c128" if dtype == C128 else "c64", radix)
+    assert any("pipe_kernel<" in lbl and "thr=512" in lbl and "L=4096" in lbl
+               for lbl in d["conv_passes"])
+    rng = np.random.default_rng(4096 + len(shape))
+    x, h = crand(rng, shape), crand(rng, shape)
+    say("radix-8 4096 axis", shape, dtype)
+    y, _ = run_conv(x, h, dtype, radix=radix)
+    ref = oracle.conv_fft(rounded(x, dtype), rounded(h, dtype))
+    check_close(y, ref, TOL[dtype])
+
 
 @pytest.mark.parametrize("radix", [2, 4])
 def test_conv1d_4096_radix_plans(radix):
