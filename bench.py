@@ -509,9 +509,14 @@ def bench_plain(pafc, torch, wl, tdtype, args, cpu_min_s=10.0, steps=None):
     kern = [i for i, l in enumerate(main_r["labels"]) if not l.startswith(("mul", "permute"))]
     all_ms = sum(main_r["ms_pass"][i] for i in kern)
     all_bytes = sum(main_r["bytes_pass"][i] for i in kern)
+    # (a plan of one launch is timed by one event pair over the whole timed
+    # sequence: its mean launch time includes the gaps between launches)
+    timing = ("one event pair over the timed sequence, span / steps"
+              if len(main_r["labels"]) == 1 and not fpc and steps > 1
+              else "an event pair around the dominant launch of every timed convolution")
     roof = roofline_obj(dom_bytes, dom_ms, traffic=load_traffic(wl["name"], dom),
                         kernel=main_r["labels"][dom], alg_bytes_per_launch=dom_bytes,
-                        avg_launch_ms=round(dom_ms, 5),
+                        avg_launch_ms=round(dom_ms, 5), launch_timing=timing,
                         all_passes={"source": "per-launch breakdown run after the timed region",
                                     "launches": len(kern), "alg_bytes": all_bytes,
                                     "ms": round(all_ms, 5),

@@ -392,8 +392,11 @@ pafc_status pafc_profile_passes(pafc_plan_t p, const void* x_dev, void* y_dev,
  * pipelined pass kernel of a plain (not prime-length or prime-factor) plan,
  * its two events are bound to the launch itself (hipExtLaunchKernel) and
  * take the dispatch's own start and end timestamps, so that no event packet
- * enters the stream around it; elsewhere they are marker packets.
- * *ms_launch receives the mean duration of that launch;
+ * enters the stream around it; elsewhere they are marker packets.  A plan
+ * of a single launch timed with ms_per_rep NULL and reps > 1 takes one pair
+ * over the whole sequence (the start of the first launch and the end of the
+ * last), and *ms_launch is its span over reps, gaps between launches
+ * included.  Otherwise *ms_launch receives the mean duration of that launch;
  * ms_per_rep[0..reps-1] (may be NULL) the time from the start of each
  * repetition to the start of the next (the end, for the last).  Same buffer
  * rules as pafc_convolve.  Blocks the host.

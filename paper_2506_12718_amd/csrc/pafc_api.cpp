@@ -2013,7 +2013,14 @@ pafc_status profile_impl(pafc_plan_t p, const void* x, void* y, hipStream_t s, i
   // one launch timed: events around it, and at the start of every
   // repetition (and the end of the last) only when per-repetition times are
   // asked for; a pipelined launch carries its pair itself
+  // A plan of one launch, timed without per-repetition times, takes one
+  // pair over the whole sequence instead (start of the first launch, end of
+  // the last) and reports its span over reps: the gaps between launches
+  // count as launch time, and no launch but the first and the last carries
+  // an event.
+  const bool span = sel == 0 && n == 1 && !ms_per_rep && reps > 1;
   auto want = [&](int r, int k) {
+    if (span) return (r == 0 && k == 0) || (r == reps - 1 && k == 1);
     return sel < 0 || k == sel || k == sel + 1 ||
            (ms_per_rep && (k == 0 || (k == n && r == reps - 1)));
   };
@@ -2029,7 +2036,12 @@ pafc_status profile_impl(pafc_plan_t p, const void* x, void* y, hipStream_t s, i
     if (st == PAFC_SUCCESS) st = from_hip(hipEventElapsedTime(&ms, a, b));
     *out = ms;
   };
-  for (int k = 0; k < n && st == PAFC_SUCCESS; ++k) {
+  if (span) {
+    double ms = 0;
+    elapsed(ev[0], ev[(size_t)(reps - 1) * stride + 1], &ms);
+    *ms_sel = ms / reps;
+  }
+  for (int k = 0; k < n && st == PAFC_SUCCESS && !span; ++k) {
     if (sel >= 0 && k != sel) continue;
     double tot = 0, ms = 0;
     for (int r = 0; r < reps; ++r) {
