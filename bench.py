@@ -932,7 +932,8 @@ def brief(o):
     if o.get("roofline"):
         r = o["roofline"]
         d["roofline_dominant_launch"] = {k: r[k] for k in ("achieved", "frac", "kernel",
-                                                           "avg_launch_ms", "traffic")
+                                                           "avg_launch_ms", "launch_timing",
+                                                           "traffic")
                                          if k in r}
     if "compare" in o:
         c = o["compare"]
