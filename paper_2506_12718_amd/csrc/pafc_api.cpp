@@ -182,6 +182,7 @@ int env_int(const char* name, int dflt);
 // Groups with R > 16 need the large register class of the kernels.
 struct GroupCaps {
   int g2 = 4;  // R = 16 (8 with 3)
+  int g4 = 2;  // R = 16 (4 with 1)
   int g3 = 3;  // R = 27 (9 with 2)
   int g5 = 2;  // R = 25 (5 with 1)
   int lim3 = 0;  // a caller's bound on g3 (0: none)
@@ -190,7 +191,7 @@ struct GroupCaps {
 int gmax_of(int r, const GroupCaps& gc) {
   switch (r) {
     case 2: return gc.g2;
-    case 4: return 2;  // R = 16
+    case 4: return gc.g4;
     case 8: return 1;  // R = 8
     case 3: return gc.g3;
     case 5: return gc.g5;
@@ -735,7 +736,8 @@ bool make_pass(const Seg& s_in, int kind, size_t elem, Pass* p,
     if (ok && !ext)
       ok = small ? items <= (uint32_t)pipe_thread_limit(r, g)
                  : items == p->threads ||
-                       (ipow64(r, g) == 8 && ng == 4 && items > p->threads &&
+                       (((ipow64(r, g) == 8 && ng == 4) || (ipow64(r, g) == 4 && ng == 6)) &&
+                        items > p->threads &&
                         items <= (uint32_t)pipe_uniform_threads(r, g, ng));
     if (ok) {
       p->pipe = true;
@@ -986,6 +988,12 @@ pafc_status plan_once(PlanCore& P, int ndim, const int64_t* dims, const int* rad
     caps.g2 = ndim == 1 && ax.n == 4096 && ax.rho.size() == 12 && ax.rho[0] == 2
                   ? env_int("PAFC_TUNE_GMAX2_4096", 3)
                   : 4;
+    // and in FP32 (not FP64, measured 1 % slower) six groups of radix 4 in a
+    // 1024-thread block run a 1-D 4096-point radix-4 transform faster than
+    // three of 4^2 in 256 threads
+    caps.g4 = ndim == 1 && ax.n == 4096 && ax.rho.size() == 6 && ax.rho[0] == 4
+                  ? env_int("PAFC_TUNE_GMAX4_4096", dtype == PAFC_C64 ? 1 : 2)
+                  : 2;
     // Cut the axis into pieces (G2): an outer piece takes its outermost
     // stages, strided over the inner length; the inner length is again an
     // axis of its own and is cut the same way while it is too long.  A piece

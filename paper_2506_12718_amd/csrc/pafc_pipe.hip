@@ -37,6 +37,7 @@ int pipe_thread_limit(int r, int g, bool dbl, int xc) {
 // folded columns) may have: 512 for 4096-long axes in four radix-8 groups,
 // as pipe_block_limit compiles them, else the radix's own limit.
 int pipe_uniform_threads(int r, int g, int ng) {
+  if (ipow(r, g) == 4 && ng == 6) return 1024;
   return ipow(r, g) == 8 && ng == 4 ? 512 : pipe_thread_limit(r, g, true, 0);
 }
 

@@ -88,7 +88,8 @@ constexpr int pipe_max_threads() {
 // 4096-long axes in four radix-8 groups (8-point items).
 template <typename T, int r, int g, int XC, int NG>
 constexpr int pipe_block_limit() {
-  return (XC > 0 && sizeof(T) == 4 && !((r == 3 || r == 5) && g == 1)) ||
+  return ipow(r, g) == 4 && NG == 6 ? 1024
+         : (XC > 0 && sizeof(T) == 4 && !((r == 3 || r == 5) && g == 1)) ||
                  (ipow(r, g) == 8 && NG == 4)
              ? 512
              : pipe_max_threads<r, g>();
@@ -544,6 +545,7 @@ __global__ void __launch_bounds__((pipe_max_threads<r, g>())) pipe_htm_kernel(co
   X(2, 4, 2) /* L = 256 */    \
   X(2, 4, 3) /* L = 4096 */   \
   X(2, 3, 4) /* L = 4096 in groups of 8 */ \
+  X(4, 1, 6) /* L = 4096 in groups of 4 */ \
   X(8, 1, 2) /* L = 64 */     \
   X(8, 1, 3) /* L = 512 */    \
   X(8, 1, 4) /* L = 4096 */   \

@@ -102,6 +102,25 @@ def test_uniform_radix_plans(n, radix):
 
 # --------------------------------------------------- config 1: 1-D n = 4096
 
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_radix4_4096_in_groups_of_four(dtype, monkeypatch):
+    """A 1-D 4096-point radix-4 transform in six 4-point groups runs the
+    pipelined kernel in one 1024-thread block (the FP32 default; FP64 asks
+    for it through PAFC_TUNE_GMAX4_4096); the result is the convolution."""
+    monkeypatch.setenv("PAFC_TUNE_GMAX4_4096", "1")
+    m = pafc()
+    d = m.describe((4096,), "c128" if dtype == C128 else "c64", [4])
+    assert d["conv_passes"][0].startswith("contig L=4096 W=1 tiles=1 thr=1024 [DIF4,")
+    assert "pipe_kernel<" in d["conv_passes"][0]
+    rng = np.random.default_rng(4444)
+    x, h = crand(rng, (4096,)), crand(rng, (4096,))
+    say("radix-4 4096 in groups of four", dtype)
+    y, rhos = run_conv(x, h, dtype, radix=[4])
+    assert rhos[0] == [4] * 6
+    ref = oracle.conv_fft(rounded(x, dtype), rounded(h, dtype))
+    check_close(y, ref, TOL[dtype])
+
+
 @pytest.mark.parametrize("shape,radix", [((4096,), [8]), ((4096,), [2]), ((3, 4096), [3, 8]),
                                          ((2, 5, 4096), [2, 5, 8]), ((8, 4096), [8, 8])])
 @pytest.mark.parametrize("dtype", DTYPES)
