@@ -930,6 +930,7 @@ struct PlanLimits {
   size_t lds = kLdsBudget;
   int g3 = 0, g5 = 0;
   bool table = true;  // take the tuning table's entries
+  bool batched = false;  // a size class of the batched form
 };
 
 pafc_status plan_once(PlanCore& P, int ndim, const int64_t* dims, const int* radix, int dtype,
@@ -985,13 +986,16 @@ pafc_status plan_once(PlanCore& P, int ndim, const int64_t* dims, const int* rad
     // A 1-D transform of 4096 radix-2 stages is one tile: four groups of
     // 2^3 in a 512-thread block run it faster than three of 2^4 in 256
     // threads (more waves to cover the LDS round trips, fewer registers)
-    caps.g2 = ndim == 1 && ax.n == 4096 && ax.rho.size() == 12 && ax.rho[0] == 2
+    const bool single4096 = ndim == 1 && ax.n == 4096 && !lim.batched;
+    caps.g2 = single4096 && ax.rho.size() == 12 && ax.rho[0] == 2
                   ? env_int("PAFC_TUNE_GMAX2_4096", 3)
                   : 4;
     // and in FP32 (not FP64, measured 1 % slower) six groups of radix 4 in a
     // 1024-thread block run a 1-D 4096-point radix-4 transform faster than
-    // three of 4^2 in 256 threads
-    caps.g4 = ndim == 1 && ax.n == 4096 && ax.rho.size() == 6 && ax.rho[0] == 4
+    // three of 4^2 in 256 threads.  Not in the batched form, whose size
+    // classes fill the device with many such problems at once (measured
+    // 1-2 % slower there).
+    caps.g4 = single4096 && ax.rho.size() == 6 && ax.rho[0] == 4
                   ? env_int("PAFC_TUNE_GMAX4_4096", dtype == PAFC_C64 ? 1 : 2)
                   : 2;
     // Cut the axis into pieces (G2): an outer piece takes its outermost
@@ -2915,7 +2919,8 @@ pafc_status pafc_batch_plan(pafc_batch_t* out, int count, const int64_t* sizes,
     b->total += n;
     if (!b->plans.count(n)) {
       pafc_plan_t p = nullptr;
-      const PlanLimits lim = form == PAFC_BATCH_PERSISTENT ? persist_limits(dtype) : PlanLimits();
+      PlanLimits lim = form == PAFC_BATCH_PERSISTENT ? persist_limits(dtype) : PlanLimits();
+      lim.batched = true;
       pafc_status st = make_plan(&p, 1, &n, nullptr, dtype, PAFC_PERM_FREE, hip_stream, lim);
       if (st != PAFC_SUCCESS) return fail(st);
       b->plans[n] = p;
